@@ -1,0 +1,224 @@
+"""Python access to the FP64 CPU oracle (``srwcr_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product package.  It shares no code
+with the HIP path.  Each function states the passage of Gong et al. (arXiv
+1804.05061) it follows; the arithmetic itself lives in the C file.
+
+Volumes are numpy arrays shaped (nz, ny, nx) (x fastest in memory); FFD
+displacements are float32 arrays shaped (3, ncz, ncy, ncx), component 0 = x.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "srwcr_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("nf", ctypes.c_int * 3), ("nm", ctypes.c_int * 3), ("n_bins", ctypes.c_int),
+                ("K", ctypes.c_int * 3), ("delta", ctypes.c_int * 3), ("role", ctypes.c_int)]
+
+
+@dataclass(frozen=True)
+class Problem:
+    """Problem statement of Sec. II: grids, L_eps + 1 bins, spatial bins, control spacing.
+
+    role 0: the moving image plays A (the model image); role 1: it plays B
+    (the estimated image) -- Sec. II-E / Table II.  spatial_bins == (1, 1, 1)
+    selects one constant region (a test-only special case)."""
+    fixed_dims: tuple   # (nx, ny, nz)
+    moving_dims: tuple
+    n_bins: int
+    spatial_bins: tuple
+    ctrl_spacing: tuple
+    role: int
+
+    def c(self) -> _Problem:
+        p = _Problem()
+        p.nf[:] = list(self.fixed_dims)
+        p.nm[:] = list(self.moving_dims)
+        p.n_bins = self.n_bins
+        p.K[:] = list(self.spatial_bins)
+        p.delta[:] = list(self.ctrl_spacing)
+        p.role = self.role
+        return p
+
+    @property
+    def ctrl_dims(self) -> tuple:
+        """n_c = floor((N - 1) / delta) + 4 per axis (eq 17 indexing), (ncx, ncy, ncz)."""
+        return tuple((n - 1) // d + 4 for n, d in zip(self.fixed_dims, self.ctrl_spacing))
+
+    @property
+    def n_regions(self) -> int:
+        return int(np.prod(self.spatial_bins))
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        fp = ctypes.POINTER(ctypes.c_float)
+        pp = ctypes.POINTER(_Problem)
+        L.orc_h.restype = ctypes.c_double
+        L.orc_h.argtypes = [ctypes.c_double]
+        L.orc_dh.restype = ctypes.c_double
+        L.orc_dh.argtypes = [ctypes.c_double, ctypes.c_int]
+        L.orc_beta.restype = ctypes.c_double
+        L.orc_beta.argtypes = [ctypes.c_int, ctypes.c_double]
+        L.orc_normalize.restype = None
+        L.orc_normalize.argtypes = [fp, ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_int, fp]
+        L.orc_axis_region_weights.restype = None
+        L.orc_axis_region_weights.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_ffd_T.restype = None
+        L.orc_ffd_T.argtypes = [pp, fp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_sample.restype = ctypes.c_double
+        L.orc_sample.argtypes = [pp, fp, dp, dp]
+        L.orc_warp.restype = None
+        L.orc_warp.argtypes = [pp, fp, fp, dp]
+        L.orc_joint_pdf.restype = ctypes.c_double
+        L.orc_joint_pdf.argtypes = [pp, fp, fp, fp, dp]
+        L.orc_srwcr_from_pdf.restype = ctypes.c_double
+        L.orc_srwcr_from_pdf.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int]
+        L.orc_value.restype = ctypes.c_double
+        L.orc_value.argtypes = [pp, fp, fp, fp]
+        L.orc_gradient.restype = ctypes.c_double
+        L.orc_gradient.argtypes = [pp, fp, fp, fp, ctypes.c_int, dp, dp]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_num_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _f32(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _f64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def h(t: float) -> float:
+    """Second-order Parzen window, eq (5)."""
+    return lib().orc_h(float(t))
+
+
+def dh(kappa: float, side: int) -> float:
+    """dh/dkappa; side -1 left derivative, +1 right derivative."""
+    return lib().orc_dh(float(kappa), int(side))
+
+
+def beta(l: int, t: float) -> float:
+    """Cubic B-spline piece beta_l(t), eq (8)."""
+    return lib().orc_beta(int(l), float(t))
+
+
+def normalize(raw: np.ndarray, lo: float, hi: float, n_bins: int) -> np.ndarray:
+    """Linear min-max normalisation to [0, L_eps] (Sec. II), FP32 arithmetic."""
+    a, ptr = _f32(raw)
+    out = np.empty_like(a)
+    lib().orc_normalize(ptr, a.size, float(lo), float(hi), int(n_bins), _f32(out)[1])
+    return out
+
+
+def axis_region_weights(x: int, N: int, K: int) -> np.ndarray:
+    """Spatial weights of the K nodes of one axis at voxel x, eqs (7, 8)."""
+    w = np.zeros(K, dtype=np.float64)
+    lib().orc_axis_region_weights(int(x), int(N), int(K), _f64(w))
+    return w
+
+
+def ffd_T(P: Problem, ffd: np.ndarray, x: int, y: int, z: int) -> np.ndarray:
+    """T(x; Phi) at one fixed voxel, eqs (8, 17)."""
+    f, fp = _f32(ffd)
+    T = np.zeros(3)
+    lib().orc_ffd_T(ctypes.byref(P.c()), fp, x, y, z, _f64(T))
+    return T
+
+
+def sample(P: Problem, moving: np.ndarray, y) -> tuple:
+    """Trilinear sample of the moving volume at moving-grid coordinates y; returns (value, dM/dy)."""
+    m, mp = _f32(moving)
+    yy = np.asarray(y, dtype=np.float64).copy()
+    g = np.zeros(3)
+    v = lib().orc_sample(ctypes.byref(P.c()), mp, _f64(yy), _f64(g))
+    return v, g
+
+
+def warp(P: Problem, moving: np.ndarray, ffd: np.ndarray) -> np.ndarray:
+    """Backward-warped moving intensity at every fixed voxel (Sec. II-F)."""
+    m, mp = _f32(moving)
+    f, fp = _f32(ffd)
+    nx, ny, nz = P.fixed_dims
+    out = np.zeros((nz, ny, nx))
+    lib().orc_warp(ctypes.byref(P.c()), mp, fp, _f64(out))
+    return out
+
+
+def joint_pdf(P: Problem, fixed: np.ndarray, moving: np.ndarray, ffd: np.ndarray):
+    """Normalised 3-D joint PDF p[r, a, b] of eq (3) and its normaliser Z."""
+    fx, fxp = _f32(fixed)
+    m, mp = _f32(moving)
+    f, fp = _f32(ffd)
+    p = np.zeros((P.n_regions, P.n_bins, P.n_bins))
+    Z = lib().orc_joint_pdf(ctypes.byref(P.c()), fxp, mp, fp, _f64(p))
+    return p, Z
+
+
+def srwcr_from_pdf(p: np.ndarray, which: int = 0) -> float:
+    """SRWCR from a joint PDF: 0 Table I loop, 1 eq (9), 2 eq (11), 3 eq (12)."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    R, nb, _ = p.shape
+    return lib().orc_srwcr_from_pdf(R, nb, _f64(p), int(which))
+
+
+def value(P: Problem, fixed: np.ndarray, moving: np.ndarray, ffd: np.ndarray) -> float:
+    """D = SRWCR(A, B, R), eq (9) evaluated by the Table I loop."""
+    fx, fxp = _f32(fixed)
+    m, mp = _f32(moving)
+    f, fp = _f32(ffd)
+    return lib().orc_value(ctypes.byref(P.c()), fxp, mp, fp)
+
+
+def gradient(P: Problem, fixed: np.ndarray, moving: np.ndarray, ffd: np.ndarray,
+             form: int = 0, want_dDdM: bool = False):
+    """(D, dD/d(displacement)[3, ncz, ncy, ncx]) by eqs (16, 17) with dD/dM from
+    eq (19)/(21) (form 0) or eq (18)/(20) + (26) (form 1)."""
+    fx, fxp = _f32(fixed)
+    m, mp = _f32(moving)
+    f, fp = _f32(ffd)
+    ncx, ncy, ncz = P.ctrl_dims
+    g = np.zeros((3, ncz, ncy, ncx))
+    nx, ny, nz = P.fixed_dims
+    dm = np.zeros((nz, ny, nx)) if want_dDdM else None
+    D = lib().orc_gradient(ctypes.byref(P.c()), fxp, mp, fp, int(form), _f64(g),
+                           _f64(dm) if dm is not None else None)
+    return (D, g, dm) if want_dDdM else (D, g)
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()

@@ -1,0 +1,596 @@
+/*
+ * srwcr_oracle.c -- plain, slow FP64 CPU oracle for the spatially
+ * region-weighted correlation ratio (SRWCR) of Gong et al. (arXiv 1804.05061)
+ * and its gradient with respect to cubic B-spline FFD displacements.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this file.  The HIP product path shares no
+ * code, header, table or helper with it, and never calls it.
+ *
+ * Every step is the paper's definition written out in double precision:
+ *   - intensities normalised to [0, L]                      (Sec. II)
+ *   - FFD T(x; Phi), node indexing and B-spline pieces      (Sec. II, eqs 8, 17)
+ *   - backward warping of M by trilinear interpolation      (Sec. II-F; reading)
+ *   - Parzen window h                                       (eq 5)
+ *   - cubic B-spline spatial distribution w(r, x)           (eqs 7, 8)
+ *   - full 3-D joint PDF p(a, b, r) and Z                   (eqs 3, 4)
+ *   - SRWCR by the Table I loop, and by eqs 9, 11, 12       (Sec. II-D)
+ *   - dD/dM by the triple sums of eq 19 (M is B) and eq 21 (M is A),
+ *     and, as a second form, by eqs 18 / 20 built from dp/dM of eq 26
+ *   - chain rule to the control points                      (eqs 16, 17)
+ * The joint PDF is kept literally: R x (L+1) x (L+1) doubles.  Per voxel only
+ * the bins where h (or h') can be non-zero are visited, which is exact.
+ *
+ * Readings where the paper is silent (listed with reasons in the design notes):
+ *   - normalisation: linear min-max, evaluated in the IEEE single precision
+ *     operations s = fl(fl(I - lo) * fl(L / (hi - lo))), clamped to [0, L];
+ *   - spatial lattice: K nodes per axis, spacing (N-1)/(K-3), node j at
+ *     (j-1)*spacing;  K == 1 on all axes selects one constant region (test);
+ *   - moving sample: trilinear, coordinates clamped to [0, M-1] per axis,
+ *     gradient 0 along a clamped axis; grids of other size are mapped by
+ *     y = (T + 1/2) * M / N - 1/2;
+ *   - derivative of h at its kinks: one-sided, the side that corresponds to
+ *     increasing the sample (left derivative in kappa), inward at s = L;
+ *   - an empty intensity bin (no mass in region r) contributes nothing; in
+ *     eq 21 its conditional mean is the voxel's own B-moment (the one-sided
+ *     limit), so that its squared deviation vanishes;
+ *   - a region with p(r) == 0 or sigma_r^2 < 1e-12 contributes nothing.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int nf[3];      /* fixed grid (x, y, z), x fastest */
+    int nm[3];      /* moving grid */
+    int n_bins;     /* L_eps + 1 */
+    int K[3];       /* spatial bins per axis (1,1,1 = one constant region) */
+    int delta[3];   /* FFD control spacing in fixed voxels */
+    int role;       /* 0: the moving image is A (model); 1: it is B (estimated) */
+} orc_problem;
+
+#define VAR_EPS 1e-12
+
+/* ---------------------------------------------------------------- eq (5) */
+double orc_h(double t)
+{
+    double u = fabs(t);
+    if (u < 0.5) return -1.8 * u * u - 0.1 * u + 1.0;
+    if (u < 1.0) return 1.8 * u * u - 3.7 * u + 1.9;
+    return 0.0;
+}
+
+/* dh/dkappa.  side < 0: left derivative (piece on (k - eps, k]);
+ * side > 0: right derivative (piece on [k, k + eps)). */
+double orc_dh(double k, int side)
+{
+    if (side < 0) {
+        if (k <= -1.0) return 0.0;
+        if (k <= -0.5) return 3.6 * k + 3.7;
+        if (k <= 0.0) return -3.6 * k + 0.1;
+        if (k <= 0.5) return -3.6 * k - 0.1;
+        if (k <= 1.0) return 3.6 * k - 3.7;
+        return 0.0;
+    }
+    if (k < -1.0) return 0.0;
+    if (k < -0.5) return 3.6 * k + 3.7;
+    if (k < 0.0) return -3.6 * k + 0.1;
+    if (k < 0.5) return -3.6 * k - 0.1;
+    if (k < 1.0) return 3.6 * k - 3.7;
+    return 0.0;
+}
+
+/* ---------------------------------------------------------------- eq (8) */
+double orc_beta(int l, double t)
+{
+    switch (l) {
+    case 0: return (1.0 - t) * (1.0 - t) * (1.0 - t) / 6.0;
+    case 1: return (3.0 * t * t * t - 6.0 * t * t + 4.0) / 6.0;
+    case 2: return (-3.0 * t * t * t + 3.0 * t * t + 3.0 * t + 1.0) / 6.0;
+    case 3: return t * t * t / 6.0;
+    }
+    return 0.0;
+}
+
+/* ------------------------------------------- Sec. II: normalise to [0, L] */
+void orc_normalize(const float *in, long n, double lo, double hi, int n_bins, float *out)
+{
+    float lo_f = (float)lo;
+    float scale_f = (float)((double)(n_bins - 1) / (hi - lo));
+    float L = (float)(n_bins - 1);
+    for (long i = 0; i < n; ++i) {
+        float d = in[i] - lo_f;      /* one IEEE single subtraction */
+        float s = d * scale_f;       /* one IEEE single multiplication */
+        if (s < 0.0f) s = 0.0f;
+        if (s > L) s = L;
+        out[i] = s;
+    }
+}
+
+/* ------------------------------------------------- control grid (eq 17) */
+void orc_ctrl_dims(const orc_problem *P, int nc[3])
+{
+    for (int e = 0; e < 3; ++e) nc[e] = (P->nf[e] - 1) / P->delta[e] + 4;
+}
+
+/* ------------------------------------- spatial weights w(r, x), eqs (7, 8)
+ * Weights of the K nodes of one axis at voxel coordinate x in [0, N-1]. */
+void orc_axis_region_weights(int x, int N, int K, double *w)
+{
+    for (int j = 0; j < K; ++j) w[j] = 0.0;
+    if (K == 1) { w[0] = 1.0; return; }
+    long num = (long)x * (long)(K - 3);
+    int c = (int)(num / (long)(N - 1));
+    if (c > K - 4) c = K - 4;
+    double t = (double)(num - (long)c * (long)(N - 1)) / (double)(N - 1);
+    for (int l = 0; l < 4; ++l) w[c + l] = orc_beta(l, t);
+}
+
+/* ----------------------------------------------- T(x; Phi), eqs (8, 17)
+ * Literal 64-term sum.  ffd holds displacements (fixed-voxel units) as
+ * float[3][ncz][ncy][ncx]; stored node index = paper index + 1. */
+void orc_ffd_T(const orc_problem *P, const float *ffd, int x, int y, int z, double T[3])
+{
+    int nc[3];
+    orc_ctrl_dims(P, nc);
+    long ncell = (long)nc[0] * nc[1] * nc[2];
+    int p[3] = {x / P->delta[0], y / P->delta[1], z / P->delta[2]};
+    double eta[3] = {(double)(x % P->delta[0]) / P->delta[0],
+                     (double)(y % P->delta[1]) / P->delta[1],
+                     (double)(z % P->delta[2]) / P->delta[2]};
+    T[0] = x; T[1] = y; T[2] = z;
+    for (int n = 0; n < 4; ++n)
+        for (int m = 0; m < 4; ++m)
+            for (int l = 0; l < 4; ++l) {
+                double b = orc_beta(l, eta[0]) * orc_beta(m, eta[1]) * orc_beta(n, eta[2]);
+                long idx = ((long)(p[2] + n) * nc[1] + (p[1] + m)) * nc[0] + (p[0] + l);
+                for (int e = 0; e < 3; ++e) T[e] += b * (double)ffd[e * ncell + idx];
+            }
+}
+
+/* ------------------------------------- backward warping: trilinear sample
+ * y: continuous moving-grid coordinates.  Returns M(y); dsdy gets dM/dy. */
+double orc_sample(const orc_problem *P, const float *mov, const double y[3], double dsdy[3])
+{
+    int i0[3], clamped[3];
+    double f[3];
+    for (int e = 0; e < 3; ++e) {
+        int M = P->nm[e];
+        double v = y[e];
+        clamped[e] = (v < 0.0 || v > (double)(M - 1));
+        if (v < 0.0) v = 0.0;
+        if (v > (double)(M - 1)) v = (double)(M - 1);
+        int i = (int)floor(v);
+        if (i > M - 2) i = M - 2;
+        i0[e] = i;
+        f[e] = v - i;
+    }
+    double val = 0.0, g[3] = {0.0, 0.0, 0.0};
+    for (int cz = 0; cz < 2; ++cz)
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+                long idx = ((long)(i0[2] + cz) * P->nm[1] + (i0[1] + cy)) * P->nm[0] + (i0[0] + cx);
+                double V = mov[idx];
+                double wx = cx ? f[0] : 1.0 - f[0];
+                double wy = cy ? f[1] : 1.0 - f[1];
+                double wz = cz ? f[2] : 1.0 - f[2];
+                val += wx * wy * wz * V;
+                g[0] += (cx ? 1.0 : -1.0) * wy * wz * V;
+                g[1] += (cy ? 1.0 : -1.0) * wx * wz * V;
+                g[2] += (cz ? 1.0 : -1.0) * wx * wy * V;
+            }
+    for (int e = 0; e < 3; ++e) dsdy[e] = clamped[e] ? 0.0 : g[e];
+    return val;
+}
+
+/* fixed voxel -> moving coordinates through T, plus dy/dT per axis */
+static void map_to_moving(const orc_problem *P, const double T[3], double y[3], double dydT[3])
+{
+    for (int e = 0; e < 3; ++e) {
+        if (P->nm[e] == P->nf[e]) {
+            y[e] = T[e];
+            dydT[e] = 1.0;
+        } else {
+            dydT[e] = (double)P->nm[e] / (double)P->nf[e];
+            y[e] = (T[e] + 0.5) * dydT[e] - 0.5;
+        }
+    }
+}
+
+/* warped, normalised moving intensity at every fixed voxel (clamped to [0, L]) */
+static double warped_sample(const orc_problem *P, const float *mov, const float *ffd,
+                            int x, int y, int z, double dsdT[3])
+{
+    double T[3], yy[3], dydT[3], g[3];
+    orc_ffd_T(P, ffd, x, y, z, T);
+    map_to_moving(P, T, yy, dydT);
+    double s = orc_sample(P, mov, yy, g);
+    double L = (double)(P->n_bins - 1);
+    if (s < 0.0) s = 0.0;
+    if (s > L) s = L;
+    if (dsdT) for (int e = 0; e < 3; ++e) dsdT[e] = g[e] * dydT[e];
+    return s;
+}
+
+void orc_warp(const orc_problem *P, const float *mov, const float *ffd, double *out)
+{
+    for (int z = 0; z < P->nf[2]; ++z)
+        for (int y = 0; y < P->nf[1]; ++y)
+            for (int x = 0; x < P->nf[0]; ++x)
+                out[((long)z * P->nf[1] + y) * P->nf[0] + x] = warped_sample(P, mov, ffd, x, y, z, NULL);
+}
+
+/* bins a with possibly non-zero h(a - s) or h'(a - s): floor(s)-1 .. floor(s)+2 */
+static int tap_bins(double s, int L, int *bins)
+{
+    int f = (int)floor(s), n = 0;
+    for (int a = f - 1; a <= f + 2; ++a)
+        if (a >= 0 && a <= L) bins[n++] = a;
+    return n;
+}
+
+/* one-sided convention for d/ds: right derivative in s (left in kappa),
+ * inward (left in s) at the top of the range s = L */
+static int deriv_side(double s, int L) { return (s >= (double)L) ? +1 : -1; }
+
+static int n_regions(const orc_problem *P) { return P->K[0] * P->K[1] * P->K[2]; }
+
+static void voxel_AB(const orc_problem *P, const float *fix, const float *mov, const float *ffd,
+                     int x, int y, int z, double *A, double *B, double dsdT[3])
+{
+    double sF = fix[((long)z * P->nf[1] + y) * P->nf[0] + x];
+    double sM = warped_sample(P, mov, ffd, x, y, z, dsdT);
+    if (P->role == 0) { *A = sM; *B = sF; }
+    else { *A = sF; *B = sM; }
+}
+
+/* ------------------------------------------ eq (3): 3-D joint PDF and Z
+ * p: R x nb x nb, p[(r * nb + a) * nb + b].  Returns Z. */
+double orc_joint_pdf(const orc_problem *P, const float *fix, const float *mov, const float *ffd, double *p)
+{
+    int R = n_regions(P), nb = P->n_bins, L = nb - 1;
+    long cells = (long)R * nb * nb;
+    memset(p, 0, sizeof(double) * cells);
+    int nthreads = 1;
+#ifdef _OPENMP
+    nthreads = omp_get_max_threads();
+#endif
+    double *priv = (double *)calloc((size_t)nthreads * cells, sizeof(double));
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *pp = priv + (long)tid * cells;
+        double *wx = (double *)malloc(sizeof(double) * P->K[0]);
+        double *wy = (double *)malloc(sizeof(double) * P->K[1]);
+        double *wz = (double *)malloc(sizeof(double) * P->K[2]);
+#pragma omp for schedule(static)
+        for (int z = 0; z < P->nf[2]; ++z) {
+            orc_axis_region_weights(z, P->nf[2], P->K[2], wz);
+            for (int y = 0; y < P->nf[1]; ++y) {
+                orc_axis_region_weights(y, P->nf[1], P->K[1], wy);
+                for (int x = 0; x < P->nf[0]; ++x) {
+                    orc_axis_region_weights(x, P->nf[0], P->K[0], wx);
+                    double A, B;
+                    voxel_AB(P, fix, mov, ffd, x, y, z, &A, &B, NULL);
+                    int ab[4], bb[4];
+                    int na = tap_bins(A, L, ab), nbb = tap_bins(B, L, bb);
+                    for (int k = 0; k < P->K[2]; ++k) {
+                        if (wz[k] == 0.0) continue;
+                        for (int j = 0; j < P->K[1]; ++j) {
+                            if (wy[j] == 0.0) continue;
+                            for (int i = 0; i < P->K[0]; ++i) {
+                                if (wx[i] == 0.0) continue;
+                                double w = wx[i] * wy[j] * wz[k];
+                                int r = (k * P->K[1] + j) * P->K[0] + i;
+                                for (int ia = 0; ia < na; ++ia) {
+                                    double ha = orc_h(ab[ia] - A);
+                                    if (ha == 0.0) continue;
+                                    for (int ib = 0; ib < nbb; ++ib) {
+                                        double hb = orc_h(bb[ib] - B);
+                                        if (hb == 0.0) continue;
+                                        pp[((long)r * nb + ab[ia]) * nb + bb[ib]] += w * ha * hb;
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        free(wx); free(wy); free(wz);
+    }
+    for (int t = 0; t < nthreads; ++t)            /* fixed merge order */
+        for (long c = 0; c < cells; ++c) p[c] += priv[(long)t * cells + c];
+    free(priv);
+    double Z = 0.0;
+    for (long c = 0; c < cells; ++c) Z += p[c];
+    if (Z > 0.0)
+        for (long c = 0; c < cells; ++c) p[c] /= Z;
+    return Z;
+}
+
+/* per-region statistics of eqs (4, 10) derived from the normalised PDF */
+typedef struct {
+    double pr;     /* p(r) */
+    double mu;     /* mu_r */
+    double var;    /* sigma_r^2 */
+    double cr;     /* CR(A, B | r) */
+    int ok;        /* p(r) > 0 and sigma_r^2 >= VAR_EPS */
+} region_stats;
+
+static void region_statistics(int R, int nb, const double *p, region_stats *st, double *pa, double *mua)
+{
+    /* pa, mua: R x nb; p_r(a) and mu_r(a) (0 where p_r(a) == 0) */
+    for (int r = 0; r < R; ++r) {
+        const double *q = p + (long)r * nb * nb;
+        double pr = 0.0;
+        for (int c = 0; c < nb * nb; ++c) pr += q[c];
+        st[r].pr = pr;
+        st[r].ok = 0;
+        st[r].mu = st[r].var = st[r].cr = 0.0;
+        for (int a = 0; a < nb; ++a) { pa[r * nb + a] = 0.0; mua[r * nb + a] = 0.0; }
+        if (!(pr > 0.0)) continue;
+        double mu = 0.0, m2 = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            double pb = 0.0;
+            for (int a = 0; a < nb; ++a) pb += q[a * nb + b] / pr;
+            mu += b * pb;
+            m2 += (double)b * b * pb;
+        }
+        double var = m2 - mu * mu;
+        st[r].mu = mu;
+        st[r].var = var;
+        for (int a = 0; a < nb; ++a) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int b = 0; b < nb; ++b) { s0 += q[a * nb + b] / pr; s1 += b * q[a * nb + b] / pr; }
+            pa[r * nb + a] = s0;
+            mua[r * nb + a] = (s0 > 0.0) ? s1 / s0 : 0.0;
+        }
+        if (var < VAR_EPS) continue;
+        st[r].ok = 1;
+        double c = 0.0;          /* Table I inner double loop */
+        for (int a = 0; a < nb; ++a)
+            for (int b = 0; b < nb; ++b)
+                c += ((double)b * b - mua[r * nb + a] * mua[r * nb + a]) * (q[a * nb + b] / pr) / var;
+        st[r].cr = 1.0 - c;
+    }
+}
+
+/* SRWCR from the joint PDF.  which: 0 Table I loop, 1 eq (9), 2 eq (11), 3 eq (12) */
+double orc_srwcr_from_pdf(int R, int nb, const double *p, int which)
+{
+    double E = 0.0;
+    double *pa = (double *)malloc(sizeof(double) * nb), *pb = (double *)malloc(sizeof(double) * nb);
+    double *mua = (double *)malloc(sizeof(double) * nb);
+    for (int r = 0; r < R; ++r) {
+        const double *q = p + (long)r * nb * nb;
+        double pr = 0.0;                                  /* eq (4) */
+        for (int c = 0; c < nb * nb; ++c) pr += q[c];
+        if (!(pr > 0.0)) continue;
+        for (int a = 0; a < nb; ++a) { pa[a] = 0.0; pb[a] = 0.0; }
+        for (int a = 0; a < nb; ++a)
+            for (int b = 0; b < nb; ++b) { pa[a] += q[a * nb + b] / pr; pb[b] += q[a * nb + b] / pr; }
+        double mu = 0.0, e2 = 0.0;                        /* eq (10) */
+        for (int b = 0; b < nb; ++b) { mu += b * pb[b]; e2 += (double)b * b * pb[b]; }
+        double var = e2 - mu * mu;
+        if (var < VAR_EPS) continue;
+        for (int a = 0; a < nb; ++a) {
+            double s1 = 0.0;
+            for (int b = 0; b < nb; ++b) s1 += b * q[a * nb + b] / pr;
+            mua[a] = (pa[a] > 0.0) ? s1 / pa[a] : 0.0;
+        }
+        if (which == 0) {                                 /* Table I, lines 11-17 */
+            double cr = 0.0;
+            for (int a = 0; a < nb; ++a)
+                for (int b = 0; b < nb; ++b)
+                    cr += ((double)b * b - mua[a] * mua[a]) * (q[a * nb + b] / pr) / var;
+            E += pr * cr;
+        } else if (which == 1) {                          /* eq (9) */
+            double s = 0.0;
+            for (int a = 0; a < nb; ++a) {
+                if (!(pa[a] > 0.0)) continue;
+                double s2 = 0.0;
+                for (int b = 0; b < nb; ++b) s2 += (double)b * b * q[a * nb + b] / pr;
+                double var_a = s2 / pa[a] - mua[a] * mua[a];
+                s += var_a * pa[a];
+            }
+            E += pr * s / var;
+        } else if (which == 2) {                          /* eq (11) */
+            double s = 0.0;
+            for (int a = 0; a < nb; ++a) s += pa[a] * mua[a] * mua[a];
+            E += pr * (e2 - s) / var;
+        } else {                                          /* eq (12) */
+            for (int a = 0; a < nb; ++a)
+                for (int b = 0; b < nb; ++b)
+                    E += ((double)b * b - mua[a] * mua[a]) / var * q[a * nb + b];
+        }
+    }
+    free(pa); free(pb); free(mua);
+    return E;
+}
+
+double orc_value(const orc_problem *P, const float *fix, const float *mov, const float *ffd)
+{
+    int R = n_regions(P), nb = P->n_bins;
+    double *p = (double *)malloc(sizeof(double) * (size_t)R * nb * nb);
+    orc_joint_pdf(P, fix, mov, ffd, p);
+    double D = orc_srwcr_from_pdf(R, nb, p, 0);
+    free(p);
+    return D;
+}
+
+/* --------------------------------------------- dD/dM at one voxel
+ * form 0: eq (19) (M is B) or eq (21) (M is A), literal triple sums.
+ * form 1: eq (18) / eq (20) with dp(a,b,r)/dM from eq (26). */
+static double dDdM_voxel(const orc_problem *P, int form, double A, double B, double Z,
+                         const double *wx, const double *wy, const double *wz,
+                         const region_stats *st, const double *pa, const double *mua)
+{
+    int nb = P->n_bins, L = nb - 1;
+    int ab[4], bb[4];
+    int na = tap_bins(A, L, ab), nbb = tap_bins(B, L, bb);
+    double m1B = 0.0;                              /* sum_b b h(b - B) */
+    for (int ib = 0; ib < nbb; ++ib) m1B += bb[ib] * orc_h(bb[ib] - B);
+    int sideA = deriv_side(A, L), sideB = deriv_side(B, L);
+    double g = 0.0;
+    for (int k = 0; k < P->K[2]; ++k) {
+        if (wz[k] == 0.0) continue;
+        for (int j = 0; j < P->K[1]; ++j) {
+            if (wy[j] == 0.0) continue;
+            for (int i = 0; i < P->K[0]; ++i) {
+                if (wx[i] == 0.0) continue;
+                int r = (k * P->K[1] + j) * P->K[0] + i;
+                if (!st[r].ok) continue;
+                double w = wx[i] * wy[j] * wz[k];
+                const region_stats *s = &st[r];
+                if (form == 0) {
+                    for (int ia = 0; ia < na; ++ia)
+                        for (int ib = 0; ib < nbb; ++ib) {
+                            int a = ab[ia], b = bb[ib];
+                            if (P->role == 1) {            /* eq (19) */
+                                double c = ((1.0 - s->cr) * ((double)b * b - 2.0 * b * s->mu)
+                                            + 2.0 * b * mua[r * nb + a] - (double)b * b) / s->var;
+                                g += c * w * orc_h(a - A) * orc_dh(b - B, sideB) / Z;
+                            } else {                       /* eq (21) */
+                                double mu_a = (pa[r * nb + a] > 0.0) ? mua[r * nb + a] : m1B;
+                                double c = (2.0 * b - mu_a) / s->var * mu_a;
+                                g += c * w * orc_h(b - B) * orc_dh(a - A, sideA) / Z;
+                            }
+                        }
+                } else {
+                    /* dp(a,b,r)/dM for this voxel, eq (26), on the tap rectangle */
+                    double dp[4][4];
+                    for (int ia = 0; ia < na; ++ia)
+                        for (int ib = 0; ib < nbb; ++ib) {
+                            int a = ab[ia], b = bb[ib];
+                            if (P->role == 1) dp[ia][ib] = -w * orc_h(a - A) * orc_dh(b - B, sideB) / Z;
+                            else dp[ia][ib] = -w * orc_dh(a - A, sideA) * orc_h(b - B) / Z;
+                        }
+                    double pr = s->pr;
+                    if (P->role == 1) {                    /* eq (18) with (22), (23) */
+                        double t_b2 = 0.0, t_b1 = 0.0, t_mu = 0.0;
+                        for (int ib = 0; ib < nbb; ++ib) {
+                            double dpb = 0.0;              /* d p_r(b) / dB */
+                            for (int ia = 0; ia < na; ++ia) dpb += dp[ia][ib] / pr;
+                            t_b2 += (double)bb[ib] * bb[ib] * dpb;
+                            t_b1 += (double)bb[ib] * dpb;
+                        }
+                        for (int ia = 0; ia < na; ++ia) {
+                            int a = ab[ia];
+                            double p_a = pa[r * nb + a];
+                            if (!(p_a > 0.0)) continue;
+                            double dmu = 0.0;              /* eq (23) */
+                            for (int ib = 0; ib < nbb; ++ib) dmu += bb[ib] * dp[ia][ib] / pr;
+                            dmu /= p_a;
+                            t_mu += 2.0 * p_a * mua[r * nb + a] * dmu;
+                        }
+                        double dvar = t_b2 - 2.0 * s->mu * t_b1;   /* eq (22) */
+                        g += pr * ((t_b2 - t_mu) / s->var - dvar / s->var * (1.0 - s->cr));
+                    } else {                               /* eq (20) with (28) */
+                        double t = 0.0;
+                        for (int ia = 0; ia < na; ++ia) {
+                            int a = ab[ia];
+                            double dpa = 0.0, sb = 0.0;
+                            for (int ib = 0; ib < nbb; ++ib) { dpa += dp[ia][ib] / pr; sb += bb[ib] * dp[ia][ib] / pr; }
+                            double p_a = pa[r * nb + a];
+                            if (p_a > 0.0) {
+                                double mu_a = mua[r * nb + a];
+                                double dmu = -dpa / p_a * mu_a + sb / p_a;
+                                t += 2.0 * p_a * mu_a * dmu + mu_a * mu_a * dpa;
+                            } else {
+                                t += m1B * m1B * dpa;      /* empty bin: limit mu = m1(B) */
+                            }
+                        }
+                        g += -pr / s->var * t;
+                    }
+                }
+            }
+        }
+    }
+    return g;
+}
+
+/* ------------------------------------------------ gradient, eqs (16, 17)
+ * grad: float64[3][ncz][ncy][ncx] = dD/d(displacement).
+ * dDdM_out (optional): dD/dM at every fixed voxel.  Returns D. */
+double orc_gradient(const orc_problem *P, const float *fix, const float *mov, const float *ffd,
+                    int form, double *grad, double *dDdM_out)
+{
+    int R = n_regions(P), nb = P->n_bins;
+    int nc[3];
+    orc_ctrl_dims(P, nc);
+    long ncell = (long)nc[0] * nc[1] * nc[2];
+    double *p = (double *)malloc(sizeof(double) * (size_t)R * nb * nb);
+    double Z = orc_joint_pdf(P, fix, mov, ffd, p);
+    double D = orc_srwcr_from_pdf(R, nb, p, 0);
+    region_stats *st = (region_stats *)malloc(sizeof(region_stats) * R);
+    double *pa = (double *)malloc(sizeof(double) * R * nb), *mua = (double *)malloc(sizeof(double) * R * nb);
+    region_statistics(R, nb, p, st, pa, mua);
+    free(p);
+    memset(grad, 0, sizeof(double) * 3 * ncell);
+    int nthreads = 1;
+#ifdef _OPENMP
+    nthreads = omp_get_max_threads();
+#endif
+    double *priv = (double *)calloc((size_t)nthreads * 3 * ncell, sizeof(double));
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *gg = priv + (long)tid * 3 * ncell;
+        double *wx = (double *)malloc(sizeof(double) * P->K[0]);
+        double *wy = (double *)malloc(sizeof(double) * P->K[1]);
+        double *wz = (double *)malloc(sizeof(double) * P->K[2]);
+#pragma omp for schedule(static)
+        for (int z = 0; z < P->nf[2]; ++z) {
+            orc_axis_region_weights(z, P->nf[2], P->K[2], wz);
+            for (int y = 0; y < P->nf[1]; ++y) {
+                orc_axis_region_weights(y, P->nf[1], P->K[1], wy);
+                for (int x = 0; x < P->nf[0]; ++x) {
+                    orc_axis_region_weights(x, P->nf[0], P->K[0], wx);
+                    double A, B, dsdT[3];
+                    voxel_AB(P, fix, mov, ffd, x, y, z, &A, &B, dsdT);
+                    double g = dDdM_voxel(P, form, A, B, Z, wx, wy, wz, st, pa, mua);
+                    if (dDdM_out) dDdM_out[((long)z * P->nf[1] + y) * P->nf[0] + x] = g;
+                    if (g == 0.0) continue;
+                    /* eq (16) with the Jacobian of eq (17) */
+                    int pc[3] = {x / P->delta[0], y / P->delta[1], z / P->delta[2]};
+                    double eta[3] = {(double)(x % P->delta[0]) / P->delta[0],
+                                     (double)(y % P->delta[1]) / P->delta[1],
+                                     (double)(z % P->delta[2]) / P->delta[2]};
+                    for (int n = 0; n < 4; ++n)
+                        for (int m = 0; m < 4; ++m)
+                            for (int l = 0; l < 4; ++l) {
+                                double b = orc_beta(l, eta[0]) * orc_beta(m, eta[1]) * orc_beta(n, eta[2]);
+                                long idx = ((long)(pc[2] + n) * nc[1] + (pc[1] + m)) * nc[0] + (pc[0] + l);
+                                for (int e = 0; e < 3; ++e) gg[e * ncell + idx] += g * dsdT[e] * b;
+                            }
+                }
+            }
+        }
+        free(wx); free(wy); free(wz);
+    }
+    for (int t = 0; t < nthreads; ++t)
+        for (long c = 0; c < 3 * ncell; ++c) grad[c] += priv[(long)t * 3 * ncell + c];
+    free(priv);
+    free(st); free(pa); free(mua);
+    return D;
+}
+
+/* number of threads the parallel loops use (reported by the CPU baseline) */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

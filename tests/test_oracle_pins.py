@@ -1,0 +1,390 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests compares the oracle with itself: each one checks a closed
+form, an invariant, a special case computed by an independent routine, brute
+force on a tiny input, or finite differences.  Citations are to Gong et al.,
+arXiv 1804.05061.
+"""
+import numpy as np
+import pytest
+
+from workloads import synth
+
+
+def P(orc, nf, nb=32, K=(4, 4, 4), d=(5, 5, 5), role=0, nm=None):
+    return orc.Problem(tuple(nf), tuple(nm or nf), nb, tuple(K), tuple(d), role)
+
+
+def cubic_bspline_kernel(u):
+    """Centred cubic B-spline B3(u) (independent closed form, not eq 8's pieces)."""
+    u = abs(u)
+    if u < 1:
+        return 2.0 / 3.0 - u * u + 0.5 * u ** 3
+    if u < 2:
+        return (2 - u) ** 3 / 6.0
+    return 0.0
+
+
+# ------------------------------------------------------------------ eq (5)
+def test_parzen_window_partition_and_continuity(orc):
+    rng = np.random.default_rng(0)
+    L = 31
+    for s in np.concatenate([rng.uniform(0, L, 200), np.arange(0, L + 0.25, 0.5)]):
+        tot = sum(orc.h(a - s) for a in range(L + 1))
+        assert abs(tot - 1.0) < 1e-14, s
+    assert orc.h(0.0) == 1.0
+    for t0 in (0.5, 1.0):        # continuity at the piece joints
+        assert abs(orc.h(t0 - 1e-12) - orc.h(t0 + 1e-12)) < 1e-10
+    assert orc.h(1.0) == 0.0 and orc.h(1.5) == 0.0
+    assert min(orc.h(t) for t in np.linspace(-1.2, 1.2, 1001)) >= 0.0
+
+
+def test_parzen_one_sided_derivatives_match_differences(orc):
+    eps = 1e-7
+    for k in np.linspace(-1.4, 1.4, 57):
+        left = (orc.h(k) - orc.h(k - eps)) / eps
+        right = (orc.h(k + eps) - orc.h(k)) / eps
+        assert abs(orc.dh(k, -1) - left) < 1e-5, k
+        assert abs(orc.dh(k, +1) - right) < 1e-5, k
+    # kinks at 0 and +-1: the two sides differ
+    assert orc.dh(0.0, -1) == pytest.approx(0.1) and orc.dh(0.0, +1) == pytest.approx(-0.1)
+
+
+# ------------------------------------------------------------------ eq (8)
+def test_bspline_pieces_are_the_cubic_bspline(orc):
+    for t in np.linspace(0, 1, 23):
+        assert abs(sum(orc.beta(l, t) for l in range(4)) - 1.0) < 1e-15
+        for l in range(4):
+            assert abs(orc.beta(l, t) - cubic_bspline_kernel(t + 1 - l)) < 1e-15
+
+
+def test_region_weights_partition_kernel_and_mirror(orc):
+    for N, K in [(64, 4), (256, 6), (128, 6), (17, 5), (9, 8), (192, 5)]:
+        spacing = (N - 1) / (K - 3)
+        for x in range(N):
+            w = orc.axis_region_weights(x, N, K)
+            assert abs(w.sum() - 1.0) < 1e-14
+            for j in range(K):                       # eq (7): B3 centred on node j at (j-1)*spacing
+                assert abs(w[j] - cubic_bspline_kernel((x - (j - 1) * spacing) / spacing)) < 1e-12
+            wm = orc.axis_region_weights(N - 1 - x, N, K)
+            assert np.allclose(w, wm[::-1], atol=1e-13)
+
+
+# ----------------------------------------------------------- eq (17), FFD
+def test_ffd_constant_and_zero_displacement(orc):
+    p = P(orc, (13, 11, 9), d=(4, 3, 5))
+    ncx, ncy, ncz = p.ctrl_dims
+    c = np.array([0.75, -1.25, 2.5], dtype=np.float32)
+    ffd = np.broadcast_to(c[:, None, None, None], (3, ncz, ncy, ncx)).copy()
+    for (x, y, z) in [(0, 0, 0), (12, 10, 8), (5, 7, 3), (3, 2, 4)]:
+        T = orc.ffd_T(p, ffd, x, y, z)
+        assert np.allclose(T, np.array([x, y, z]) + c, atol=1e-13)
+        T0 = orc.ffd_T(p, np.zeros_like(ffd), x, y, z)
+        assert np.array_equal(T0, [x, y, z])
+
+
+def test_ffd_linear_precision(orc):
+    """Cubic B-splines reproduce linear functions: coefficients sampled from an
+    affine map at node positions (paper index i at i*delta) give that map."""
+    p = P(orc, (21, 17, 13), d=(5, 4, 3))
+    ncx, ncy, ncz = p.ctrl_dims
+    Amat = np.array([[0.01, -0.02, 0.03], [0.0, 0.015, -0.01], [-0.02, 0.005, 0.01]])
+    ffd = np.zeros((3, ncz, ncy, ncx), dtype=np.float64)
+    for k in range(ncz):
+        for j in range(ncy):
+            for i in range(ncx):
+                pos = np.array([(i - 1) * 5, (j - 1) * 4, (k - 1) * 3], dtype=np.float64)
+                ffd[:, k, j, i] = Amat @ pos
+    ffd = ffd.astype(np.float32)
+    for (x, y, z) in [(0, 0, 0), (20, 16, 12), (7, 9, 5), (13, 3, 11)]:
+        T = orc.ffd_T(p, ffd, x, y, z)
+        exp = np.array([x, y, z]) + Amat @ np.array([x, y, z])
+        assert np.allclose(T, exp, atol=2e-6)        # float32 coefficients
+
+
+def test_integer_shift_warp_is_a_shift(orc):
+    rng = np.random.default_rng(1)
+    nx, ny, nz = 12, 10, 8
+    mov = rng.uniform(0, 31, size=(nz, ny, nx)).astype(np.float32)
+    p = P(orc, (nx, ny, nz), d=(3, 3, 3))
+    ncx, ncy, ncz = p.ctrl_dims
+    ffd = np.zeros((3, ncz, ncy, ncx), dtype=np.float32)
+    ffd[0] += 2.0
+    ffd[1] -= 1.0
+    w = orc.warp(p, mov, ffd)
+    assert np.allclose(w[:, 1:, :nx - 2], mov[:, :ny - 1, 2:], atol=1e-12)
+    w0 = orc.warp(p, mov, np.zeros_like(ffd))
+    assert np.array_equal(w0, mov.astype(np.float64))
+
+
+# ------------------------------------------------------- trilinear sample
+def test_trilinear_reproduces_affine_and_gradient(orc):
+    nx, ny, nz = 7, 6, 5
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    vol = (1.5 + 0.25 * x - 0.5 * y + 0.125 * z).astype(np.float32)
+    p = P(orc, (nx, ny, nz))
+    rng = np.random.default_rng(2)
+    for _ in range(50):
+        yy = rng.uniform([0, 0, 0], [nx - 1, ny - 1, nz - 1])
+        v, g = orc.sample(p, vol, yy)
+        assert abs(v - (1.5 + 0.25 * yy[0] - 0.5 * yy[1] + 0.125 * yy[2])) < 1e-12
+        assert np.allclose(g, [0.25, -0.5, 0.125], atol=1e-12)
+    v, g = orc.sample(p, vol, [-3.0, 2.5, 10.0])     # clamped x and z
+    assert abs(v - (1.5 + 0 - 1.25 + 0.5)) < 1e-12
+    assert g[0] == 0.0 and g[2] == 0.0 and abs(g[1] + 0.5) < 1e-12
+
+
+# ----------------------------------------------------- normalisation
+def test_normalize_is_ieee_single_formula(orc):
+    rng = np.random.default_rng(3)
+    raw = rng.normal(0, 300, size=10000).astype(np.float32)
+    lo, hi = float(raw.min()), float(raw.max())
+    out = orc.normalize(raw, lo, hi, 64)
+    exp = (raw - np.float32(lo)) * np.float32(63.0 / (hi - lo))    # numpy float32 ops round per op
+    exp = np.clip(exp, 0, 63).astype(np.float32)
+    assert np.array_equal(out, exp)
+    assert out.min() == 0.0 and abs(out.max() - 63.0) < 1e-4
+
+
+# ---------------------------------------------------------- eqs (3), (4)
+def test_joint_pdf_sums_and_region_marginal(orc):
+    w1 = synth.blobs(n=16)
+    p = P(orc, (16, 16, 16), K=(4, 5, 4))
+    f = orc.normalize(w1.fixed, w1.fixed.min(), w1.fixed.max(), 32)
+    m = orc.normalize(w1.moving, w1.moving.min(), w1.moving.max(), 32)
+    ffd = synth.random_ffd(p.ctrl_dims, 0.7, 1)
+    pdf, Z = orc.joint_pdf(p, f, m, ffd)
+    assert abs(pdf.sum() - 1.0) < 1e-13
+    assert abs(Z - 16 ** 3) < 1e-9                       # sum_r w = 1 at every voxel
+    # p(r) = (1/Z) sum_x w(r, x): independent of the images
+    pdf2, _ = orc.joint_pdf(p, m, f, np.zeros_like(ffd))
+    pr_exp = np.zeros(p.n_regions)
+    for z in range(16):
+        wz = orc.axis_region_weights(z, 16, 4)
+        for y in range(16):
+            wy = orc.axis_region_weights(y, 16, 5)
+            for x in range(16):
+                wx = orc.axis_region_weights(x, 16, 4)
+                pr_exp += np.einsum("k,j,i->kji", wz, wy, wx).ravel()
+    pr_exp /= 16 ** 3
+    assert np.allclose(pdf.sum(axis=(1, 2)), pr_exp, atol=1e-14)
+    assert np.allclose(pdf2.sum(axis=(1, 2)), pr_exp, atol=1e-14)
+
+
+def test_joint_pdf_brute_force_all_bins(orc):
+    """Literal eq (3) over every (a, b, r) on a tiny volume vs the oracle's tap-restricted sum."""
+    rng = np.random.default_rng(4)
+    nx, ny, nz, nb = 5, 4, 4, 8
+    p = P(orc, (nx, ny, nz), nb=nb, K=(4, 4, 5), d=(2, 2, 2), role=1)
+    f = rng.uniform(0, nb - 1, size=(nz, ny, nx)).astype(np.float32)
+    f[0, 0, 0], f[1, 1, 1] = 0.0, nb - 1.0                 # range ends
+    m = rng.uniform(0, nb - 1, size=(nz, ny, nx)).astype(np.float32)
+    ffd = synth.random_ffd(p.ctrl_dims, 0.6, 4)
+    pdf, Z = orc.joint_pdf(p, f, m, ffd)
+    warped = orc.warp(p, m, ffd)
+    ref = np.zeros_like(pdf)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                w = np.einsum("k,j,i->kji", orc.axis_region_weights(z, nz, 5), orc.axis_region_weights(y, ny, 4),
+                              orc.axis_region_weights(x, nx, 4)).ravel()
+                A, B = float(f[z, y, x]), warped[z, y, x]        # role 1: moving is B
+                ha = np.array([orc.h(a - A) for a in range(nb)])
+                hb = np.array([orc.h(b - B) for b in range(nb)])
+                ref += w[:, None, None] * ha[None, :, None] * hb[None, None, :]
+    assert abs(ref.sum() - Z) < 1e-10
+    assert np.allclose(pdf, ref / ref.sum(), atol=1e-15)
+
+
+# ------------------------------------------------- eqs (9), (11), (12)
+@pytest.mark.parametrize("role", [0, 1])
+def test_srwcr_forms_agree_and_range(orc, role):
+    w1 = synth.blobs(n=20)
+    p = P(orc, (20, 20, 20), K=(4, 4, 5), role=role)
+    f = orc.normalize(w1.fixed, w1.fixed.min(), w1.fixed.max(), 32)
+    m = orc.normalize(w1.moving, w1.moving.min(), w1.moving.max(), 32)
+    ffd = synth.random_ffd(p.ctrl_dims, 1.0, 2)
+    pdf, Z = orc.joint_pdf(p, f, m, ffd)
+    vals = [orc.srwcr_from_pdf(pdf, w) for w in range(4)]
+    assert max(vals) - min(vals) < 1e-13
+    assert 0.0 <= vals[0] <= 1.0
+    assert abs(orc.value(p, f, m, ffd) - vals[0]) < 1e-15
+
+
+# ------------------------------------- exact functional dependence: D = 0
+@pytest.mark.parametrize("role", [0, 1])
+def test_D_zero_for_exact_function_on_bin_centres(orc, role):
+    """B = f(A) with both images integer-valued (bin centres): every regional
+    conditional variance is zero, so D = 0 and 1 - D = 1 (Sec. II-D)."""
+    rng = np.random.default_rng(5)
+    nx, ny, nz, nb = 12, 11, 10, 16
+    labels = rng.integers(0, nb, size=(nz, ny, nx))
+    fmap = rng.permutation(nb)                               # injective, non-monotone
+    A = labels.astype(np.float32)
+    B = fmap[labels].astype(np.float32)
+    p = P(orc, (nx, ny, nz), nb=nb, K=(4, 4, 4), d=(3, 3, 3), role=role)
+    fixed, moving = (B, A) if role == 0 else (A, B)
+    ffd = np.zeros((3,) + p.ctrl_dims[::-1], dtype=np.float32)
+    D = orc.value(p, fixed, moving, ffd)
+    assert abs(D) < 1e-14
+    # a non-functional pair is strictly positive
+    D2 = orc.value(p, fixed, rng.permutation(moving.ravel()).reshape(moving.shape), ffd)
+    assert D2 > 1e-3
+
+
+# ---------------------------------- one constant region: D = 1 - CR, eq (2)
+def global_cr_numpy(A, B, nb):
+    """Correlation ratio of eq (2) from a 2-D Parzen histogram (independent numpy)."""
+    def weights(s):
+        s = s.ravel().astype(np.float64)
+        k = np.minimum(np.floor(s), nb - 2).astype(int)
+        t = s - k
+        w0 = np.where(t < 0.5, 1 - 0.1 * t - 1.8 * t * t, 1.9 - 3.7 * t + 1.8 * t * t)
+        Wm = np.zeros((s.size, nb))
+        Wm[np.arange(s.size), k] += w0
+        Wm[np.arange(s.size), k + 1] += 1 - w0
+        return Wm
+    H = weights(A).T @ weights(B)                       # (a, b)
+    H /= H.sum()
+    pa, pb = H.sum(1), H.sum(0)
+    b = np.arange(nb)
+    mu = (b * pb).sum()
+    var = (b * b * pb).sum() - mu * mu
+    nz = pa > 0
+    mua = (H[nz] @ b) / pa[nz]
+    vara = (H[nz] @ (b * b)) / pa[nz] - mua ** 2
+    return 1.0 - (vara * pa[nz]).sum() / var
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_single_region_is_global_correlation_ratio(orc, role):
+    w1 = synth.blobs(n=18)
+    nb = 32
+    f = orc.normalize(w1.fixed, w1.fixed.min(), w1.fixed.max(), nb)
+    m = orc.normalize(w1.moving, w1.moving.min(), w1.moving.max(), nb)
+    p = P(orc, (18, 18, 18), nb=nb, K=(1, 1, 1), role=role)
+    ffd = synth.random_ffd(p.ctrl_dims, 1.0, 3)
+    D = orc.value(p, f, m, ffd)
+    warped = orc.warp(p, m, ffd)
+    A, B = (warped, f) if role == 0 else (f, warped)
+    assert abs(D - (1.0 - global_cr_numpy(A, B, nb))) < 1e-13
+
+
+# -------------------------------------------- affine rescaling invariance
+@pytest.mark.parametrize("role", [0, 1])
+def test_affine_rescaling_of_moving_leaves_D_unchanged(orc, role):
+    """An increasing affine map is removed exactly by the min-max normalisation;
+    a decreasing one flips s -> L - s, an exact symmetry of both roles."""
+    w1 = synth.blobs(n=16)
+    nb = 32
+    raw_m = np.rint(31 * (w1.moving - w1.moving.min()) / (w1.moving.max() - w1.moving.min())).astype(np.float32)
+    f = orc.normalize(w1.fixed, w1.fixed.min(), w1.fixed.max(), nb)
+    p = P(orc, (16, 16, 16), nb=nb, K=(4, 4, 4), role=role)
+    ffd = synth.random_ffd(p.ctrl_dims, 1.0, 5)
+    D0 = orc.value(p, f, orc.normalize(raw_m, 0, 31, nb), ffd)
+    up = (2 * raw_m + 5).astype(np.float32)               # exact in float32
+    D1 = orc.value(p, f, orc.normalize(up, 5, 67, nb), ffd)
+    down = (31 - raw_m).astype(np.float32)
+    D2 = orc.value(p, f, orc.normalize(down, 0, 31, nb), ffd)
+    assert abs(D1 - D0) < 1e-14
+    assert abs(D2 - D0) < 1e-13
+    # a non-linear monotone map is not an exact symmetry (bins are linear in intensity)
+    sq = (raw_m ** 2).astype(np.float32)
+    D3 = orc.value(p, f, orc.normalize(sq, 0, 961, nb), ffd)
+    assert abs(D3 - D0) > 1e-6
+
+
+# ------------------------------------------------------ gradient algebra
+@pytest.mark.parametrize("role", [0, 1])
+def test_gradient_eq19_21_match_eq18_20(orc, role):
+    w1 = synth.blobs(n=14)
+    nb = 16
+    f = orc.normalize(w1.fixed, w1.fixed.min(), w1.fixed.max(), nb)
+    m = orc.normalize(w1.moving, w1.moving.min(), w1.moving.max(), nb)
+    p = P(orc, (14, 14, 14), nb=nb, K=(4, 5, 4), d=(4, 4, 4), role=role)
+    ffd = synth.random_ffd(p.ctrl_dims, 0.8, 6)
+    D0, g0, dm0 = orc.gradient(p, f, m, ffd, form=0, want_dDdM=True)
+    D1, g1, dm1 = orc.gradient(p, f, m, ffd, form=1, want_dDdM=True)
+    assert D0 == D1
+    assert np.abs(dm0 - dm1).max() <= 1e-12 * np.abs(dm0).max()
+    assert np.linalg.norm(g0 - g1) <= 1e-12 * np.linalg.norm(g0)
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_gradient_central_differences_16cube(orc, role):
+    """Central differences of the oracle value on 16^3 smooth blobs (delta 5,
+    7^3 control grid, K = 4, 32 bins, Phi ~ N(0, 1 vox), h = 1e-4)."""
+    fr, mr = synth.smooth_pair((16, 16, 16), k=role)
+    nb = 32
+    f = orc.normalize(fr, fr.min(), fr.max(), nb)
+    m = orc.normalize(mr, mr.min(), mr.max(), nb)
+    p = P(orc, (16, 16, 16), nb=nb, K=(4, 4, 4), d=(5, 5, 5), role=role)
+    ffd = synth.random_ffd(p.ctrl_dims, 1.0, 8 + role)
+    D, g = orc.gradient(p, f, m, ffd)
+    rng = np.random.default_rng(9)
+    flat = np.argsort(-np.abs(g).ravel())
+    idx = np.concatenate([flat[:60], rng.choice(flat[60:], 60, replace=False)])
+    hstep = 1e-4
+    fd = []
+    for i in idx:
+        e = np.zeros(g.size, dtype=np.float64)
+        e[i] = hstep
+        fp_ = (ffd.astype(np.float64).ravel() + e).astype(np.float32)
+        fm_ = (ffd.astype(np.float64).ravel() - e).astype(np.float32)
+        hh = (fp_.astype(np.float64) - fm_.astype(np.float64))[i]
+        fd.append((orc.value(p, f, m, fp_.reshape(ffd.shape)) - orc.value(p, f, m, fm_.reshape(ffd.shape))) / hh)
+    fd = np.array(fd)
+    an = g.ravel()[idx]
+    rel = np.linalg.norm(fd - an) / np.linalg.norm(an)
+    assert rel < 1e-4, rel
+
+
+# ------------------------------------------------ known stationary points
+def test_zero_gradient_separated_levels_role_A(orc):
+    """(Z-A): role A, piecewise-constant labels on non-integer bin positions at
+    least 2 bins apart and B = f(A): every tap stays inside a one-bin-wide
+    plateau of the regional means, so dD/dA = 0 at every voxel and the FFD
+    gradient vanishes exactly at Phi = 0."""
+    rng = np.random.default_rng(10)
+    nx, ny, nz, nb = 12, 10, 9, 32
+    levels = np.array([2.3, 6.6, 11.4, 17.8, 25.2])
+    lab = (np.floor(np.arange(nx)[None, None, :] / 3) + np.floor(np.arange(ny)[None, :, None] / 4)
+           + np.floor(np.arange(nz)[:, None, None] / 3)).astype(int) % len(levels)
+    lab = np.broadcast_to(lab, (nz, ny, nx))
+    A = levels[lab].astype(np.float32)
+    B = levels[rng.permutation(len(levels))][lab].astype(np.float32)
+    p = P(orc, (nx, ny, nz), nb=nb, K=(4, 4, 4), d=(3, 3, 3), role=0)
+    ffd = np.zeros((3,) + p.ctrl_dims[::-1], dtype=np.float32)
+    D, g = orc.gradient(p, B, A, ffd)
+    assert D > 1e-6
+    assert np.abs(g).max() < 1e-15
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_mirror_ramp_gradient_symmetry(orc, role):
+    """(Z-B): M a ramp along x, F an odd profile about the centre, lattices
+    mirror-symmetric (delta | N-1): mirror + intensity flip is a symmetry, so
+    g_y = g_z = 0 and g_x is antisymmetric under x -> mirror."""
+    nx, ny, nz, nb = 26, 6, 6, 32
+    xs = np.arange(nx, dtype=np.float64)
+    # moving: s = 19/16 x + 21/32, exact in float32, never on a bin edge, and
+    # L - s(x) = s(25 - x) exactly; linear in x, so one-sided trilinear
+    # differences at the on-grid samples of Phi = 0 equal the two-sided ones
+    ramp = np.broadcast_to((xs * 19.0 / 16.0 + 21.0 / 32.0)[None, None, :], (nz, ny, nx)).astype(np.float32)
+    # fixed: an odd profile about the centre on a 1/256 grid, F(25 - x) = L - F(x) exactly
+    half = np.round(256 * (15.5 + 15.5 * np.sin(np.pi * (xs[:13] - 12.5) / 25.0))) / 256.0
+    prof = np.concatenate([half, 31.0 - half[::-1]])
+    odd = np.broadcast_to(prof[None, None, :], (nz, ny, nx)).astype(np.float32)
+    p = P(orc, (nx, ny, nz), nb=nb, K=(4, 4, 4), d=(5, 5, 5), role=role)
+    ffd = np.zeros((3,) + p.ctrl_dims[::-1], dtype=np.float32)
+    D, g = orc.gradient(p, odd, ramp, ffd)
+    scale = np.abs(g[0]).max()
+    assert scale > 1e-8
+    assert np.abs(g[1]).max() <= 1e-12 * scale and np.abs(g[2]).max() <= 1e-12 * scale
+    # stored node i sits at (i - 1) * delta; the mirror x -> (nx - 1) - x maps
+    # node i to node (ncx - 2) - i; node ncx - 1 carries no weight at all.
+    gx = g[0]
+    n = gx.shape[2]
+    assert np.abs(gx[:, :, n - 1]).max() == 0.0
+    assert np.abs(gx[:, :, :n - 1] + gx[:, :, n - 2::-1]).max() <= 1e-12 * scale
+    assert abs(gx.sum()) <= 1e-12 * np.abs(gx).sum()
