@@ -1,0 +1,177 @@
+/*
+ * srwcr.h -- C ABI of the MI355X (gfx950) implementation of the spatially
+ * region-weighted correlation ratio (SRWCR) and its analytic gradient with
+ * respect to cubic B-spline free-form-deformation (FFD) displacements,
+ * after Gong et al., "Non-rigid image registration using spatially
+ * region-weighted correlation ratio and GPU-acceleration" (arXiv 1804.05061).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Volumes are dense, x fastest: element (x, y, z) of an (nx, ny, nz) grid
+ *    sits at index (z * ny + y) * nx + x.
+ *  - "Device pointer" means memory allocated on the current HIP device (for
+ *    example by PyTorch); the caller owns it, the library never frees it.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  The
+ *    value, gradient and warp calls only enqueue work on it and return; results
+ *    are valid once the stream reaches them.  No call here allocates device
+ *    memory after srwcr_plan_create, and none synchronises the device except
+ *    where stated.
+ *  - Every function returns an srwcr_status; on failure nothing was enqueued,
+ *    and srwcr_last_error() returns a thread-local message.
+ *  - FFD displacements are float32 [3][ncz][ncy][ncx] (component 0 = x), in
+ *    fixed-voxel units; T(x) = x + sum beta_l beta_m beta_n d (Sec. II, eqs 8
+ *    and 17).  Stored node index = the paper's node index + 1, so
+ *    nc = floor((N - 1) / delta) + 4 per axis.
+ */
+#ifndef SRWCR_H
+#define SRWCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SRWCR_OK = 0,
+    SRWCR_E_INVALID_ARG = -1,   /* a size, count, role or dtype out of range, or a NULL pointer */
+    SRWCR_E_DEGENERATE = -2,    /* a normalisation range with hi <= lo */
+    SRWCR_E_WORKSPACE = -3,     /* workspace smaller than srwcr_workspace_bytes() */
+    SRWCR_E_HIP = -4,           /* a HIP runtime call failed (message has the HIP error string) */
+    SRWCR_E_UNSUPPORTED = -5,   /* a valid request this build does not handle */
+    SRWCR_E_NONFINITE = -6,     /* NaN or Inf found where finite data is required */
+    SRWCR_E_LINESEARCH = -7     /* register_lbfgs: the line search found no acceptable step */
+} srwcr_status;
+
+/* Which image plays the model image A and which the estimated image B of
+ * Sec. II-A.  Table II of the paper finds the moving image as A best. */
+typedef enum { SRWCR_MOVING_AS_A = 0, SRWCR_MOVING_AS_B = 1 } srwcr_role;
+
+/* Storage type of a normalised intensity volume. */
+typedef enum { SRWCR_F32 = 0, SRWCR_F16 = 1, SRWCR_BF16 = 2 } srwcr_dtype;
+
+/* The problem statement of Sec. II: minimise D(F, M o T(.; Phi)) over Phi. */
+typedef struct {
+    int32_t fixed_dims[3];     /* (nx, ny, nz) of F, each >= 2 */
+    int32_t moving_dims[3];    /* (mx, my, mz) of M, each >= 2 */
+    int32_t n_bins;            /* L_eps + 1 intensity bins, 2..64 (the paper uses 32) */
+    int32_t spatial_bins[3];   /* K cubic B-spline spatial bins per axis, each 4..64 */
+    int32_t ctrl_spacing[3];   /* FFD control spacing delta in fixed voxels, each >= 1 */
+    int32_t role;              /* srwcr_role */
+    int32_t fixed_dtype;       /* srwcr_dtype of the normalised fixed volume */
+    int32_t moving_dtype;      /* srwcr_dtype of the normalised moving volume */
+} srwcr_problem;
+
+typedef struct srwcr_plan srwcr_plan;
+
+/* Number of FFD control nodes per axis: floor((N - 1) / delta) + 4 (eq 17). */
+int srwcr_ctrl_dims(const srwcr_problem *prob, int32_t out_nc[3]);
+
+/* Validate `prob` and build a plan: per-axis spatial-weight tables, FFD weight
+ * tables and the launch geometry, uploaded once to the current device.  The
+ * plan is immutable and may be shared by concurrent calls on different
+ * streams provided each call has its own workspace.  Spatial bins: K nodes per
+ * axis at spacing (N - 1) / (K - 3), node j at (j - 1) * spacing (eqs 7, 8). */
+int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out);
+void srwcr_plan_destroy(srwcr_plan *plan);
+
+/* Device workspace bytes srwcr_eval / srwcr_grad need (moment slots in FP64,
+ * per-region tables, gradient accumulators).  Callers allocate it once. */
+size_t srwcr_workspace_bytes(const srwcr_plan *plan);
+
+/* a1 -- intensity normalisation of Sec. II.  out[i] = clamp(fl32(fl32(in[i]
+ * - (float)lo) * (float)(L / (hi - lo))), 0, L), L = n_bins - 1, stored in
+ * `out_dtype` (round to nearest even for F16 / BF16).  in: device float32[n];
+ * out: device buffer of n elements of out_dtype.  Runs once per image pair. */
+int srwcr_normalize(const float *in, int64_t n, double lo, double hi, int32_t n_bins,
+                    void *out, int32_t out_dtype, void *stream);
+
+/* Minimum and maximum of a device float32 volume (a helper for choosing the
+ * normalisation range; synchronises `stream` and writes host doubles).
+ * Returns SRWCR_E_NONFINITE when the volume holds NaN or Inf. */
+int srwcr_minmax(const float *in, int64_t n, double *lo, double *hi, void *stream);
+
+/* SRWCR value D (eq 9; a dissimilarity in [0, 1], 0 for a perfect functional
+ * dependence).  fixed, moving: device volumes normalised to [0, L] in the
+ * plan's dtypes; ffd: device float32 displacements; d_value: device double.
+ * Steps: FFD evaluation, trilinear backward warping of M (coordinates clamped
+ * to the grid; grids of different size mapped by y = (T + 1/2) M / N - 1/2),
+ * second-order Parzen window (eq 5), cubic B-spline spatial weights (eq 7),
+ * joint moments of the 3-D PDF (eq 3) and the per-region correlation ratios
+ * (eqs 4, 9-12) finalised in FP64. */
+int srwcr_eval(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd,
+               double *d_value, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Value and gradient dD/d(displacement) (eqs 15-21): d_value as srwcr_eval,
+ * d_grad a device float32 array shaped like ffd.  The warped intensities are
+ * recomputed, never stored. */
+int srwcr_grad(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd,
+               double *d_value, float *d_grad, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Backward-warped moving volume on the fixed grid: out[x] = M(T(x)) with the
+ * interpolation of srwcr_eval (Sec. II-F).  moving: normalised device volume in
+ * the plan's moving dtype; out: device float32 volume of the fixed dims. */
+int ffd_warp(const srwcr_plan *plan, const void *moving, const float *ffd, float *out, void *stream);
+
+/* Options and report of register_lbfgs (Sec. II-F). */
+typedef struct {
+    int32_t levels;            /* pyramid levels, 1..3 (paper: 3) */
+    int32_t max_iter[3];       /* per level, coarsest first (paper: 200, 200, 120) */
+    int32_t history;           /* L-BFGS corrections m (paper: 5) */
+    int32_t stall_window;      /* stop when D is stable over this many iterations (paper: 20) */
+    double stall_tol;          /* relative stability threshold of D over the window */
+    double bending_weight;     /* w_p of eq (1); 0 disables the bending-energy term */
+} srwcr_lbfgs_opts;
+
+typedef struct {
+    int32_t iterations[3];     /* iterations run per level */
+    int32_t evaluations[3];    /* value+gradient evaluations per level */
+    double initial_value[3];   /* cost at the start of each level */
+    double final_value[3];     /* cost at the end of each level */
+    int32_t status[3];         /* srwcr_status per level */
+} srwcr_lbfgs_report;
+
+/* Fill `opts` with the paper's settings (3 levels, 200/200/120, m = 5, 20). */
+void srwcr_lbfgs_default_opts(srwcr_lbfgs_opts *opts);
+
+/* Multi-resolution L-BFGS registration of Sec. II-F minimising eq (1).
+ * fixed, moving: device float32 volumes already normalised to [0, L] (the
+ * finest level); ffd_inout: host float32 displacements at the finest level,
+ * read as the start and overwritten with the result.  Coarser levels use
+ * half-resolution volumes (Gaussian sigma 1 voxel, then every other voxel) and
+ * the same control spacing in level voxels; displacements are carried up by
+ * doubling and B-spline subdivision.  Synchronous; allocates its own temporaries. */
+int register_lbfgs(const srwcr_problem *prob, const float *fixed, const float *moving, float *ffd_inout,
+                   const srwcr_lbfgs_opts *opts, srwcr_lbfgs_report *report, void *stream);
+
+/* ---- diagnostics (used by the test-suite; not needed for registration) ---- */
+
+/* Run only the value pass and copy the raw joint moments of eq (3) summed over
+ * b -- per region r and A-bin a: P = sum w h(a - A), S1 = sum w h(a - A) m1(B),
+ * S2 = sum w h(a - A) m2(B) with m1, m2 the Parzen moments of B -- into the
+ * device array d_moments, double [R][n_bins][3], R = Kx Ky Kz (x fastest). */
+int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd,
+                        double *d_moments, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Launch geometry of a plan: number of work items and LDS bytes per workgroup
+ * of the value and gradient passes.  Any output pointer may be NULL. */
+int srwcr_plan_info(const srwcr_plan *plan, int32_t *n_items, int32_t *value_lds, int32_t *grad_lds);
+
+/* Per-kernel timing of srwcr_grad with HIP events on the caller's stream.
+ * srwcr_profile(plan, 1) starts a session (up to 4096 calls are recorded, the
+ * first call creates the events), srwcr_profile(plan, 0) stops recording.
+ * srwcr_profile_read synchronises the recorded events and returns the summed
+ * milliseconds of the five phases -- zeroing, value pass, finalisation,
+ * gradient pass, gradient output -- and the number of calls recorded.  Not
+ * thread-safe: profile one stream at a time. */
+int srwcr_profile(const srwcr_plan *plan, int32_t enable);
+int srwcr_profile_read(const srwcr_plan *plan, double ms[5], int32_t *calls);
+
+/* Thread-local description of the last failure on this thread. */
+const char *srwcr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SRWCR_H */

@@ -1,0 +1,255 @@
+"""SRWCR on MI355X: the spatially region-weighted correlation ratio and its
+analytic gradient with respect to cubic B-spline FFD displacements
+(Gong et al., arXiv 1804.05061), computed by hand-written gfx950 kernels
+behind the C ABI of include/srwcr.h.
+
+This module only marshals arguments: PyTorch provides device memory and the
+current stream; every step of the computation runs in libsrwcr.so.  Volumes
+are torch tensors shaped (nz, ny, nx) on the GPU; FFD displacements are
+float32 tensors shaped (3, ncz, ncy, ncx) in fixed-voxel units.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import SrwcrError
+
+MOVING_AS_A, MOVING_AS_B = 0, 1
+F32, F16, BF16 = 0, 1, 2
+_TORCH_DT = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
+_DT_OF = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+
+__all__ = ["Problem", "Plan", "normalize", "minmax", "register_lbfgs", "LbfgsOptions", "SrwcrError",
+           "MOVING_AS_A", "MOVING_AS_B", "F32", "F16", "BF16", "SRWCRLoss"]
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need_cuda(t: torch.Tensor, name: str, dtype=None, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+@dataclass(frozen=True)
+class Problem:
+    """Problem statement (Sec. II): grids (x, y, z), L_eps + 1 intensity bins,
+    spatial bins per axis, FFD control spacing, role of the moving image and
+    storage dtypes of the normalised volumes."""
+    fixed_dims: tuple
+    moving_dims: tuple
+    n_bins: int
+    spatial_bins: tuple
+    ctrl_spacing: tuple
+    role: int = MOVING_AS_A
+    fixed_dtype: int = F32
+    moving_dtype: int = F32
+
+    def c(self) -> _lib.SrwcrProblem:
+        p = _lib.SrwcrProblem()
+        p.fixed_dims[:] = [int(v) for v in self.fixed_dims]
+        p.moving_dims[:] = [int(v) for v in self.moving_dims]
+        p.n_bins = int(self.n_bins)
+        p.spatial_bins[:] = [int(v) for v in self.spatial_bins]
+        p.ctrl_spacing[:] = [int(v) for v in self.ctrl_spacing]
+        p.role = int(self.role)
+        p.fixed_dtype = int(self.fixed_dtype)
+        p.moving_dtype = int(self.moving_dtype)
+        return p
+
+    @property
+    def ctrl_dims(self) -> tuple:
+        nc = (ctypes.c_int32 * 3)()
+        _lib.check(_lib.load().srwcr_ctrl_dims(ctypes.byref(self.c()), nc))
+        return tuple(nc)
+
+    @property
+    def fixed_shape(self):
+        return tuple(self.fixed_dims[::-1])
+
+    @property
+    def moving_shape(self):
+        return tuple(self.moving_dims[::-1])
+
+    @property
+    def ffd_shape(self):
+        return (3,) + tuple(self.ctrl_dims[::-1])
+
+
+class Plan:
+    """A plan (device tables and launch geometry) plus its own workspace."""
+
+    def __init__(self, problem: Problem, device=None):
+        self.problem = problem
+        L = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        with torch.cuda.device(self.device):
+            h = ctypes.c_void_p()
+            _lib.check(L.srwcr_plan_create(ctypes.byref(problem.c()), ctypes.byref(h)))
+            self._h = h
+            self.workspace_bytes = int(L.srwcr_workspace_bytes(h))
+            self.workspace = torch.zeros(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().srwcr_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        n, v, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.load().srwcr_plan_info(self._h, ctypes.byref(n), ctypes.byref(v), ctypes.byref(g)))
+        return {"n_items": n.value, "value_lds": v.value, "grad_lds": g.value}
+
+    def _check_inputs(self, fixed, moving, ffd):
+        p = self.problem
+        _need_cuda(fixed, "fixed", _TORCH_DT[p.fixed_dtype], p.fixed_shape)
+        _need_cuda(moving, "moving", _TORCH_DT[p.moving_dtype], p.moving_shape)
+        _need_cuda(ffd, "ffd", torch.float32, p.ffd_shape)
+
+    def eval(self, fixed, moving, ffd, out=None):
+        """SRWCR value D (eq 9) as a 0-dim float64 device tensor."""
+        self._check_inputs(fixed, moving, ffd)
+        if out is None:
+            out = torch.empty((), dtype=torch.float64, device=fixed.device)
+        _lib.check(_lib.load().srwcr_eval(self._h, _ptr(fixed), _ptr(moving), _ptr(ffd), _ptr(out),
+                                          _ptr(self.workspace), self.workspace_bytes, _stream()))
+        return out
+
+    def grad(self, fixed, moving, ffd, value_out=None, grad_out=None):
+        """(D, dD/d displacement) -- eqs (15)-(21)."""
+        self._check_inputs(fixed, moving, ffd)
+        if value_out is None:
+            value_out = torch.empty((), dtype=torch.float64, device=fixed.device)
+        if grad_out is None:
+            grad_out = torch.empty(self.problem.ffd_shape, dtype=torch.float32, device=fixed.device)
+        _lib.check(_lib.load().srwcr_grad(self._h, _ptr(fixed), _ptr(moving), _ptr(ffd), _ptr(value_out),
+                                          _ptr(grad_out), _ptr(self.workspace), self.workspace_bytes, _stream()))
+        return value_out, grad_out
+
+    def warp(self, moving, ffd, out=None):
+        """Backward-warped moving volume on the fixed grid (float32)."""
+        p = self.problem
+        _need_cuda(moving, "moving", _TORCH_DT[p.moving_dtype], p.moving_shape)
+        _need_cuda(ffd, "ffd", torch.float32, p.ffd_shape)
+        if out is None:
+            out = torch.empty(p.fixed_shape, dtype=torch.float32, device=moving.device)
+        _lib.check(_lib.load().ffd_warp(self._h, _ptr(moving), _ptr(ffd), _ptr(out), _stream()))
+        return out
+
+    def profile(self, enable: bool):
+        """Start (True) or stop (False) per-kernel HIP-event timing of grad()."""
+        _lib.check(_lib.load().srwcr_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """Summed milliseconds per phase of the grad() calls recorded so far."""
+        ms = (ctypes.c_double * 5)()
+        n = ctypes.c_int32()
+        _lib.check(_lib.load().srwcr_profile_read(self._h, ms, ctypes.byref(n)))
+        names = ["zero", "value", "finalize", "grad", "grad_out"]
+        return {"calls": n.value, **{k: ms[i] for i, k in enumerate(names)}}
+
+    def debug_moments(self, fixed, moving, ffd):
+        """Raw (P, S1, S2) moment slots [R, n_bins, 3] of the value pass."""
+        self._check_inputs(fixed, moving, ffd)
+        R = int(torch.tensor(self.problem.spatial_bins).prod())
+        out = torch.empty((R, self.problem.n_bins, 3), dtype=torch.float64, device=fixed.device)
+        _lib.check(_lib.load().srwcr_debug_moments(self._h, _ptr(fixed), _ptr(moving), _ptr(ffd), _ptr(out),
+                                                   _ptr(self.workspace), self.workspace_bytes, _stream()))
+        return out
+
+
+def normalize(raw: torch.Tensor, lo: float, hi: float, n_bins: int, dtype=torch.float32) -> torch.Tensor:
+    """Intensities mapped linearly to [0, L_eps] (Sec. II), stored in `dtype`."""
+    _need_cuda(raw, "raw", torch.float32)
+    out = torch.empty(raw.shape, dtype=dtype, device=raw.device)
+    _lib.check(_lib.load().srwcr_normalize(_ptr(raw), raw.numel(), float(lo), float(hi), int(n_bins), _ptr(out),
+                                           _DT_OF[dtype], _stream()))
+    return out
+
+
+def minmax(raw: torch.Tensor):
+    """(min, max) of a float32 device volume; raises on NaN / Inf."""
+    _need_cuda(raw, "raw", torch.float32)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _lib.check(_lib.load().srwcr_minmax(_ptr(raw), raw.numel(), ctypes.byref(lo), ctypes.byref(hi), _stream()))
+    return lo.value, hi.value
+
+
+@dataclass
+class LbfgsOptions:
+    levels: int = 3
+    max_iter: tuple = (200, 200, 120)
+    history: int = 5
+    stall_window: int = 20
+    stall_tol: float = 1e-6
+    bending_weight: float = 0.0
+
+    def c(self) -> _lib.SrwcrLbfgsOpts:
+        o = _lib.SrwcrLbfgsOpts()
+        o.levels = self.levels
+        o.max_iter[:] = list(self.max_iter)
+        o.history = self.history
+        o.stall_window = self.stall_window
+        o.stall_tol = self.stall_tol
+        o.bending_weight = self.bending_weight
+        return o
+
+
+def register_lbfgs(problem: Problem, fixed: torch.Tensor, moving: torch.Tensor, ffd, options=None):
+    """Multi-resolution L-BFGS registration (Sec. II-F).  `ffd` is a host float32
+    numpy array (3, ncz, ncy, ncx), updated in place; returns the report."""
+    import numpy as np
+    _need_cuda(fixed, "fixed", torch.float32, problem.fixed_shape)
+    _need_cuda(moving, "moving", torch.float32, problem.moving_shape)
+    if not (isinstance(ffd, np.ndarray) and ffd.dtype == np.float32 and ffd.flags.c_contiguous):
+        raise TypeError("ffd must be a C-contiguous float32 numpy array")
+    opts = (options or LbfgsOptions()).c()
+    rep = _lib.SrwcrLbfgsReport()
+    _lib.check(_lib.load().register_lbfgs(ctypes.byref(problem.c()), _ptr(fixed), _ptr(moving),
+                                          ffd.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts),
+                                          ctypes.byref(rep), _stream()))
+    return {"iterations": list(rep.iterations), "evaluations": list(rep.evaluations),
+            "initial_value": list(rep.initial_value), "final_value": list(rep.final_value),
+            "status": list(rep.status)}
+
+
+class SRWCRLoss(torch.autograd.Function):
+    """D = SRWCR as a differentiable function of the FFD displacements.
+
+    forward runs srwcr_eval; backward re-runs srwcr_grad (the warped volume is
+    recomputed, never stored) and scales by grad_output."""
+
+    @staticmethod
+    def forward(ctx, ffd, fixed, moving, plan):
+        ctx.plan = plan
+        ctx.save_for_backward(ffd, fixed, moving)
+        return plan.eval(fixed, moving, ffd.detach().contiguous()).clone()
+
+    @staticmethod
+    def backward(ctx, grad_output):
+        ffd, fixed, moving = ctx.saved_tensors
+        _, g = ctx.plan.grad(fixed, moving, ffd.detach().contiguous())
+        return (g * grad_output.to(torch.float32)), None, None, None

@@ -1,0 +1,514 @@
+// srwcr_host.cpp -- C ABI of the SRWCR library: validation, plans, workspace
+// layout and launch sequences (see include/srwcr.h for the contract).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "srwcr.h"
+#include "srwcr_internal.h"
+
+using namespace srwcr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(SRWCR_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int validate_problem(const srwcr_problem *p)
+{
+    if (!p) return fail(SRWCR_E_INVALID_ARG, "problem is NULL");
+    for (int e = 0; e < 3; ++e) {
+        if (p->fixed_dims[e] < 2 || p->moving_dims[e] < 2)
+            return fail(SRWCR_E_INVALID_ARG, "grid axis %d must have at least 2 voxels (fixed %d, moving %d)", e,
+                        p->fixed_dims[e], p->moving_dims[e]);
+        if (p->spatial_bins[e] < 4 || p->spatial_bins[e] > 64)
+            return fail(SRWCR_E_INVALID_ARG, "spatial_bins[%d] = %d outside 4..64", e, p->spatial_bins[e]);
+        if (p->ctrl_spacing[e] < 1)
+            return fail(SRWCR_E_INVALID_ARG, "ctrl_spacing[%d] = %d must be >= 1", e, p->ctrl_spacing[e]);
+        if ((int64_t)p->fixed_dims[e] > (1 << 20) || (int64_t)p->moving_dims[e] > (1 << 20))
+            return fail(SRWCR_E_INVALID_ARG, "grid axis %d too long", e);
+    }
+    if (p->n_bins < 2 || p->n_bins > kMaxBins)
+        return fail(SRWCR_E_INVALID_ARG, "n_bins = %d outside 2..%d", p->n_bins, kMaxBins);
+    if (p->role != SRWCR_MOVING_AS_A && p->role != SRWCR_MOVING_AS_B)
+        return fail(SRWCR_E_INVALID_ARG, "role = %d is neither MOVING_AS_A nor MOVING_AS_B", p->role);
+    for (int d : {p->fixed_dtype, p->moving_dtype})
+        if (d < SRWCR_F32 || d > SRWCR_BF16) return fail(SRWCR_E_INVALID_ARG, "dtype %d unknown", d);
+    return SRWCR_OK;
+}
+
+double bspline_piece(int l, double t)
+{
+    switch (l) {
+    case 0: return (1 - t) * (1 - t) * (1 - t) / 6.0;
+    case 1: return (3 * t * t * t - 6 * t * t + 4) / 6.0;
+    case 2: return (-3 * t * t * t + 3 * t * t + 3 * t + 1) / 6.0;
+    default: return t * t * t / 6.0;
+    }
+}
+
+}  // namespace
+
+struct srwcr_plan {
+    srwcr_problem prob;
+    Geom g;
+    std::vector<void *> dev_allocs;
+    WorkItem *items = nullptr;
+    int nitems = 0;
+    size_t value_lds = 0, grad_lds = 0;
+    WsLayout ws;
+    int device = 0;
+    // diagnostics: per-phase HIP events recorded by srwcr_grad while profiling is on
+    mutable bool profiling = false;
+    mutable std::vector<hipEvent_t> ev_pool;
+    mutable size_t ev_used = 0;
+    mutable int32_t prof_calls = 0;
+};
+
+namespace {
+constexpr int kPhases = 5;            // zero, value, finalise, gradient, gradient output
+constexpr size_t kProfCalls = 4096;   // calls recorded per profiling session
+
+// record event `k` of the current profiled call (no-op when profiling is off)
+void prof_mark(const srwcr_plan *P, int k, hipStream_t s)
+{
+    if (!P->profiling) return;
+    const size_t base = (size_t)P->prof_calls * (kPhases + 1);
+    if (base + kPhases + 1 > P->ev_pool.size()) return;
+    (void)hipEventRecord(P->ev_pool[base + k], s);
+}
+}  // namespace
+
+extern "C" {
+
+const char *srwcr_last_error(void) { return g_last_error.c_str(); }
+
+int srwcr_ctrl_dims(const srwcr_problem *prob, int32_t out_nc[3])
+{
+    if (!prob || !out_nc) return fail(SRWCR_E_INVALID_ARG, "NULL argument");
+    for (int e = 0; e < 3; ++e) {
+        if (prob->fixed_dims[e] < 2 || prob->ctrl_spacing[e] < 1)
+            return fail(SRWCR_E_INVALID_ARG, "invalid fixed_dims / ctrl_spacing on axis %d", e);
+        out_nc[e] = (prob->fixed_dims[e] - 1) / prob->ctrl_spacing[e] + 4;
+    }
+    return SRWCR_OK;
+}
+
+void srwcr_plan_destroy(srwcr_plan *plan)
+{
+    if (!plan) return;
+    for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
+    for (void *p : plan->dev_allocs) (void)hipFree(p);
+    delete plan;
+}
+
+int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
+{
+    if (!out) return fail(SRWCR_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int st = validate_problem(prob);
+    if (st != SRWCR_OK) return st;
+    srwcr_plan *P = new srwcr_plan();
+    P->prob = *prob;
+    Geom &g = P->g;
+    std::memset(&g, 0, sizeof g);
+    for (int e = 0; e < 3; ++e) {
+        g.nf[e] = prob->fixed_dims[e];
+        g.nm[e] = prob->moving_dims[e];
+        g.K[e] = prob->spatial_bins[e];
+        g.delta[e] = prob->ctrl_spacing[e];
+        g.nc[e] = (g.nf[e] - 1) / g.delta[e] + 4;
+        g.same_grid[e] = g.nm[e] == g.nf[e];
+        g.ratio[e] = (float)((double)g.nm[e] / (double)g.nf[e]);
+    }
+    g.nb = prob->n_bins;
+    g.role = prob->role;
+    g.fdt = prob->fixed_dtype;
+    g.mdt = prob->moving_dtype;
+    g.R = g.K[0] * g.K[1] * g.K[2];
+    const double nvox = (double)g.nf[0] * g.nf[1] * g.nf[2];
+    g.inv_Z = 1.0 / nvox;     // sum_r w(r, x) = 1 and sum_a h = 1 make Z the voxel count (eq 3)
+
+    auto upload = [&](const void *host, size_t bytes, void **dev) -> int {
+        hipError_t e = hipMalloc(dev, bytes);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan tables)");
+        P->dev_allocs.push_back(*dev);
+        e = hipMemcpy(*dev, host, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan tables)");
+        return SRWCR_OK;
+    };
+
+    // per-axis tables
+    std::vector<std::vector<int>> cells(3);
+    for (int e = 0; e < 3; ++e) {
+        const int N = g.nf[e], K = g.K[e];
+        std::vector<int> sp_cell(N), ffd_p(N), mv_base(N);
+        std::vector<float4> sp_w(N), ffd_w(N);
+        std::vector<float> mv_frac(N);
+        for (int x = 0; x < N; ++x) {
+            // spatial bins: node j at (j - 1) (N - 1) / (K - 3); integer cell arithmetic
+            const long num = (long)x * (K - 3);
+            int c = (int)(num / (N - 1));
+            if (c > K - 4) c = K - 4;
+            const double t = (double)(num - (long)c * (N - 1)) / (double)(N - 1);
+            sp_cell[x] = c;
+            sp_w[x] = make_float4((float)bspline_piece(0, t), (float)bspline_piece(1, t), (float)bspline_piece(2, t),
+                                  (float)bspline_piece(3, t));
+            // FFD: p = floor(x / delta), eta = (x mod delta) / delta (eq 17)
+            const int d = g.delta[e];
+            ffd_p[x] = x / d;
+            const double eta = (double)(x % d) / d;
+            ffd_w[x] = make_float4((float)bspline_piece(0, eta), (float)bspline_piece(1, eta),
+                                   (float)bspline_piece(2, eta), (float)bspline_piece(3, eta));
+            // moving-grid mapping y = (x + 1/2) M / N - 1/2 (+ u M / N)
+            const double yv = ((double)x + 0.5) * g.nm[e] / g.nf[e] - 0.5;
+            const double fl = std::floor(yv);
+            mv_base[x] = (int)fl;
+            mv_frac[x] = (float)(yv - fl);
+        }
+        cells[e] = sp_cell;
+        void *d;
+        if ((st = upload(sp_cell.data(), N * sizeof(int), &d))) goto bad;
+        g.sp_cell[e] = (const int *)d;
+        if ((st = upload(sp_w.data(), N * sizeof(float4), &d))) goto bad;
+        g.sp_w[e] = (const float4 *)d;
+        if ((st = upload(ffd_p.data(), N * sizeof(int), &d))) goto bad;
+        g.ffd_p[e] = (const int *)d;
+        if ((st = upload(ffd_w.data(), N * sizeof(float4), &d))) goto bad;
+        g.ffd_w[e] = (const float4 *)d;
+        if ((st = upload(mv_base.data(), N * sizeof(int), &d))) goto bad;
+        g.mv_base[e] = (const int *)d;
+        if ((st = upload(mv_frac.data(), N * sizeof(float), &d))) goto bad;
+        g.mv_frac[e] = (const float *)d;
+    }
+
+    {
+        // work items: boxes inside one spatial cell, sized for ~600 items and the LDS budget
+        int dev = 0;
+        hipError_t he = hipGetDevice(&dev);
+        if (he != hipSuccess) { st = hip_fail(he, "hipGetDevice"); goto bad; }
+        P->device = dev;
+        int max_lds = 0;
+        he = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (he != hipSuccess) { st = hip_fail(he, "hipDeviceGetAttribute(shared memory)"); goto bad; }
+        P->value_lds = value_lds_bytes(g);
+        if (P->value_lds > (size_t)max_lds) {
+            st = fail(SRWCR_E_UNSUPPORTED, "value pass needs %zu B of LDS, device allows %d", P->value_lds, max_lds);
+            goto bad;
+        }
+        std::vector<int> lo[3], hi[3];
+        for (int e = 0; e < 3; ++e) {
+            lo[e].assign(g.K[e] - 3, -1);
+            hi[e].assign(g.K[e] - 3, -1);
+            for (int x = 0; x < g.nf[e]; ++x) {
+                const int c = cells[e][x];
+                if (lo[e][c] < 0) lo[e][c] = x;
+                hi[e][c] = x + 1;
+            }
+        }
+        const double target = std::min(65536.0, std::max(2048.0, nvox / 600.0));
+        int xc_max = 256, yc_max = 0, zc_max = 0;
+        std::vector<WorkItem> items;
+        for (int attempt = 0; attempt < 64; ++attempt) {
+            items.clear();
+            size_t worst_lds = 0;
+            for (int cz = 0; cz < g.K[2] - 3; ++cz) {
+                if (lo[2][cz] < 0) continue;
+                for (int cy = 0; cy < g.K[1] - 3; ++cy) {
+                    if (lo[1][cy] < 0) continue;
+                    for (int cx = 0; cx < g.K[0] - 3; ++cx) {
+                        if (lo[0][cx] < 0) continue;
+                        const int xw = hi[0][cx] - lo[0][cx], yw = hi[1][cy] - lo[1][cy], zw = hi[2][cz] - lo[2][cz];
+                        const int xc = std::min(xw, xc_max);
+                        const double side = std::sqrt(target / xc);
+                        int yc = std::max(1, std::min(yw, (int)std::lround(side * 1.5)));
+                        if (yc_max) yc = std::min(yc, yc_max);
+                        int zc = std::max(1, std::min(zw, (int)std::ceil(target / ((double)xc * yc))));
+                        if (zc_max) zc = std::min(zc, zc_max);
+                        for (int z0 = lo[2][cz]; z0 < hi[2][cz]; z0 += zc)
+                            for (int y0 = lo[1][cy]; y0 < hi[1][cy]; y0 += yc)
+                                for (int x0 = lo[0][cx]; x0 < hi[0][cx]; x0 += xc) {
+                                    WorkItem w{};
+                                    w.x0 = x0; w.x1 = std::min(x0 + xc, hi[0][cx]);
+                                    w.y0 = y0; w.y1 = std::min(y0 + yc, hi[1][cy]);
+                                    w.z0 = z0; w.z1 = std::min(z0 + zc, hi[2][cz]);
+                                    w.cx = cx; w.cy = cy; w.cz = cz;
+                                    w.gx0 = w.x0 / g.delta[0];
+                                    w.gy0 = w.y0 / g.delta[1];
+                                    w.gz0 = w.z0 / g.delta[2];
+                                    w.gnx = (w.x1 - 1) / g.delta[0] - w.gx0 + 4;
+                                    w.gny = (w.y1 - 1) / g.delta[1] - w.gy0 + 4;
+                                    w.gnz = (w.z1 - 1) / g.delta[2] - w.gz0 + 4;
+                                    worst_lds = std::max(worst_lds, grad_lds_bytes(g, w.gnx, w.gny, w.gnz));
+                                    items.push_back(w);
+                                }
+                        (void)yw;
+                    }
+                }
+            }
+            if (worst_lds <= (size_t)max_lds) {
+                P->grad_lds = worst_lds;
+                break;
+            }
+            // shrink the boxes until the gradient pass fits in LDS
+            if (xc_max > 64) xc_max /= 2;
+            else {
+                yc_max = yc_max ? std::max(1, yc_max / 2) : 32;
+                zc_max = zc_max ? std::max(1, zc_max / 2) : 16;
+                if (yc_max == 1 && zc_max == 1 && attempt > 40) {
+                    st = fail(SRWCR_E_UNSUPPORTED, "gradient pass does not fit in %d B of LDS", max_lds);
+                    goto bad;
+                }
+            }
+        }
+        if (P->grad_lds == 0) {
+            st = fail(SRWCR_E_UNSUPPORTED, "no work decomposition fits the gradient pass in LDS");
+            goto bad;
+        }
+        P->nitems = (int)items.size();
+        void *d;
+        if ((st = upload(items.data(), items.size() * sizeof(WorkItem), &d))) goto bad;
+        P->items = (WorkItem *)d;
+    }
+
+    {
+        // workspace: zeroed block first (moments, gradient accumulators, ticket)
+        WsLayout &w = P->ws;
+        const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
+        size_t off = 0;
+        w.moments = off;
+        off += (size_t)g.R * g.nb * 3 * sizeof(double);
+        w.grad = off;
+        off += 3 * ncell * sizeof(double);
+        w.counter = off;
+        off += sizeof(double);
+        off = align_up(off, 256);
+        w.region = off;
+        off += (size_t)g.R * 4 * sizeof(double);
+        off = align_up(off, 256);
+        w.tables = off;
+        off += (size_t)g.R * g.nb * 4 * sizeof(float);
+        off = align_up(off, 256);
+        w.alpha = off;
+        off += (size_t)g.R * sizeof(float);
+        w.total = align_up(off, 256);
+    }
+    *out = P;
+    return SRWCR_OK;
+bad:
+    srwcr_plan_destroy(P);
+    return st;
+}
+
+size_t srwcr_workspace_bytes(const srwcr_plan *plan) { return plan ? plan->ws.total : 0; }
+
+int srwcr_normalize(const float *in, int64_t n, double lo, double hi, int32_t n_bins, void *out, int32_t out_dtype,
+                    void *stream)
+{
+    if (!in || !out) return fail(SRWCR_E_INVALID_ARG, "NULL volume");
+    if (n <= 0) return fail(SRWCR_E_INVALID_ARG, "n = %lld must be positive", (long long)n);
+    if (n_bins < 2 || n_bins > kMaxBins) return fail(SRWCR_E_INVALID_ARG, "n_bins = %d outside 2..%d", n_bins, kMaxBins);
+    if (out_dtype < SRWCR_F32 || out_dtype > SRWCR_BF16) return fail(SRWCR_E_INVALID_ARG, "dtype %d unknown", out_dtype);
+    if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(SRWCR_E_NONFINITE, "normalisation range is not finite");
+    if (!(hi > lo)) return fail(SRWCR_E_DEGENERATE, "normalisation range hi (%g) <= lo (%g)", hi, lo);
+    const float lo_f = (float)lo;
+    const float scale = (float)((double)(n_bins - 1) / (hi - lo));
+    HIP_TRY(launch_normalize(in, n, lo_f, scale, (float)(n_bins - 1), out, out_dtype, (hipStream_t)stream),
+            "normalize launch");
+    return SRWCR_OK;
+}
+
+int srwcr_minmax(const float *in, int64_t n, double *lo, double *hi, void *stream)
+{
+    if (!in || !lo || !hi) return fail(SRWCR_E_INVALID_ARG, "NULL argument");
+    if (n <= 0) return fail(SRWCR_E_INVALID_ARG, "n must be positive");
+    const int nblocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    float *partial = nullptr;
+    HIP_TRY(hipMalloc(&partial, (size_t)nblocks * 3 * sizeof(float)), "hipMalloc(minmax)");
+    hipError_t e = launch_minmax(in, n, partial, nblocks, (hipStream_t)stream);
+    std::vector<float> h((size_t)nblocks * 3);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), partial, h.size() * sizeof(float), hipMemcpyDeviceToHost,
+                                            (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    (void)hipFree(partial);
+    if (e != hipSuccess) return hip_fail(e, "minmax");
+    float mn = INFINITY, mx = -INFINITY, bad = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        mn = std::min(mn, h[3 * b]);
+        mx = std::max(mx, h[3 * b + 1]);
+        bad += h[3 * b + 2];
+    }
+    if (bad > 0) return fail(SRWCR_E_NONFINITE, "volume holds %.0f non-finite values", bad);
+    *lo = mn;
+    *hi = mx;
+    return SRWCR_OK;
+}
+
+static int check_call(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd, void *ws,
+                      size_t ws_bytes)
+{
+    if (!plan) return fail(SRWCR_E_INVALID_ARG, "plan is NULL");
+    if (!fixed || !moving || !ffd) return fail(SRWCR_E_INVALID_ARG, "NULL volume or FFD pointer");
+    if (!ws) return fail(SRWCR_E_INVALID_ARG, "workspace is NULL");
+    if (ws_bytes < plan->ws.total)
+        return fail(SRWCR_E_WORKSPACE, "workspace has %zu B, the plan needs %zu B", ws_bytes, plan->ws.total);
+    return SRWCR_OK;
+}
+
+static int run_value(const srwcr_plan *P, const void *fixed, const void *moving, const float *ffd, double *d_value,
+                     unsigned char *ws, hipStream_t s)
+{
+    const Geom &g = P->g;
+    double *moments = (double *)(ws + P->ws.moments);
+    const size_t nzero = (P->ws.counter + sizeof(double) - P->ws.moments) / sizeof(double);
+    prof_mark(P, 0, s);
+    HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
+    prof_mark(P, 1, s);
+    HIP_TRY(launch_value(g, P->items, P->nitems, fixed, moving, ffd, moments, P->value_lds, s), "value launch");
+    prof_mark(P, 2, s);
+    HIP_TRY(launch_finalize(g, moments, (double *)(ws + P->ws.region), (float *)(ws + P->ws.tables),
+                            (float *)(ws + P->ws.alpha), (unsigned *)(ws + P->ws.counter), d_value, s),
+            "finalize launch");
+    prof_mark(P, 3, s);
+    return SRWCR_OK;
+}
+
+int srwcr_eval(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd, double *d_value,
+               void *workspace, size_t workspace_bytes, void *stream)
+{
+    int st = check_call(plan, fixed, moving, ffd, workspace, workspace_bytes);
+    if (st) return st;
+    if (!d_value) return fail(SRWCR_E_INVALID_ARG, "d_value is NULL");
+    return run_value(plan, fixed, moving, ffd, d_value, (unsigned char *)workspace, (hipStream_t)stream);
+}
+
+int srwcr_grad(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd, double *d_value,
+               float *d_grad, void *workspace, size_t workspace_bytes, void *stream)
+{
+    int st = check_call(plan, fixed, moving, ffd, workspace, workspace_bytes);
+    if (st) return st;
+    if (!d_value || !d_grad) return fail(SRWCR_E_INVALID_ARG, "d_value or d_grad is NULL");
+    unsigned char *ws = (unsigned char *)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    st = run_value(plan, fixed, moving, ffd, d_value, ws, s);
+    if (st) return st;
+    const Geom &g = plan->g;
+    double *grad = (double *)(ws + plan->ws.grad);
+    HIP_TRY(launch_grad(g, plan->items, plan->nitems, fixed, moving, ffd, (const float *)(ws + plan->ws.tables),
+                        (const float *)(ws + plan->ws.alpha), grad, plan->grad_lds, s),
+            "gradient launch");
+    prof_mark(plan, 4, s);
+    const size_t n = 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2];
+    HIP_TRY(launch_grad_out(grad, d_grad, n, s), "gradient output launch");
+    prof_mark(plan, 5, s);
+    if (plan->profiling && (size_t)(plan->prof_calls + 1) * (kPhases + 1) <= plan->ev_pool.size()) ++plan->prof_calls;
+    return SRWCR_OK;
+}
+
+int ffd_warp(const srwcr_plan *plan, const void *moving, const float *ffd, float *out, void *stream)
+{
+    if (!plan || !moving || !ffd || !out) return fail(SRWCR_E_INVALID_ARG, "NULL argument");
+    HIP_TRY(launch_warp(plan->g, moving, ffd, out, (hipStream_t)stream), "warp launch");
+    return SRWCR_OK;
+}
+
+int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd,
+                        double *d_moments, void *workspace, size_t workspace_bytes, void *stream)
+{
+    int st = check_call(plan, fixed, moving, ffd, workspace, workspace_bytes);
+    if (st) return st;
+    if (!d_moments) return fail(SRWCR_E_INVALID_ARG, "d_moments is NULL");
+    unsigned char *ws = (unsigned char *)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    double *moments = (double *)(ws + plan->ws.moments);
+    const size_t nzero = (plan->ws.counter + sizeof(double) - plan->ws.moments) / sizeof(double);
+    HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
+    HIP_TRY(launch_value(plan->g, plan->items, plan->nitems, fixed, moving, ffd, moments, plan->value_lds, s),
+            "value launch");
+    const size_t bytes = (size_t)plan->g.R * plan->g.nb * 3 * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(d_moments, moments, bytes, hipMemcpyDeviceToDevice, s), "moments copy");
+    return SRWCR_OK;
+}
+
+int srwcr_plan_info(const srwcr_plan *plan, int32_t *n_items, int32_t *value_lds, int32_t *grad_lds)
+{
+    if (!plan) return fail(SRWCR_E_INVALID_ARG, "plan is NULL");
+    if (n_items) *n_items = plan->nitems;
+    if (value_lds) *value_lds = (int32_t)plan->value_lds;
+    if (grad_lds) *grad_lds = (int32_t)plan->grad_lds;
+    return SRWCR_OK;
+}
+
+int srwcr_profile(const srwcr_plan *plan, int32_t enable)
+{
+    if (!plan) return fail(SRWCR_E_INVALID_ARG, "plan is NULL");
+    if (enable && plan->ev_pool.empty()) {
+        plan->ev_pool.resize(kProfCalls * (kPhases + 1));
+        for (auto &e : plan->ev_pool) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+    }
+    plan->profiling = enable != 0;
+    plan->prof_calls = 0;
+    return SRWCR_OK;
+}
+
+int srwcr_profile_read(const srwcr_plan *plan, double ms[5], int32_t *calls)
+{
+    if (!plan || !ms) return fail(SRWCR_E_INVALID_ARG, "NULL argument");
+    for (int k = 0; k < kPhases; ++k) ms[k] = 0.0;
+    for (int32_t c = 0; c < plan->prof_calls; ++c) {
+        const size_t base = (size_t)c * (kPhases + 1);
+        HIP_TRY(hipEventSynchronize(plan->ev_pool[base + kPhases]), "hipEventSynchronize");
+        for (int k = 0; k < kPhases; ++k) {
+            float t = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&t, plan->ev_pool[base + k], plan->ev_pool[base + k + 1]),
+                    "hipEventElapsedTime");
+            ms[k] += t;
+        }
+    }
+    if (calls) *calls = plan->prof_calls;
+    return SRWCR_OK;
+}
+
+void srwcr_lbfgs_default_opts(srwcr_lbfgs_opts *o)
+{
+    if (!o) return;
+    o->levels = 3;
+    o->max_iter[0] = 200;
+    o->max_iter[1] = 200;
+    o->max_iter[2] = 120;
+    o->history = 5;
+    o->stall_window = 20;
+    o->stall_tol = 1e-6;
+    o->bending_weight = 0.0;
+}
+
+}  // extern "C"

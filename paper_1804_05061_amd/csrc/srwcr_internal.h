@@ -1,0 +1,80 @@
+// srwcr_internal.h -- types shared by the host library and the gfx950 kernels.
+// Not part of the public ABI (include/srwcr.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srwcr {
+
+constexpr int kMaxBins = 64;      // L_eps + 1 <= 64: one wave lane per intensity bin
+constexpr int kWave = 64;         // CDNA wavefront width
+constexpr int kWin = 5;           // intensity-bin window of the value-pass wave reduction
+constexpr int kGWin = 5;          // intensity-bin window of the gradient-pass row tables
+constexpr int kValueThreads = 1024;
+constexpr int kGradThreads = 1024;
+constexpr int kMaxNodeSeg = 68;   // FFD x-nodes one 64-voxel row segment can touch (delta >= 1)
+
+// One unit of work of the value and gradient passes: a box of fixed voxels that
+// lies inside a single spatial-bin cell, so that all its voxels share the same
+// 4x4x4 regions (eq 7).  x covers the cell's full x-range.
+struct WorkItem {
+    int x0, x1, y0, y1, z0, z1;   // half-open voxel ranges
+    int cx, cy, cz;               // spatial cell; regions (cx+i, cy+j, cz+k), i,j,k in 0..3
+    int gx0, gy0, gz0;            // first FFD node of the item's control support
+    int gnx, gny, gnz;            // extent of that support
+    int pad;
+};
+
+// Everything a kernel needs to know about a problem, passed by value.
+struct Geom {
+    int nf[3];        // fixed grid
+    int nm[3];        // moving grid
+    int nc[3];        // FFD control grid
+    int K[3];         // spatial bins per axis
+    int delta[3];     // FFD spacing
+    int nb;           // intensity bins (L + 1)
+    int role;         // 0: moving is A, 1: moving is B
+    int fdt, mdt;     // storage dtypes of the normalised volumes
+    int R;            // K[0] K[1] K[2]
+    int same_grid[3]; // moving axis length == fixed axis length
+    float ratio[3];   // nm / nf per axis
+    double inv_Z;     // 1 / number of fixed voxels
+    // per-axis tables (device pointers)
+    const int *sp_cell[3];     // spatial cell of each fixed coordinate, 0..K-4
+    const float4 *sp_w[3];     // its four cubic B-spline weights (eq 8)
+    const int *ffd_p[3];       // x / delta
+    const float4 *ffd_w[3];    // beta_0..3((x mod delta) / delta)
+    const int *mv_base[3];     // floor((x + 1/2) M / N - 1/2) (unequal grids only)
+    const float *mv_frac[3];   // (x + 1/2) M / N - 1/2 - base
+};
+
+// Workspace layout (device bytes, offsets from the workspace base).
+struct WsLayout {
+    size_t moments;    // double [R][nb][3]   (P, S1, S2)
+    size_t region;     // double [R][4]       per-region results written by finalise
+    size_t tables;     // float  [R][nb][4]   gradient tables (role dependent)
+    size_t alpha;      // float  [R]          role B: CR_r / (sigma_r^2 Z)
+    size_t grad;       // double [3][nc]      gradient accumulators
+    size_t counter;    // unsigned            finalise ticket
+    size_t total;
+};
+
+// Launchers (srwcr_kernels.hip).
+hipError_t launch_zero(double *p, size_t n, hipStream_t s);
+hipError_t launch_normalize(const float *in, int64_t n, float lo, float scale, float L, void *out, int dt,
+                            hipStream_t s);
+hipError_t launch_minmax(const float *in, int64_t n, float *partial, int nblocks, hipStream_t s);
+hipError_t launch_value(const Geom &g, const WorkItem *items, int nitems, const void *fixed, const void *moving,
+                        const float *ffd, double *moments, size_t lds_bytes, hipStream_t s);
+hipError_t launch_finalize(const Geom &g, double *moments, double *region, float *tables, float *alpha,
+                           unsigned *counter, double *d_value, hipStream_t s);
+hipError_t launch_grad(const Geom &g, const WorkItem *items, int nitems, const void *fixed, const void *moving,
+                       const float *ffd, const float *tables, const float *alpha, double *grad,
+                       size_t lds_bytes, hipStream_t s);
+hipError_t launch_grad_out(const double *grad, float *out, size_t n, hipStream_t s);
+hipError_t launch_warp(const Geom &g, const void *moving, const float *ffd, float *out, hipStream_t s);
+size_t value_lds_bytes(const Geom &g);
+size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz);
+
+}  // namespace srwcr

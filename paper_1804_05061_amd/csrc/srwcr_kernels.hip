@@ -1,0 +1,844 @@
+// srwcr_kernels.hip -- gfx950 kernels for the SRWCR value and gradient
+// (Gong et al., arXiv 1804.05061).
+//
+// Work decomposition.  The fixed grid is cut into work items that each lie in
+// one spatial-bin cell, so every voxel of an item shares the same 4x4x4
+// regions (eq 7).  One workgroup takes one item; its waves take 64-voxel row
+// segments (lane = x).  Along a row the y and z weights of the regions and of
+// the FFD are wave-uniform, which makes both B-spline sums separable.
+//
+// Value pass (eqs 3, 5, 7, 17).  Per voxel: FFD displacement from per-row
+// contracted coefficients, trilinear sample of the moving image, two Parzen
+// taps of A and the Parzen moments m1, m2 of B.  The joint PDF is never
+// formed: summed over b, eq (3) only needs per (region, A-bin) the moments
+// P = sum w h(a - A), S1 = sum w h(a - A) m1(B), S2 = sum w h(a - A) m2(B).
+// A wave folds its 64 voxels into a 5-bin window x 4 x-nodes x 3 moments
+// (60 values) and sums them across lanes with a register transpose
+// (v_permlane32/16_swap and DPP), so no two lanes ever update the same LDS
+// address; each lane then spreads one total over the 16 (y, z) regions with
+// FP64 LDS atomics.  Lanes outside the window are taken in a further pass.
+// The item histogram is merged into the global FP64 moments once per item.
+//
+// Finalisation (eqs 4, 9-12, 18-21) runs in FP64, one wave per region, and
+// writes D and per-region gradient tables (FP32, scaled by 1/(Z sigma_r^2)).
+//
+// Gradient pass (eqs 16-21).  Recomputes the warp (nothing per voxel is
+// stored), interpolates the region tables through the same separable weights
+// (window row-tables per wave), forms q = dD/ds * grad M * dy/dT per voxel and
+// scatters it to the FFD nodes: per-cell moments along x, then FP64 LDS
+// atomics over the 16 (y, z) node weights, merged globally once per item.
+#include "srwcr_internal.h"
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+namespace srwcr {
+
+// ------------------------------------------------------------ small helpers
+template <int DT>
+__device__ __forceinline__ float ld_int(const void *p, size_t i)
+{
+    if constexpr (DT == 0) {
+        return reinterpret_cast<const float *>(p)[i];
+    } else if constexpr (DT == 1) {
+        return __half2float(reinterpret_cast<const __half *>(p)[i]);
+    } else {
+        unsigned short b = reinterpret_cast<const unsigned short *>(p)[i];
+        return __uint_as_float(((unsigned)b) << 16);
+    }
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ int wave_min_i(int v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d));
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+
+// Pairwise exchange-and-add steps of the 64 x 64 register transpose.
+__device__ __forceinline__ float xadd_swap32(float a, float b)
+{
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xadd_swap16(float a, float b)
+{
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+// lanes whose bit is clear keep `a`, the others `b`; each adds its xor-partner's copy
+__device__ __forceinline__ float xadd_x8(float a, float b, bool hi)
+{
+    float keep = hi ? b : a, send = hi ? a : b;
+    return keep + dpp<0x128>(send);                 // row_ror:8 == lane ^ 8
+}
+__device__ __forceinline__ float xadd_x4(float a, float b, bool hi)
+{
+    float keep = hi ? b : a, send = hi ? a : b;
+    return keep + dpp<0x1B>(dpp<0x141>(send));      // half-mirror (^7) then quad reverse (^3)
+}
+__device__ __forceinline__ float xadd_x2(float a, float b, bool hi)
+{
+    float keep = hi ? b : a, send = hi ? a : b;
+    return keep + dpp<0x4E>(send);                  // quad_perm [2,3,0,1]
+}
+__device__ __forceinline__ float xadd_x1(float a, float b, bool hi)
+{
+    float keep = hi ? b : a, send = hi ? a : b;
+    return keep + dpp<0xB1>(send);                  // quad_perm [1,0,3,2]
+}
+
+// Lane l returns sum over all 64 lanes of v[l].  Must run with all lanes active.
+__device__ __forceinline__ float wave_transpose_sum(const float (&v)[64], int lane)
+{
+    float w32[32], w16[16], w8[8], w4[4], w2[2];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) w32[i] = xadd_swap32(v[i], v[i + 32]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) w16[i] = xadd_swap16(w32[i], w32[i + 16]);
+    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w8[i] = xadd_x8(w16[i], w16[i + 8], b3);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w4[i] = xadd_x4(w8[i], w8[i + 4], b2);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) w2[i] = xadd_x2(w4[i], w4[i + 2], b1);
+    return xadd_x1(w2[0], w2[1], b0);
+}
+
+// Second-order Parzen window (eq 5) in two-tap form: s = k + t, t in [0, 1],
+// h(t) on bin k and h(1 - t) = 1 - h(t) on bin k + 1.
+__device__ __forceinline__ void parzen(float s, int L, int &k, float &t, float &w0, float &w1)
+{
+    int kk = (int)s;                         // s >= 0
+    if (kk > L - 1) kk = L - 1;
+    float tt = s - (float)kk;
+    float w = (tt < 0.5f) ? 1.0f - tt * (0.1f + 1.8f * tt) : 1.9f - tt * (3.7f - 1.8f * tt);
+    w = fminf(fmaxf(w, 0.0f), 1.0f);
+    k = kk;
+    t = tt;
+    w0 = w;
+    w1 = 1.0f - w;
+}
+// d h(t) / ds for the lower tap; the upper tap has the opposite sign
+__device__ __forceinline__ float parzen_dw0(float t) { return (t < 0.5f) ? -0.1f - 3.6f * t : -3.7f + 3.6f * t; }
+
+// FFD displacement of the 64 voxels of a row segment (eqs 8, 17).  The wave
+// first contracts the y and z B-spline weights into per-x-node coefficients
+// c1[e][n] (one node per lane), then each lane applies its four x weights.
+__device__ __forceinline__ void ffd_row(const Geom &g, const float *__restrict__ ffd, int xs, int xe, int y, int z,
+                                        int xc, float *c1, int lane, float u[3])
+{
+    const int py = g.ffd_p[1][y], pz = g.ffd_p[2][z];
+    const float4 by = g.ffd_w[1][y], bz = g.ffd_w[2][z];
+    const int px_lo = g.ffd_p[0][xs], px_hi = g.ffd_p[0][xe - 1];
+    const int nn = px_hi - px_lo + 4;
+    const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
+    const float wy[4] = {by.x, by.y, by.z, by.w}, wz[4] = {bz.x, bz.y, bz.z, bz.w};
+    for (int t = lane; t < 3 * nn; t += kWave) {
+        const int e = t / nn, n = t - e * nn;
+        const float *dp = ffd + e * ncell + ((size_t)pz * g.nc[1] + py) * g.nc[0] + px_lo + n;
+        float acc = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            float r = 0.0f;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) r = fmaf(wy[b], dp[((size_t)c * g.nc[1] + b) * g.nc[0]], r);
+            acc = fmaf(wz[c], r, acc);
+        }
+        c1[e * kMaxNodeSeg + n] = acc;
+    }
+    wave_sync();
+    const int px = g.ffd_p[0][xc] - px_lo;
+    const float4 bx = g.ffd_w[0][xc];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const float *c = c1 + e * kMaxNodeSeg + px;
+        u[e] = fmaf(bx.x, c[0], fmaf(bx.y, c[1], fmaf(bx.z, c[2], bx.w * c[3])));
+    }
+    wave_sync();
+}
+
+// Backward warping: trilinear sample of the moving volume at T(x) mapped to
+// the moving grid, coordinates clamped to [0, M - 1]; grad (if non-null) gets
+// dM/dy, zero along clamped axes.  y = base + frac + u * ratio keeps the
+// integer part exact.
+template <int MDT>
+__device__ __forceinline__ float sample_moving(const Geom &g, const void *__restrict__ mov, int x, int y, int z,
+                                               const float u[3], float *grad)
+{
+    const int coord[3] = {x, y, z};
+    int i0[3];
+    float f[3];
+    bool cl[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int M = g.nm[e];
+        int b;
+        float t;
+        if (g.same_grid[e]) {
+            b = coord[e];
+            t = u[e];
+        } else {
+            b = g.mv_base[e][coord[e]];
+            t = fmaf(u[e], g.ratio[e], g.mv_frac[e][coord[e]]);
+        }
+        const float ft = floorf(t);
+        int i = b + (int)ft;
+        float fr = t - ft;
+        bool c = false;
+        if (i < 0) { i = 0; fr = 0.0f; c = true; }
+        else if (i > M - 1 || (i == M - 1 && fr > 0.0f)) { i = M - 1; fr = 0.0f; c = true; }
+        if (i == M - 1) { i = M - 2; fr = 1.0f; }
+        i0[e] = i;
+        f[e] = fr;
+        cl[e] = c;
+    }
+    const size_t sx = 1, sy = (size_t)g.nm[0], sz = (size_t)g.nm[0] * g.nm[1];
+    const size_t base = i0[2] * sz + i0[1] * sy + i0[0];
+    const float v000 = ld_int<MDT>(mov, base), v100 = ld_int<MDT>(mov, base + sx);
+    const float v010 = ld_int<MDT>(mov, base + sy), v110 = ld_int<MDT>(mov, base + sy + sx);
+    const float v001 = ld_int<MDT>(mov, base + sz), v101 = ld_int<MDT>(mov, base + sz + sx);
+    const float v011 = ld_int<MDT>(mov, base + sz + sy), v111 = ld_int<MDT>(mov, base + sz + sy + sx);
+    // lerp(a, b, f) = a - f a + f b: exact at f = 0 and at f = 1 (the last grid plane)
+    auto lerp = [](float a, float b, float t) { return fmaf(t, b, fmaf(-t, a, a)); };
+    const float a00 = lerp(v000, v100, f[0]), a10 = lerp(v010, v110, f[0]);
+    const float a01 = lerp(v001, v101, f[0]), a11 = lerp(v011, v111, f[0]);
+    const float b0 = lerp(a00, a10, f[1]), b1 = lerp(a01, a11, f[1]);
+    const float val = lerp(b0, b1, f[2]);
+    if (grad) {
+        const float d00 = v100 - v000, d10 = v110 - v010, d01 = v101 - v001, d11 = v111 - v011;
+        const float dy0 = fmaf(f[1], d10 - d00, d00), dy1 = fmaf(f[1], d11 - d01, d01);
+        grad[0] = cl[0] ? 0.0f : fmaf(f[2], dy1 - dy0, dy0);
+        const float e0 = a10 - a00, e1 = a11 - a01;
+        grad[1] = cl[1] ? 0.0f : fmaf(f[2], e1 - e0, e0);
+        grad[2] = cl[2] ? 0.0f : b1 - b0;
+    }
+    return val;
+}
+
+// ------------------------------------------------------------------ zero
+__global__ void k_zero(double *p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+hipError_t launch_zero(double *p, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    int blocks = (int)std::min<size_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------- a1: normalisation
+template <int DT>
+__global__ void k_normalize(const float *__restrict__ in, int64_t n, float lo, float scale, float L, void *out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        // two separately rounded single-precision operations (no contraction)
+        float d = __fsub_rn(in[i], lo);
+        float s = __fmul_rn(d, scale);
+        s = fminf(fmaxf(s, 0.0f), L);
+        if constexpr (DT == 0) {
+            reinterpret_cast<float *>(out)[i] = s;
+        } else if constexpr (DT == 1) {
+            reinterpret_cast<__half *>(out)[i] = __float2half_rn(s);
+        } else {
+            // round to nearest even into bfloat16 (s is finite and non-negative)
+            unsigned b = __float_as_uint(s);
+            b += 0x7fffu + ((b >> 16) & 1u);
+            reinterpret_cast<unsigned short *>(out)[i] = (unsigned short)(b >> 16);
+        }
+    }
+}
+
+hipError_t launch_normalize(const float *in, int64_t n, float lo, float scale, float L, void *out, int dt,
+                            hipStream_t s)
+{
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    if (blocks < 1) blocks = 1;
+    if (dt == 0) hipLaunchKernelGGL(k_normalize<0>, dim3(blocks), dim3(256), 0, s, in, n, lo, scale, L, out);
+    else if (dt == 1) hipLaunchKernelGGL(k_normalize<1>, dim3(blocks), dim3(256), 0, s, in, n, lo, scale, L, out);
+    else hipLaunchKernelGGL(k_normalize<2>, dim3(blocks), dim3(256), 0, s, in, n, lo, scale, L, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- min / max
+// partial[3 * b + 0..2] = (min, max, count of non-finite values) of block b
+__global__ void k_minmax(const float *__restrict__ in, int64_t n, float *partial)
+{
+    __shared__ float smin[256], smax[256], sbad[256];
+    float mn = INFINITY, mx = -INFINITY, bad = 0.0f;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float v = in[i];
+        if (!isfinite(v)) { bad += 1.0f; continue; }
+        mn = fminf(mn, v);
+        mx = fmaxf(mx, v);
+    }
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    sbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) {
+            smin[threadIdx.x] = fminf(smin[threadIdx.x], smin[threadIdx.x + d]);
+            smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + d]);
+            sbad[threadIdx.x] += sbad[threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[3 * blockIdx.x + 0] = smin[0];
+        partial[3 * blockIdx.x + 1] = smax[0];
+        partial[3 * blockIdx.x + 2] = sbad[0];
+    }
+}
+
+hipError_t launch_minmax(const float *in, int64_t n, float *partial, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_minmax, dim3(nblocks), dim3(256), 0, s, in, n, partial);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ value pass
+size_t value_lds_bytes(const Geom &g)
+{
+    return (size_t)64 * g.nb * 3 * sizeof(double) + (size_t)(kValueThreads / kWave) * 3 * kMaxNodeSeg * sizeof(float);
+}
+
+template <int FDT, int MDT>
+__global__ void __launch_bounds__(kValueThreads)
+k_value(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixed, const void *__restrict__ moving,
+        const float *__restrict__ ffd, double *__restrict__ moments)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nb = g.nb, L = nb - 1;
+    double *H = reinterpret_cast<double *>(smem);                       // [64 regions][nb][3]
+    const int nH = 64 * nb * 3;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwaves = blockDim.x >> 6;
+    float *c1 = reinterpret_cast<float *>(H + nH) + wave * 3 * kMaxNodeSeg;
+    const WorkItem it = items[blockIdx.x];
+
+    for (int i = threadIdx.x; i < nH; i += blockDim.x) H[i] = 0.0;
+    __syncthreads();
+
+    const int nseg = (it.x1 - it.x0 + kWave - 1) / kWave;
+    const int ny = it.y1 - it.y0, nz = it.z1 - it.z0;
+    const int nunits = nseg * ny * nz;
+    for (int unit = wave; unit < nunits; unit += nwaves) {
+        const int seg = unit % nseg, row = unit / nseg;
+        const int y = it.y0 + row % ny, z = it.z0 + row / ny;
+        const int xs = it.x0 + seg * kWave, xe = min(xs + kWave, it.x1);
+        const int x = xs + lane;
+        const bool valid = x < xe;
+        const int xc = valid ? x : xe - 1;
+
+        float u[3];
+        ffd_row(g, ffd, xs, xe, y, z, xc, c1, lane, u);
+        float sm = sample_moving<MDT>(g, moving, xc, y, z, u, nullptr);
+        sm = fminf(fmaxf(sm, 0.0f), (float)L);
+        const float sf = ld_int<FDT>(fixed, ((size_t)z * g.nf[1] + y) * g.nf[0] + xc);
+        const float sA = g.role ? sf : sm, sB = g.role ? sm : sf;
+        int kA, kB;
+        float tA, tB, a0, a1, b0w, b1w;
+        parzen(sA, L, kA, tA, a0, a1);
+        parzen(sB, L, kB, tB, b0w, b1w);
+        const float m1 = (float)kB + b1w;
+        const float m2 = fmaf((float)(2 * kB + 1), b1w, (float)(kB * kB));
+
+        const float4 wx4 = g.sp_w[0][xc];
+        const float wx[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
+        float wxv[12];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            wxv[3 * i + 0] = wx[i];
+            wxv[3 * i + 1] = wx[i] * m1;
+            wxv[3 * i + 2] = wx[i] * m2;
+        }
+        const float4 wy4 = g.sp_w[1][y], wz4 = g.sp_w[2][z];
+        const float wyv[4] = {wy4.x, wy4.y, wy4.z, wy4.w}, wzv[4] = {wz4.x, wz4.y, wz4.z, wz4.w};
+
+        bool pending = valid;
+        for (;;) {
+            const int kmin = wave_min_i(pending ? kA : 0x7fffffff);
+            if (kmin == 0x7fffffff) break;
+            const int o = kA - kmin;
+            const bool inw = pending && o <= kWin - 2;
+            float V[64];
+#pragma unroll
+            for (int w = 0; w < kWin; ++w) {
+                const float tw = inw ? ((o == w) ? a0 : ((o == w - 1) ? a1 : 0.0f)) : 0.0f;
+#pragma unroll
+                for (int q = 0; q < 12; ++q) V[w * 12 + q] = tw * wxv[q];
+            }
+#pragma unroll
+            for (int q = kWin * 12; q < 64; ++q) V[q] = 0.0f;
+            const float T = wave_transpose_sum(V, lane);
+            if (lane < kWin * 12 && T != 0.0f) {
+                const int w = lane / 12, rem = lane - 12 * w, i = rem / 3, m = rem - 3 * i;
+                const int a = kmin + w;
+                if (a <= L) {
+#pragma unroll
+                    for (int kz = 0; kz < 4; ++kz)
+#pragma unroll
+                        for (int jy = 0; jy < 4; ++jy) {
+                            const int r = (kz * 4 + jy) * 4 + i;
+                            atomicAdd(&H[(r * nb + a) * 3 + m], (double)(T * (wyv[jy] * wzv[kz])));
+                        }
+                }
+            }
+            pending = pending && !inw;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nH; e += blockDim.x) {
+        const double v = H[e];
+        if (v != 0.0) {
+            const int m = e % 3, ra = e / 3, a = ra % nb, r = ra / nb;
+            const int i = r & 3, j = (r >> 2) & 3, k = r >> 4;
+            const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
+            unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], v);
+        }
+    }
+}
+
+#define SRWCR_DISPATCH_DT(KERNEL, FDT_V, MDT_V, ...)                                                   \
+    do {                                                                                                 \
+        if ((FDT_V) == 0 && (MDT_V) == 0) hipLaunchKernelGGL((KERNEL<0, 0>), __VA_ARGS__);               \
+        else if ((FDT_V) == 0 && (MDT_V) == 1) hipLaunchKernelGGL((KERNEL<0, 1>), __VA_ARGS__);          \
+        else if ((FDT_V) == 0 && (MDT_V) == 2) hipLaunchKernelGGL((KERNEL<0, 2>), __VA_ARGS__);          \
+        else if ((FDT_V) == 1 && (MDT_V) == 0) hipLaunchKernelGGL((KERNEL<1, 0>), __VA_ARGS__);          \
+        else if ((FDT_V) == 1 && (MDT_V) == 1) hipLaunchKernelGGL((KERNEL<1, 1>), __VA_ARGS__);          \
+        else if ((FDT_V) == 1 && (MDT_V) == 2) hipLaunchKernelGGL((KERNEL<1, 2>), __VA_ARGS__);          \
+        else if ((FDT_V) == 2 && (MDT_V) == 0) hipLaunchKernelGGL((KERNEL<2, 0>), __VA_ARGS__);          \
+        else if ((FDT_V) == 2 && (MDT_V) == 1) hipLaunchKernelGGL((KERNEL<2, 1>), __VA_ARGS__);          \
+        else hipLaunchKernelGGL((KERNEL<2, 2>), __VA_ARGS__);                                           \
+    } while (0)
+
+template <typename F>
+static hipError_t set_lds(F *kernel, size_t bytes)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+static hipError_t set_value_lds(int fdt, int mdt, size_t bytes)
+{
+    hipError_t e = hipSuccess;
+#define SRWCR_SET(F, M) if (fdt == F && mdt == M) e = set_lds(k_value<F, M>, bytes);
+    SRWCR_SET(0, 0) SRWCR_SET(0, 1) SRWCR_SET(0, 2) SRWCR_SET(1, 0) SRWCR_SET(1, 1) SRWCR_SET(1, 2)
+    SRWCR_SET(2, 0) SRWCR_SET(2, 1) SRWCR_SET(2, 2)
+#undef SRWCR_SET
+    return e;
+}
+
+hipError_t launch_value(const Geom &g, const WorkItem *items, int nitems, const void *fixed, const void *moving,
+                        const float *ffd, double *moments, size_t lds_bytes, hipStream_t s)
+{
+    hipError_t e = set_value_lds(g.fdt, g.mdt, lds_bytes);
+    if (e != hipSuccess) return e;
+    SRWCR_DISPATCH_DT(k_value, g.fdt, g.mdt, dim3(nitems), dim3(kValueThreads), lds_bytes, s, g, items, fixed,
+                      moving, ffd, moments);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------- finalisation
+// One wave per region r (lane = intensity bin a).  region[4 r + 0..3] =
+// (U_r / sigma_r^2, p_r, sigma_r^2, CR_r); the last wave to finish sums the
+// per-region terms in region order and writes D = (1/Z) sum_r U_r / sigma_r^2.
+__global__ void __launch_bounds__(64)
+k_finalize(Geom g, const double *__restrict__ moments, double *region, float *tables, float *alpha,
+           unsigned *counter, double *d_value)
+{
+    const int r = blockIdx.x, a = threadIdx.x, nb = g.nb;
+    double P = 0.0, S1 = 0.0, S2 = 0.0;
+    if (a < nb) {
+        const double *mp = moments + ((size_t)r * nb + a) * 3;
+        P = mp[0];
+        S1 = mp[1];
+        S2 = mp[2];
+    }
+    const double Pr = wave_sum_d(P), S1r = wave_sum_d(S1), S2r = wave_sum_d(S2);
+    const bool filled = P > 0.0;
+    const double mu_a = filled ? S1 / P : 0.0;
+    const double U = wave_sum_d(filled ? S2 - S1 * mu_a : 0.0);
+    double var = 0.0;
+    bool ok = Pr > 0.0;
+    if (ok) {
+        const double mu = S1r / Pr;
+        var = S2r / Pr - mu * mu;
+        ok = var >= 1e-12;
+    }
+    const double mu_r = ok ? S1r / Pr : 0.0;
+    const double omc = ok ? U / (Pr * var) : 0.0;       // 1 - CR_r
+    const double cr = ok ? 1.0 - omc : 0.0;
+    const double s = ok ? g.inv_Z / var : 0.0;
+    float *tp = tables + ((size_t)r * nb + a) * 4;
+    if (g.role == 1) {
+        // moving is B: E'_a = 2 mu_r(a) - 2 (1 - CR_r) mu_r, scaled by 1/(Z sigma^2)
+        if (a < nb) {
+            const double E = (filled ? 2.0 * mu_a : 0.0) - 2.0 * omc * mu_r;
+            tp[0] = (float)(s * E);
+            tp[1] = tp[2] = tp[3] = 0.0f;
+        }
+        if (a == 0) alpha[r] = (float)(s * cr);
+    } else {
+        // moving is A: coefficients of m1^2, m1, 1 in
+        // (m1 - mu(a))^2 - (m1 - mu(a+1))^2, an empty bin's square taken as 0
+        const double mu_n = __shfl_down(mu_a, 1);
+        const int fill_n = __shfl_down(filled ? 1 : 0, 1);
+        if (a < nb) {
+            double c2 = 0.0, c1 = 0.0, c0 = 0.0;
+            const bool f0 = filled, f1 = (a + 1 < nb) && fill_n;
+            if (f0 && f1) {
+                c1 = 2.0 * (mu_n - mu_a);
+                c0 = -(mu_n - mu_a) * (mu_n + mu_a);
+            } else if (f0) {
+                c2 = 1.0;
+                c1 = -2.0 * mu_a;
+                c0 = mu_a * mu_a;
+            } else if (f1) {
+                c2 = -1.0;
+                c1 = 2.0 * mu_n;
+                c0 = -mu_n * mu_n;
+            }
+            tp[0] = (float)(s * c2);
+            tp[1] = (float)(s * c1);
+            tp[2] = (float)(s * c0);
+            tp[3] = 0.0f;
+        }
+        if (a == 0) alpha[r] = 0.0f;
+    }
+    if (a == 0) {
+        region[4 * r + 0] = ok ? U / var : 0.0;
+        region[4 * r + 1] = Pr;
+        region[4 * r + 2] = var;
+        region[4 * r + 3] = cr;
+        __threadfence();
+        const unsigned ticket = atomicAdd(counter, 1u);
+        if (ticket == (unsigned)g.R - 1) {
+            __threadfence();
+            double D = 0.0;
+            for (int q = 0; q < g.R; ++q) D += __hip_atomic_load(&region[4 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            *d_value = D * g.inv_Z;
+            *counter = 0u;
+        }
+    }
+}
+
+hipError_t launch_finalize(const Geom &g, double *moments, double *region, float *tables, float *alpha,
+                           unsigned *counter, double *d_value, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(g.R), dim3(64), 0, s, g, moments, region, tables, alpha, counter, d_value);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------- gradient pass
+constexpr int kGradScratch = 1024;   // floats of per-wave scratch
+
+size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz)
+{
+    const size_t tab = (size_t)64 * g.nb * 3 * sizeof(float) + 64 * sizeof(float);
+    const size_t G = (size_t)gnx * gny * gnz * 3 * sizeof(double);
+    const size_t scratch = (size_t)(kGradThreads / kWave) * kGradScratch * sizeof(float);
+    return G + tab + scratch;
+}
+
+template <int FDT, int MDT>
+__global__ void __launch_bounds__(kGradThreads)
+k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixed, const void *__restrict__ moving,
+       const float *__restrict__ ffd, const float *__restrict__ tables, const float *__restrict__ alpha,
+       double *__restrict__ grad)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nb = g.nb, L = nb - 1;
+    const WorkItem it = items[blockIdx.x];
+    const int nG = it.gnx * it.gny * it.gnz * 3;
+    double *G = reinterpret_cast<double *>(smem);                       // [gnz][gny][gnx][3]
+    float *tab = reinterpret_cast<float *>(G + nG);                      // [64][nb][3]
+    float *alph = tab + 64 * nb * 3;                                     // [64]
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwaves = blockDim.x >> 6;
+    float *scr = alph + 64 + wave * kGradScratch;
+
+    for (int i = threadIdx.x; i < nG; i += blockDim.x) G[i] = 0.0;
+    for (int i = threadIdx.x; i < 64 * nb; i += blockDim.x) {
+        const int rl = i / nb, a = i - rl * nb;
+        const int ii = rl & 3, jj = (rl >> 2) & 3, kk = rl >> 4;
+        const int R = ((it.cz + kk) * g.K[1] + (it.cy + jj)) * g.K[0] + (it.cx + ii);
+        const float *tp = tables + ((size_t)R * nb + a) * 4;
+        tab[(rl * nb + a) * 3 + 0] = tp[0];
+        tab[(rl * nb + a) * 3 + 1] = tp[1];
+        tab[(rl * nb + a) * 3 + 2] = tp[2];
+        if (a == 0) alph[rl] = alpha[R];
+    }
+    __syncthreads();
+
+    const int nseg = (it.x1 - it.x0 + kWave - 1) / kWave;
+    const int ny = it.y1 - it.y0, nz = it.z1 - it.z0;
+    const int nunits = nseg * ny * nz;
+    for (int unit = wave; unit < nunits; unit += nwaves) {
+        const int seg = unit % nseg, row = unit / nseg;
+        const int y = it.y0 + row % ny, z = it.z0 + row / ny;
+        const int xs = it.x0 + seg * kWave, xe = min(xs + kWave, it.x1);
+        const int x = xs + lane;
+        const bool valid = x < xe;
+        const int xc = valid ? x : xe - 1;
+
+        float u[3], dm[3];
+        ffd_row(g, ffd, xs, xe, y, z, xc, scr, lane, u);
+        float sm = sample_moving<MDT>(g, moving, xc, y, z, u, dm);
+        sm = fminf(fmaxf(sm, 0.0f), (float)L);
+        const float sf = ld_int<FDT>(fixed, ((size_t)z * g.nf[1] + y) * g.nf[0] + xc);
+        const float sA = g.role ? sf : sm, sB = g.role ? sm : sf;
+        int kA, kB;
+        float tA, tB, a0, a1, b0w, b1w;
+        parzen(sA, L, kA, tA, a0, a1);
+        parzen(sB, L, kB, tB, b0w, b1w);
+        const float m1 = (float)kB + b1w;
+        const float4 wx4 = g.sp_w[0][xc];
+        const float wx[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
+        const float4 wy4 = g.sp_w[1][y], wz4 = g.sp_w[2][z];
+        const float wyv[4] = {wy4.x, wy4.y, wy4.z, wy4.w}, wzv[4] = {wz4.x, wz4.y, wz4.z, wz4.w};
+
+        // dD/ds_M through window row tables: T_row[i][slot] = sum_jk w_j w_k T[(i,j,k)][kmin + slot]
+        float gs = 0.0f;
+        bool pending = valid;
+        float *rowt = scr;                                           // <= 64 floats
+        for (;;) {
+            const int kmin = wave_min_i(pending ? kA : 0x7fffffff);
+            if (kmin == 0x7fffffff) break;
+            const int o = kA - kmin;
+            const bool inw = pending && o <= kGWin - 1;
+            if (g.role == 0) {
+                if (lane < 4 * kGWin * 3) {                          // (i, slot, c)
+                    const int i = lane / (kGWin * 3), rem = lane - i * kGWin * 3;
+                    const int sl = rem / 3, c = rem - 3 * sl;
+                    const int a = kmin + sl;
+                    float acc = 0.0f;
+                    if (a <= L - 1) {
+#pragma unroll
+                        for (int kz = 0; kz < 4; ++kz)
+#pragma unroll
+                            for (int jy = 0; jy < 4; ++jy)
+                                acc = fmaf(wyv[jy] * wzv[kz], tab[((((kz * 4 + jy) * 4 + i) * nb) + a) * 3 + c], acc);
+                    }
+                    rowt[lane] = acc;
+                }
+                wave_sync();
+                if (inw) {
+                    float C[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        float acc = 0.0f;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) acc = fmaf(wx[i], rowt[(i * kGWin + o) * 3 + c], acc);
+                        C[c] = acc;
+                    }
+                    gs = parzen_dw0(tA) * fmaf(fmaf(C[0], m1, C[1]), m1, C[2]);
+                }
+            } else {
+                constexpr int NS = kGWin + 1;                        // slots kmin .. kmin + kGWin
+                if (lane < 4 * NS) {
+                    const int i = lane / NS, sl = lane - i * NS, a = kmin + sl;
+                    float acc = 0.0f;
+                    if (a <= L) {
+#pragma unroll
+                        for (int kz = 0; kz < 4; ++kz)
+#pragma unroll
+                            for (int jy = 0; jy < 4; ++jy)
+                                acc = fmaf(wyv[jy] * wzv[kz], tab[((((kz * 4 + jy) * 4 + i) * nb) + a) * 3], acc);
+                    }
+                    rowt[lane] = acc;
+                } else if (lane < 4 * NS + 4) {
+                    const int i = lane - 4 * NS;
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int kz = 0; kz < 4; ++kz)
+#pragma unroll
+                        for (int jy = 0; jy < 4; ++jy) acc = fmaf(wyv[jy] * wzv[kz], alph[(kz * 4 + jy) * 4 + i], acc);
+                    rowt[lane] = acc;
+                }
+                wave_sync();
+                if (inw) {
+                    const float k21 = (float)(2 * kB + 1);
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float t = k21 * rowt[4 * NS + i] - a0 * rowt[i * NS + o] - a1 * rowt[i * NS + o + 1];
+                        acc = fmaf(wx[i], t, acc);
+                    }
+                    gs = -parzen_dw0(tB) * acc;                      // d m1 / d s_B = -d w0 / d s
+                }
+            }
+            wave_sync();
+            pending = pending && !inw;
+        }
+
+        // q = dD/ds * dM/dy * dy/dT  (eq 16)
+        float q[3];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) q[e] = valid ? gs * dm[e] * g.ratio[e] : 0.0f;
+
+        // scatter to control points (eq 17): per FFD cell p of the segment the
+        // four moments M[p][l][e] = sum_{x in p} beta_l(eta_x) q_e(x) ...
+        const int dx = g.delta[0];
+        const int px_lo = g.ffd_p[0][xs], px_hi = g.ffd_p[0][xe - 1];
+        const int np = px_hi - px_lo + 1, nn = np + 3;
+        float *qb = scr;                                             // [64][3]
+        float *cm = scr + 3 * kWave;                                 // [np][4][3]
+#pragma unroll
+        for (int e = 0; e < 3; ++e) qb[lane * 3 + e] = q[e];
+        wave_sync();
+        for (int t = lane; t < np * 3; t += kWave) {
+            const int p = t / 3, e = t - 3 * p;
+            const int xa = max(xs, (px_lo + p) * dx), xb = min(xe, (px_lo + p + 1) * dx);
+            float m0 = 0.0f, m1_ = 0.0f, m2_ = 0.0f, m3 = 0.0f;
+            for (int xx = xa; xx < xb; ++xx) {
+                const float v = qb[(xx - xs) * 3 + e];
+                const float4 b = g.ffd_w[0][xx];
+                m0 = fmaf(b.x, v, m0);
+                m1_ = fmaf(b.y, v, m1_);
+                m2_ = fmaf(b.z, v, m2_);
+                m3 = fmaf(b.w, v, m3);
+            }
+            cm[(p * 4 + 0) * 3 + e] = m0;
+            cm[(p * 4 + 1) * 3 + e] = m1_;
+            cm[(p * 4 + 2) * 3 + e] = m2_;
+            cm[(p * 4 + 3) * 3 + e] = m3;
+        }
+        wave_sync();
+        // ... node sums R1[n][e] = sum_l M[n - l][l][e], then the 16 (y, z) node weights
+        const int py = g.ffd_p[1][y], pz = g.ffd_p[2][z];
+        const float4 by = g.ffd_w[1][y], bz = g.ffd_w[2][z];
+        const float byv[4] = {by.x, by.y, by.z, by.w}, bzv[4] = {bz.x, bz.y, bz.z, bz.w};
+        for (int t = lane; t < nn * 3; t += kWave) {
+            const int n = t / 3, e = t - 3 * n;
+            float r1 = 0.0f;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int p = n - l;
+                if (p >= 0 && p < np) r1 += cm[(p * 4 + l) * 3 + e];
+            }
+            if (r1 != 0.0f) {
+                const int gx = px_lo + n - it.gx0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int gy = py + b - it.gy0, gz = pz + c - it.gz0;
+                        atomicAdd(&G[((gz * it.gny + gy) * it.gnx + gx) * 3 + e], (double)(r1 * (byv[b] * bzv[c])));
+                    }
+            }
+        }
+        wave_sync();
+    }
+    __syncthreads();
+    const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
+    for (int i = threadIdx.x; i < nG; i += blockDim.x) {
+        const double v = G[i];
+        if (v != 0.0) {
+            const int e = i % 3, c = i / 3;
+            const int gx = c % it.gnx, gy = (c / it.gnx) % it.gny, gz = c / (it.gnx * it.gny);
+            const size_t node = ((size_t)(gz + it.gz0) * g.nc[1] + (gy + it.gy0)) * g.nc[0] + (gx + it.gx0);
+            unsafeAtomicAdd(&grad[e * ncell + node], v);
+        }
+    }
+}
+
+static hipError_t set_grad_lds(int fdt, int mdt, size_t bytes)
+{
+    hipError_t e = hipSuccess;
+#define SRWCR_SET(F, M) if (fdt == F && mdt == M) e = set_lds(k_grad<F, M>, bytes);
+    SRWCR_SET(0, 0) SRWCR_SET(0, 1) SRWCR_SET(0, 2) SRWCR_SET(1, 0) SRWCR_SET(1, 1) SRWCR_SET(1, 2)
+    SRWCR_SET(2, 0) SRWCR_SET(2, 1) SRWCR_SET(2, 2)
+#undef SRWCR_SET
+    return e;
+}
+
+hipError_t launch_grad(const Geom &g, const WorkItem *items, int nitems, const void *fixed, const void *moving,
+                       const float *ffd, const float *tables, const float *alpha, double *grad, size_t lds_bytes,
+                       hipStream_t s)
+{
+    hipError_t e = set_grad_lds(g.fdt, g.mdt, lds_bytes);
+    if (e != hipSuccess) return e;
+    SRWCR_DISPATCH_DT(k_grad, g.fdt, g.mdt, dim3(nitems), dim3(kGradThreads), lds_bytes, s, g, items, fixed,
+                      moving, ffd, tables, alpha, grad);
+    return hipGetLastError();
+}
+
+__global__ void k_grad_out(const double *__restrict__ grad, float *__restrict__ out, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (float)grad[i];
+}
+
+hipError_t launch_grad_out(const double *grad, float *out, size_t n, hipStream_t s)
+{
+    int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_grad_out, dim3(blocks), dim3(256), 0, s, grad, out, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- ffd_warp
+template <int MDT>
+__global__ void __launch_bounds__(256) k_warp(Geom g, const void *__restrict__ moving, const float *__restrict__ ffd,
+                                              float *__restrict__ out)
+{
+    __shared__ float c1s[4][3 * kMaxNodeSeg];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nseg = (g.nf[0] + kWave - 1) / kWave;
+    const long unit = (long)blockIdx.x * 4 + wave;
+    const long nunits = (long)nseg * g.nf[1] * g.nf[2];
+    if (unit >= nunits) return;                          // wave-uniform exit
+    const int seg = (int)(unit % nseg);
+    const long row = unit / nseg;
+    const int y = (int)(row % g.nf[1]), z = (int)(row / g.nf[1]);
+    const int xs = seg * kWave, xe = min(xs + kWave, g.nf[0]);
+    const int x = xs + lane;
+    const bool valid = x < xe;
+    const int xc = valid ? x : xe - 1;
+    float u[3];
+    ffd_row(g, ffd, xs, xe, y, z, xc, c1s[wave], lane, u);
+    float v = sample_moving<MDT>(g, moving, xc, y, z, u, nullptr);
+    v = fminf(fmaxf(v, 0.0f), (float)(g.nb - 1));
+    if (valid) out[((size_t)z * g.nf[1] + y) * g.nf[0] + x] = v;
+}
+
+hipError_t launch_warp(const Geom &g, const void *moving, const float *ffd, float *out, hipStream_t s)
+{
+    const long nseg = (g.nf[0] + kWave - 1) / kWave;
+    const long nunits = nseg * g.nf[1] * g.nf[2];
+    const int blocks = (int)((nunits + 3) / 4);
+    if (g.mdt == 0) hipLaunchKernelGGL(k_warp<0>, dim3(blocks), dim3(256), 0, s, g, moving, ffd, out);
+    else if (g.mdt == 1) hipLaunchKernelGGL(k_warp<1>, dim3(blocks), dim3(256), 0, s, g, moving, ffd, out);
+    else hipLaunchKernelGGL(k_warp<2>, dim3(blocks), dim3(256), 0, s, g, moving, ffd, out);
+    return hipGetLastError();
+}
+
+}  // namespace srwcr

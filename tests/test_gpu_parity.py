@@ -1,0 +1,160 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Gates (spec tolerances): SRWCR value within 1e-5 relative, gradient
+within 1e-4 relative L2, normalised intensities and fixed-image bins
+bit-exact.  Inputs are seeded synthetic volumes; sizes span several work
+items, ragged tails, unequal fixed / moving grids and both roles.
+"""
+import numpy as np
+import pytest
+
+from workloads import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+VALUE_TOL = 1e-5
+GRAD_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_1804_05061_amd as S
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return S
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def prepare(S, orc, fixed_raw, moving_raw, nb, K, delta, role, fdt=0, mdt=0):
+    fl, fh = float(fixed_raw.min()), float(fixed_raw.max())
+    ml, mh = float(moving_raw.min()), float(moving_raw.max())
+    tdt = {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}
+    f_g = S.normalize(dev(fixed_raw), fl, fh, nb, tdt[fdt])
+    m_g = S.normalize(dev(moving_raw), ml, mh, nb, tdt[mdt])
+    fdims = tuple(fixed_raw.shape[::-1])
+    mdims = tuple(moving_raw.shape[::-1])
+    prob = S.Problem(fdims, mdims, nb, K, delta, role, fdt, mdt)
+    P = orc.Problem(fdims, mdims, nb, K, delta, role)
+    # the oracle sees exactly the stored (possibly 16-bit) normalised values
+    f_o = f_g.float().cpu().numpy()
+    m_o = m_g.float().cpu().numpy()
+    return prob, P, f_g, m_g, f_o, m_o
+
+
+def oracle_moments(orc, P, f, m, ffd):
+    pdf, Z = orc.joint_pdf(P, f, m, ffd)
+    b = np.arange(P.n_bins, dtype=np.float64)
+    return np.stack([pdf.sum(2) * Z, (pdf * b).sum(2) * Z, (pdf * b * b).sum(2) * Z], axis=-1)
+
+
+def check_value_grad(S, orc, prob, P, f_g, m_g, f_o, m_o, ffd, label=""):
+    plan = S.Plan(prob)
+    D, g = plan.grad(f_g, m_g, dev(ffd))
+    D2 = plan.eval(f_g, m_g, dev(ffd))
+    torch.cuda.synchronize()
+    D, D2, g = float(D.item()), float(D2.item()), g.cpu().numpy().astype(np.float64)
+    Dr, gr = orc.gradient(P, f_o, m_o, ffd)
+    rel_v = abs(D - Dr) / abs(Dr)
+    rel_g = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    print(f"{label} items={plan.info()['n_items']} D={D:.12f} oracle={Dr:.12f} rel={rel_v:.2e} "
+          f"grad relL2={rel_g:.2e}", flush=True)
+    # the cross-workgroup FP64 merge is atomic, so its summation order may vary
+    assert abs(D - D2) <= 1e-12 * abs(D), "srwcr_eval and srwcr_grad disagree on D"
+    assert rel_v <= VALUE_TOL, (label, D, Dr, rel_v)
+    assert rel_g <= GRAD_TOL, (label, rel_g)
+    return plan, D, g
+
+
+def test_normalize_bit_exact_and_minmax(S, orc):
+    w = synth.blobs(n=40)
+    x = dev(w.fixed)
+    lo, hi = S.minmax(x)
+    assert lo == float(w.fixed.min()) and hi == float(w.fixed.max())
+    for nb in (32, 64, 17):
+        got = S.normalize(x, lo, hi, nb).cpu().numpy()
+        assert np.array_equal(got, orc.normalize(w.fixed, lo, hi, nb))
+    h16 = S.normalize(x, lo, hi, 64, torch.float16).cpu().numpy()
+    ref = orc.normalize(w.fixed, lo, hi, 64)
+    assert np.array_equal(h16, ref.astype(np.float16))
+    b16 = S.normalize(x, lo, hi, 64, torch.bfloat16).float().cpu().numpy()
+    assert np.array_equal(b16, torch.from_numpy(ref).to(torch.bfloat16).float().numpy())
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_moments_blobs64(S, orc, role):
+    w = synth.blobs()
+    prob, P, f_g, m_g, f_o, m_o = prepare(S, orc, w.fixed, w.moving, 32, (4, 4, 4), (8, 8, 8), role)
+    ffd = synth.random_ffd(prob.ctrl_dims, 1.0, 11)
+    plan = S.Plan(prob)
+    mg = plan.debug_moments(f_g, m_g, dev(ffd)).cpu().numpy()
+    mo = oracle_moments(orc, P, f_o, m_o, ffd)
+    err = np.abs(mg - mo) / (np.abs(mo).max(axis=(0, 1)) + 1e-30)
+    print("moment rel err", err.max(axis=(0, 1)), flush=True)
+    assert err.max() < 1e-6
+
+
+@pytest.mark.parametrize("role", [0, 1])
+@pytest.mark.parametrize("sigma", [0.0, 1.0])
+def test_blobs64_value_and_gradient(S, orc, role, sigma):
+    """Workload 1: 64^3 blobs, 32 bins, 4x4x4 regions, FFD spacing 8."""
+    w = synth.blobs()
+    prob, P, f_g, m_g, f_o, m_o = prepare(S, orc, w.fixed, w.moving, 32, (4, 4, 4), (8, 8, 8), role)
+    ffd = synth.random_ffd(prob.ctrl_dims, sigma, 12) if sigma else np.zeros(prob.ffd_shape, np.float32)
+    check_value_grad(S, orc, prob, P, f_g, m_g, f_o, m_o, ffd, f"blobs64 role={role} sigma={sigma}")
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_ragged_grid(S, orc, role):
+    """Odd sizes: ragged row segments, cells of unequal width, 24 bins."""
+    w = synth.blobs(n=48)
+    fixed = np.ascontiguousarray(w.fixed[:23, :29, :37])
+    moving = np.ascontiguousarray(w.moving[:23, :29, :37])
+    prob, P, f_g, m_g, f_o, m_o = prepare(S, orc, fixed, moving, 24, (5, 4, 6), (3, 4, 5), role)
+    ffd = synth.random_ffd(prob.ctrl_dims, 0.8, 13)
+    check_value_grad(S, orc, prob, P, f_g, m_g, f_o, m_o, ffd, f"ragged role={role}")
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_unequal_grids(S, orc, role):
+    """Moving grid half the fixed grid (the CT/PET set-up of workload 4, small)."""
+    w = synth.blobs(n=40)
+    fixed = w.fixed[:32, :36, :40]
+    moving = np.ascontiguousarray(w.moving[:32:2, :36:2, :40:2])
+    prob, P, f_g, m_g, f_o, m_o = prepare(S, orc, np.ascontiguousarray(fixed), moving, 48, (5, 5, 5), (8, 8, 8),
+                                          role)
+    ffd = synth.random_ffd(prob.ctrl_dims, 1.5, 14)
+    check_value_grad(S, orc, prob, P, f_g, m_g, f_o, m_o, ffd, f"unequal role={role}")
+
+
+def test_ffd_warp_matches_oracle(S, orc):
+    w = synth.blobs(n=40)
+    fixed = np.ascontiguousarray(w.fixed[:31, :35, :40])
+    moving = np.ascontiguousarray(w.moving[:31, :35, :40])
+    prob, P, f_g, m_g, f_o, m_o = prepare(S, orc, fixed, moving, 32, (4, 4, 4), (5, 5, 5), 0)
+    ffd = synth.random_ffd(prob.ctrl_dims, 3.0, 15)     # large enough to push samples off the grid
+    plan = S.Plan(prob)
+    got = plan.warp(m_g, dev(ffd)).cpu().numpy()
+    ref = orc.warp(P, m_o, ffd)
+    assert np.abs(got - ref).max() < 2e-4
+    zero = plan.warp(m_g, dev(np.zeros_like(ffd))).cpu().numpy()
+    assert np.array_equal(zero, m_o)
+
+
+def test_invalid_arguments_raise(S):
+    with pytest.raises(S.SrwcrError):
+        S.Plan(S.Problem((1, 8, 8), (8, 8, 8), 32, (4, 4, 4), (4, 4, 4)))
+    with pytest.raises(S.SrwcrError):
+        S.Plan(S.Problem((8, 8, 8), (8, 8, 8), 65, (4, 4, 4), (4, 4, 4)))
+    with pytest.raises(S.SrwcrError):
+        S.Plan(S.Problem((8, 8, 8), (8, 8, 8), 32, (3, 4, 4), (4, 4, 4)))
+    with pytest.raises(S.SrwcrError):
+        S.Plan(S.Problem((8, 8, 8), (8, 8, 8), 32, (4, 4, 4), (0, 4, 4)))
+    with pytest.raises(S.SrwcrError):
+        S.normalize(dev(np.ones(10, np.float32)), 1.0, 1.0, 32)
+    x = np.ones(1000, np.float32)
+    x[7] = np.nan
+    with pytest.raises(S.SrwcrError):
+        S.minmax(dev(x))
