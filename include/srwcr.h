@@ -145,6 +145,20 @@ void srwcr_lbfgs_default_opts(srwcr_lbfgs_opts *opts);
 int register_lbfgs(const srwcr_problem *prob, const float *fixed, const float *moving, float *ffd_inout,
                    const srwcr_lbfgs_opts *opts, srwcr_lbfgs_report *report, void *stream);
 
+/* Carry displacements from a pyramid level to the next finer one: u_f(x) =
+ * 2 u_c(x / 2) represented exactly on the finer lattice by cubic B-spline
+ * subdivision (fine node 2i = (c[i-1] + 6 c[i] + c[i+1]) / 8, node 2i + 1 =
+ * (c[i] + c[i+1]) / 2, paper node indices; nodes outside the coarse lattice
+ * count as 0).  Host arrays float32 [3][nc_z][nc_y][nc_x]. */
+int srwcr_refine_ffd(const int32_t coarse_nc[3], const float *coarse, const int32_t fine_nc[3], float *fine);
+
+/* Bending energy C_p of eq (1) (the constraint term, after Rueckert et al.):
+ * the mean over control-node positions inside the fixed grid of
+ * sum_e [u_xx^2 + u_yy^2 + u_zz^2 + 2 (u_xy^2 + u_xz^2 + u_yz^2)] of the FFD
+ * displacement u.  Host arrays; `grad` (optional) receives dC_p/dd.
+ * Returns -1 on invalid arguments. */
+double srwcr_bending_energy(const srwcr_problem *prob, const float *ffd, float *grad);
+
 /* ---- diagnostics (used by the test-suite; not needed for registration) ---- */
 
 /* Run only the value pass and copy the raw joint moments of eq (3) summed over

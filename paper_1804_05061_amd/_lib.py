@@ -15,7 +15,8 @@ STATUS_NAMES = {0: "SRWCR_OK", -1: "SRWCR_E_INVALID_ARG", -2: "SRWCR_E_DEGENERAT
 EXPORTED = ["srwcr_ctrl_dims", "srwcr_plan_create", "srwcr_plan_destroy", "srwcr_workspace_bytes",
             "srwcr_normalize", "srwcr_minmax", "srwcr_eval", "srwcr_grad", "ffd_warp",
             "srwcr_lbfgs_default_opts", "register_lbfgs", "srwcr_debug_moments", "srwcr_plan_info",
-            "srwcr_profile", "srwcr_profile_read", "srwcr_last_error"]
+            "srwcr_profile", "srwcr_profile_read", "srwcr_refine_ffd", "srwcr_bending_energy",
+            "srwcr_last_error"]
 
 
 class SrwcrProblem(ctypes.Structure):
@@ -72,6 +73,8 @@ def load() -> ctypes.CDLL:
         "srwcr_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "srwcr_profile": (ctypes.c_int, [vp, i32]),
         "srwcr_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]),
+        "srwcr_refine_ffd": (ctypes.c_int, [ctypes.POINTER(i32), vp, ctypes.POINTER(i32), vp]),
+        "srwcr_bending_energy": (ctypes.c_double, [pp, vp, vp]),
         "srwcr_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -235,43 +235,56 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
                 hi[e][c] = x + 1;
             }
         }
+        // x chunks: runs of up to xmax voxels that touch at most two spatial
+        // cells, so their regions fit the 5 x-node block of a work item
+        auto x_chunks = [&](int xmax) {
+            std::vector<std::pair<int, int>> ch;
+            for (int x = 0; x < g.nf[0];) {
+                const int c = cells[0][x];
+                int end = std::min(g.nf[0], x + xmax);
+                if (c + 2 < g.K[0] - 3 && lo[0][c + 2] >= 0) end = std::min(end, lo[0][c + 2]);
+                for (int cc = c + 2; cc < g.K[0] - 3; ++cc)
+                    if (lo[0][cc] >= 0) { end = std::min(end, lo[0][cc]); break; }
+                ch.push_back({x, end});
+                x = end;
+            }
+            return ch;
+        };
         const double target = std::min(65536.0, std::max(2048.0, nvox / 600.0));
-        int xc_max = 256, yc_max = 0, zc_max = 0;
+        int xc_max = 128, yc_max = 0, zc_max = 0;
         std::vector<WorkItem> items;
         for (int attempt = 0; attempt < 64; ++attempt) {
             items.clear();
             size_t worst_lds = 0;
+            const auto xch = x_chunks(xc_max);
             for (int cz = 0; cz < g.K[2] - 3; ++cz) {
                 if (lo[2][cz] < 0) continue;
                 for (int cy = 0; cy < g.K[1] - 3; ++cy) {
                     if (lo[1][cy] < 0) continue;
-                    for (int cx = 0; cx < g.K[0] - 3; ++cx) {
-                        if (lo[0][cx] < 0) continue;
-                        const int xw = hi[0][cx] - lo[0][cx], yw = hi[1][cy] - lo[1][cy], zw = hi[2][cz] - lo[2][cz];
-                        const int xc = std::min(xw, xc_max);
-                        const double side = std::sqrt(target / xc);
+                    const int yw = hi[1][cy] - lo[1][cy], zw = hi[2][cz] - lo[2][cz];
+                    for (const auto &xr : xch) {
+                        const int xw = xr.second - xr.first;
+                        const double side = std::sqrt(target / xw);
                         int yc = std::max(1, std::min(yw, (int)std::lround(side * 1.5)));
                         if (yc_max) yc = std::min(yc, yc_max);
-                        int zc = std::max(1, std::min(zw, (int)std::ceil(target / ((double)xc * yc))));
+                        int zc = std::max(1, std::min(zw, (int)std::ceil(target / ((double)xw * yc))));
                         if (zc_max) zc = std::min(zc, zc_max);
                         for (int z0 = lo[2][cz]; z0 < hi[2][cz]; z0 += zc)
-                            for (int y0 = lo[1][cy]; y0 < hi[1][cy]; y0 += yc)
-                                for (int x0 = lo[0][cx]; x0 < hi[0][cx]; x0 += xc) {
-                                    WorkItem w{};
-                                    w.x0 = x0; w.x1 = std::min(x0 + xc, hi[0][cx]);
-                                    w.y0 = y0; w.y1 = std::min(y0 + yc, hi[1][cy]);
-                                    w.z0 = z0; w.z1 = std::min(z0 + zc, hi[2][cz]);
-                                    w.cx = cx; w.cy = cy; w.cz = cz;
-                                    w.gx0 = w.x0 / g.delta[0];
-                                    w.gy0 = w.y0 / g.delta[1];
-                                    w.gz0 = w.z0 / g.delta[2];
-                                    w.gnx = (w.x1 - 1) / g.delta[0] - w.gx0 + 4;
-                                    w.gny = (w.y1 - 1) / g.delta[1] - w.gy0 + 4;
-                                    w.gnz = (w.z1 - 1) / g.delta[2] - w.gz0 + 4;
-                                    worst_lds = std::max(worst_lds, grad_lds_bytes(g, w.gnx, w.gny, w.gnz));
-                                    items.push_back(w);
-                                }
-                        (void)yw;
+                            for (int y0 = lo[1][cy]; y0 < hi[1][cy]; y0 += yc) {
+                                WorkItem w{};
+                                w.x0 = xr.first; w.x1 = xr.second;
+                                w.y0 = y0; w.y1 = std::min(y0 + yc, hi[1][cy]);
+                                w.z0 = z0; w.z1 = std::min(z0 + zc, hi[2][cz]);
+                                w.cx = cells[0][w.x0]; w.cy = cy; w.cz = cz;
+                                w.gx0 = w.x0 / g.delta[0];
+                                w.gy0 = w.y0 / g.delta[1];
+                                w.gz0 = w.z0 / g.delta[2];
+                                w.gnx = (w.x1 - 1) / g.delta[0] - w.gx0 + 4;
+                                w.gny = (w.y1 - 1) / g.delta[1] - w.gy0 + 4;
+                                w.gnz = (w.z1 - 1) / g.delta[2] - w.gz0 + 4;
+                                worst_lds = std::max(worst_lds, grad_lds_bytes(g, w.gnx, w.gny, w.gnz));
+                                items.push_back(w);
+                            }
                     }
                 }
             }
@@ -289,10 +302,6 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
                     goto bad;
                 }
             }
-        }
-        if (P->grad_lds == 0) {
-            st = fail(SRWCR_E_UNSUPPORTED, "no work decomposition fits the gradient pass in LDS");
-            goto bad;
         }
         P->nitems = (int)items.size();
         void *d;

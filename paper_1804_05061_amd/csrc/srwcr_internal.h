@@ -9,18 +9,21 @@ namespace srwcr {
 
 constexpr int kMaxBins = 64;      // L_eps + 1 <= 64: one wave lane per intensity bin
 constexpr int kWave = 64;         // CDNA wavefront width
-constexpr int kWin = 5;           // intensity-bin window of the value-pass wave reduction
-constexpr int kGWin = 5;          // intensity-bin window of the gradient-pass row tables
+constexpr int kXN = 5;            // x-nodes of a work item (its x-range spans at most two spatial cells)
+constexpr int kNReg = kXN * 16;   // regions of a work item: 5 (x) x 4 (y) x 4 (z)
+constexpr int kWin = 4;           // bin slots of one value-pass window (A-bins kmin .. kmin + 3)
+constexpr int kGWinA = 4;         // gradient-pass window, moving image as A (one slot per voxel)
+constexpr int kGWinB = 5;         // gradient-pass window, moving image as B (two slots per voxel)
 constexpr int kValueThreads = 1024;
 constexpr int kGradThreads = 1024;
 constexpr int kMaxNodeSeg = 68;   // FFD x-nodes one 64-voxel row segment can touch (delta >= 1)
 
-// One unit of work of the value and gradient passes: a box of fixed voxels that
-// lies inside a single spatial-bin cell, so that all its voxels share the same
-// 4x4x4 regions (eq 7).  x covers the cell's full x-range.
+// One unit of work of the value and gradient passes: a box of fixed voxels
+// inside one spatial-bin cell along y and z and at most two cells along x, so
+// that all its voxels draw their 64 regions (eq 7) from the same 5x4x4 block.
 struct WorkItem {
     int x0, x1, y0, y1, z0, z1;   // half-open voxel ranges
-    int cx, cy, cz;               // spatial cell; regions (cx+i, cy+j, cz+k), i,j,k in 0..3
+    int cx, cy, cz;               // first region of the block: (cx+i, cy+j, cz+k), i < 5, j, k < 4
     int gx0, gy0, gz0;            // first FFD node of the item's control support
     int gnx, gny, gnz;            // extent of that support
     int pad;
@@ -74,6 +77,8 @@ hipError_t launch_grad(const Geom &g, const WorkItem *items, int nitems, const v
                        size_t lds_bytes, hipStream_t s);
 hipError_t launch_grad_out(const double *grad, float *out, size_t n, hipStream_t s);
 hipError_t launch_warp(const Geom &g, const void *moving, const float *ffd, float *out, hipStream_t s);
+hipError_t launch_downsample(const float *in, int nx, int ny, int nz, float *out, int ox, int oy, int oz,
+                             hipStream_t s);
 size_t value_lds_bytes(const Geom &g);
 size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz);
 

@@ -322,9 +322,58 @@ hipError_t launch_minmax(const float *in, int64_t n, float *partial, int nblocks
 }
 
 // ------------------------------------------------------------ value pass
+// Region stride of the item histogram in doubles: 3 nb plus a pad that puts
+// consecutive regions 24 LDS banks apart, so the 60 lanes of one FP64 atomic
+// (4 bin slots x 5 x-nodes x 3 moments) touch each bank at most twice.
+__host__ __device__ __forceinline__ int hist_stride(int nb) { return 3 * nb + (((24 - 6 * nb) % 64 + 64) % 64) / 2; }
+
 size_t value_lds_bytes(const Geom &g)
 {
-    return (size_t)64 * g.nb * 3 * sizeof(double) + (size_t)(kValueThreads / kWave) * 3 * kMaxNodeSeg * sizeof(float);
+    return (size_t)kNReg * hist_stride(g.nb) * sizeof(double) +
+           (size_t)(kValueThreads / kWave) * 3 * kMaxNodeSeg * sizeof(float);
+}
+
+// Wave-uniform minimum: butterfly inside each 16-lane row (DPP), then the
+// four row results through scalar reads.
+__device__ __forceinline__ int wave_min_dpp(int v)
+{
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xf, 0xf, false));  // row_ror:4
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false));  // row_ror:8
+    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return min(min(r0, r1), min(r2, r3));
+}
+
+__device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// One bin window of the value pass: lanes with `inw` put their taps on the
+// window slots o and o + 1 (bins kbase + o, kbase + o + 1); the wave sums the
+// 4 slots x 15 (x-node, moment) values across lanes and each lane spreads one
+// total over the 16 (y, z) regions of its column.
+__device__ __forceinline__ void value_window(double *H, int rs, int nb, int L, bool inw, int o, int kbase, float a0,
+                                             float a1, const float (&wxv)[15], const float (&wyz)[16], int lane)
+{
+    float V[64];
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) {
+        const float tw = inw ? ((o == w) ? a0 : ((o == w - 1) ? a1 : 0.0f)) : 0.0f;
+#pragma unroll
+        for (int q = 0; q < 15; ++q) V[w * 15 + q] = tw * wxv[q];
+    }
+#pragma unroll
+    for (int q = kWin * 15; q < 64; ++q) V[q] = 0.0f;
+    const float T = wave_transpose_sum(V, lane);
+    if (lane < kWin * 15 && T != 0.0f) {
+        const int w = lane / 15, q = lane - 15 * w, i = q / 3, m = q - 3 * i;
+        const int a = kbase + w;
+        if (a <= L) {
+            double *h = H + i * rs + a * 3 + m;
+#pragma unroll
+            for (int jk = 0; jk < 16; ++jk) atomicAdd(h + jk * kXN * rs, (double)(T * wyz[jk]));
+        }
+    }
 }
 
 template <int FDT, int MDT>
@@ -333,9 +382,9 @@ k_value(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fix
         const float *__restrict__ ffd, double *__restrict__ moments)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int nb = g.nb, L = nb - 1;
-    double *H = reinterpret_cast<double *>(smem);                       // [64 regions][nb][3]
-    const int nH = 64 * nb * 3;
+    const int nb = g.nb, L = nb - 1, rs = hist_stride(nb);
+    double *H = reinterpret_cast<double *>(smem);     // [16 (y,z)][5 x][rs]: region (i, j, k) at ((k*4+j)*5+i)*rs
+    const int nH = kNReg * rs;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
@@ -369,58 +418,56 @@ k_value(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fix
         const float m1 = (float)kB + b1w;
         const float m2 = fmaf((float)(2 * kB + 1), b1w, (float)(kB * kB));
 
+        // x weights on the item's 5 x-nodes (the lane's cell is it.cx or it.cx + 1)
         const float4 wx4 = g.sp_w[0][xc];
-        const float wx[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
-        float wxv[12];
+        const int ox = g.sp_cell[0][xc] - it.cx;
+        const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
+        float wxv[15];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            wxv[3 * i + 0] = wx[i];
-            wxv[3 * i + 1] = wx[i] * m1;
-            wxv[3 * i + 2] = wx[i] * m2;
+        for (int n = 0; n < kXN; ++n) {
+            const float wn = (n - ox >= 0 && n - ox < 4) ? wl[(n - ox) & 3] : 0.0f;
+            wxv[3 * n + 0] = wn;
+            wxv[3 * n + 1] = wn * m1;
+            wxv[3 * n + 2] = wn * m2;
         }
         const float4 wy4 = g.sp_w[1][y], wz4 = g.sp_w[2][z];
         const float wyv[4] = {wy4.x, wy4.y, wy4.z, wy4.w}, wzv[4] = {wz4.x, wz4.y, wz4.z, wz4.w};
+        float wyz[16];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) wyz[k * 4 + j] = wyv[j] * wzv[k];
 
+        // bin windows, two per pass: A-bins [kmin, kmin + 2] of the pending lanes
+        constexpr int BIG = 0x7fffffff;
         bool pending = valid;
-        for (;;) {
-            const int kmin = wave_min_i(pending ? kA : 0x7fffffff);
-            if (kmin == 0x7fffffff) break;
-            const int o = kA - kmin;
-            const bool inw = pending && o <= kWin - 2;
-            float V[64];
-#pragma unroll
-            for (int w = 0; w < kWin; ++w) {
-                const float tw = inw ? ((o == w) ? a0 : ((o == w - 1) ? a1 : 0.0f)) : 0.0f;
-#pragma unroll
-                for (int q = 0; q < 12; ++q) V[w * 12 + q] = tw * wxv[q];
+        for (int pass = 0; pass <= nb; ++pass) {
+            int k1 = wave_min_dpp(pending ? kA : BIG);
+            if (k1 == BIG) break;
+            bool in1 = pending && kA >= k1 && kA - k1 <= kWin - 2;
+            if (wave_ballot(in1) == 0ull) {                     // never stall: take the first pending lane
+                k1 = __builtin_amdgcn_readlane(kA, (int)__builtin_ctzll(wave_ballot(pending)));
+                in1 = pending && kA >= k1 && kA - k1 <= kWin - 2;
             }
-#pragma unroll
-            for (int q = kWin * 12; q < 64; ++q) V[q] = 0.0f;
-            const float T = wave_transpose_sum(V, lane);
-            if (lane < kWin * 12 && T != 0.0f) {
-                const int w = lane / 12, rem = lane - 12 * w, i = rem / 3, m = rem - 3 * i;
-                const int a = kmin + w;
-                if (a <= L) {
-#pragma unroll
-                    for (int kz = 0; kz < 4; ++kz)
-#pragma unroll
-                        for (int jy = 0; jy < 4; ++jy) {
-                            const int r = (kz * 4 + jy) * 4 + i;
-                            atomicAdd(&H[(r * nb + a) * 3 + m], (double)(T * (wyv[jy] * wzv[kz])));
-                        }
-                }
-            }
-            pending = pending && !inw;
+            const bool rest = pending && !in1;
+            const int k2 = wave_min_dpp(rest ? kA : BIG);
+            const bool in2 = rest && k2 != BIG && kA >= k2 && kA - k2 <= kWin - 2;
+            value_window(H, rs, nb, L, in1, kA - k1, k1, a0, a1, wxv, wyz, lane);
+            if (k2 != BIG) value_window(H, rs, nb, L, in2, kA - k2, k2, a0, a1, wxv, wyz, lane);
+            pending = rest && !in2;
         }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nH; e += blockDim.x) {
         const double v = H[e];
         if (v != 0.0) {
-            const int m = e % 3, ra = e / 3, a = ra % nb, r = ra / nb;
-            const int i = r & 3, j = (r >> 2) & 3, k = r >> 4;
-            const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
-            unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], v);
+            const int rl = e / rs, rem = e - rl * rs;
+            const int a = rem / 3, m = rem - 3 * a;
+            const int i = rl % kXN, jk = rl / kXN, j = jk & 3, k = jk >> 2;
+            if (a < nb && it.cx + i < g.K[0]) {
+                const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
+                unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], v);
+            }
         }
     }
 }
@@ -559,9 +606,13 @@ hipError_t launch_finalize(const Geom &g, double *moments, double *region, float
 // --------------------------------------------------------- gradient pass
 constexpr int kGradScratch = 1024;   // floats of per-wave scratch
 
+// Region stride of the LDS copy of the gradient tables in floats: 3 nb plus a
+// pad that puts consecutive regions 12 banks apart (conflict-free row tables).
+__host__ __device__ __forceinline__ int tab_stride(int nb) { return 3 * nb + ((12 - 3 * nb) % 64 + 64) % 64; }
+
 size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz)
 {
-    const size_t tab = (size_t)64 * g.nb * 3 * sizeof(float) + 64 * sizeof(float);
+    const size_t tab = (size_t)kNReg * tab_stride(g.nb) * sizeof(float) + kNReg * sizeof(float);
     const size_t G = (size_t)gnx * gny * gnz * 3 * sizeof(double);
     const size_t scratch = (size_t)(kGradThreads / kWave) * kGradScratch * sizeof(float);
     return G + tab + scratch;
@@ -574,27 +625,34 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
        double *__restrict__ grad)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int nb = g.nb, L = nb - 1;
+    const int nb = g.nb, L = nb - 1, ts = tab_stride(nb);
     const WorkItem it = items[blockIdx.x];
     const int nG = it.gnx * it.gny * it.gnz * 3;
     double *G = reinterpret_cast<double *>(smem);                       // [gnz][gny][gnx][3]
-    float *tab = reinterpret_cast<float *>(G + nG);                      // [64][nb][3]
-    float *alph = tab + 64 * nb * 3;                                     // [64]
+    float *tab = reinterpret_cast<float *>(G + nG);                      // [80 regions][ts]: (a, c) at a*3 + c
+    float *alph = tab + kNReg * ts;                                      // [80]
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
-    float *scr = alph + 64 + wave * kGradScratch;
+    float *scr = alph + kNReg + wave * kGradScratch;
 
     for (int i = threadIdx.x; i < nG; i += blockDim.x) G[i] = 0.0;
-    for (int i = threadIdx.x; i < 64 * nb; i += blockDim.x) {
+    for (int i = threadIdx.x; i < kNReg * nb; i += blockDim.x) {
         const int rl = i / nb, a = i - rl * nb;
-        const int ii = rl & 3, jj = (rl >> 2) & 3, kk = rl >> 4;
-        const int R = ((it.cz + kk) * g.K[1] + (it.cy + jj)) * g.K[0] + (it.cx + ii);
-        const float *tp = tables + ((size_t)R * nb + a) * 4;
-        tab[(rl * nb + a) * 3 + 0] = tp[0];
-        tab[(rl * nb + a) * 3 + 1] = tp[1];
-        tab[(rl * nb + a) * 3 + 2] = tp[2];
-        if (a == 0) alph[rl] = alpha[R];
+        const int ii = rl % kXN, jk = rl / kXN, jj = jk & 3, kk = jk >> 2;
+        float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f, al = 0.0f;
+        if (it.cx + ii < g.K[0]) {
+            const int R = ((it.cz + kk) * g.K[1] + (it.cy + jj)) * g.K[0] + (it.cx + ii);
+            const float *tp = tables + ((size_t)R * nb + a) * 4;
+            t0 = tp[0];
+            t1 = tp[1];
+            t2 = tp[2];
+            al = alpha[R];
+        }
+        tab[rl * ts + a * 3 + 0] = t0;
+        tab[rl * ts + a * 3 + 1] = t1;
+        tab[rl * ts + a * 3 + 2] = t2;
+        if (a == 0) alph[rl] = al;
     }
     __syncthreads();
 
@@ -621,31 +679,43 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
         parzen(sB, L, kB, tB, b0w, b1w);
         const float m1 = (float)kB + b1w;
         const float4 wx4 = g.sp_w[0][xc];
-        const float wx[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
+        const int ox = g.sp_cell[0][xc] - it.cx;
+        const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
+        float wx5[kXN];
+#pragma unroll
+        for (int n = 0; n < kXN; ++n) wx5[n] = (n - ox >= 0 && n - ox < 4) ? wl[(n - ox) & 3] : 0.0f;
         const float4 wy4 = g.sp_w[1][y], wz4 = g.sp_w[2][z];
         const float wyv[4] = {wy4.x, wy4.y, wy4.z, wy4.w}, wzv[4] = {wz4.x, wz4.y, wz4.z, wz4.w};
 
-        // dD/ds_M through window row tables: T_row[i][slot] = sum_jk w_j w_k T[(i,j,k)][kmin + slot]
+        // dD/ds_M: the region tables interpolated by w(r, x) = wx wy wz through
+        // window row tables T_row[i][slot] = sum_jk wy_j wz_k T[(i, j, k)][kmin + slot]
+        constexpr int BIG = 0x7fffffff;
         float gs = 0.0f;
         bool pending = valid;
         float *rowt = scr;                                           // <= 64 floats
-        for (;;) {
-            const int kmin = wave_min_i(pending ? kA : 0x7fffffff);
-            if (kmin == 0x7fffffff) break;
+        const int W = g.role == 0 ? kGWinA : kGWinB - 1;             // voxels taken per window: o in [0, W - 1]
+        for (int pass = 0; pass <= nb; ++pass) {
+            int kmin = wave_min_dpp(pending ? kA : BIG);
+            if (kmin == BIG) break;
+            bool inw = pending && kA >= kmin && kA - kmin <= W - 1;
+            if (wave_ballot(inw) == 0ull) {
+                kmin = __builtin_amdgcn_readlane(kA, (int)__builtin_ctzll(wave_ballot(pending)));
+                inw = pending && kA >= kmin && kA - kmin <= W - 1;
+            }
             const int o = kA - kmin;
-            const bool inw = pending && o <= kGWin - 1;
             if (g.role == 0) {
-                if (lane < 4 * kGWin * 3) {                          // (i, slot, c)
-                    const int i = lane / (kGWin * 3), rem = lane - i * kGWin * 3;
+                if (lane < kXN * kGWinA * 3) {                       // (i, slot, c)
+                    const int i = lane / (kGWinA * 3), rem = lane - i * kGWinA * 3;
                     const int sl = rem / 3, c = rem - 3 * sl;
                     const int a = kmin + sl;
                     float acc = 0.0f;
                     if (a <= L - 1) {
+                        const float *tp = tab + i * ts + a * 3 + c;
 #pragma unroll
                         for (int kz = 0; kz < 4; ++kz)
 #pragma unroll
                             for (int jy = 0; jy < 4; ++jy)
-                                acc = fmaf(wyv[jy] * wzv[kz], tab[((((kz * 4 + jy) * 4 + i) * nb) + a) * 3 + c], acc);
+                                acc = fmaf(wyv[jy] * wzv[kz], tp[(kz * 4 + jy) * kXN * ts], acc);
                     }
                     rowt[lane] = acc;
                 }
@@ -656,31 +726,33 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
                     for (int c = 0; c < 3; ++c) {
                         float acc = 0.0f;
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) acc = fmaf(wx[i], rowt[(i * kGWin + o) * 3 + c], acc);
+                        for (int i = 0; i < kXN; ++i) acc = fmaf(wx5[i], rowt[(i * kGWinA + o) * 3 + c], acc);
                         C[c] = acc;
                     }
                     gs = parzen_dw0(tA) * fmaf(fmaf(C[0], m1, C[1]), m1, C[2]);
                 }
             } else {
-                constexpr int NS = kGWin + 1;                        // slots kmin .. kmin + kGWin
-                if (lane < 4 * NS) {
+                constexpr int NS = kGWinB;                           // slots kmin .. kmin + 4
+                if (lane < kXN * NS) {
                     const int i = lane / NS, sl = lane - i * NS, a = kmin + sl;
                     float acc = 0.0f;
                     if (a <= L) {
+                        const float *tp = tab + i * ts + a * 3;
 #pragma unroll
                         for (int kz = 0; kz < 4; ++kz)
 #pragma unroll
                             for (int jy = 0; jy < 4; ++jy)
-                                acc = fmaf(wyv[jy] * wzv[kz], tab[((((kz * 4 + jy) * 4 + i) * nb) + a) * 3], acc);
+                                acc = fmaf(wyv[jy] * wzv[kz], tp[(kz * 4 + jy) * kXN * ts], acc);
                     }
                     rowt[lane] = acc;
-                } else if (lane < 4 * NS + 4) {
-                    const int i = lane - 4 * NS;
+                } else if (lane < kXN * NS + kXN) {
+                    const int i = lane - kXN * NS;
                     float acc = 0.0f;
 #pragma unroll
                     for (int kz = 0; kz < 4; ++kz)
 #pragma unroll
-                        for (int jy = 0; jy < 4; ++jy) acc = fmaf(wyv[jy] * wzv[kz], alph[(kz * 4 + jy) * 4 + i], acc);
+                        for (int jy = 0; jy < 4; ++jy)
+                            acc = fmaf(wyv[jy] * wzv[kz], alph[(kz * 4 + jy) * kXN + i], acc);
                     rowt[lane] = acc;
                 }
                 wave_sync();
@@ -688,9 +760,9 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
                     const float k21 = (float)(2 * kB + 1);
                     float acc = 0.0f;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const float t = k21 * rowt[4 * NS + i] - a0 * rowt[i * NS + o] - a1 * rowt[i * NS + o + 1];
-                        acc = fmaf(wx[i], t, acc);
+                    for (int i = 0; i < kXN; ++i) {
+                        const float t = k21 * rowt[kXN * NS + i] - a0 * rowt[i * NS + o] - a1 * rowt[i * NS + o + 1];
+                        acc = fmaf(wx5[i], t, acc);
                     }
                     gs = -parzen_dw0(tB) * acc;                      // d m1 / d s_B = -d w0 / d s
                 }
@@ -838,6 +910,49 @@ hipError_t launch_warp(const Geom &g, const void *moving, const float *ffd, floa
     if (g.mdt == 0) hipLaunchKernelGGL(k_warp<0>, dim3(blocks), dim3(256), 0, s, g, moving, ffd, out);
     else if (g.mdt == 1) hipLaunchKernelGGL(k_warp<1>, dim3(blocks), dim3(256), 0, s, g, moving, ffd, out);
     else hipLaunchKernelGGL(k_warp<2>, dim3(blocks), dim3(256), 0, s, g, moving, ffd, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- pyramid level
+// Next-coarser level of the registration pyramid: Gaussian smoothing with
+// sigma = 1 voxel (taps -3..3, edges clamped) sampled at every other voxel,
+// corner aligned: out(X) = (G * in)(2 X).
+__global__ void __launch_bounds__(256) k_downsample(const float *__restrict__ in, int nx, int ny, int nz,
+                                                    float *__restrict__ out, int ox, int oy, int oz)
+{
+    const long n = (long)ox * oy * oz;
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int X = (int)(i % ox), Y = (int)((i / ox) % oy), Z = (int)(i / ((long)ox * oy));
+    float w[7];
+    float wsum = 0.0f;
+#pragma unroll
+    for (int d = -3; d <= 3; ++d) {
+        w[d + 3] = expf(-0.5f * (float)(d * d));
+        wsum += w[d + 3];
+    }
+    float acc = 0.0f;
+    for (int dz = -3; dz <= 3; ++dz) {
+        const int z = min(max(2 * Z + dz, 0), nz - 1);
+        for (int dy = -3; dy <= 3; ++dy) {
+            const int y = min(max(2 * Y + dy, 0), ny - 1);
+            const float wzy = w[dz + 3] * w[dy + 3];
+            const float *row = in + ((size_t)z * ny + y) * nx;
+            float r = 0.0f;
+#pragma unroll
+            for (int dx = -3; dx <= 3; ++dx) r = fmaf(w[dx + 3], row[min(max(2 * X + dx, 0), nx - 1)], r);
+            acc = fmaf(wzy, r, acc);
+        }
+    }
+    out[i] = acc / (wsum * wsum * wsum);
+}
+
+hipError_t launch_downsample(const float *in, int nx, int ny, int nz, float *out, int ox, int oy, int oz,
+                             hipStream_t s)
+{
+    const long n = (long)ox * oy * oz;
+    hipLaunchKernelGGL(k_downsample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, nx, ny, nz, out, ox,
+                       oy, oz);
     return hipGetLastError();
 }
 

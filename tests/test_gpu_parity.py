@@ -158,3 +158,52 @@ def test_invalid_arguments_raise(S):
     x[7] = np.nan
     with pytest.raises(S.SrwcrError):
         S.minmax(dev(x))
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_narrow_cells_and_unit_spacing(S, orc, role):
+    """Spatial cells narrower than a wave (x chunks of two cells, partial
+    segments) and FFD spacing 1 (the widest control support per segment)."""
+    w = synth.blobs(n=40)
+    fixed = np.ascontiguousarray(w.fixed[:20, :30, :40])
+    moving = np.ascontiguousarray(w.moving[:20, :30, :40])
+    prob, P, f_g, m_g, f_o, m_o = prepare(S, orc, fixed, moving, 16, (10, 8, 6), (1, 3, 2), role)
+    ffd = synth.random_ffd(prob.ctrl_dims, 0.3, 16)
+    check_value_grad(S, orc, prob, P, f_g, m_g, f_o, m_o, ffd, f"narrow role={role}")
+
+
+def test_two_bins(S, orc):
+    """L_eps = 1: every tap lands on bins 0 and 1."""
+    w = synth.blobs(n=24)
+    prob, P, f_g, m_g, f_o, m_o = prepare(S, orc, w.fixed, w.moving, 2, (4, 4, 4), (6, 6, 6), 0)
+    ffd = synth.random_ffd(prob.ctrl_dims, 1.0, 17)
+    check_value_grad(S, orc, prob, P, f_g, m_g, f_o, m_o, ffd, "two bins")
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_constant_estimated_image(S, orc, role):
+    """A constant estimated image B on a bin centre has sigma_r^2 = 0 in every
+    region: all regions are skipped, D = 0 and the gradient vanishes.  Off a
+    bin centre the Parzen window (eq 5) spreads it over two bins: sigma_r^2 =
+    w0 w1 > 0, no A-bin explains any of it, and D = 1 exactly."""
+    w = synth.blobs(n=24)
+    nb = 32
+    lo, hi = float(w.moving.min()), float(w.moving.max())
+    varying = S.normalize(dev(w.moving), lo, hi, nb)
+    prob = S.Problem(w.fixed_dims, w.moving_dims, nb, (4, 4, 4), (6, 6, 6), role)
+    ffd_np = synth.random_ffd(prob.ctrl_dims, 1.0, 18)
+    ffd = dev(ffd_np)
+    plan = S.Plan(prob)
+    for level, expect in ((7.0, 0.0), (7.25, 1.0)):
+        const = torch.full_like(varying, level)
+        fixed, moving = (const, varying) if role == 0 else (varying, const)
+        D, g = plan.grad(fixed, moving, ffd)
+        torch.cuda.synchronize()
+        P = orc.Problem(prob.fixed_dims, prob.moving_dims, nb, (4, 4, 4), (6, 6, 6), role)
+        Dr, gr = orc.gradient(P, fixed.cpu().numpy(), moving.cpu().numpy(), ffd_np)
+        assert abs(Dr - expect) < 1e-12
+        assert abs(float(D.item()) - expect) < 1e-6, (level, float(D.item()))
+        if expect == 0.0:
+            assert float(g.abs().max().item()) == 0.0
+        gg = g.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(gg - gr) <= GRAD_TOL * max(np.linalg.norm(gr), 1e-12) + 1e-12
