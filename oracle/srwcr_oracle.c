@@ -34,7 +34,9 @@
  *   - an empty intensity bin (no mass in region r) contributes nothing; in
  *     eq 21 its conditional mean is the voxel's own B-moment (the one-sided
  *     limit), so that its squared deviation vanishes;
- *   - a region with p(r) == 0 or sigma_r^2 < 1e-12 contributes nothing.
+ *   - a region with p(r) == 0, or whose B variance is at most 1e-5 of its
+ *     second moment (sigma_r^2 <= 1e-5 E_r[b^2], B constant to 0.3 %),
+ *     contributes nothing.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -52,7 +54,7 @@ typedef struct {
     int role;       /* 0: the moving image is A (model); 1: it is B (estimated) */
 } orc_problem;
 
-#define VAR_EPS 1e-12
+#define VAR_REL 1e-5   /* degenerate region: sigma_r^2 <= VAR_REL * E_r[b^2] */
 
 /* ---------------------------------------------------------------- eq (5) */
 double orc_h(double t)
@@ -321,7 +323,7 @@ typedef struct {
     double mu;     /* mu_r */
     double var;    /* sigma_r^2 */
     double cr;     /* CR(A, B | r) */
-    int ok;        /* p(r) > 0 and sigma_r^2 >= VAR_EPS */
+    int ok;        /* p(r) > 0 and sigma_r^2 > VAR_REL E_r[b^2] */
 } region_stats;
 
 static void region_statistics(int R, int nb, const double *p, region_stats *st, double *pa, double *mua)
@@ -346,13 +348,14 @@ static void region_statistics(int R, int nb, const double *p, region_stats *st, 
         double var = m2 - mu * mu;
         st[r].mu = mu;
         st[r].var = var;
+        const double e2 = m2;
         for (int a = 0; a < nb; ++a) {
             double s0 = 0.0, s1 = 0.0;
             for (int b = 0; b < nb; ++b) { s0 += q[a * nb + b] / pr; s1 += b * q[a * nb + b] / pr; }
             pa[r * nb + a] = s0;
             mua[r * nb + a] = (s0 > 0.0) ? s1 / s0 : 0.0;
         }
-        if (var < VAR_EPS) continue;
+        if (var <= VAR_REL * e2) continue;
         st[r].ok = 1;
         double c = 0.0;          /* Table I inner double loop */
         for (int a = 0; a < nb; ++a)
@@ -379,7 +382,7 @@ double orc_srwcr_from_pdf(int R, int nb, const double *p, int which)
         double mu = 0.0, e2 = 0.0;                        /* eq (10) */
         for (int b = 0; b < nb; ++b) { mu += b * pb[b]; e2 += (double)b * b * pb[b]; }
         double var = e2 - mu * mu;
-        if (var < VAR_EPS) continue;
+        if (var <= VAR_REL * e2) continue;
         for (int a = 0; a < nb; ++a) {
             double s1 = 0.0;
             for (int b = 0; b < nb; ++b) s1 += b * q[a * nb + b] / pr;

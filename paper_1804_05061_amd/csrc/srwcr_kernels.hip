@@ -535,9 +535,11 @@ k_finalize(Geom g, const double *__restrict__ moments, double *region, float *ta
     double var = 0.0;
     bool ok = Pr > 0.0;
     if (ok) {
-        const double mu = S1r / Pr;
-        var = S2r / Pr - mu * mu;
-        ok = var >= 1e-12;
+        // degenerate region (B constant to 0.3 %): sigma_r^2 <= 1e-5 E_r[b^2], a
+        // margin of ~50x over the rounding of the FP32 window sums
+        const double mu = S1r / Pr, e2 = S2r / Pr;
+        var = e2 - mu * mu;
+        ok = var > 1e-5 * e2;
     }
     const double mu_r = ok ? S1r / Pr : 0.0;
     const double omc = ok ? U / (Pr * var) : 0.0;       // 1 - CR_r

@@ -1,0 +1,89 @@
+"""Full-size parity on the benchmark workloads, in the launch configuration
+bench.py times: the value and the whole gradient against the FP64 oracle
+(which finishes these sizes in seconds with all host threads).
+
+Workload 3 also reports the precision pattern: 16-bit intensity storage with
+FP32 arithmetic, checked end to end against the oracle on the FP32 data
+(gate 1e-3) and, arithmetic only, against the oracle on the stored 16-bit
+values (gates 1e-5 / 1e-4)."""
+import numpy as np
+import pytest
+
+from workloads import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def run_gpu(S, w, dtype, role=0, sigma=2.0, k=2):
+    tdt = {S.F32: torch.float32, S.F16: torch.float16, S.BF16: torch.bfloat16}[dtype]
+    fr, mr = torch.from_numpy(w.fixed).cuda(), torch.from_numpy(w.moving).cuda()
+    flo, fhi = S.minmax(fr)
+    mlo, mhi = S.minmax(mr)
+    f = S.normalize(fr, flo, fhi, w.n_bins, tdt)
+    m = S.normalize(mr, mlo, mhi, w.n_bins, tdt)
+    prob = S.Problem(w.fixed_dims, w.moving_dims, w.n_bins, w.spatial_bins, w.ctrl_spacing, role, dtype, dtype)
+    ffd = synth.random_ffd(prob.ctrl_dims, sigma, k)
+    D, g = S.Plan(prob).grad(f, m, torch.from_numpy(ffd).cuda())
+    torch.cuda.synchronize()
+    return (float(D.item()), g.cpu().numpy().astype(np.float64), ffd, (flo, fhi, mlo, mhi),
+            f.float().cpu().numpy(), m.float().cpu().numpy())
+
+
+def oracle_grad(orc, w, ffd, rng_, role=0, fixed=None, moving=None):
+    flo, fhi, mlo, mhi = rng_
+    fo = orc.normalize(w.fixed, flo, fhi, w.n_bins) if fixed is None else fixed
+    mo = orc.normalize(w.moving, mlo, mhi, w.n_bins) if moving is None else moving
+    P = orc.Problem(w.fixed_dims, w.moving_dims, w.n_bins, w.spatial_bins, w.ctrl_spacing, role)
+    return orc.gradient(P, fo, mo, ffd)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_1804_05061_amd as S
+    return S
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_ct256_full_size(S, orc, role):
+    """Workload 2 at 256x256x128, the benchmark configuration."""
+    w = synth.ct_phantom()
+    D, g, ffd, r, _, _ = run_gpu(S, w, S.F32, role)
+    Dr, gr = oracle_grad(orc, w, ffd, r, role)
+    print(f"ct256 role={role} D={D:.12f} oracle={Dr:.12f} rel={abs(D - Dr) / Dr:.2e} grad={rel(g, gr):.2e}",
+          flush=True)
+    assert abs(D - Dr) <= 1e-5 * abs(Dr)
+    assert rel(g, gr) <= 1e-4
+
+
+def test_ctpet_full_size(S, orc):
+    """Workload 4: CT-like 192^3 fixed, PET-like 96^3 moving (unequal grids)."""
+    w = synth.ct_pet()
+    D, g, ffd, r, _, _ = run_gpu(S, w, S.F32, 0, sigma=2.0, k=4)
+    Dr, gr = oracle_grad(orc, w, ffd, r)
+    print(f"ctpet D={D:.12f} oracle={Dr:.12f} rel={abs(D - Dr) / Dr:.2e} grad={rel(g, gr):.2e}", flush=True)
+    assert abs(D - Dr) <= 1e-5 * abs(Dr)
+    assert rel(g, gr) <= 1e-4
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_oct512_precision(S, orc, dtype):
+    """Workload 3 at 512x512x128: FP32, FP16 and BF16 storage."""
+    w = synth.oct_layers()
+    dt = {"f32": S.F32, "f16": S.F16, "bf16": S.BF16}[dtype]
+    D, g, ffd, r, f_st, m_st = run_gpu(S, w, dt, 0, sigma=2.0, k=3)
+    Dr, gr = oracle_grad(orc, w, ffd, r)                      # FP32 data, FP64 arithmetic
+    e2e_v, e2e_g = abs(D - Dr) / Dr, rel(g, gr)
+    Dq, gq = oracle_grad(orc, w, ffd, r, fixed=f_st, moving=m_st)   # stored values, FP64 arithmetic
+    ar_v, ar_g = abs(D - Dq) / Dq, rel(g, gq)
+    print(f"oct512 {dtype}: end-to-end value {e2e_v:.2e} grad {e2e_g:.2e}; arithmetic-only value {ar_v:.2e} "
+          f"grad {ar_g:.2e}", flush=True)
+    assert ar_v <= 1e-5 and ar_g <= 1e-4
+    if dtype == "f32":
+        assert e2e_v <= 1e-5 and e2e_g <= 1e-4
+    else:
+        assert e2e_v <= 1e-3

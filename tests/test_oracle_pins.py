@@ -388,3 +388,23 @@ def test_mirror_ramp_gradient_symmetry(orc, role):
     assert np.abs(gx[:, :, n - 1]).max() == 0.0
     assert np.abs(gx[:, :, :n - 1] + gx[:, :, n - 2::-1]).max() <= 1e-12 * scale
     assert abs(gx.sum()) <= 1e-12 * np.abs(gx).sum()
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_constant_estimated_image_closed_forms(orc, role):
+    """B constant on a bin centre: sigma_r^2 = 0 in every region, all regions
+    are degenerate and D = 0.  B constant off a bin centre: every voxel has the
+    same two-bin Parzen distribution of B, no A-bin explains any of its
+    variance (CR_r = 0) and D = sum_r p(r) = 1."""
+    w = synth.blobs(n=14)
+    nb = 32
+    varying = orc.normalize(w.moving, w.moving.min(), w.moving.max(), nb)
+    p = P(orc, (14, 14, 14), nb=nb, K=(4, 4, 4), d=(4, 4, 4), role=role)
+    ffd = synth.random_ffd(p.ctrl_dims, 0.8, 23)
+    for level, expect in ((7.0, 0.0), (7.25, 1.0)):
+        const = np.full_like(varying, level)
+        fixed, moving = (const, varying) if role == 0 else (varying, const)
+        D, g = orc.gradient(p, fixed, moving, ffd)
+        assert abs(D - expect) < 1e-12
+        if expect == 0.0:
+            assert np.abs(g).max() == 0.0
