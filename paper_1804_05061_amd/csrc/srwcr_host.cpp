@@ -149,6 +149,7 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         g.nc[e] = (g.nf[e] - 1) / g.delta[e] + 4;
         g.same_grid[e] = g.nm[e] == g.nf[e];
         g.ratio[e] = (float)((double)g.nm[e] / (double)g.nf[e]);
+        g.ratio_d[e] = (double)g.nm[e] / (double)g.nf[e];
     }
     g.nb = prob->n_bins;
     g.role = prob->role;
@@ -172,8 +173,9 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
     for (int e = 0; e < 3; ++e) {
         const int N = g.nf[e], K = g.K[e];
         std::vector<int> sp_cell(N), ffd_p(N), mv_base(N);
-        std::vector<float4> sp_w(N), ffd_w(N);
-        std::vector<float> mv_frac(N);
+        std::vector<float4> sp_w(N);
+        std::vector<double4> ffd_w(N);
+        std::vector<double> mv_frac(N);
         for (int x = 0; x < N; ++x) {
             // spatial bins: node j at (j - 1) (N - 1) / (K - 3); integer cell arithmetic
             const long num = (long)x * (K - 3);
@@ -187,13 +189,13 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
             const int d = g.delta[e];
             ffd_p[x] = x / d;
             const double eta = (double)(x % d) / d;
-            ffd_w[x] = make_float4((float)bspline_piece(0, eta), (float)bspline_piece(1, eta),
-                                   (float)bspline_piece(2, eta), (float)bspline_piece(3, eta));
+            ffd_w[x] = make_double4(bspline_piece(0, eta), bspline_piece(1, eta), bspline_piece(2, eta),
+                                    bspline_piece(3, eta));
             // moving-grid mapping y = (x + 1/2) M / N - 1/2 (+ u M / N)
             const double yv = ((double)x + 0.5) * g.nm[e] / g.nf[e] - 0.5;
             const double fl = std::floor(yv);
             mv_base[x] = (int)fl;
-            mv_frac[x] = (float)(yv - fl);
+            mv_frac[x] = yv - fl;
         }
         cells[e] = sp_cell;
         void *d;
@@ -203,12 +205,12 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         g.sp_w[e] = (const float4 *)d;
         if ((st = upload(ffd_p.data(), N * sizeof(int), &d))) goto bad;
         g.ffd_p[e] = (const int *)d;
-        if ((st = upload(ffd_w.data(), N * sizeof(float4), &d))) goto bad;
-        g.ffd_w[e] = (const float4 *)d;
+        if ((st = upload(ffd_w.data(), N * sizeof(double4), &d))) goto bad;
+        g.ffd_w[e] = (const double4 *)d;
         if ((st = upload(mv_base.data(), N * sizeof(int), &d))) goto bad;
         g.mv_base[e] = (const int *)d;
-        if ((st = upload(mv_frac.data(), N * sizeof(float), &d))) goto bad;
-        g.mv_frac[e] = (const float *)d;
+        if ((st = upload(mv_frac.data(), N * sizeof(double), &d))) goto bad;
+        g.mv_frac[e] = (const double *)d;
     }
 
     {

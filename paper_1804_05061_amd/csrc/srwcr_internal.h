@@ -47,9 +47,10 @@ struct Geom {
     const int *sp_cell[3];     // spatial cell of each fixed coordinate, 0..K-4
     const float4 *sp_w[3];     // its four cubic B-spline weights (eq 8)
     const int *ffd_p[3];       // x / delta
-    const float4 *ffd_w[3];    // beta_0..3((x mod delta) / delta)
+    const double4 *ffd_w[3];   // beta_0..3((x mod delta) / delta), FP64 (the warp runs in FP64)
     const int *mv_base[3];     // floor((x + 1/2) M / N - 1/2) (unequal grids only)
-    const float *mv_frac[3];   // (x + 1/2) M / N - 1/2 - base
+    const double *mv_frac[3];  // (x + 1/2) M / N - 1/2 - base
+    double ratio_d[3];         // nm / nf per axis
 };
 
 // Workspace layout (device bytes, offsets from the workspace base).

@@ -142,38 +142,40 @@ __device__ __forceinline__ void parzen(float s, int L, int &k, float &t, float &
 // d h(t) / ds for the lower tap; the upper tap has the opposite sign
 __device__ __forceinline__ float parzen_dw0(float t) { return (t < 0.5f) ? -0.1f - 3.6f * t : -3.7f + 3.6f * t; }
 
-// FFD displacement of the 64 voxels of a row segment (eqs 8, 17).  The wave
-// first contracts the y and z B-spline weights into per-x-node coefficients
-// c1[e][n] (one node per lane), then each lane applies its four x weights.
+// FFD displacement of the 64 voxels of a row segment (eqs 8, 17), in FP64.
+// The wave first contracts the y and z B-spline weights into per-x-node
+// coefficients c1[e][n] (one node per lane), then each lane applies its four
+// x weights.  The warp runs in FP64 (full rate on CDNA, like non-packed FP32)
+// so that the bin of a warped sample is decided as the FP64 definition does.
 __device__ __forceinline__ void ffd_row(const Geom &g, const float *__restrict__ ffd, int xs, int xe, int y, int z,
-                                        int xc, float *c1, int lane, float u[3])
+                                        int xc, double *c1, int lane, double u[3])
 {
     const int py = g.ffd_p[1][y], pz = g.ffd_p[2][z];
-    const float4 by = g.ffd_w[1][y], bz = g.ffd_w[2][z];
+    const double4 by = g.ffd_w[1][y], bz = g.ffd_w[2][z];
     const int px_lo = g.ffd_p[0][xs], px_hi = g.ffd_p[0][xe - 1];
     const int nn = px_hi - px_lo + 4;
     const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
-    const float wy[4] = {by.x, by.y, by.z, by.w}, wz[4] = {bz.x, bz.y, bz.z, bz.w};
+    const double wy[4] = {by.x, by.y, by.z, by.w}, wz[4] = {bz.x, bz.y, bz.z, bz.w};
     for (int t = lane; t < 3 * nn; t += kWave) {
         const int e = t / nn, n = t - e * nn;
         const float *dp = ffd + e * ncell + ((size_t)pz * g.nc[1] + py) * g.nc[0] + px_lo + n;
-        float acc = 0.0f;
+        double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            float r = 0.0f;
+            double r = 0.0;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) r = fmaf(wy[b], dp[((size_t)c * g.nc[1] + b) * g.nc[0]], r);
-            acc = fmaf(wz[c], r, acc);
+            for (int b = 0; b < 4; ++b) r = fma(wy[b], (double)dp[((size_t)c * g.nc[1] + b) * g.nc[0]], r);
+            acc = fma(wz[c], r, acc);
         }
         c1[e * kMaxNodeSeg + n] = acc;
     }
     wave_sync();
     const int px = g.ffd_p[0][xc] - px_lo;
-    const float4 bx = g.ffd_w[0][xc];
+    const double4 bx = g.ffd_w[0][xc];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-        const float *c = c1 + e * kMaxNodeSeg + px;
-        u[e] = fmaf(bx.x, c[0], fmaf(bx.y, c[1], fmaf(bx.z, c[2], bx.w * c[3])));
+        const double *c = c1 + e * kMaxNodeSeg + px;
+        u[e] = fma(bx.x, c[0], fma(bx.y, c[1], fma(bx.z, c[2], bx.w * c[3])));
     }
     wave_sync();
 }
@@ -181,59 +183,74 @@ __device__ __forceinline__ void ffd_row(const Geom &g, const float *__restrict__
 // Backward warping: trilinear sample of the moving volume at T(x) mapped to
 // the moving grid, coordinates clamped to [0, M - 1]; grad (if non-null) gets
 // dM/dy, zero along clamped axes.  y = base + frac + u * ratio keeps the
-// integer part exact.
+// integer part exact.  FP64 arithmetic on the stored intensities.
 template <int MDT>
-__device__ __forceinline__ float sample_moving(const Geom &g, const void *__restrict__ mov, int x, int y, int z,
-                                               const float u[3], float *grad)
+__device__ __forceinline__ double sample_moving(const Geom &g, const void *__restrict__ mov, int x, int y, int z,
+                                                const double u[3], double *grad)
 {
     const int coord[3] = {x, y, z};
     int i0[3];
-    float f[3];
+    double f[3];
     bool cl[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         const int M = g.nm[e];
         int b;
-        float t;
+        double t;
         if (g.same_grid[e]) {
             b = coord[e];
             t = u[e];
         } else {
             b = g.mv_base[e][coord[e]];
-            t = fmaf(u[e], g.ratio[e], g.mv_frac[e][coord[e]]);
+            t = fma(u[e], g.ratio_d[e], g.mv_frac[e][coord[e]]);
         }
-        const float ft = floorf(t);
+        const double ft = floor(t);
         int i = b + (int)ft;
-        float fr = t - ft;
+        double fr = t - ft;
         bool c = false;
-        if (i < 0) { i = 0; fr = 0.0f; c = true; }
-        else if (i > M - 1 || (i == M - 1 && fr > 0.0f)) { i = M - 1; fr = 0.0f; c = true; }
-        if (i == M - 1) { i = M - 2; fr = 1.0f; }
+        if (i < 0) { i = 0; fr = 0.0; c = true; }
+        else if (i > M - 1 || (i == M - 1 && fr > 0.0)) { i = M - 1; fr = 0.0; c = true; }
+        if (i == M - 1) { i = M - 2; fr = 1.0; }
         i0[e] = i;
         f[e] = fr;
         cl[e] = c;
     }
     const size_t sx = 1, sy = (size_t)g.nm[0], sz = (size_t)g.nm[0] * g.nm[1];
     const size_t base = i0[2] * sz + i0[1] * sy + i0[0];
-    const float v000 = ld_int<MDT>(mov, base), v100 = ld_int<MDT>(mov, base + sx);
-    const float v010 = ld_int<MDT>(mov, base + sy), v110 = ld_int<MDT>(mov, base + sy + sx);
-    const float v001 = ld_int<MDT>(mov, base + sz), v101 = ld_int<MDT>(mov, base + sz + sx);
-    const float v011 = ld_int<MDT>(mov, base + sz + sy), v111 = ld_int<MDT>(mov, base + sz + sy + sx);
+    const double v000 = ld_int<MDT>(mov, base), v100 = ld_int<MDT>(mov, base + sx);
+    const double v010 = ld_int<MDT>(mov, base + sy), v110 = ld_int<MDT>(mov, base + sy + sx);
+    const double v001 = ld_int<MDT>(mov, base + sz), v101 = ld_int<MDT>(mov, base + sz + sx);
+    const double v011 = ld_int<MDT>(mov, base + sz + sy), v111 = ld_int<MDT>(mov, base + sz + sy + sx);
     // lerp(a, b, f) = a - f a + f b: exact at f = 0 and at f = 1 (the last grid plane)
-    auto lerp = [](float a, float b, float t) { return fmaf(t, b, fmaf(-t, a, a)); };
-    const float a00 = lerp(v000, v100, f[0]), a10 = lerp(v010, v110, f[0]);
-    const float a01 = lerp(v001, v101, f[0]), a11 = lerp(v011, v111, f[0]);
-    const float b0 = lerp(a00, a10, f[1]), b1 = lerp(a01, a11, f[1]);
-    const float val = lerp(b0, b1, f[2]);
+    auto lerp = [](double a, double b, double t) { return fma(t, b, fma(-t, a, a)); };
+    const double a00 = lerp(v000, v100, f[0]), a10 = lerp(v010, v110, f[0]);
+    const double a01 = lerp(v001, v101, f[0]), a11 = lerp(v011, v111, f[0]);
+    const double b0 = lerp(a00, a10, f[1]), b1 = lerp(a01, a11, f[1]);
+    const double val = lerp(b0, b1, f[2]);
     if (grad) {
-        const float d00 = v100 - v000, d10 = v110 - v010, d01 = v101 - v001, d11 = v111 - v011;
-        const float dy0 = fmaf(f[1], d10 - d00, d00), dy1 = fmaf(f[1], d11 - d01, d01);
-        grad[0] = cl[0] ? 0.0f : fmaf(f[2], dy1 - dy0, dy0);
-        const float e0 = a10 - a00, e1 = a11 - a01;
-        grad[1] = cl[1] ? 0.0f : fmaf(f[2], e1 - e0, e0);
-        grad[2] = cl[2] ? 0.0f : b1 - b0;
+        const double d00 = v100 - v000, d10 = v110 - v010, d01 = v101 - v001, d11 = v111 - v011;
+        const double dy0 = fma(f[1], d10 - d00, d00), dy1 = fma(f[1], d11 - d01, d01);
+        grad[0] = cl[0] ? 0.0 : fma(f[2], dy1 - dy0, dy0);
+        const double e0 = a10 - a00, e1 = a11 - a01;
+        grad[1] = cl[1] ? 0.0 : fma(f[2], e1 - e0, e0);
+        grad[2] = cl[2] ? 0.0 : b1 - b0;
     }
     return val;
+}
+
+// Parzen taps of a warped FP64 sample: the bin is decided in FP64, the
+// in-bin position is then rounded to FP32.
+__device__ __forceinline__ void parzen_d(double s, int L, int &k, float &t, float &w0, float &w1)
+{
+    int kk = (int)s;                         // s >= 0
+    if (kk > L - 1) kk = L - 1;
+    const float tt = (float)(s - (double)kk);
+    float w = (tt < 0.5f) ? 1.0f - tt * (0.1f + 1.8f * tt) : 1.9f - tt * (3.7f - 1.8f * tt);
+    w = fminf(fmaxf(w, 0.0f), 1.0f);
+    k = kk;
+    t = tt;
+    w0 = w;
+    w1 = 1.0f - w;
 }
 
 // ------------------------------------------------------------------ zero
@@ -330,7 +347,7 @@ __host__ __device__ __forceinline__ int hist_stride(int nb) { return 3 * nb + ((
 size_t value_lds_bytes(const Geom &g)
 {
     return (size_t)kNReg * hist_stride(g.nb) * sizeof(double) +
-           (size_t)(kValueThreads / kWave) * 3 * kMaxNodeSeg * sizeof(float);
+           (size_t)(kValueThreads / kWave) * 3 * kMaxNodeSeg * sizeof(double);
 }
 
 // Wave-uniform minimum: butterfly inside each 16-lane row (DPP), then the
@@ -388,7 +405,7 @@ k_value(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fix
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
-    float *c1 = reinterpret_cast<float *>(H + nH) + wave * 3 * kMaxNodeSeg;
+    double *c1 = H + nH + wave * 3 * kMaxNodeSeg;
     const WorkItem it = items[blockIdx.x];
 
     for (int i = threadIdx.x; i < nH; i += blockDim.x) H[i] = 0.0;
@@ -405,16 +422,18 @@ k_value(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fix
         const bool valid = x < xe;
         const int xc = valid ? x : xe - 1;
 
-        float u[3];
+        double u[3];
         ffd_row(g, ffd, xs, xe, y, z, xc, c1, lane, u);
-        float sm = sample_moving<MDT>(g, moving, xc, y, z, u, nullptr);
-        sm = fminf(fmaxf(sm, 0.0f), (float)L);
+        double sm = sample_moving<MDT>(g, moving, xc, y, z, u, nullptr);
+        sm = fmin(fmax(sm, 0.0), (double)L);
         const float sf = ld_int<FDT>(fixed, ((size_t)z * g.nf[1] + y) * g.nf[0] + xc);
-        const float sA = g.role ? sf : sm, sB = g.role ? sm : sf;
-        int kA, kB;
-        float tA, tB, a0, a1, b0w, b1w;
-        parzen(sA, L, kA, tA, a0, a1);
-        parzen(sB, L, kB, tB, b0w, b1w);
+        int kM, kF;
+        float tM, tF, m0w, m1w, f0w, f1w;
+        parzen_d(sm, L, kM, tM, m0w, m1w);
+        parzen(sf, L, kF, tF, f0w, f1w);
+        const int kA = g.role ? kF : kM, kB = g.role ? kM : kF;
+        const float a0 = g.role ? f0w : m0w, a1 = g.role ? f1w : m1w;
+        const float b1w = g.role ? m1w : f1w;
         const float m1 = (float)kB + b1w;
         const float m2 = fmaf((float)(2 * kB + 1), b1w, (float)(kB * kB));
 
@@ -669,16 +688,19 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
         const bool valid = x < xe;
         const int xc = valid ? x : xe - 1;
 
-        float u[3], dm[3];
-        ffd_row(g, ffd, xs, xe, y, z, xc, scr, lane, u);
-        float sm = sample_moving<MDT>(g, moving, xc, y, z, u, dm);
-        sm = fminf(fmaxf(sm, 0.0f), (float)L);
+        double u[3], dm[3];
+        ffd_row(g, ffd, xs, xe, y, z, xc, reinterpret_cast<double *>(scr), lane, u);
+        double sm = sample_moving<MDT>(g, moving, xc, y, z, u, dm);
+        sm = fmin(fmax(sm, 0.0), (double)L);
         const float sf = ld_int<FDT>(fixed, ((size_t)z * g.nf[1] + y) * g.nf[0] + xc);
-        const float sA = g.role ? sf : sm, sB = g.role ? sm : sf;
-        int kA, kB;
-        float tA, tB, a0, a1, b0w, b1w;
-        parzen(sA, L, kA, tA, a0, a1);
-        parzen(sB, L, kB, tB, b0w, b1w);
+        int kM, kF;
+        float tM, tF, m0w, m1w, f0w, f1w;
+        parzen_d(sm, L, kM, tM, m0w, m1w);
+        parzen(sf, L, kF, tF, f0w, f1w);
+        const int kA = g.role ? kF : kM, kB = g.role ? kM : kF;
+        const float tA = g.role ? tF : tM, tB = g.role ? tM : tF;
+        const float a0 = g.role ? f0w : m0w, a1 = g.role ? f1w : m1w;
+        const float b1w = g.role ? m1w : f1w;
         const float m1 = (float)kB + b1w;
         const float4 wx4 = g.sp_w[0][xc];
         const int ox = g.sp_cell[0][xc] - it.cx;
@@ -776,7 +798,7 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
         // q = dD/ds * dM/dy * dy/dT  (eq 16)
         float q[3];
 #pragma unroll
-        for (int e = 0; e < 3; ++e) q[e] = valid ? gs * dm[e] * g.ratio[e] : 0.0f;
+        for (int e = 0; e < 3; ++e) q[e] = valid ? gs * (float)dm[e] * g.ratio[e] : 0.0f;
 
         // scatter to control points (eq 17): per FFD cell p of the segment the
         // four moments M[p][l][e] = sum_{x in p} beta_l(eta_x) q_e(x) ...
@@ -794,11 +816,11 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
             float m0 = 0.0f, m1_ = 0.0f, m2_ = 0.0f, m3 = 0.0f;
             for (int xx = xa; xx < xb; ++xx) {
                 const float v = qb[(xx - xs) * 3 + e];
-                const float4 b = g.ffd_w[0][xx];
-                m0 = fmaf(b.x, v, m0);
-                m1_ = fmaf(b.y, v, m1_);
-                m2_ = fmaf(b.z, v, m2_);
-                m3 = fmaf(b.w, v, m3);
+                const double4 b = g.ffd_w[0][xx];
+                m0 = fmaf((float)b.x, v, m0);
+                m1_ = fmaf((float)b.y, v, m1_);
+                m2_ = fmaf((float)b.z, v, m2_);
+                m3 = fmaf((float)b.w, v, m3);
             }
             cm[(p * 4 + 0) * 3 + e] = m0;
             cm[(p * 4 + 1) * 3 + e] = m1_;
@@ -808,8 +830,9 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
         wave_sync();
         // ... node sums R1[n][e] = sum_l M[n - l][l][e], then the 16 (y, z) node weights
         const int py = g.ffd_p[1][y], pz = g.ffd_p[2][z];
-        const float4 by = g.ffd_w[1][y], bz = g.ffd_w[2][z];
-        const float byv[4] = {by.x, by.y, by.z, by.w}, bzv[4] = {bz.x, bz.y, bz.z, bz.w};
+        const double4 by = g.ffd_w[1][y], bz = g.ffd_w[2][z];
+        const float byv[4] = {(float)by.x, (float)by.y, (float)by.z, (float)by.w};
+        const float bzv[4] = {(float)bz.x, (float)bz.y, (float)bz.z, (float)bz.w};
         for (int t = lane; t < nn * 3; t += kWave) {
             const int n = t / 3, e = t - 3 * n;
             float r1 = 0.0f;
@@ -883,7 +906,7 @@ template <int MDT>
 __global__ void __launch_bounds__(256) k_warp(Geom g, const void *__restrict__ moving, const float *__restrict__ ffd,
                                               float *__restrict__ out)
 {
-    __shared__ float c1s[4][3 * kMaxNodeSeg];
+    __shared__ double c1s[4][3 * kMaxNodeSeg];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nseg = (g.nf[0] + kWave - 1) / kWave;
@@ -897,11 +920,11 @@ __global__ void __launch_bounds__(256) k_warp(Geom g, const void *__restrict__ m
     const int x = xs + lane;
     const bool valid = x < xe;
     const int xc = valid ? x : xe - 1;
-    float u[3];
+    double u[3];
     ffd_row(g, ffd, xs, xe, y, z, xc, c1s[wave], lane, u);
-    float v = sample_moving<MDT>(g, moving, xc, y, z, u, nullptr);
-    v = fminf(fmaxf(v, 0.0f), (float)(g.nb - 1));
-    if (valid) out[((size_t)z * g.nf[1] + y) * g.nf[0] + x] = v;
+    double v = sample_moving<MDT>(g, moving, xc, y, z, u, nullptr);
+    v = fmin(fmax(v, 0.0), (double)(g.nb - 1));
+    if (valid) out[((size_t)z * g.nf[1] + y) * g.nf[0] + x] = (float)v;
 }
 
 hipError_t launch_warp(const Geom &g, const void *moving, const float *ffd, float *out, hipStream_t s)
