@@ -222,6 +222,15 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         int max_lds = 0;
         he = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         if (he != hipSuccess) { st = hip_fail(he, "hipDeviceGetAttribute(shared memory)"); goto bad; }
+        // item rows: 2 x 64 voxels per wave when the FFD x-spacing leaves room in
+        // the per-wave scratch, else 64
+        g.xw = g.delta[0] >= 3 ? kSlots * kWave : kWave;
+        g.c1n = (g.xw - 1) / g.delta[0] + 5;
+        {
+            const int np_max = (g.xw - 1) / g.delta[0] + 2;
+            int scr = std::max(6 * g.c1n, std::max(64, 3 * kSlots * kWave + 12 * np_max));
+            g.gscr = (scr + 3) / 4 * 4;
+        }
         P->value_lds = value_lds_bytes(g);
         if (P->value_lds > (size_t)max_lds) {
             st = fail(SRWCR_E_UNSUPPORTED, "value pass needs %zu B of LDS, device allows %d", P->value_lds, max_lds);
@@ -253,7 +262,7 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
             return ch;
         };
         const double target = std::min(65536.0, std::max(2048.0, nvox / 600.0));
-        int xc_max = 128, yc_max = 0, zc_max = 0;
+        int xc_max = g.xw, yc_max = 0, zc_max = 0;
         std::vector<WorkItem> items;
         for (int attempt = 0; attempt < 64; ++attempt) {
             items.clear();

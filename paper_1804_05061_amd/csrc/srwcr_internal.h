@@ -14,9 +14,10 @@ constexpr int kNReg = kXN * 16;   // regions of a work item: 5 (x) x 4 (y) x 4 (
 constexpr int kWin = 4;           // bin slots of one value-pass window (A-bins kmin .. kmin + 3)
 constexpr int kGWinA = 4;         // gradient-pass window, moving image as A (one slot per voxel)
 constexpr int kGWinB = 5;         // gradient-pass window, moving image as B (two slots per voxel)
-constexpr int kValueThreads = 1024;
-constexpr int kGradThreads = 1024;
+constexpr int kValueThreads = 768;
+constexpr int kGradThreads = 768;
 constexpr int kMaxNodeSeg = 68;   // FFD x-nodes one 64-voxel row segment can touch (delta >= 1)
+constexpr int kSlots = 2;         // voxels per lane: an item row holds up to 2 x 64 voxels
 
 // One unit of work of the value and gradient passes: a box of fixed voxels
 // inside one spatial-bin cell along y and z and at most two cells along x, so
@@ -51,6 +52,9 @@ struct Geom {
     const int *mv_base[3];     // floor((x + 1/2) M / N - 1/2) (unequal grids only)
     const double *mv_frac[3];  // (x + 1/2) M / N - 1/2 - base
     double ratio_d[3];         // nm / nf per axis
+    int xw;                    // x-width of the work items (64 or 128 voxels)
+    int c1n;                   // FFD x-nodes an item row touches at most: (xw - 1) / delta + 5
+    int gscr;                  // floats of per-wave scratch in the gradient pass
 };
 
 // Workspace layout (device bytes, offsets from the workspace base).

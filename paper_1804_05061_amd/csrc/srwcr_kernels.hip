@@ -180,6 +180,46 @@ __device__ __forceinline__ void ffd_row(const Geom &g, const float *__restrict__
     wave_sync();
 }
 
+// Per-row FFD coefficients c1[e][n] = sum_{m,n'} beta_m(eta_y) beta_n'(eta_z)
+// d_e[pz + n'][py + m][px_lo + n] for the x-nodes of an item row [xs, xe)
+// (one node-component per lane, FP64, 32-bit element offsets).
+__device__ __forceinline__ int ffd_c1(const Geom &g, const float *__restrict__ ffd, int xs, int xe, int y, int z,
+                                      double *c1, int lane)
+{
+    const int py = g.ffd_p[1][y], pz = g.ffd_p[2][z];
+    const double4 by = g.ffd_w[1][y], bz = g.ffd_w[2][z];
+    const int px_lo = g.ffd_p[0][xs], px_hi = g.ffd_p[0][xe - 1];
+    const int nn = px_hi - px_lo + 4;
+    const unsigned sy = (unsigned)g.nc[0], sz = (unsigned)g.nc[0] * g.nc[1], ncell = sz * g.nc[2];
+    const double wy[4] = {by.x, by.y, by.z, by.w}, wz[4] = {bz.x, bz.y, bz.z, bz.w};
+    for (int t = lane; t < 3 * nn; t += kWave) {
+        const int e = t / nn, n = t - e * nn;
+        const unsigned off = e * ncell + pz * sz + py * sy + (unsigned)(px_lo + n);
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double r = 0.0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) r = fma(wy[b], (double)ffd[off + c * sz + b * sy], r);
+            acc = fma(wz[c], r, acc);
+        }
+        c1[e * g.c1n + n] = acc;
+    }
+    return px_lo;
+}
+
+// Displacement of voxel xc from the row coefficients (four x weights).
+__device__ __forceinline__ void ffd_u(const Geom &g, const double *c1, int px_lo, int xc, double u[3])
+{
+    const int px = g.ffd_p[0][xc] - px_lo;
+    const double4 bx = g.ffd_w[0][xc];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const double *c = c1 + e * g.c1n + px;
+        u[e] = fma(bx.x, c[0], fma(bx.y, c[1], fma(bx.z, c[2], bx.w * c[3])));
+    }
+}
+
 // Backward warping: trilinear sample of the moving volume at T(x) mapped to
 // the moving grid, coordinates clamped to [0, M - 1]; grad (if non-null) gets
 // dM/dy, zero along clamped axes.  y = base + frac + u * ratio keeps the
@@ -347,7 +387,7 @@ __host__ __device__ __forceinline__ int hist_stride(int nb) { return 3 * nb + ((
 size_t value_lds_bytes(const Geom &g)
 {
     return (size_t)kNReg * hist_stride(g.nb) * sizeof(double) +
-           (size_t)(kValueThreads / kWave) * 3 * kMaxNodeSeg * sizeof(double);
+           (size_t)(kValueThreads / kWave) * 3 * g.c1n * sizeof(double);
 }
 
 // Wave-uniform minimum: butterfly inside each 16-lane row (DPP), then the
@@ -365,19 +405,33 @@ __device__ __forceinline__ int wave_min_dpp(int v)
 
 __device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
-// One bin window of the value pass: lanes with `inw` put their taps on the
-// window slots o and o + 1 (bins kbase + o, kbase + o + 1); the wave sums the
-// 4 slots x 15 (x-node, moment) values across lanes and each lane spreads one
-// total over the 16 (y, z) regions of its column.
-__device__ __forceinline__ void value_window(double *H, int rs, int nb, int L, bool inw, int o, int kbase, float a0,
-                                             float a1, const float (&wxv)[15], const float (&wyz)[16], int lane)
+// Per-voxel quantities of the value pass.
+struct VoxA {
+    int k;          // A-bin (lower tap)
+    float a0, a1;   // Parzen weights of bins k and k + 1
+    float wxv[15];  // x-node weight (5 nodes) times (1, m1(B), m2(B))
+};
+
+// Window slot weight of a voxel: a0 on slot o, a1 on slot o + 1.
+__device__ __forceinline__ float slot_w(bool in, int o, int w, float a0, float a1)
+{
+    return in ? ((o == w) ? a0 : ((o == w - 1) ? a1 : 0.0f)) : 0.0f;
+}
+
+// One bin window of the value pass over the lane's two voxels: their taps go
+// to window slots (bins kbase + o, kbase + o + 1); the wave sums 4 slots x 15
+// (x-node, moment) values across lanes and each lane spreads one total over
+// the 16 (y, z) regions of its column with FP64 LDS atomics.
+__device__ __forceinline__ void value_window(double *H, int rs, int L, int kbase, const VoxA (&v)[kSlots],
+                                             const bool (&in)[kSlots], const float (&wyz)[16], int lane)
 {
     float V[64];
 #pragma unroll
     for (int w = 0; w < kWin; ++w) {
-        const float tw = inw ? ((o == w) ? a0 : ((o == w - 1) ? a1 : 0.0f)) : 0.0f;
+        const float t0 = slot_w(in[0], v[0].k - kbase, w, v[0].a0, v[0].a1);
+        const float t1 = slot_w(in[1], v[1].k - kbase, w, v[1].a0, v[1].a1);
 #pragma unroll
-        for (int q = 0; q < 15; ++q) V[w * 15 + q] = tw * wxv[q];
+        for (int q = 0; q < 15; ++q) V[w * 15 + q] = fmaf(t1, v[1].wxv[q], t0 * v[0].wxv[q]);
     }
 #pragma unroll
     for (int q = kWin * 15; q < 64; ++q) V[q] = 0.0f;
@@ -405,50 +459,54 @@ k_value(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fix
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
-    double *c1 = H + nH + wave * 3 * kMaxNodeSeg;
+    double *c1 = H + nH + wave * 3 * g.c1n;
     const WorkItem it = items[blockIdx.x];
 
     for (int i = threadIdx.x; i < nH; i += blockDim.x) H[i] = 0.0;
     __syncthreads();
 
-    const int nseg = (it.x1 - it.x0 + kWave - 1) / kWave;
     const int ny = it.y1 - it.y0, nz = it.z1 - it.z0;
-    const int nunits = nseg * ny * nz;
-    for (int unit = wave; unit < nunits; unit += nwaves) {
-        const int seg = unit % nseg, row = unit / nseg;
+    const int xs = it.x0, xe = it.x1;                    // xe - xs <= 64 kSlots
+    for (int row = wave; row < ny * nz; row += nwaves) {
         const int y = it.y0 + row % ny, z = it.z0 + row / ny;
-        const int xs = it.x0 + seg * kWave, xe = min(xs + kWave, it.x1);
-        const int x = xs + lane;
-        const bool valid = x < xe;
-        const int xc = valid ? x : xe - 1;
-
-        double u[3];
-        ffd_row(g, ffd, xs, xe, y, z, xc, c1, lane, u);
-        double sm = sample_moving<MDT>(g, moving, xc, y, z, u, nullptr);
-        sm = fmin(fmax(sm, 0.0), (double)L);
-        const float sf = ld_int<FDT>(fixed, ((size_t)z * g.nf[1] + y) * g.nf[0] + xc);
-        int kM, kF;
-        float tM, tF, m0w, m1w, f0w, f1w;
-        parzen_d(sm, L, kM, tM, m0w, m1w);
-        parzen(sf, L, kF, tF, f0w, f1w);
-        const int kA = g.role ? kF : kM, kB = g.role ? kM : kF;
-        const float a0 = g.role ? f0w : m0w, a1 = g.role ? f1w : m1w;
-        const float b1w = g.role ? m1w : f1w;
-        const float m1 = (float)kB + b1w;
-        const float m2 = fmaf((float)(2 * kB + 1), b1w, (float)(kB * kB));
-
-        // x weights on the item's 5 x-nodes (the lane's cell is it.cx or it.cx + 1)
-        const float4 wx4 = g.sp_w[0][xc];
-        const int ox = g.sp_cell[0][xc] - it.cx;
-        const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
-        float wxv[15];
+        const int px_lo = ffd_c1(g, ffd, xs, xe, y, z, c1, lane);
+        wave_sync();
+        VoxA v[kSlots];
+        bool pend[kSlots];
 #pragma unroll
-        for (int n = 0; n < kXN; ++n) {
-            const float wn = (n - ox >= 0 && n - ox < 4) ? wl[(n - ox) & 3] : 0.0f;
-            wxv[3 * n + 0] = wn;
-            wxv[3 * n + 1] = wn * m1;
-            wxv[3 * n + 2] = wn * m2;
+        for (int sl = 0; sl < kSlots; ++sl) {
+            const int x = xs + sl * kWave + lane;
+            pend[sl] = x < xe;
+            const int xc = pend[sl] ? x : xe - 1;
+            double u[3];
+            ffd_u(g, c1, px_lo, xc, u);
+            double sm = sample_moving<MDT>(g, moving, xc, y, z, u, nullptr);
+            sm = fmin(fmax(sm, 0.0), (double)L);
+            const float sf = ld_int<FDT>(fixed, ((size_t)z * g.nf[1] + y) * g.nf[0] + xc);
+            int kM, kF;
+            float tM, tF, m0w, m1w, f0w, f1w;
+            parzen_d(sm, L, kM, tM, m0w, m1w);
+            parzen(sf, L, kF, tF, f0w, f1w);
+            const int kB = g.role ? kM : kF;
+            const float b1w = g.role ? m1w : f1w;
+            v[sl].k = g.role ? kF : kM;
+            v[sl].a0 = g.role ? f0w : m0w;
+            v[sl].a1 = g.role ? f1w : m1w;
+            const float m1 = (float)kB + b1w;
+            const float m2 = fmaf((float)(2 * kB + 1), b1w, (float)(kB * kB));
+            // x weights on the item's 5 x-nodes (the voxel's cell is it.cx or it.cx + 1)
+            const float4 wx4 = g.sp_w[0][xc];
+            const int ox = g.sp_cell[0][xc] - it.cx;
+            const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
+#pragma unroll
+            for (int n = 0; n < kXN; ++n) {
+                const float wn = (n - ox >= 0 && n - ox < 4) ? wl[(n - ox) & 3] : 0.0f;
+                v[sl].wxv[3 * n + 0] = wn;
+                v[sl].wxv[3 * n + 1] = wn * m1;
+                v[sl].wxv[3 * n + 2] = wn * m2;
+            }
         }
+        wave_sync();                                   // c1 is rewritten by the next row
         const float4 wy4 = g.sp_w[1][y], wz4 = g.sp_w[2][z];
         const float wyv[4] = {wy4.x, wy4.y, wy4.z, wy4.w}, wzv[4] = {wz4.x, wz4.y, wz4.z, wz4.w};
         float wyz[16];
@@ -457,35 +515,42 @@ k_value(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fix
 #pragma unroll
             for (int j = 0; j < 4; ++j) wyz[k * 4 + j] = wyv[j] * wzv[k];
 
-        // bin windows, two per pass: A-bins [kmin, kmin + 2] of the pending lanes
+        // bin windows, two per pass: A-bins [kmin, kmin + 2] of the pending taps
         constexpr int BIG = 0x7fffffff;
-        bool pending = valid;
-        for (int pass = 0; pass <= nb; ++pass) {
-            int k1 = wave_min_dpp(pending ? kA : BIG);
+        for (int pass = 0; pass <= 2 * nb; ++pass) {
+            int k1 = wave_min_dpp(min(pend[0] ? v[0].k : BIG, pend[1] ? v[1].k : BIG));
             if (k1 == BIG) break;
-            bool in1 = pending && kA >= k1 && kA - k1 <= kWin - 2;
-            if (wave_ballot(in1) == 0ull) {                     // never stall: take the first pending lane
-                k1 = __builtin_amdgcn_readlane(kA, (int)__builtin_ctzll(wave_ballot(pending)));
-                in1 = pending && kA >= k1 && kA - k1 <= kWin - 2;
+            bool in1[kSlots], rest[kSlots], in2[kSlots];
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) in1[sl] = pend[sl] && v[sl].k >= k1 && v[sl].k - k1 <= kWin - 2;
+            if (wave_ballot(in1[0] || in1[1]) == 0ull) {      // never stall: take the first pending lane
+                const int key = min(pend[0] ? v[0].k : BIG, pend[1] ? v[1].k : BIG);
+                k1 = __builtin_amdgcn_readlane(key, (int)__builtin_ctzll(wave_ballot(key != BIG)));
+#pragma unroll
+                for (int sl = 0; sl < kSlots; ++sl) in1[sl] = pend[sl] && v[sl].k >= k1 && v[sl].k - k1 <= kWin - 2;
             }
-            const bool rest = pending && !in1;
-            const int k2 = wave_min_dpp(rest ? kA : BIG);
-            const bool in2 = rest && k2 != BIG && kA >= k2 && kA - k2 <= kWin - 2;
-            value_window(H, rs, nb, L, in1, kA - k1, k1, a0, a1, wxv, wyz, lane);
-            if (k2 != BIG) value_window(H, rs, nb, L, in2, kA - k2, k2, a0, a1, wxv, wyz, lane);
-            pending = rest && !in2;
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) rest[sl] = pend[sl] && !in1[sl];
+            const int k2 = wave_min_dpp(min(rest[0] ? v[0].k : BIG, rest[1] ? v[1].k : BIG));
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl)
+                in2[sl] = rest[sl] && k2 != BIG && v[sl].k >= k2 && v[sl].k - k2 <= kWin - 2;
+            value_window(H, rs, L, k1, v, in1, wyz, lane);
+            if (k2 != BIG) value_window(H, rs, L, k2, v, in2, wyz, lane);
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) pend[sl] = rest[sl] && !in2[sl];
         }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nH; e += blockDim.x) {
-        const double v = H[e];
-        if (v != 0.0) {
+        const double val = H[e];
+        if (val != 0.0) {
             const int rl = e / rs, rem = e - rl * rs;
             const int a = rem / 3, m = rem - 3 * a;
             const int i = rl % kXN, jk = rl / kXN, j = jk & 3, k = jk >> 2;
             if (a < nb && it.cx + i < g.K[0]) {
                 const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
-                unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], v);
+                unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], val);
             }
         }
     }
@@ -625,7 +690,6 @@ hipError_t launch_finalize(const Geom &g, double *moments, double *region, float
 }
 
 // --------------------------------------------------------- gradient pass
-constexpr int kGradScratch = 1024;   // floats of per-wave scratch
 
 // Region stride of the LDS copy of the gradient tables in floats: 3 nb plus a
 // pad that puts consecutive regions 12 banks apart (conflict-free row tables).
@@ -635,11 +699,19 @@ size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz)
 {
     const size_t tab = (size_t)kNReg * tab_stride(g.nb) * sizeof(float) + kNReg * sizeof(float);
     const size_t G = (size_t)gnx * gny * gnz * 3 * sizeof(double);
-    const size_t scratch = (size_t)(kGradThreads / kWave) * kGradScratch * sizeof(float);
+    const size_t scratch = (size_t)(kGradThreads / kWave) * g.gscr * sizeof(float);
     return G + tab + scratch;
 }
 
-template <int FDT, int MDT>
+// Per-voxel quantities of the gradient pass.
+struct VoxG {
+    int kA, kB;
+    float tA, tB, a0, a1, m1;
+    float wx5[kXN];
+    float dm[3];      // dM/dy (FP32)
+};
+
+template <int FDT, int MDT, int ROLE>
 __global__ void __launch_bounds__(kGradThreads)
 k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixed, const void *__restrict__ moving,
        const float *__restrict__ ffd, const float *__restrict__ tables, const float *__restrict__ alpha,
@@ -655,7 +727,7 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
-    float *scr = alph + kNReg + wave * kGradScratch;
+    float *scr = alph + kNReg + wave * g.gscr;
 
     for (int i = threadIdx.x; i < nG; i += blockDim.x) G[i] = 0.0;
     for (int i = threadIdx.x; i < kNReg * nb; i += blockDim.x) {
@@ -677,57 +749,68 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
     }
     __syncthreads();
 
-    const int nseg = (it.x1 - it.x0 + kWave - 1) / kWave;
     const int ny = it.y1 - it.y0, nz = it.z1 - it.z0;
-    const int nunits = nseg * ny * nz;
-    for (int unit = wave; unit < nunits; unit += nwaves) {
-        const int seg = unit % nseg, row = unit / nseg;
+    const int xs = it.x0, xe = it.x1;
+    for (int row = wave; row < ny * nz; row += nwaves) {
         const int y = it.y0 + row % ny, z = it.z0 + row / ny;
-        const int xs = it.x0 + seg * kWave, xe = min(xs + kWave, it.x1);
-        const int x = xs + lane;
-        const bool valid = x < xe;
-        const int xc = valid ? x : xe - 1;
-
-        double u[3], dm[3];
-        ffd_row(g, ffd, xs, xe, y, z, xc, reinterpret_cast<double *>(scr), lane, u);
-        double sm = sample_moving<MDT>(g, moving, xc, y, z, u, dm);
-        sm = fmin(fmax(sm, 0.0), (double)L);
-        const float sf = ld_int<FDT>(fixed, ((size_t)z * g.nf[1] + y) * g.nf[0] + xc);
-        int kM, kF;
-        float tM, tF, m0w, m1w, f0w, f1w;
-        parzen_d(sm, L, kM, tM, m0w, m1w);
-        parzen(sf, L, kF, tF, f0w, f1w);
-        const int kA = g.role ? kF : kM, kB = g.role ? kM : kF;
-        const float tA = g.role ? tF : tM, tB = g.role ? tM : tF;
-        const float a0 = g.role ? f0w : m0w, a1 = g.role ? f1w : m1w;
-        const float b1w = g.role ? m1w : f1w;
-        const float m1 = (float)kB + b1w;
-        const float4 wx4 = g.sp_w[0][xc];
-        const int ox = g.sp_cell[0][xc] - it.cx;
-        const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
-        float wx5[kXN];
+        double *c1 = reinterpret_cast<double *>(scr);
+        const int px_lo = ffd_c1(g, ffd, xs, xe, y, z, c1, lane);
+        wave_sync();
+        VoxG v[kSlots];
+        bool pend[kSlots];
 #pragma unroll
-        for (int n = 0; n < kXN; ++n) wx5[n] = (n - ox >= 0 && n - ox < 4) ? wl[(n - ox) & 3] : 0.0f;
+        for (int sl = 0; sl < kSlots; ++sl) {
+            const int x = xs + sl * kWave + lane;
+            pend[sl] = x < xe;
+            const int xc = pend[sl] ? x : xe - 1;
+            double u[3], dm[3];
+            ffd_u(g, c1, px_lo, xc, u);
+            double sm = sample_moving<MDT>(g, moving, xc, y, z, u, dm);
+            sm = fmin(fmax(sm, 0.0), (double)L);
+            const float sf = ld_int<FDT>(fixed, ((size_t)z * g.nf[1] + y) * g.nf[0] + xc);
+            int kM, kF;
+            float tM, tF, m0w, m1w, f0w, f1w;
+            parzen_d(sm, L, kM, tM, m0w, m1w);
+            parzen(sf, L, kF, tF, f0w, f1w);
+            v[sl].kA = ROLE ? kF : kM;
+            v[sl].kB = ROLE ? kM : kF;
+            v[sl].tA = ROLE ? tF : tM;
+            v[sl].tB = ROLE ? tM : tF;
+            v[sl].a0 = ROLE ? f0w : m0w;
+            v[sl].a1 = ROLE ? f1w : m1w;
+            v[sl].m1 = (float)v[sl].kB + (ROLE ? m1w : f1w);
+            const float4 wx4 = g.sp_w[0][xc];
+            const int ox = g.sp_cell[0][xc] - it.cx;
+            const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
+#pragma unroll
+            for (int n = 0; n < kXN; ++n) v[sl].wx5[n] = (n - ox >= 0 && n - ox < 4) ? wl[(n - ox) & 3] : 0.0f;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) v[sl].dm[e] = (float)dm[e];
+        }
+        wave_sync();                                   // scratch is reused below
         const float4 wy4 = g.sp_w[1][y], wz4 = g.sp_w[2][z];
         const float wyv[4] = {wy4.x, wy4.y, wy4.z, wy4.w}, wzv[4] = {wz4.x, wz4.y, wz4.z, wz4.w};
 
         // dD/ds_M: the region tables interpolated by w(r, x) = wx wy wz through
         // window row tables T_row[i][slot] = sum_jk wy_j wz_k T[(i, j, k)][kmin + slot]
         constexpr int BIG = 0x7fffffff;
-        float gs = 0.0f;
-        bool pending = valid;
+        float gs[kSlots] = {0.0f, 0.0f};
         float *rowt = scr;                                           // <= 64 floats
-        const int W = g.role == 0 ? kGWinA : kGWinB - 1;             // voxels taken per window: o in [0, W - 1]
-        for (int pass = 0; pass <= nb; ++pass) {
-            int kmin = wave_min_dpp(pending ? kA : BIG);
+        const int W = ROLE == 0 ? kGWinA : kGWinB - 1;             // voxels taken per window: o in [0, W - 1]
+        for (int pass = 0; pass <= 2 * nb; ++pass) {
+            int kmin = wave_min_dpp(min(pend[0] ? v[0].kA : BIG, pend[1] ? v[1].kA : BIG));
             if (kmin == BIG) break;
-            bool inw = pending && kA >= kmin && kA - kmin <= W - 1;
-            if (wave_ballot(inw) == 0ull) {
-                kmin = __builtin_amdgcn_readlane(kA, (int)__builtin_ctzll(wave_ballot(pending)));
-                inw = pending && kA >= kmin && kA - kmin <= W - 1;
+            bool inw[kSlots];
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) inw[sl] = pend[sl] && v[sl].kA >= kmin && v[sl].kA - kmin <= W - 1;
+            if (wave_ballot(inw[0] || inw[1]) == 0ull) {
+                const int key = min(pend[0] ? v[0].kA : BIG, pend[1] ? v[1].kA : BIG);
+                kmin = __builtin_amdgcn_readlane(key, (int)__builtin_ctzll(wave_ballot(key != BIG)));
+#pragma unroll
+                for (int sl = 0; sl < kSlots; ++sl)
+                    inw[sl] = pend[sl] && v[sl].kA >= kmin && v[sl].kA - kmin <= W - 1;
             }
-            const int o = kA - kmin;
-            if (g.role == 0) {
+            if (ROLE == 0) {
                 if (lane < kXN * kGWinA * 3) {                       // (i, slot, c)
                     const int i = lane / (kGWinA * 3), rem = lane - i * kGWinA * 3;
                     const int sl = rem / 3, c = rem - 3 * sl;
@@ -744,16 +827,20 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
                     rowt[lane] = acc;
                 }
                 wave_sync();
-                if (inw) {
-                    float C[3];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        float acc = 0.0f;
+                for (int sl = 0; sl < kSlots; ++sl) {
+                    if (inw[sl]) {
+                        const int o = v[sl].kA - kmin;
+                        float C[3];
 #pragma unroll
-                        for (int i = 0; i < kXN; ++i) acc = fmaf(wx5[i], rowt[(i * kGWinA + o) * 3 + c], acc);
-                        C[c] = acc;
+                        for (int c = 0; c < 3; ++c) {
+                            float acc = 0.0f;
+#pragma unroll
+                            for (int i = 0; i < kXN; ++i) acc = fmaf(v[sl].wx5[i], rowt[(i * kGWinA + o) * 3 + c], acc);
+                            C[c] = acc;
+                        }
+                        gs[sl] = parzen_dw0(v[sl].tA) * fmaf(fmaf(C[0], v[sl].m1, C[1]), v[sl].m1, C[2]);
                     }
-                    gs = parzen_dw0(tA) * fmaf(fmaf(C[0], m1, C[1]), m1, C[2]);
                 }
             } else {
                 constexpr int NS = kGWinB;                           // slots kmin .. kmin + 4
@@ -780,47 +867,52 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
                     rowt[lane] = acc;
                 }
                 wave_sync();
-                if (inw) {
-                    const float k21 = (float)(2 * kB + 1);
-                    float acc = 0.0f;
 #pragma unroll
-                    for (int i = 0; i < kXN; ++i) {
-                        const float t = k21 * rowt[kXN * NS + i] - a0 * rowt[i * NS + o] - a1 * rowt[i * NS + o + 1];
-                        acc = fmaf(wx5[i], t, acc);
+                for (int sl = 0; sl < kSlots; ++sl) {
+                    if (inw[sl]) {
+                        const int o = v[sl].kA - kmin;
+                        const float k21 = (float)(2 * v[sl].kB + 1);
+                        float acc = 0.0f;
+#pragma unroll
+                        for (int i = 0; i < kXN; ++i) {
+                            const float t = k21 * rowt[kXN * NS + i] - v[sl].a0 * rowt[i * NS + o] -
+                                            v[sl].a1 * rowt[i * NS + o + 1];
+                            acc = fmaf(v[sl].wx5[i], t, acc);
+                        }
+                        gs[sl] = -parzen_dw0(v[sl].tB) * acc;          // d m1 / d s_B = -d w0 / d s
                     }
-                    gs = -parzen_dw0(tB) * acc;                      // d m1 / d s_B = -d w0 / d s
                 }
             }
             wave_sync();
-            pending = pending && !inw;
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) pend[sl] = pend[sl] && !inw[sl];
         }
 
-        // q = dD/ds * dM/dy * dy/dT  (eq 16)
-        float q[3];
-#pragma unroll
-        for (int e = 0; e < 3; ++e) q[e] = valid ? gs * (float)dm[e] * g.ratio[e] : 0.0f;
-
-        // scatter to control points (eq 17): per FFD cell p of the segment the
-        // four moments M[p][l][e] = sum_{x in p} beta_l(eta_x) q_e(x) ...
+        // q = dD/ds * dM/dy * dy/dT  (eq 16), then the scatter to the control
+        // points (eq 17): per FFD cell p of the row the four moments
+        // M[p][l][e] = sum_{x in p} beta_l(eta_x) q_e(x) ...
         const int dx = g.delta[0];
-        const int px_lo = g.ffd_p[0][xs], px_hi = g.ffd_p[0][xe - 1];
+        const int px_hi = g.ffd_p[0][xe - 1];
         const int np = px_hi - px_lo + 1, nn = np + 3;
-        float *qb = scr;                                             // [64][3]
-        float *cm = scr + 3 * kWave;                                 // [np][4][3]
+        float *qb = scr;                                             // [128][3]
+        float *cm = scr + 3 * kSlots * kWave;                        // [np][4][3]
 #pragma unroll
-        for (int e = 0; e < 3; ++e) qb[lane * 3 + e] = q[e];
+        for (int sl = 0; sl < kSlots; ++sl)
+#pragma unroll
+            for (int e = 0; e < 3; ++e)
+                qb[(sl * kWave + lane) * 3 + e] = gs[sl] * v[sl].dm[e] * g.ratio[e];
         wave_sync();
         for (int t = lane; t < np * 3; t += kWave) {
             const int p = t / 3, e = t - 3 * p;
             const int xa = max(xs, (px_lo + p) * dx), xb = min(xe, (px_lo + p + 1) * dx);
             float m0 = 0.0f, m1_ = 0.0f, m2_ = 0.0f, m3 = 0.0f;
             for (int xx = xa; xx < xb; ++xx) {
-                const float v = qb[(xx - xs) * 3 + e];
+                const float q = qb[(xx - xs) * 3 + e];
                 const double4 b = g.ffd_w[0][xx];
-                m0 = fmaf((float)b.x, v, m0);
-                m1_ = fmaf((float)b.y, v, m1_);
-                m2_ = fmaf((float)b.z, v, m2_);
-                m3 = fmaf((float)b.w, v, m3);
+                m0 = fmaf((float)b.x, q, m0);
+                m1_ = fmaf((float)b.y, q, m1_);
+                m2_ = fmaf((float)b.z, q, m2_);
+                m3 = fmaf((float)b.w, q, m3);
             }
             cm[(p * 4 + 0) * 3 + e] = m0;
             cm[(p * 4 + 1) * 3 + e] = m1_;
@@ -857,20 +949,23 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
     __syncthreads();
     const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
     for (int i = threadIdx.x; i < nG; i += blockDim.x) {
-        const double v = G[i];
-        if (v != 0.0) {
+        const double val = G[i];
+        if (val != 0.0) {
             const int e = i % 3, c = i / 3;
             const int gx = c % it.gnx, gy = (c / it.gnx) % it.gny, gz = c / (it.gnx * it.gny);
             const size_t node = ((size_t)(gz + it.gz0) * g.nc[1] + (gy + it.gy0)) * g.nc[0] + (gx + it.gx0);
-            unsafeAtomicAdd(&grad[e * ncell + node], v);
+            unsafeAtomicAdd(&grad[e * ncell + node], val);
         }
     }
 }
 
-static hipError_t set_grad_lds(int fdt, int mdt, size_t bytes)
+static hipError_t set_grad_lds(int fdt, int mdt, int role, size_t bytes)
 {
     hipError_t e = hipSuccess;
-#define SRWCR_SET(F, M) if (fdt == F && mdt == M) e = set_lds(k_grad<F, M>, bytes);
+#define SRWCR_SET(F, M)                                                     \
+    if (fdt == F && mdt == M) {                                             \
+        e = role ? set_lds(k_grad<F, M, 1>, bytes) : set_lds(k_grad<F, M, 0>, bytes); \
+    }
     SRWCR_SET(0, 0) SRWCR_SET(0, 1) SRWCR_SET(0, 2) SRWCR_SET(1, 0) SRWCR_SET(1, 1) SRWCR_SET(1, 2)
     SRWCR_SET(2, 0) SRWCR_SET(2, 1) SRWCR_SET(2, 2)
 #undef SRWCR_SET
@@ -881,10 +976,20 @@ hipError_t launch_grad(const Geom &g, const WorkItem *items, int nitems, const v
                        const float *ffd, const float *tables, const float *alpha, double *grad, size_t lds_bytes,
                        hipStream_t s)
 {
-    hipError_t e = set_grad_lds(g.fdt, g.mdt, lds_bytes);
+    hipError_t e = set_grad_lds(g.fdt, g.mdt, g.role, lds_bytes);
     if (e != hipSuccess) return e;
-    SRWCR_DISPATCH_DT(k_grad, g.fdt, g.mdt, dim3(nitems), dim3(kGradThreads), lds_bytes, s, g, items, fixed,
-                      moving, ffd, tables, alpha, grad);
+#define SRWCR_GRAD(F, M)                                                                                     \
+    if (g.fdt == F && g.mdt == M) {                                                                          \
+        if (g.role)                                                                                          \
+            hipLaunchKernelGGL((k_grad<F, M, 1>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, g, items, fixed, \
+                               moving, ffd, tables, alpha, grad);                                            \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_grad<F, M, 0>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, g, items, fixed, \
+                               moving, ffd, tables, alpha, grad);                                            \
+    }
+    SRWCR_GRAD(0, 0) SRWCR_GRAD(0, 1) SRWCR_GRAD(0, 2) SRWCR_GRAD(1, 0) SRWCR_GRAD(1, 1) SRWCR_GRAD(1, 2)
+    SRWCR_GRAD(2, 0) SRWCR_GRAD(2, 1) SRWCR_GRAD(2, 2)
+#undef SRWCR_GRAD
     return hipGetLastError();
 }
 
