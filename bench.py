@@ -25,6 +25,21 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "SRWCR value+gradient voxel-evals/s at 256x256x128; % of HBM roofline"
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1804_05061_amd", "csrc", "srwcr_kernels.hip")
+
+# HBM traffic of the dominant kernel per launch, from rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE) over this benchmark, each scaled by what the
+# same counter reads for k_normalize, a copy of known size (32 MiB read,
+# 32 MiB written at 256x256x128 FP32): fetch x 2.00, write x 1.00.  Keyed by
+# the SHA-256 of the kernel source the counters were taken on, so the figure
+# is reported as null once the kernels change.
+TRAFFIC = {}
+
+
+def kernel_source_sha():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
 
 
 def parse():
@@ -36,6 +51,8 @@ def parse():
     ap.add_argument("--cpu-slices", type=int, default=32, help="z-slices of the oracle sample")
     ap.add_argument("--cold", action="store_true", help="also time steps with the last-level cache flushed")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--workload", default="ct256", choices=["ct256", "breathing4d"],
+                    help="ct256: the headline single pair; breathing4d: 9 phase pairs x 3 levels, batched")
     return ap.parse_args()
 
 
@@ -45,6 +62,8 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path has no multi-GPU mode",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "breathing4d":
+        return bench_breathing4d(args)
     import numpy as np
     import torch
 
@@ -102,6 +121,11 @@ def main():
                 "alg_bytes_per_launch": alg_bytes, "mean_ms": round(kern[dom], 5),
                 "phase_ms": {k: round(v / prof["calls"], 5) for k, v in prof.items() if k != "calls"}}
 
+    rec = TRAFFIC.get((kernel_source_sha(), dom, dt[2]))
+    if rec is not None:
+        roofline["traffic"] = rec["fetch_bytes"] + rec["write_bytes"]
+        roofline["traffic_detail"] = rec
+
     cold = None
     if args.cold:
         flush = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")   # 512 MiB > last-level cache
@@ -146,6 +170,94 @@ def main():
     }
     if cold is not None:
         line["cold_ms_per_step"] = round(cold, 5)
+    print(json.dumps(line), flush=True)
+
+
+def bench_breathing4d(args):
+    """9 breathing-phase pairs (80..128 of 128 slices of a 256x256 CT-like
+    phantom) x 3 pyramid levels = 27 problems, 64 bins, 6x6x6 spatial bins, FFD
+    spacing 10 level voxels: one srwcr_grad_batched call (replayed from a HIP
+    graph) against 27 plain srwcr_grad calls."""
+    import numpy as np
+    from scipy import ndimage
+
+    from workloads import synth
+    t0 = time.time()
+    pairs = synth.breathing_phases(workers=min(10, os.cpu_count() or 1))    # before the GPU is touched
+    print(f"[bench] 9 phase pairs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    import torch
+
+    import paper_1804_05061_amd as S
+    torch.cuda.set_device(0)
+    dt = {"f32": (S.F32, torch.float32, 4), "f16": (S.F16, torch.float16, 2),
+          "bf16": (S.BF16, torch.bfloat16, 2)}[args.dtype]
+    nb, K, delta = 64, (6, 6, 6), (10, 10, 10)
+    plans, inputs, alg_bytes, nvox = [], [], 0, 0
+    for pi, (f_raw, m_raw) in enumerate(pairs):
+        # normalise once at the finest level, then Gaussian (sigma 1 voxel) and every second voxel
+        lv_f = [S.normalize(torch.from_numpy(f_raw).cuda(), f_raw.min(), f_raw.max(), nb).cpu().numpy()]
+        lv_m = [S.normalize(torch.from_numpy(m_raw).cuda(), m_raw.min(), m_raw.max(), nb).cpu().numpy()]
+        for _ in range(2):
+            lv_f.append(np.ascontiguousarray(ndimage.gaussian_filter(lv_f[-1], 1.0)[::2, ::2, ::2]))
+            lv_m.append(np.ascontiguousarray(ndimage.gaussian_filter(lv_m[-1], 1.0)[::2, ::2, ::2]))
+        for lv in range(3):
+            nz, ny, nx = lv_f[lv].shape
+            prob = S.Problem((nx, ny, nz), (nx, ny, nz), nb, K, delta, S.MOVING_AS_A, dt[0], dt[0])
+            ffd = torch.from_numpy(synth.random_ffd(prob.ctrl_dims, 2.0, 5, salt=10 * pi + lv)).cuda()
+            plans.append(S.Plan(prob))
+            inputs.append((torch.from_numpy(lv_f[lv]).cuda().to(dt[1]), torch.from_numpy(lv_m[lv]).cuda().to(dt[1]),
+                           ffd))
+            nvox += nx * ny * nz
+            alg_bytes += 2 * 2 * dt[2] * nx * ny * nz          # F and M read once per pass, two passes
+    batch = S.Batch(plans)
+    vals = torch.empty(len(plans), dtype=torch.float64, device="cuda")
+    grads = [torch.empty(p.problem.ffd_shape, dtype=torch.float32, device="cuda") for p in plans]
+    single_v = [torch.empty((), dtype=torch.float64, device="cuda") for _ in plans]
+
+    def sequential():
+        for p, (f, m, d), v, g in zip(plans, inputs, single_v, grads):
+            p.grad(f, m, d, v, g)
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - a) / steps
+
+    for _ in range(args.warmup):
+        sequential()
+        batch.grad(inputs, vals, grads)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batch.grad(inputs, vals, grads)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.grad(inputs, vals, grads)
+    graph.replay()
+    torch.cuda.synchronize()
+    ms_seq = timed(sequential, args.steps)
+    ms_batch = timed(lambda: batch.grad(inputs, vals, grads), args.steps)
+    ms_graph = timed(graph.replay, args.steps)
+    D0 = float(vals[0].item())
+    print(f"[bench] sequential {ms_seq:.3f} ms, batched {ms_batch:.3f} ms, graph {ms_graph:.3f} ms, D[0]={D0:.10f}",
+          file=sys.stderr, flush=True)
+    line = {
+        "metric": "breathing 4-D batch: SRWCR value+gradient voxel-evals/s (27 problems per evaluation)",
+        "value": round(nvox / (ms_graph * 1e-3), 1), "unit": "voxel-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_graph, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": f"9 breathing-phase pairs x 3 levels of a 256x256x128 CT-like phantom, {args.dtype} "
+                               f"storage, {nb} bins, 6x6x6 spatial bins, FFD spacing 10, moving as A",
+                   "problems": len(plans), "voxels": nvox, "parallelism": "single GPU"},
+        "pairs_per_s": round(len(pairs) / (ms_graph * 1e-3), 2),
+        "alg_gb_per_s": round(alg_bytes / (ms_graph * 1e-3) / 1e9, 2),
+        "ms_sequential_27_calls": round(ms_seq, 5), "ms_batched_eager": round(ms_batch, 5),
+        "ms_batched_graph": round(ms_graph, 5), "speedup_vs_sequential": round(ms_seq / ms_graph, 3),
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -109,6 +109,34 @@ int srwcr_eval(const srwcr_plan *plan, const void *fixed, const void *moving, co
 int srwcr_grad(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd,
                double *d_value, float *d_grad, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Batched value + gradient over up to SRWCR_MAX_BATCH independent problems
+ * (e.g. the phases of a 4-D series times the levels of their pyramids): one
+ * launch per pass covers every problem, so small problems share the device
+ * instead of running one after another.  Each problem is computed exactly as
+ * srwcr_grad computes it (Sec. II-D, eqs 15-21).
+ *
+ * srwcr_batch_create: plans[0..n-1] must share role and storage dtypes and
+ * outlive the batch (their device tables are referenced, not copied).
+ * srwcr_grad_batched: items[p] holds problem p's device pointers, with the
+ * meaning of srwcr_grad's arguments; the workspace (srwcr_batch_workspace_bytes)
+ * is the caller's.  The call only enqueues kernels on `stream`: no allocation,
+ * no host synchronisation, no memset node, so it may be captured in a graph. */
+#define SRWCR_MAX_BATCH 32
+typedef struct srwcr_batch srwcr_batch;
+typedef struct {
+    const void *fixed;         /* device, normalised, the plan's fixed dtype */
+    const void *moving;        /* device, normalised, the plan's moving dtype */
+    const float *ffd;          /* device float32 [3][ncz][ncy][ncx] */
+    double *d_value;           /* device double: D */
+    float *d_grad;             /* device float32, layout of ffd: dD/d(displacement) */
+} srwcr_batch_item;
+
+int srwcr_batch_create(int32_t n, const srwcr_plan *const *plans, srwcr_batch **out);
+void srwcr_batch_destroy(srwcr_batch *batch);
+size_t srwcr_batch_workspace_bytes(const srwcr_batch *batch);
+int srwcr_grad_batched(const srwcr_batch *batch, const srwcr_batch_item *items, void *workspace,
+                       size_t workspace_bytes, void *stream);
+
 /* Backward-warped moving volume on the fixed grid: out[x] = M(T(x)) with the
  * interpolation of srwcr_eval (Sec. II-F).  moving: normalised device volume in
  * the plan's moving dtype; out: device float32 volume of the fixed dims. */

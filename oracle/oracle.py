@@ -101,6 +101,8 @@ def lib():
         L.orc_warp.argtypes = [pp, fp, fp, dp]
         L.orc_joint_pdf.restype = ctypes.c_double
         L.orc_joint_pdf.argtypes = [pp, fp, fp, fp, dp]
+        L.orc_joint_mass_box.restype = None
+        L.orc_joint_mass_box.argtypes = [pp, fp, fp, fp, ctypes.POINTER(ctypes.c_int), dp]
         L.orc_srwcr_from_pdf.restype = ctypes.c_double
         L.orc_srwcr_from_pdf.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int]
         L.orc_value.restype = ctypes.c_double
@@ -187,6 +189,62 @@ def joint_pdf(P: Problem, fixed: np.ndarray, moving: np.ndarray, ffd: np.ndarray
     p = np.zeros((P.n_regions, P.n_bins, P.n_bins))
     Z = lib().orc_joint_pdf(ctypes.byref(P.c()), fxp, mp, fp, _f64(p))
     return p, Z
+
+
+def joint_mass_box(P: Problem, fixed: np.ndarray, moving: np.ndarray, ffd: np.ndarray, box,
+                   q: np.ndarray | None = None) -> np.ndarray:
+    """Unnormalised eq (3) mass of the voxels in box = (x0, x1, y0, y1, z0, z1)
+    (half-open), added to q[r, a, b] (a new zero array when q is None)."""
+    fx, fxp = _f32(fixed)
+    m, mp = _f32(moving)
+    f, fp = _f32(ffd)
+    if q is None:
+        q = np.zeros((P.n_regions, P.n_bins, P.n_bins))
+    assert q.dtype == np.float64 and q.flags.c_contiguous and q.shape == (P.n_regions, P.n_bins, P.n_bins)
+    b = (ctypes.c_int * 6)(*[int(v) for v in box])
+    lib().orc_joint_mass_box(ctypes.byref(P.c()), fxp, mp, fp, b, _f64(q))
+    return q
+
+
+def node_support_box(P: Problem, node) -> tuple:
+    """Fixed voxels whose warp T (eq 17, stored node index = paper index + 1)
+    involves control node (i, j, k): floor(x / delta) in [i - 3, i] per axis."""
+    box = []
+    for n, d, N in zip(node, P.ctrl_spacing, P.fixed_dims):
+        box += [max(0, (n - 3) * d), min(N, (n + 1) * d)]
+    return tuple(box)
+
+
+def fd_control_points(P: Problem, fixed: np.ndarray, moving: np.ndarray, ffd: np.ndarray, points,
+                      h: float, threads: int | None = None) -> np.ndarray:
+    """Central finite differences of D (eq 9, Table I loop) with respect to
+    single displacement components points = [(e, k, j, i), ...] (component e
+    of stored node (i, j, k)).
+
+    Eq (3) is a sum over voxels, so the perturbed Z p is the unperturbed Z p
+    minus the old and plus the new mass of the voxels whose warp the node
+    changes; D+ and D- are then computed from their normalised PDFs.  The step
+    is the one float32 storage actually takes: (d + h) - (d - h) after rounding."""
+    from concurrent.futures import ThreadPoolExecutor
+    ffd = np.ascontiguousarray(ffd, dtype=np.float32)
+    p, Z = joint_pdf(P, fixed, moving, ffd)
+    q_full = p * Z
+
+    def one(pt):
+        e, k, j, i = pt
+        box = node_support_box(P, (i, j, k))
+        q_rest = q_full - joint_mass_box(P, fixed, moving, ffd, box)
+        Ds, steps = [], []
+        for sgn in (+1.0, -1.0):
+            f2 = ffd.copy()
+            f2[e, k, j, i] = np.float32(float(ffd[e, k, j, i]) + sgn * h)
+            steps.append(float(f2[e, k, j, i]))
+            q = joint_mass_box(P, fixed, moving, f2, box, q_rest.copy())
+            Ds.append(srwcr_from_pdf(q / q.sum()))
+        return (Ds[0] - Ds[1]) / (steps[0] - steps[1])
+
+    with ThreadPoolExecutor(max_workers=threads or os.cpu_count() or 1) as ex:
+        return np.array(list(ex.map(one, list(points))))
 
 
 def srwcr_from_pdf(p: np.ndarray, which: int = 0) -> float:

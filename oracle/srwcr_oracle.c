@@ -250,10 +250,68 @@ static void voxel_AB(const orc_problem *P, const float *fix, const float *mov, c
 }
 
 /* ------------------------------------------ eq (3): 3-D joint PDF and Z
- * p: R x nb x nb, p[(r * nb + a) * nb + b].  Returns Z. */
+ * One voxel's unnormalised term of eq (3): q[r][a][b] += w(r, x) h(a - A(x))
+ * h(b - B(x)) over the regions with w != 0 and the bins with h != 0 (exact).
+ * wx, wy, wz: the voxel's per-axis region weights (eq 8). */
+static void voxel_mass(const orc_problem *P, const float *fix, const float *mov, const float *ffd,
+                       int x, int y, int z, const double *wx, const double *wy, const double *wz, double *q)
+{
+    int nb = P->n_bins, L = nb - 1;
+    double A, B;
+    voxel_AB(P, fix, mov, ffd, x, y, z, &A, &B, NULL);
+    int ab[4], bb[4];
+    int na = tap_bins(A, L, ab), nbb = tap_bins(B, L, bb);
+    for (int k = 0; k < P->K[2]; ++k) {
+        if (wz[k] == 0.0) continue;
+        for (int j = 0; j < P->K[1]; ++j) {
+            if (wy[j] == 0.0) continue;
+            for (int i = 0; i < P->K[0]; ++i) {
+                if (wx[i] == 0.0) continue;
+                double w = wx[i] * wy[j] * wz[k];
+                int r = (k * P->K[1] + j) * P->K[0] + i;
+                for (int ia = 0; ia < na; ++ia) {
+                    double ha = orc_h(ab[ia] - A);
+                    if (ha == 0.0) continue;
+                    for (int ib = 0; ib < nbb; ++ib) {
+                        double hb = orc_h(bb[ib] - B);
+                        if (hb == 0.0) continue;
+                        q[((long)r * nb + ab[ia]) * nb + bb[ib]] += w * ha * hb;
+                    }
+                }
+            }
+        }
+    }
+}
+
+/* Unnormalised eq (3) mass of the voxels of one box, added to q (R x nb x nb):
+ * q[r][a][b] += sum over x in [box0, box1) x [box2, box3) x [box4, box5) of
+ * w(r, x) h(a - A(x)) h(b - B(x)).  Serial.  Eq (3) is a plain sum over the
+ * voxels, so the masses of the boxes of a partition add up to Z p(a, b, r);
+ * the finite-difference checks use this to re-evaluate only the voxels whose
+ * warp a control-point perturbation changes. */
+void orc_joint_mass_box(const orc_problem *P, const float *fix, const float *mov, const float *ffd,
+                        const int box[6], double *q)
+{
+    double *wx = (double *)malloc(sizeof(double) * P->K[0]);
+    double *wy = (double *)malloc(sizeof(double) * P->K[1]);
+    double *wz = (double *)malloc(sizeof(double) * P->K[2]);
+    for (int z = box[4]; z < box[5]; ++z) {
+        orc_axis_region_weights(z, P->nf[2], P->K[2], wz);
+        for (int y = box[2]; y < box[3]; ++y) {
+            orc_axis_region_weights(y, P->nf[1], P->K[1], wy);
+            for (int x = box[0]; x < box[1]; ++x) {
+                orc_axis_region_weights(x, P->nf[0], P->K[0], wx);
+                voxel_mass(P, fix, mov, ffd, x, y, z, wx, wy, wz, q);
+            }
+        }
+    }
+    free(wx); free(wy); free(wz);
+}
+
+/* p: R x nb x nb, p[(r * nb + a) * nb + b].  Returns Z. */
 double orc_joint_pdf(const orc_problem *P, const float *fix, const float *mov, const float *ffd, double *p)
 {
-    int R = n_regions(P), nb = P->n_bins, L = nb - 1;
+    int R = n_regions(P), nb = P->n_bins;
     long cells = (long)R * nb * nb;
     memset(p, 0, sizeof(double) * cells);
     int nthreads = 1;
@@ -278,30 +336,7 @@ double orc_joint_pdf(const orc_problem *P, const float *fix, const float *mov, c
                 orc_axis_region_weights(y, P->nf[1], P->K[1], wy);
                 for (int x = 0; x < P->nf[0]; ++x) {
                     orc_axis_region_weights(x, P->nf[0], P->K[0], wx);
-                    double A, B;
-                    voxel_AB(P, fix, mov, ffd, x, y, z, &A, &B, NULL);
-                    int ab[4], bb[4];
-                    int na = tap_bins(A, L, ab), nbb = tap_bins(B, L, bb);
-                    for (int k = 0; k < P->K[2]; ++k) {
-                        if (wz[k] == 0.0) continue;
-                        for (int j = 0; j < P->K[1]; ++j) {
-                            if (wy[j] == 0.0) continue;
-                            for (int i = 0; i < P->K[0]; ++i) {
-                                if (wx[i] == 0.0) continue;
-                                double w = wx[i] * wy[j] * wz[k];
-                                int r = (k * P->K[1] + j) * P->K[0] + i;
-                                for (int ia = 0; ia < na; ++ia) {
-                                    double ha = orc_h(ab[ia] - A);
-                                    if (ha == 0.0) continue;
-                                    for (int ib = 0; ib < nbb; ++ib) {
-                                        double hb = orc_h(bb[ib] - B);
-                                        if (hb == 0.0) continue;
-                                        pp[((long)r * nb + ab[ia]) * nb + bb[ib]] += w * ha * hb;
-                                    }
-                                }
-                            }
-                        }
-                    }
+                    voxel_mass(P, fix, mov, ffd, x, y, z, wx, wy, wz, pp);
                 }
             }
         }

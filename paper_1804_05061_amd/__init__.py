@@ -23,7 +23,7 @@ F32, F16, BF16 = 0, 1, 2
 _TORCH_DT = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
 _DT_OF = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
 
-__all__ = ["Problem", "Plan", "normalize", "minmax", "register_lbfgs", "LbfgsOptions", "SrwcrError",
+__all__ = ["Problem", "Plan", "Batch", "normalize", "minmax", "register_lbfgs", "LbfgsOptions", "SrwcrError",
            "MOVING_AS_A", "MOVING_AS_B", "F32", "F16", "BF16", "SRWCRLoss"]
 
 
@@ -179,6 +179,58 @@ class Plan:
         _lib.check(_lib.load().srwcr_debug_moments(self._h, _ptr(fixed), _ptr(moving), _ptr(ffd), _ptr(out),
                                                    _ptr(self.workspace), self.workspace_bytes, _stream()))
         return out
+
+
+class Batch:
+    """Independent problems (plans) evaluated by one launch per pass
+    (srwcr_grad_batched).  The plans must share role and storage dtypes and
+    are kept alive by the batch."""
+
+    def __init__(self, plans):
+        plans = list(plans)
+        if not 1 <= len(plans) <= _lib.MAX_BATCH:
+            raise ValueError(f"a batch holds 1..{_lib.MAX_BATCH} plans, got {len(plans)}")
+        self.plans = plans
+        self.device = plans[0].device
+        L = _lib.load()
+        arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+        with torch.cuda.device(self.device):
+            h = ctypes.c_void_p()
+            _lib.check(L.srwcr_batch_create(len(plans), arr, ctypes.byref(h)))
+            self._h = h
+            self.workspace_bytes = int(L.srwcr_batch_workspace_bytes(h))
+            self.workspace = torch.zeros(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().srwcr_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def grad(self, inputs, values=None, grads=None):
+        """inputs: [(fixed, moving, ffd)] per plan.  Returns (values float64
+        tensor [n], [dD/d displacement per problem])."""
+        n = len(self.plans)
+        if len(inputs) != n:
+            raise ValueError(f"{len(inputs)} inputs for {n} plans")
+        for pl, (f, m, d) in zip(self.plans, inputs):
+            pl._check_inputs(f, m, d)
+        if values is None:
+            values = torch.empty(n, dtype=torch.float64, device=self.device)
+        if grads is None:
+            grads = [torch.empty(pl.problem.ffd_shape, dtype=torch.float32, device=self.device) for pl in self.plans]
+        _need_cuda(values, "values", torch.float64, (n,))
+        for pl, g in zip(self.plans, grads):
+            _need_cuda(g, "grad", torch.float32, pl.problem.ffd_shape)
+        items = (_lib.SrwcrBatchItem * n)()
+        for i, ((f, m, d), g) in enumerate(zip(inputs, grads)):
+            items[i] = _lib.SrwcrBatchItem(_ptr(f), _ptr(m), _ptr(d), values.data_ptr() + 8 * i, _ptr(g))
+        _lib.check(_lib.load().srwcr_grad_batched(self._h, items, _ptr(self.workspace), self.workspace_bytes,
+                                                  _stream()))
+        return values, grads
 
 
 def normalize(raw: torch.Tensor, lo: float, hi: float, n_bins: int, dtype=torch.float32) -> torch.Tensor:

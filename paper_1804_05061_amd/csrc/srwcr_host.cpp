@@ -15,6 +15,8 @@
 
 using namespace srwcr;
 
+static_assert(kMaxBatch == SRWCR_MAX_BATCH, "batch limit of the ABI and the kernels differ");
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -81,8 +83,10 @@ double bspline_piece(int l, double t)
 struct srwcr_plan {
     srwcr_problem prob;
     Geom g;
+    Geom *geom_dev = nullptr;     // g on the device (kernels read it through a one-problem array)
     std::vector<void *> dev_allocs;
     WorkItem *items = nullptr;
+    std::vector<WorkItem> items_host;
     int nitems = 0;
     size_t value_lds = 0, grad_lds = 0;
     WsLayout ws;
@@ -315,6 +319,7 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
             }
         }
         P->nitems = (int)items.size();
+        P->items_host = items;
         void *d;
         if ((st = upload(items.data(), items.size() * sizeof(WorkItem), &d))) goto bad;
         P->items = (WorkItem *)d;
@@ -341,6 +346,14 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         w.alpha = off;
         off += (size_t)g.R * sizeof(float);
         w.total = align_up(off, 256);
+        g.ws = w;
+        void *d;
+        if ((st = upload(&g, sizeof(Geom), &d))) goto bad;
+        P->geom_dev = (Geom *)d;
+    }
+    {
+        hipError_t he = prepare_kernels();
+        if (he != hipSuccess) { st = hip_fail(he, "kernel attributes"); goto bad; }
     }
     *out = P;
     return SRWCR_OK;
@@ -404,8 +417,17 @@ static int check_call(const srwcr_plan *plan, const void *fixed, const void *mov
     return SRWCR_OK;
 }
 
-static int run_value(const srwcr_plan *P, const void *fixed, const void *moving, const float *ffd, double *d_value,
-                     unsigned char *ws, hipStream_t s)
+static BatchArgs one_problem(const void *fixed, const void *moving, const float *ffd, double *d_value,
+                             float *d_grad)
+{
+    BatchArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.n = 1;
+    a.p[0] = ProbPtrs{fixed, moving, ffd, d_value, d_grad};
+    return a;
+}
+
+static int run_value(const srwcr_plan *P, const BatchArgs &args, unsigned char *ws, hipStream_t s)
 {
     const Geom &g = P->g;
     double *moments = (double *)(ws + P->ws.moments);
@@ -413,11 +435,9 @@ static int run_value(const srwcr_plan *P, const void *fixed, const void *moving,
     prof_mark(P, 0, s);
     HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
     prof_mark(P, 1, s);
-    HIP_TRY(launch_value(g, P->items, P->nitems, fixed, moving, ffd, moments, P->value_lds, s), "value launch");
+    HIP_TRY(launch_value(P->geom_dev, g.fdt, g.mdt, P->items, P->nitems, args, ws, P->value_lds, s), "value launch");
     prof_mark(P, 2, s);
-    HIP_TRY(launch_finalize(g, moments, (double *)(ws + P->ws.region), (float *)(ws + P->ws.tables),
-                            (float *)(ws + P->ws.alpha), (unsigned *)(ws + P->ws.counter), d_value, s),
-            "finalize launch");
+    HIP_TRY(launch_finalize(P->geom_dev, 1, g.R, args, ws, s), "finalize launch");
     prof_mark(P, 3, s);
     return SRWCR_OK;
 }
@@ -428,7 +448,8 @@ int srwcr_eval(const srwcr_plan *plan, const void *fixed, const void *moving, co
     int st = check_call(plan, fixed, moving, ffd, workspace, workspace_bytes);
     if (st) return st;
     if (!d_value) return fail(SRWCR_E_INVALID_ARG, "d_value is NULL");
-    return run_value(plan, fixed, moving, ffd, d_value, (unsigned char *)workspace, (hipStream_t)stream);
+    return run_value(plan, one_problem(fixed, moving, ffd, d_value, nullptr), (unsigned char *)workspace,
+                     (hipStream_t)stream);
 }
 
 int srwcr_grad(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd, double *d_value,
@@ -439,16 +460,15 @@ int srwcr_grad(const srwcr_plan *plan, const void *fixed, const void *moving, co
     if (!d_value || !d_grad) return fail(SRWCR_E_INVALID_ARG, "d_value or d_grad is NULL");
     unsigned char *ws = (unsigned char *)workspace;
     hipStream_t s = (hipStream_t)stream;
-    st = run_value(plan, fixed, moving, ffd, d_value, ws, s);
+    const BatchArgs args = one_problem(fixed, moving, ffd, d_value, d_grad);
+    st = run_value(plan, args, ws, s);
     if (st) return st;
     const Geom &g = plan->g;
-    double *grad = (double *)(ws + plan->ws.grad);
-    HIP_TRY(launch_grad(g, plan->items, plan->nitems, fixed, moving, ffd, (const float *)(ws + plan->ws.tables),
-                        (const float *)(ws + plan->ws.alpha), grad, plan->grad_lds, s),
+    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.mdt, g.role, plan->items, plan->nitems, args, ws, plan->grad_lds, s),
             "gradient launch");
     prof_mark(plan, 4, s);
     const size_t n = 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2];
-    HIP_TRY(launch_grad_out(grad, d_grad, n, s), "gradient output launch");
+    HIP_TRY(launch_grad_out(plan->geom_dev, 1, n, args, ws, s), "gradient output launch");
     prof_mark(plan, 5, s);
     if (plan->profiling && (size_t)(plan->prof_calls + 1) * (kPhases + 1) <= plan->ev_pool.size()) ++plan->prof_calls;
     return SRWCR_OK;
@@ -472,7 +492,9 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
     double *moments = (double *)(ws + plan->ws.moments);
     const size_t nzero = (plan->ws.counter + sizeof(double) - plan->ws.moments) / sizeof(double);
     HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
-    HIP_TRY(launch_value(plan->g, plan->items, plan->nitems, fixed, moving, ffd, moments, plan->value_lds, s),
+    const Geom &g = plan->g;
+    HIP_TRY(launch_value(plan->geom_dev, g.fdt, g.mdt, plan->items, plan->nitems,
+                         one_problem(fixed, moving, ffd, nullptr, nullptr), ws, plan->value_lds, s),
             "value launch");
     const size_t bytes = (size_t)plan->g.R * plan->g.nb * 3 * sizeof(double);
     HIP_TRY(hipMemcpyAsync(d_moments, moments, bytes, hipMemcpyDeviceToDevice, s), "moments copy");
@@ -515,6 +537,131 @@ int srwcr_profile_read(const srwcr_plan *plan, double ms[5], int32_t *calls)
         }
     }
     if (calls) *calls = plan->prof_calls;
+    return SRWCR_OK;
+}
+
+// ------------------------------------------------------------------ batches
+struct srwcr_batch {
+    std::vector<const srwcr_plan *> plans;   // not owned: their per-axis tables are referenced
+    int fdt = 0, mdt = 0, role = 0;
+    Geom *geoms_dev = nullptr;
+    WorkItem *items_dev = nullptr;
+    int nitems = 0;
+    size_t value_lds = 0, grad_lds = 0, ws_total = 0, zero_bytes = 0, max_params = 0;
+    int max_regions = 0;
+};
+
+void srwcr_batch_destroy(srwcr_batch *b)
+{
+    if (!b) return;
+    if (b->geoms_dev) (void)hipFree(b->geoms_dev);
+    if (b->items_dev) (void)hipFree(b->items_dev);
+    delete b;
+}
+
+int srwcr_batch_create(int32_t n, const srwcr_plan *const *plans, srwcr_batch **out)
+{
+    if (!out) return fail(SRWCR_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!plans) return fail(SRWCR_E_INVALID_ARG, "plans is NULL");
+    if (n < 1 || n > kMaxBatch) return fail(SRWCR_E_INVALID_ARG, "batch of %d problems outside 1..%d", n, kMaxBatch);
+    for (int p = 0; p < n; ++p) {
+        if (!plans[p]) return fail(SRWCR_E_INVALID_ARG, "plans[%d] is NULL", p);
+        const Geom &g = plans[p]->g, &g0 = plans[0]->g;
+        if (g.fdt != g0.fdt || g.mdt != g0.mdt || g.role != g0.role)
+            return fail(SRWCR_E_INVALID_ARG, "plans[%d] differs from plans[0] in role or storage dtypes", p);
+        if (plans[p]->device != plans[0]->device)
+            return fail(SRWCR_E_INVALID_ARG, "plans[%d] was made on another device", p);
+    }
+    srwcr_batch *b = new srwcr_batch();
+    b->plans.assign(plans, plans + n);
+    b->fdt = plans[0]->g.fdt;
+    b->mdt = plans[0]->g.mdt;
+    b->role = plans[0]->g.role;
+    // workspace: every problem's zeroed block (moments, gradient, ticket) first, then the rest
+    std::vector<Geom> geoms(n);
+    size_t off = 0;
+    for (int p = 0; p < n; ++p) {
+        const Geom &g = plans[p]->g;
+        geoms[p] = g;
+        WsLayout &w = geoms[p].ws;
+        const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
+        w.moments = off;
+        off += (size_t)g.R * g.nb * 3 * sizeof(double);
+        w.grad = off;
+        off += 3 * ncell * sizeof(double);
+        w.counter = off;
+        off += sizeof(double);
+        off = align_up(off, 256);
+        b->max_regions = std::max(b->max_regions, g.R);
+        b->max_params = std::max(b->max_params, 3 * ncell);
+        b->value_lds = std::max(b->value_lds, plans[p]->value_lds);
+        b->grad_lds = std::max(b->grad_lds, plans[p]->grad_lds);
+    }
+    b->zero_bytes = off;
+    for (int p = 0; p < n; ++p) {
+        const Geom &g = plans[p]->g;
+        WsLayout &w = geoms[p].ws;
+        w.region = off;
+        off = align_up(off + (size_t)g.R * 4 * sizeof(double), 256);
+        w.tables = off;
+        off = align_up(off + (size_t)g.R * g.nb * 4 * sizeof(float), 256);
+        w.alpha = off;
+        off = align_up(off + (size_t)g.R * sizeof(float), 256);
+        w.total = 0;
+    }
+    b->ws_total = off;
+    // one work list: the largest boxes first, so the small problems fill the tail
+    std::vector<WorkItem> items;
+    for (int p = 0; p < n; ++p)
+        for (WorkItem w : plans[p]->items_host) {
+            w.prob = p;
+            items.push_back(w);
+        }
+    auto vox = [](const WorkItem &w) { return (long)(w.x1 - w.x0) * (w.y1 - w.y0) * (w.z1 - w.z0); };
+    std::stable_sort(items.begin(), items.end(), [&](const WorkItem &a, const WorkItem &c) { return vox(a) > vox(c); });
+    b->nitems = (int)items.size();
+    hipError_t e = hipMalloc(&b->geoms_dev, n * sizeof(Geom));
+    if (e == hipSuccess) e = hipMemcpy(b->geoms_dev, geoms.data(), n * sizeof(Geom), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !items.empty()) e = hipMalloc(&b->items_dev, items.size() * sizeof(WorkItem));
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpy(b->items_dev, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        srwcr_batch_destroy(b);
+        return hip_fail(e, "batch tables");
+    }
+    *out = b;
+    return SRWCR_OK;
+}
+
+size_t srwcr_batch_workspace_bytes(const srwcr_batch *b) { return b ? b->ws_total : 0; }
+
+int srwcr_grad_batched(const srwcr_batch *b, const srwcr_batch_item *items, void *workspace, size_t workspace_bytes,
+                       void *stream)
+{
+    if (!b || !items) return fail(SRWCR_E_INVALID_ARG, "NULL batch or items");
+    if (!workspace) return fail(SRWCR_E_INVALID_ARG, "workspace is NULL");
+    if (workspace_bytes < b->ws_total)
+        return fail(SRWCR_E_WORKSPACE, "workspace has %zu B, the batch needs %zu B", workspace_bytes, b->ws_total);
+    const int n = (int)b->plans.size();
+    BatchArgs args;
+    std::memset(&args, 0, sizeof args);
+    args.n = n;
+    for (int p = 0; p < n; ++p) {
+        const srwcr_batch_item &it = items[p];
+        if (!it.fixed || !it.moving || !it.ffd || !it.d_value || !it.d_grad)
+            return fail(SRWCR_E_INVALID_ARG, "items[%d] has a NULL pointer", p);
+        args.p[p] = ProbPtrs{it.fixed, it.moving, it.ffd, it.d_value, it.d_grad};
+    }
+    unsigned char *ws = (unsigned char *)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_zero((double *)ws, b->zero_bytes / sizeof(double), s), "zero launch");
+    HIP_TRY(launch_value(b->geoms_dev, b->fdt, b->mdt, b->items_dev, b->nitems, args, ws, b->value_lds, s),
+            "value launch");
+    HIP_TRY(launch_finalize(b->geoms_dev, n, b->max_regions, args, ws, s), "finalize launch");
+    HIP_TRY(launch_grad(b->geoms_dev, b->fdt, b->mdt, b->role, b->items_dev, b->nitems, args, ws, b->grad_lds, s),
+            "gradient launch");
+    HIP_TRY(launch_grad_out(b->geoms_dev, n, b->max_params, args, ws, s), "gradient output launch");
     return SRWCR_OK;
 }
 

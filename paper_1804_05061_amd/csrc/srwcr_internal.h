@@ -18,6 +18,7 @@ constexpr int kValueThreads = 768;
 constexpr int kGradThreads = 768;
 constexpr int kMaxNodeSeg = 68;   // FFD x-nodes one 64-voxel row segment can touch (delta >= 1)
 constexpr int kSlots = 2;         // voxels per lane: an item row holds up to 2 x 64 voxels
+constexpr int kMaxBatch = 32;     // problems of one batched launch
 
 // One unit of work of the value and gradient passes: a box of fixed voxels
 // inside one spatial-bin cell along y and z and at most two cells along x, so
@@ -27,7 +28,34 @@ struct WorkItem {
     int cx, cy, cz;               // first region of the block: (cx+i, cy+j, cz+k), i < 5, j, k < 4
     int gx0, gy0, gz0;            // first FFD node of the item's control support
     int gnx, gny, gnz;            // extent of that support
+    int prob;                     // problem of a batched launch (0 for a single plan)
+};
+
+// Workspace layout (device bytes, offsets from the workspace base of a launch).
+struct WsLayout {
+    size_t moments;    // double [R][nb][3]   (P, S1, S2)
+    size_t region;     // double [R][4]       per-region results written by finalise
+    size_t tables;     // float  [R][nb][4]   gradient tables (role dependent)
+    size_t alpha;      // float  [R]          role B: CR_r / (sigma_r^2 Z)
+    size_t grad;       // double [3][nc]      gradient accumulators
+    size_t counter;    // unsigned            finalise ticket
+    size_t total;
+};
+
+// Per-call device pointers of one problem, passed by value in the kernel
+// arguments (up to kMaxBatch of them per launch).
+struct ProbPtrs {
+    const void *fixed;
+    const void *moving;
+    const float *ffd;
+    double *value;     // D
+    float *grad;       // dD/d(displacement), layout of ffd (unused by value-only calls)
+};
+
+struct BatchArgs {
+    int n;
     int pad;
+    ProbPtrs p[kMaxBatch];
 };
 
 // Everything a kernel needs to know about a problem, passed by value.
@@ -55,35 +83,27 @@ struct Geom {
     int xw;                    // x-width of the work items (64 or 128 voxels)
     int c1n;                   // FFD x-nodes an item row touches at most: (xw - 1) / delta + 5
     int gscr;                  // floats of per-wave scratch in the gradient pass
+    WsLayout ws;               // this problem's slots in the workspace of a launch
 };
 
-// Workspace layout (device bytes, offsets from the workspace base).
-struct WsLayout {
-    size_t moments;    // double [R][nb][3]   (P, S1, S2)
-    size_t region;     // double [R][4]       per-region results written by finalise
-    size_t tables;     // float  [R][nb][4]   gradient tables (role dependent)
-    size_t alpha;      // float  [R]          role B: CR_r / (sigma_r^2 Z)
-    size_t grad;       // double [3][nc]      gradient accumulators
-    size_t counter;    // unsigned            finalise ticket
-    size_t total;
-};
-
-// Launchers (srwcr_kernels.hip).
+// Launchers (srwcr_kernels.hip).  `geoms` is a device array with one Geom per
+// problem; items carry their problem index; `ws` is the launch's workspace base.
 hipError_t launch_zero(double *p, size_t n, hipStream_t s);
 hipError_t launch_normalize(const float *in, int64_t n, float lo, float scale, float L, void *out, int dt,
                             hipStream_t s);
 hipError_t launch_minmax(const float *in, int64_t n, float *partial, int nblocks, hipStream_t s);
-hipError_t launch_value(const Geom &g, const WorkItem *items, int nitems, const void *fixed, const void *moving,
-                        const float *ffd, double *moments, size_t lds_bytes, hipStream_t s);
-hipError_t launch_finalize(const Geom &g, double *moments, double *region, float *tables, float *alpha,
-                           unsigned *counter, double *d_value, hipStream_t s);
-hipError_t launch_grad(const Geom &g, const WorkItem *items, int nitems, const void *fixed, const void *moving,
-                       const float *ffd, const float *tables, const float *alpha, double *grad,
-                       size_t lds_bytes, hipStream_t s);
-hipError_t launch_grad_out(const double *grad, float *out, size_t n, hipStream_t s);
+hipError_t launch_value(const Geom *geoms, int fdt, int mdt, const WorkItem *items, int nitems, const BatchArgs &args,
+                        unsigned char *ws, size_t lds_bytes, hipStream_t s);
+hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const BatchArgs &args, unsigned char *ws,
+                           hipStream_t s);
+hipError_t launch_grad(const Geom *geoms, int fdt, int mdt, int role, const WorkItem *items, int nitems,
+                       const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s);
+hipError_t launch_grad_out(const Geom *geoms, int nprob, size_t max_params, const BatchArgs &args, unsigned char *ws,
+                           hipStream_t s);
 hipError_t launch_warp(const Geom &g, const void *moving, const float *ffd, float *out, hipStream_t s);
 hipError_t launch_downsample(const float *in, int nx, int ny, int nz, float *out, int ox, int oy, int oz,
                              hipStream_t s);
+hipError_t prepare_kernels();   // once per device: LDS limits of the value and gradient kernels
 size_t value_lds_bytes(const Geom &g);
 size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz);
 

@@ -449,10 +449,15 @@ __device__ __forceinline__ void value_window(double *H, int rs, int L, int kbase
 
 template <int FDT, int MDT>
 __global__ void __launch_bounds__(kValueThreads)
-k_value(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixed, const void *__restrict__ moving,
-        const float *__restrict__ ffd, double *__restrict__ moments)
+k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, BatchArgs args, unsigned char *ws)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    const WorkItem it = items[blockIdx.x];
+    const Geom &g = geoms[it.prob];
+    const void *__restrict__ fixed = args.p[it.prob].fixed;
+    const void *__restrict__ moving = args.p[it.prob].moving;
+    const float *__restrict__ ffd = args.p[it.prob].ffd;
+    double *__restrict__ moments = reinterpret_cast<double *>(ws + g.ws.moments);
     const int nb = g.nb, L = nb - 1, rs = hist_stride(nb);
     double *H = reinterpret_cast<double *>(smem);     // [16 (y,z)][5 x][rs]: region (i, j, k) at ((k*4+j)*5+i)*rs
     const int nH = kNReg * rs;
@@ -460,7 +465,6 @@ k_value(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fix
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
     double *c1 = H + nH + wave * 3 * g.c1n;
-    const WorkItem it = items[blockIdx.x];
 
     for (int i = threadIdx.x; i < nH; i += blockDim.x) H[i] = 0.0;
     __syncthreads();
@@ -576,23 +580,11 @@ static hipError_t set_lds(F *kernel, size_t bytes)
                                (int)bytes);
 }
 
-static hipError_t set_value_lds(int fdt, int mdt, size_t bytes)
+hipError_t launch_value(const Geom *geoms, int fdt, int mdt, const WorkItem *items, int nitems, const BatchArgs &args,
+                        unsigned char *ws, size_t lds_bytes, hipStream_t s)
 {
-    hipError_t e = hipSuccess;
-#define SRWCR_SET(F, M) if (fdt == F && mdt == M) e = set_lds(k_value<F, M>, bytes);
-    SRWCR_SET(0, 0) SRWCR_SET(0, 1) SRWCR_SET(0, 2) SRWCR_SET(1, 0) SRWCR_SET(1, 1) SRWCR_SET(1, 2)
-    SRWCR_SET(2, 0) SRWCR_SET(2, 1) SRWCR_SET(2, 2)
-#undef SRWCR_SET
-    return e;
-}
-
-hipError_t launch_value(const Geom &g, const WorkItem *items, int nitems, const void *fixed, const void *moving,
-                        const float *ffd, double *moments, size_t lds_bytes, hipStream_t s)
-{
-    hipError_t e = set_value_lds(g.fdt, g.mdt, lds_bytes);
-    if (e != hipSuccess) return e;
-    SRWCR_DISPATCH_DT(k_value, g.fdt, g.mdt, dim3(nitems), dim3(kValueThreads), lds_bytes, s, g, items, fixed,
-                      moving, ffd, moments);
+    if (nitems <= 0) return hipSuccess;
+    SRWCR_DISPATCH_DT(k_value, fdt, mdt, dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args, ws);
     return hipGetLastError();
 }
 
@@ -601,10 +593,17 @@ hipError_t launch_value(const Geom &g, const WorkItem *items, int nitems, const 
 // (U_r / sigma_r^2, p_r, sigma_r^2, CR_r); the last wave to finish sums the
 // per-region terms in region order and writes D = (1/Z) sum_r U_r / sigma_r^2.
 __global__ void __launch_bounds__(64)
-k_finalize(Geom g, const double *__restrict__ moments, double *region, float *tables, float *alpha,
-           unsigned *counter, double *d_value)
+k_finalize(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
 {
+    const Geom &g = geoms[blockIdx.y];
     const int r = blockIdx.x, a = threadIdx.x, nb = g.nb;
+    if (r >= g.R) return;
+    const double *__restrict__ moments = reinterpret_cast<const double *>(ws + g.ws.moments);
+    double *region = reinterpret_cast<double *>(ws + g.ws.region);
+    float *tables = reinterpret_cast<float *>(ws + g.ws.tables);
+    float *alpha = reinterpret_cast<float *>(ws + g.ws.alpha);
+    unsigned *counter = reinterpret_cast<unsigned *>(ws + g.ws.counter);
+    double *d_value = args.p[blockIdx.y].value;
     double P = 0.0, S1 = 0.0, S2 = 0.0;
     if (a < nb) {
         const double *mp = moments + ((size_t)r * nb + a) * 3;
@@ -682,10 +681,10 @@ k_finalize(Geom g, const double *__restrict__ moments, double *region, float *ta
     }
 }
 
-hipError_t launch_finalize(const Geom &g, double *moments, double *region, float *tables, float *alpha,
-                           unsigned *counter, double *d_value, hipStream_t s)
+hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const BatchArgs &args, unsigned char *ws,
+                           hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(g.R), dim3(64), 0, s, g, moments, region, tables, alpha, counter, d_value);
+    hipLaunchKernelGGL(k_finalize, dim3(max_regions, nprob), dim3(64), 0, s, geoms, args, ws);
     return hipGetLastError();
 }
 
@@ -713,13 +712,18 @@ struct VoxG {
 
 template <int FDT, int MDT, int ROLE>
 __global__ void __launch_bounds__(kGradThreads)
-k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixed, const void *__restrict__ moving,
-       const float *__restrict__ ffd, const float *__restrict__ tables, const float *__restrict__ alpha,
-       double *__restrict__ grad)
+k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, BatchArgs args, unsigned char *ws)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int nb = g.nb, L = nb - 1, ts = tab_stride(nb);
     const WorkItem it = items[blockIdx.x];
+    const Geom &g = geoms[it.prob];
+    const void *__restrict__ fixed = args.p[it.prob].fixed;
+    const void *__restrict__ moving = args.p[it.prob].moving;
+    const float *__restrict__ ffd = args.p[it.prob].ffd;
+    const float *__restrict__ tables = reinterpret_cast<const float *>(ws + g.ws.tables);
+    const float *__restrict__ alpha = reinterpret_cast<const float *>(ws + g.ws.alpha);
+    double *__restrict__ grad = reinterpret_cast<double *>(ws + g.ws.grad);
+    const int nb = g.nb, L = nb - 1, ts = tab_stride(nb);
     const int nG = it.gnx * it.gny * it.gnz * 3;
     double *G = reinterpret_cast<double *>(smem);                       // [gnz][gny][gnx][3]
     float *tab = reinterpret_cast<float *>(G + nG);                      // [80 regions][ts]: (a, c) at a*3 + c
@@ -959,33 +963,18 @@ k_grad(Geom g, const WorkItem *__restrict__ items, const void *__restrict__ fixe
     }
 }
 
-static hipError_t set_grad_lds(int fdt, int mdt, int role, size_t bytes)
+hipError_t launch_grad(const Geom *geoms, int fdt, int mdt, int role, const WorkItem *items, int nitems,
+                       const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s)
 {
-    hipError_t e = hipSuccess;
-#define SRWCR_SET(F, M)                                                     \
-    if (fdt == F && mdt == M) {                                             \
-        e = role ? set_lds(k_grad<F, M, 1>, bytes) : set_lds(k_grad<F, M, 0>, bytes); \
-    }
-    SRWCR_SET(0, 0) SRWCR_SET(0, 1) SRWCR_SET(0, 2) SRWCR_SET(1, 0) SRWCR_SET(1, 1) SRWCR_SET(1, 2)
-    SRWCR_SET(2, 0) SRWCR_SET(2, 1) SRWCR_SET(2, 2)
-#undef SRWCR_SET
-    return e;
-}
-
-hipError_t launch_grad(const Geom &g, const WorkItem *items, int nitems, const void *fixed, const void *moving,
-                       const float *ffd, const float *tables, const float *alpha, double *grad, size_t lds_bytes,
-                       hipStream_t s)
-{
-    hipError_t e = set_grad_lds(g.fdt, g.mdt, g.role, lds_bytes);
-    if (e != hipSuccess) return e;
-#define SRWCR_GRAD(F, M)                                                                                     \
-    if (g.fdt == F && g.mdt == M) {                                                                          \
-        if (g.role)                                                                                          \
-            hipLaunchKernelGGL((k_grad<F, M, 1>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, g, items, fixed, \
-                               moving, ffd, tables, alpha, grad);                                            \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_grad<F, M, 0>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, g, items, fixed, \
-                               moving, ffd, tables, alpha, grad);                                            \
+    if (nitems <= 0) return hipSuccess;
+#define SRWCR_GRAD(F, M)                                                                                      \
+    if (fdt == F && mdt == M) {                                                                               \
+        if (role)                                                                                             \
+            hipLaunchKernelGGL((k_grad<F, M, 1>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, geoms, items, \
+                               args, ws);                                                                     \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_grad<F, M, 0>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, geoms, items, \
+                               args, ws);                                                                     \
     }
     SRWCR_GRAD(0, 0) SRWCR_GRAD(0, 1) SRWCR_GRAD(0, 2) SRWCR_GRAD(1, 0) SRWCR_GRAD(1, 1) SRWCR_GRAD(1, 2)
     SRWCR_GRAD(2, 0) SRWCR_GRAD(2, 1) SRWCR_GRAD(2, 2)
@@ -993,16 +982,46 @@ hipError_t launch_grad(const Geom &g, const WorkItem *items, int nitems, const v
     return hipGetLastError();
 }
 
-__global__ void k_grad_out(const double *__restrict__ grad, float *__restrict__ out, size_t n)
+// The largest dynamic LDS of the value and gradient kernels is raised to the
+// device limit once per device, outside any stream capture.
+hipError_t prepare_kernels()
 {
+    static bool done[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 64 && done[dev]) return hipSuccess;
+    int max_lds = 0;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    const size_t b = (size_t)max_lds;
+#define SRWCR_SET(F, M)                                                         \
+    if (e == hipSuccess) e = set_lds(k_value<F, M>, b);                         \
+    if (e == hipSuccess) e = set_lds(k_grad<F, M, 0>, b);                       \
+    if (e == hipSuccess) e = set_lds(k_grad<F, M, 1>, b);
+    SRWCR_SET(0, 0) SRWCR_SET(0, 1) SRWCR_SET(0, 2) SRWCR_SET(1, 0) SRWCR_SET(1, 1) SRWCR_SET(1, 2)
+    SRWCR_SET(2, 0) SRWCR_SET(2, 1) SRWCR_SET(2, 2)
+#undef SRWCR_SET
+    if (e == hipSuccess && dev < 64) done[dev] = true;
+    return e;
+}
+
+// FP64 accumulators to the caller's FP32 gradient; blockIdx.y = problem.
+__global__ void k_grad_out(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
+{
+    const Geom &g = geoms[blockIdx.y];
+    const double *__restrict__ grad = reinterpret_cast<const double *>(ws + g.ws.grad);
+    float *__restrict__ out = args.p[blockIdx.y].grad;
+    const size_t n = 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2];
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         out[i] = (float)grad[i];
 }
 
-hipError_t launch_grad_out(const double *grad, float *out, size_t n, hipStream_t s)
+hipError_t launch_grad_out(const Geom *geoms, int nprob, size_t max_params, const BatchArgs &args, unsigned char *ws,
+                           hipStream_t s)
 {
-    int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_grad_out, dim3(blocks), dim3(256), 0, s, grad, out, n);
+    const int blocks = (int)std::min<size_t>((max_params + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_grad_out, dim3(blocks, nprob), dim3(256), 0, s, geoms, args, ws);
     return hipGetLastError();
 }
 

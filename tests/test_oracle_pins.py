@@ -196,6 +196,48 @@ def test_joint_pdf_brute_force_all_bins(orc):
     assert np.allclose(pdf, ref / ref.sum(), atol=1e-15)
 
 
+def test_joint_mass_boxes_partition_the_pdf(orc):
+    """Eq (3) is a sum over voxels: the box masses of a partition of the grid add
+    up to Z p, and each box holds exactly its voxel count (sum_r w = 1 and the
+    Parzen window sums to 1 in both images)."""
+    w1 = synth.blobs(n=16)
+    p = P(orc, (16, 14, 12), K=(4, 5, 4), nb=16, role=1)
+    f = orc.normalize(w1.fixed[:12, :14, :16], w1.fixed.min(), w1.fixed.max(), 16)
+    m = orc.normalize(w1.moving[:12, :14, :16], w1.moving.min(), w1.moving.max(), 16)
+    ffd = synth.random_ffd(p.ctrl_dims, 0.8, 2)
+    pdf, Z = orc.joint_pdf(p, f, m, ffd)
+    q = np.zeros_like(pdf)
+    for xs in ((0, 7), (7, 16)):
+        for ys in ((0, 3), (3, 14)):
+            for zs in ((0, 5), (5, 9), (9, 12)):
+                box = xs + ys + zs
+                qb = orc.joint_mass_box(p, f, m, ffd, box)
+                nvox = (xs[1] - xs[0]) * (ys[1] - ys[0]) * (zs[1] - zs[0])
+                assert abs(qb.sum() - nvox) < 1e-10 * nvox
+                q += qb
+    assert np.allclose(q, pdf * Z, rtol=0, atol=1e-12)
+
+
+def test_fd_harness_matches_full_reevaluation(orc):
+    """The support-box finite differences equal central differences of full
+    re-evaluations of D (perturbing one node changes T only where the node's
+    cubic B-spline weight can be non-zero, eq 17)."""
+    fr, mr = synth.smooth_pair((18, 16, 15), k=3)
+    p = P(orc, (18, 16, 15), nb=24, K=(4, 4, 5), d=(4, 5, 4), role=0)
+    f = orc.normalize(fr, fr.min(), fr.max(), 24)
+    m = orc.normalize(mr, mr.min(), mr.max(), 24)
+    ffd = synth.random_ffd(p.ctrl_dims, 1.0, 5)
+    pts = [(0, 2, 3, 2), (1, 4, 2, 5), (2, 3, 4, 3), (0, 0, 0, 0), (2, 6, 6, 7)]
+    h = 1e-3
+    fd = orc.fd_control_points(p, f, m, ffd, pts, h)
+    for (e, k, j, i), v in zip(pts, fd):
+        fp_, fm_ = ffd.copy(), ffd.copy()
+        fp_[e, k, j, i] = np.float32(float(ffd[e, k, j, i]) + h)
+        fm_[e, k, j, i] = np.float32(float(ffd[e, k, j, i]) - h)
+        ref = (orc.value(p, f, m, fp_) - orc.value(p, f, m, fm_)) / (float(fp_[e, k, j, i]) - float(fm_[e, k, j, i]))
+        assert abs(v - ref) <= 1e-12 + 1e-7 * abs(ref), (e, k, j, i, v, ref)   # D rounding / 2h ~ 1e-14
+
+
 # ------------------------------------------------- eqs (9), (11), (12)
 @pytest.mark.parametrize("role", [0, 1])
 def test_srwcr_forms_agree_and_range(orc, role):

@@ -287,22 +287,35 @@ def ct_pet(n=192, k=4):
 
 
 # ----------------------------------------------------------- 4-D phases
-def breathing_phases(shape=(128, 256, 256), k=5, n_phases=9):
-    """Workload 5: phase 0 and phases 1..9 of a breathing cycle, cropped to
-    80 + 6 (k - 1) centre slices.  Returns a list of (fixed, moving) raw pairs."""
+def _phase_labels(ells, shape, amp):
+    """Label volume of one breathing phase (amp None: the reference phase)."""
+    u = None
+    if amp is not None:
+        u = np.zeros((3,) + tuple(shape), dtype=np.float32)
+        u[2] = breathing_field(shape, amp)
+    return _render_slabwise(lambda xs, ys, zs: _render_labels(ells, shape, xs, ys, zs), shape, u)
+
+
+def breathing_phases(shape=(128, 256, 256), k=5, n_phases=9, workers=1):
+    """Workload 5: phase 0 and phases 1..9 of a breathing cycle, pair k cropped
+    to the centre (80 + 6 (k - 1)) / 128 of the slices.  Returns a list of
+    (fixed, moving) raw pairs.  `workers` > 1 renders the phases in forked
+    processes (the random draws stay in the calling process, in order)."""
     rng = rng_for(k)
     ells = _ellipsoids(rng, shape)
     nz = shape[0]
-    lab0 = _render_slabwise(lambda xs, ys, zs: _render_labels(ells, shape, xs, ys, zs), shape, None)
-    fixed_full = _labels_to_hu(lab0) + rng.normal(0, 20.0, size=shape).astype(np.float32)
+    amps = [None] + [3.0 + 12.0 * (ph - 1) / (n_phases - 1) for ph in range(1, n_phases + 1)]
+    if workers > 1:
+        import multiprocessing
+        with multiprocessing.get_context("fork").Pool(min(workers, len(amps))) as pool:
+            labs = pool.starmap(_phase_labels, [(ells, shape, a) for a in amps])
+    else:
+        labs = [_phase_labels(ells, shape, a) for a in amps]
+    fixed_full = _labels_to_hu(labs[0]) + rng.normal(0, 20.0, size=shape).astype(np.float32)
     pairs = []
     for ph in range(1, n_phases + 1):
-        amp = 3.0 + 12.0 * (ph - 1) / (n_phases - 1)
-        u = np.zeros((3,) + shape, dtype=np.float32)
-        u[2] = breathing_field(shape, amp)
-        lab = _render_slabwise(lambda xs, ys, zs: _render_labels(ells, shape, xs, ys, zs), shape, u)
-        mov = _labels_to_hu(lab) + rng.normal(0, 20.0, size=shape).astype(np.float32)
-        zk = 80 + 6 * (ph - 1)
+        mov = _labels_to_hu(labs[ph]) + rng.normal(0, 20.0, size=shape).astype(np.float32)
+        zk = nz * (80 + 6 * (ph - 1)) // 128      # 80, 86, ..., 128 slices of 128
         z0 = (nz - zk) // 2
         pairs.append((np.ascontiguousarray(fixed_full[z0:z0 + zk]), np.ascontiguousarray(mov[z0:z0 + zk])))
     return pairs
