@@ -109,6 +109,18 @@ int srwcr_eval(const srwcr_plan *plan, const void *fixed, const void *moving, co
 int srwcr_grad(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd,
                double *d_value, float *d_grad, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Dense-displacement variants (a loss for learning-based registration): the
+ * warp is T(x) = x + u(x) with u a device float32 field [3][nz][ny][nx] on the
+ * fixed grid (fixed-voxel units), instead of the FFD of eq 17; everything
+ * else is srwcr_eval / srwcr_grad.  srwcr_grad_dense writes d_grad, a device
+ * float32 [3][nz][ny][nx] array, with dD/du(x) = dD/dM(x) dM/dy dy/dT, the
+ * per-voxel factor of eq 16 (dT/du = 1); nothing is scattered.  The plan's
+ * ctrl_spacing is unused by these calls. */
+int srwcr_eval_dense(const srwcr_plan *plan, const void *fixed, const void *moving, const float *field,
+                     double *d_value, void *workspace, size_t workspace_bytes, void *stream);
+int srwcr_grad_dense(const srwcr_plan *plan, const void *fixed, const void *moving, const float *field,
+                     double *d_value, float *d_grad, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Batched value + gradient over up to SRWCR_MAX_BATCH independent problems
  * (e.g. the phases of a 4-D series times the levels of their pyramids): one
  * launch per pass covers every problem, so small problems share the device

@@ -34,7 +34,8 @@ def build(force: bool = True) -> str:
 
 class _Problem(ctypes.Structure):
     _fields_ = [("nf", ctypes.c_int * 3), ("nm", ctypes.c_int * 3), ("n_bins", ctypes.c_int),
-                ("K", ctypes.c_int * 3), ("delta", ctypes.c_int * 3), ("role", ctypes.c_int)]
+                ("K", ctypes.c_int * 3), ("delta", ctypes.c_int * 3), ("role", ctypes.c_int),
+                ("dense", ctypes.c_int)]
 
 
 @dataclass(frozen=True)
@@ -43,13 +44,16 @@ class Problem:
 
     role 0: the moving image plays A (the model image); role 1: it plays B
     (the estimated image) -- Sec. II-E / Table II.  spatial_bins == (1, 1, 1)
-    selects one constant region (a test-only special case)."""
+    selects one constant region (a test-only special case).  dense: the
+    displacements are a dense field u (3, nz, ny, nx) on the fixed grid,
+    T(x) = x + u(x), instead of FFD coefficients."""
     fixed_dims: tuple   # (nx, ny, nz)
     moving_dims: tuple
     n_bins: int
     spatial_bins: tuple
     ctrl_spacing: tuple
     role: int
+    dense: bool = False
 
     def c(self) -> _Problem:
         p = _Problem()
@@ -59,6 +63,7 @@ class Problem:
         p.K[:] = list(self.spatial_bins)
         p.delta[:] = list(self.ctrl_spacing)
         p.role = self.role
+        p.dense = 1 if self.dense else 0
         return p
 
     @property
@@ -208,7 +213,11 @@ def joint_mass_box(P: Problem, fixed: np.ndarray, moving: np.ndarray, ffd: np.nd
 
 def node_support_box(P: Problem, node) -> tuple:
     """Fixed voxels whose warp T (eq 17, stored node index = paper index + 1)
-    involves control node (i, j, k): floor(x / delta) in [i - 3, i] per axis."""
+    involves control node (i, j, k): floor(x / delta) in [i - 3, i] per axis.
+    For a dense field, (i, j, k) is a voxel and its box is that voxel."""
+    if P.dense:
+        i, j, k = node
+        return (i, i + 1, j, j + 1, k, k + 1)
     box = []
     for n, d, N in zip(node, P.ctrl_spacing, P.fixed_dims):
         box += [max(0, (n - 3) * d), min(N, (n + 1) * d)]
@@ -219,7 +228,7 @@ def fd_control_points(P: Problem, fixed: np.ndarray, moving: np.ndarray, ffd: np
                       h: float, threads: int | None = None) -> np.ndarray:
     """Central finite differences of D (eq 9, Table I loop) with respect to
     single displacement components points = [(e, k, j, i), ...] (component e
-    of stored node (i, j, k)).
+    of stored node (i, j, k), or of voxel (i, j, k) of a dense field).
 
     Eq (3) is a sum over voxels, so the perturbed Z p is the unperturbed Z p
     minus the old and plus the new mass of the voxels whose warp the node
@@ -265,13 +274,14 @@ def value(P: Problem, fixed: np.ndarray, moving: np.ndarray, ffd: np.ndarray) ->
 def gradient(P: Problem, fixed: np.ndarray, moving: np.ndarray, ffd: np.ndarray,
              form: int = 0, want_dDdM: bool = False):
     """(D, dD/d(displacement)[3, ncz, ncy, ncx]) by eqs (16, 17) with dD/dM from
-    eq (19)/(21) (form 0) or eq (18)/(20) + (26) (form 1)."""
+    eq (19)/(21) (form 0) or eq (18)/(20) + (26) (form 1).  For a dense field
+    (P.dense) the gradient is dD/du[3, nz, ny, nx], eq (16) per voxel."""
     fx, fxp = _f32(fixed)
     m, mp = _f32(moving)
     f, fp = _f32(ffd)
     ncx, ncy, ncz = P.ctrl_dims
-    g = np.zeros((3, ncz, ncy, ncx))
     nx, ny, nz = P.fixed_dims
+    g = np.zeros((3, nz, ny, nx)) if P.dense else np.zeros((3, ncz, ncy, ncx))
     dm = np.zeros((nz, ny, nx)) if want_dDdM else None
     D = lib().orc_gradient(ctypes.byref(P.c()), fxp, mp, fp, int(form), _f64(g),
                            _f64(dm) if dm is not None else None)

@@ -18,6 +18,7 @@
  *   - dD/dM by the triple sums of eq 19 (M is B) and eq 21 (M is A),
  *     and, as a second form, by eqs 18 / 20 built from dp/dM of eq 26
  *   - chain rule to the control points                      (eqs 16, 17)
+ *   - or, for a dense displacement field, dD/du(x) per voxel  (eq 16)
  * The joint PDF is kept literally: R x (L+1) x (L+1) doubles.  Per voxel only
  * the bins where h (or h') can be non-zero are visited, which is exact.
  *
@@ -52,6 +53,8 @@ typedef struct {
     int K[3];       /* spatial bins per axis (1,1,1 = one constant region) */
     int delta[3];   /* FFD control spacing in fixed voxels */
     int role;       /* 0: the moving image is A (model); 1: it is B (estimated) */
+    int dense;      /* 0: displacements are FFD coefficients (eq 17); 1: a dense field
+                       u[3][nz][ny][nx] on the fixed grid, T(x) = x + u(x) */
 } orc_problem;
 
 #define VAR_REL 1e-5   /* degenerate region: sigma_r^2 <= VAR_REL * E_r[b^2] */
@@ -202,12 +205,26 @@ static void map_to_moving(const orc_problem *P, const double T[3], double y[3], 
     }
 }
 
+/* T(x): the FFD of eq 17, or x + u(x) for a dense displacement field */
+static void voxel_T(const orc_problem *P, const float *disp, int x, int y, int z, double T[3])
+{
+    if (!P->dense) {
+        orc_ffd_T(P, disp, x, y, z, T);
+        return;
+    }
+    long nvox = (long)P->nf[0] * P->nf[1] * P->nf[2];
+    long idx = ((long)z * P->nf[1] + y) * P->nf[0] + x;
+    T[0] = x + (double)disp[idx];
+    T[1] = y + (double)disp[nvox + idx];
+    T[2] = z + (double)disp[2 * nvox + idx];
+}
+
 /* warped, normalised moving intensity at every fixed voxel (clamped to [0, L]) */
 static double warped_sample(const orc_problem *P, const float *mov, const float *ffd,
                             int x, int y, int z, double dsdT[3])
 {
     double T[3], yy[3], dydT[3], g[3];
-    orc_ffd_T(P, ffd, x, y, z, T);
+    voxel_T(P, ffd, x, y, z, T);
     map_to_moving(P, T, yy, dydT);
     double s = orc_sample(P, mov, yy, g);
     double L = (double)(P->n_bins - 1);
@@ -555,7 +572,8 @@ static double dDdM_voxel(const orc_problem *P, int form, double A, double B, dou
 }
 
 /* ------------------------------------------------ gradient, eqs (16, 17)
- * grad: float64[3][ncz][ncy][ncx] = dD/d(displacement).
+ * grad: float64[3][ncz][ncy][ncx] = dD/d(displacement); for a dense field
+ * (P->dense) float64[3][nz][ny][nx] = dD/du(x), eq 16 with dT/du = 1.
  * dDdM_out (optional): dD/dM at every fixed voxel.  Returns D. */
 double orc_gradient(const orc_problem *P, const float *fix, const float *mov, const float *ffd,
                     int form, double *grad, double *dDdM_out)
@@ -563,7 +581,8 @@ double orc_gradient(const orc_problem *P, const float *fix, const float *mov, co
     int R = n_regions(P), nb = P->n_bins;
     int nc[3];
     orc_ctrl_dims(P, nc);
-    long ncell = (long)nc[0] * nc[1] * nc[2];
+    long nvox = (long)P->nf[0] * P->nf[1] * P->nf[2];
+    long ncell = P->dense ? nvox : (long)nc[0] * nc[1] * nc[2];
     double *p = (double *)malloc(sizeof(double) * (size_t)R * nb * nb);
     double Z = orc_joint_pdf(P, fix, mov, ffd, p);
     double D = orc_srwcr_from_pdf(R, nb, p, 0);
@@ -576,14 +595,14 @@ double orc_gradient(const orc_problem *P, const float *fix, const float *mov, co
 #ifdef _OPENMP
     nthreads = omp_get_max_threads();
 #endif
-    double *priv = (double *)calloc((size_t)nthreads * 3 * ncell, sizeof(double));
+    double *priv = P->dense ? NULL : (double *)calloc((size_t)nthreads * 3 * ncell, sizeof(double));
 #pragma omp parallel
     {
         int tid = 0;
 #ifdef _OPENMP
         tid = omp_get_thread_num();
 #endif
-        double *gg = priv + (long)tid * 3 * ncell;
+        double *gg = P->dense ? grad : priv + (long)tid * 3 * ncell;
         double *wx = (double *)malloc(sizeof(double) * P->K[0]);
         double *wy = (double *)malloc(sizeof(double) * P->K[1]);
         double *wz = (double *)malloc(sizeof(double) * P->K[2]);
@@ -597,7 +616,12 @@ double orc_gradient(const orc_problem *P, const float *fix, const float *mov, co
                     double A, B, dsdT[3];
                     voxel_AB(P, fix, mov, ffd, x, y, z, &A, &B, dsdT);
                     double g = dDdM_voxel(P, form, A, B, Z, wx, wy, wz, st, pa, mua);
-                    if (dDdM_out) dDdM_out[((long)z * P->nf[1] + y) * P->nf[0] + x] = g;
+                    long vi = ((long)z * P->nf[1] + y) * P->nf[0] + x;
+                    if (dDdM_out) dDdM_out[vi] = g;
+                    if (P->dense) {                /* eq (16): dT/du = 1 */
+                        for (int e = 0; e < 3; ++e) gg[e * nvox + vi] = g * dsdT[e];
+                        continue;
+                    }
                     if (g == 0.0) continue;
                     /* eq (16) with the Jacobian of eq (17) */
                     int pc[3] = {x / P->delta[0], y / P->delta[1], z / P->delta[2]};
@@ -616,8 +640,9 @@ double orc_gradient(const orc_problem *P, const float *fix, const float *mov, co
         }
         free(wx); free(wy); free(wz);
     }
-    for (int t = 0; t < nthreads; ++t)
-        for (long c = 0; c < 3 * ncell; ++c) grad[c] += priv[(long)t * 3 * ncell + c];
+    if (!P->dense)
+        for (int t = 0; t < nthreads; ++t)
+            for (long c = 0; c < 3 * ncell; ++c) grad[c] += priv[(long)t * 3 * ncell + c];
     free(priv);
     free(st); free(pa); free(mua);
     return D;

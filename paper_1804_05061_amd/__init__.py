@@ -24,7 +24,7 @@ _TORCH_DT = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
 _DT_OF = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
 
 __all__ = ["Problem", "Plan", "Batch", "normalize", "minmax", "register_lbfgs", "LbfgsOptions", "SrwcrError",
-           "MOVING_AS_A", "MOVING_AS_B", "F32", "F16", "BF16", "SRWCRLoss"]
+           "MOVING_AS_A", "MOVING_AS_B", "F32", "F16", "BF16", "SRWCRLoss", "SRWCRDenseLoss"]
 
 
 def _stream():
@@ -90,6 +90,11 @@ class Problem:
     def ffd_shape(self):
         return (3,) + tuple(self.ctrl_dims[::-1])
 
+    @property
+    def field_shape(self):
+        """Dense displacement field u[3][nz][ny][nx] on the fixed grid."""
+        return (3,) + tuple(self.fixed_dims[::-1])
+
 
 class Plan:
     """A plan (device tables and launch geometry) plus its own workspace."""
@@ -147,6 +152,33 @@ class Plan:
             grad_out = torch.empty(self.problem.ffd_shape, dtype=torch.float32, device=fixed.device)
         _lib.check(_lib.load().srwcr_grad(self._h, _ptr(fixed), _ptr(moving), _ptr(ffd), _ptr(value_out),
                                           _ptr(grad_out), _ptr(self.workspace), self.workspace_bytes, _stream()))
+        return value_out, grad_out
+
+    def _check_dense(self, fixed, moving, field):
+        p = self.problem
+        _need_cuda(fixed, "fixed", _TORCH_DT[p.fixed_dtype], p.fixed_shape)
+        _need_cuda(moving, "moving", _TORCH_DT[p.moving_dtype], p.moving_shape)
+        _need_cuda(field, "field", torch.float32, p.field_shape)
+
+    def eval_dense(self, fixed, moving, field, out=None):
+        """D with the warp T(x) = x + u(x) of a dense field u[3][nz][ny][nx]."""
+        self._check_dense(fixed, moving, field)
+        if out is None:
+            out = torch.empty((), dtype=torch.float64, device=fixed.device)
+        _lib.check(_lib.load().srwcr_eval_dense(self._h, _ptr(fixed), _ptr(moving), _ptr(field), _ptr(out),
+                                                _ptr(self.workspace), self.workspace_bytes, _stream()))
+        return out
+
+    def grad_dense(self, fixed, moving, field, value_out=None, grad_out=None):
+        """(D, dD/du[3][nz][ny][nx]) for a dense displacement field (eq 16 per voxel)."""
+        self._check_dense(fixed, moving, field)
+        if value_out is None:
+            value_out = torch.empty((), dtype=torch.float64, device=fixed.device)
+        if grad_out is None:
+            grad_out = torch.empty(self.problem.field_shape, dtype=torch.float32, device=fixed.device)
+        _lib.check(_lib.load().srwcr_grad_dense(self._h, _ptr(fixed), _ptr(moving), _ptr(field), _ptr(value_out),
+                                                _ptr(grad_out), _ptr(self.workspace), self.workspace_bytes,
+                                                _stream()))
         return value_out, grad_out
 
     def warp(self, moving, ffd, out=None):
@@ -304,4 +336,22 @@ class SRWCRLoss(torch.autograd.Function):
     def backward(ctx, grad_output):
         ffd, fixed, moving = ctx.saved_tensors
         _, g = ctx.plan.grad(fixed, moving, ffd.detach().contiguous())
+        return (g * grad_output.to(torch.float32)), None, None, None
+
+
+class SRWCRDenseLoss(torch.autograd.Function):
+    """D = SRWCR as a differentiable function of a dense displacement field
+    u[3][nz][ny][nx] (T(x) = x + u(x)), e.g. the output of a registration
+    network.  backward re-runs srwcr_grad_dense and scales by grad_output."""
+
+    @staticmethod
+    def forward(ctx, field, fixed, moving, plan):
+        ctx.plan = plan
+        ctx.save_for_backward(field, fixed, moving)
+        return plan.eval_dense(fixed, moving, field.detach().contiguous()).clone()
+
+    @staticmethod
+    def backward(ctx, grad_output):
+        field, fixed, moving = ctx.saved_tensors
+        _, g = ctx.plan.grad_dense(fixed, moving, field.detach().contiguous())
         return (g * grad_output.to(torch.float32)), None, None, None

@@ -16,7 +16,7 @@ EXPORTED = ["srwcr_ctrl_dims", "srwcr_plan_create", "srwcr_plan_destroy", "srwcr
             "srwcr_normalize", "srwcr_minmax", "srwcr_eval", "srwcr_grad", "ffd_warp",
             "srwcr_lbfgs_default_opts", "register_lbfgs", "srwcr_debug_moments", "srwcr_plan_info",
             "srwcr_profile", "srwcr_profile_read", "srwcr_refine_ffd", "srwcr_bending_energy",
-            "srwcr_batch_create", "srwcr_batch_destroy", "srwcr_batch_workspace_bytes", "srwcr_grad_batched",
+            "srwcr_eval_dense", "srwcr_grad_dense", "srwcr_batch_create", "srwcr_batch_destroy", "srwcr_batch_workspace_bytes", "srwcr_grad_batched",
             "srwcr_last_error"]
 
 MAX_BATCH = 32
@@ -83,6 +83,8 @@ def load() -> ctypes.CDLL:
         "srwcr_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]),
         "srwcr_refine_ffd": (ctypes.c_int, [ctypes.POINTER(i32), vp, ctypes.POINTER(i32), vp]),
         "srwcr_bending_energy": (ctypes.c_double, [pp, vp, vp]),
+        "srwcr_eval_dense": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
+        "srwcr_grad_dense": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "srwcr_batch_create": (ctypes.c_int, [i32, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
         "srwcr_batch_destroy": (None, [vp]),
         "srwcr_batch_workspace_bytes": (sz, [vp]),

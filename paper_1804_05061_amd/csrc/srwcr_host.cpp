@@ -427,7 +427,7 @@ static BatchArgs one_problem(const void *fixed, const void *moving, const float 
     return a;
 }
 
-static int run_value(const srwcr_plan *P, const BatchArgs &args, unsigned char *ws, hipStream_t s)
+static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, unsigned char *ws, hipStream_t s)
 {
     const Geom &g = P->g;
     double *moments = (double *)(ws + P->ws.moments);
@@ -435,7 +435,8 @@ static int run_value(const srwcr_plan *P, const BatchArgs &args, unsigned char *
     prof_mark(P, 0, s);
     HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
     prof_mark(P, 1, s);
-    HIP_TRY(launch_value(P->geom_dev, g.fdt, g.mdt, P->items, P->nitems, args, ws, P->value_lds, s), "value launch");
+    HIP_TRY(launch_value(P->geom_dev, g.fdt, g.mdt, dense, P->items, P->nitems, args, ws, P->value_lds, s),
+            "value launch");
     prof_mark(P, 2, s);
     HIP_TRY(launch_finalize(P->geom_dev, 1, g.R, args, ws, s), "finalize launch");
     prof_mark(P, 3, s);
@@ -448,7 +449,17 @@ int srwcr_eval(const srwcr_plan *plan, const void *fixed, const void *moving, co
     int st = check_call(plan, fixed, moving, ffd, workspace, workspace_bytes);
     if (st) return st;
     if (!d_value) return fail(SRWCR_E_INVALID_ARG, "d_value is NULL");
-    return run_value(plan, one_problem(fixed, moving, ffd, d_value, nullptr), (unsigned char *)workspace,
+    return run_value(plan, one_problem(fixed, moving, ffd, d_value, nullptr), 0, (unsigned char *)workspace,
+                     (hipStream_t)stream);
+}
+
+int srwcr_eval_dense(const srwcr_plan *plan, const void *fixed, const void *moving, const float *field,
+                     double *d_value, void *workspace, size_t workspace_bytes, void *stream)
+{
+    int st = check_call(plan, fixed, moving, field, workspace, workspace_bytes);
+    if (st) return st;
+    if (!d_value) return fail(SRWCR_E_INVALID_ARG, "d_value is NULL");
+    return run_value(plan, one_problem(fixed, moving, field, d_value, nullptr), 1, (unsigned char *)workspace,
                      (hipStream_t)stream);
 }
 
@@ -461,16 +472,35 @@ int srwcr_grad(const srwcr_plan *plan, const void *fixed, const void *moving, co
     unsigned char *ws = (unsigned char *)workspace;
     hipStream_t s = (hipStream_t)stream;
     const BatchArgs args = one_problem(fixed, moving, ffd, d_value, d_grad);
-    st = run_value(plan, args, ws, s);
+    st = run_value(plan, args, 0, ws, s);
     if (st) return st;
     const Geom &g = plan->g;
-    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.mdt, g.role, plan->items, plan->nitems, args, ws, plan->grad_lds, s),
+    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.mdt, g.role, 0, plan->items, plan->nitems, args, ws, plan->grad_lds,
+                        s),
             "gradient launch");
     prof_mark(plan, 4, s);
     const size_t n = 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2];
     HIP_TRY(launch_grad_out(plan->geom_dev, 1, n, args, ws, s), "gradient output launch");
     prof_mark(plan, 5, s);
     if (plan->profiling && (size_t)(plan->prof_calls + 1) * (kPhases + 1) <= plan->ev_pool.size()) ++plan->prof_calls;
+    return SRWCR_OK;
+}
+
+int srwcr_grad_dense(const srwcr_plan *plan, const void *fixed, const void *moving, const float *field,
+                     double *d_value, float *d_grad, void *workspace, size_t workspace_bytes, void *stream)
+{
+    int st = check_call(plan, fixed, moving, field, workspace, workspace_bytes);
+    if (st) return st;
+    if (!d_value || !d_grad) return fail(SRWCR_E_INVALID_ARG, "d_value or d_grad is NULL");
+    unsigned char *ws = (unsigned char *)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    const BatchArgs args = one_problem(fixed, moving, field, d_value, d_grad);
+    st = run_value(plan, args, 1, ws, s);
+    if (st) return st;
+    const Geom &g = plan->g;
+    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.mdt, g.role, 1, plan->items, plan->nitems, args, ws, plan->grad_lds,
+                        s),
+            "gradient launch");
     return SRWCR_OK;
 }
 
@@ -493,7 +523,7 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
     const size_t nzero = (plan->ws.counter + sizeof(double) - plan->ws.moments) / sizeof(double);
     HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
     const Geom &g = plan->g;
-    HIP_TRY(launch_value(plan->geom_dev, g.fdt, g.mdt, plan->items, plan->nitems,
+    HIP_TRY(launch_value(plan->geom_dev, g.fdt, g.mdt, 0, plan->items, plan->nitems,
                          one_problem(fixed, moving, ffd, nullptr, nullptr), ws, plan->value_lds, s),
             "value launch");
     const size_t bytes = (size_t)plan->g.R * plan->g.nb * 3 * sizeof(double);
@@ -656,10 +686,10 @@ int srwcr_grad_batched(const srwcr_batch *b, const srwcr_batch_item *items, void
     unsigned char *ws = (unsigned char *)workspace;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_zero((double *)ws, b->zero_bytes / sizeof(double), s), "zero launch");
-    HIP_TRY(launch_value(b->geoms_dev, b->fdt, b->mdt, b->items_dev, b->nitems, args, ws, b->value_lds, s),
+    HIP_TRY(launch_value(b->geoms_dev, b->fdt, b->mdt, 0, b->items_dev, b->nitems, args, ws, b->value_lds, s),
             "value launch");
     HIP_TRY(launch_finalize(b->geoms_dev, n, b->max_regions, args, ws, s), "finalize launch");
-    HIP_TRY(launch_grad(b->geoms_dev, b->fdt, b->mdt, b->role, b->items_dev, b->nitems, args, ws, b->grad_lds, s),
+    HIP_TRY(launch_grad(b->geoms_dev, b->fdt, b->mdt, b->role, 0, b->items_dev, b->nitems, args, ws, b->grad_lds, s),
             "gradient launch");
     HIP_TRY(launch_grad_out(b->geoms_dev, n, b->max_params, args, ws, s), "gradient output launch");
     return SRWCR_OK;

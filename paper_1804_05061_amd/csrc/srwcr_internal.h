@@ -47,7 +47,7 @@ struct WsLayout {
 struct ProbPtrs {
     const void *fixed;
     const void *moving;
-    const float *ffd;
+    const float *ffd;  // FFD coefficients, or a dense field [3][nz][ny][nx]
     double *value;     // D
     float *grad;       // dD/d(displacement), layout of ffd (unused by value-only calls)
 };
@@ -92,11 +92,11 @@ hipError_t launch_zero(double *p, size_t n, hipStream_t s);
 hipError_t launch_normalize(const float *in, int64_t n, float lo, float scale, float L, void *out, int dt,
                             hipStream_t s);
 hipError_t launch_minmax(const float *in, int64_t n, float *partial, int nblocks, hipStream_t s);
-hipError_t launch_value(const Geom *geoms, int fdt, int mdt, const WorkItem *items, int nitems, const BatchArgs &args,
-                        unsigned char *ws, size_t lds_bytes, hipStream_t s);
+hipError_t launch_value(const Geom *geoms, int fdt, int mdt, int dense, const WorkItem *items, int nitems,
+                        const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s);
 hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const BatchArgs &args, unsigned char *ws,
                            hipStream_t s);
-hipError_t launch_grad(const Geom *geoms, int fdt, int mdt, int role, const WorkItem *items, int nitems,
+hipError_t launch_grad(const Geom *geoms, int fdt, int mdt, int role, int dense, const WorkItem *items, int nitems,
                        const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s);
 hipError_t launch_grad_out(const Geom *geoms, int nprob, size_t max_params, const BatchArgs &args, unsigned char *ws,
                            hipStream_t s);

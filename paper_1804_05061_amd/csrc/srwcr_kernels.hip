@@ -220,6 +220,16 @@ __device__ __forceinline__ void ffd_u(const Geom &g, const double *c1, int px_lo
     }
 }
 
+// Displacement of fixed voxel (x, y, z) from a dense field u[3][nz][ny][nx]
+// (T(x) = x + u(x)), widened to FP64 like the FFD path.
+__device__ __forceinline__ void dense_u(const Geom &g, const float *__restrict__ field, int x, int y, int z, double u[3])
+{
+    const size_t nv = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
+    const size_t vi = ((size_t)z * g.nf[1] + y) * g.nf[0] + x;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) u[e] = (double)field[e * nv + vi];
+}
+
 // Backward warping: trilinear sample of the moving volume at T(x) mapped to
 // the moving grid, coordinates clamped to [0, M - 1]; grad (if non-null) gets
 // dM/dy, zero along clamped axes.  y = base + frac + u * ratio keeps the
@@ -379,15 +389,17 @@ hipError_t launch_minmax(const float *in, int64_t n, float *partial, int nblocks
 }
 
 // ------------------------------------------------------------ value pass
-// Region stride of the item histogram in doubles: 3 nb plus a pad that puts
-// consecutive regions 24 LDS banks apart, so the 60 lanes of one FP64 atomic
-// (4 bin slots x 5 x-nodes x 3 moments) touch each bank at most twice.
-__host__ __device__ __forceinline__ int hist_stride(int nb) { return 3 * nb + (((24 - 6 * nb) % 64 + 64) % 64) / 2; }
+// Item histogram layout: H[((a * 3 + m) * 5 + i) * kHS + jk] holds moment m of
+// A-bin a in region (i, j, k) of the item's 5 x 4 x 4 block, jk = 4 k + j.
+// The 16 (y, z) regions of one (a, m, i) are adjacent, so a lane's 16 atomics
+// share one address with immediate offsets; the pad of one double puts the 60
+// lanes of a window (consecutive (a, m, i)) on 32 distinct bank pairs, so an
+// atomic touches each bank at most twice.
+constexpr int kHS = 17;
 
 size_t value_lds_bytes(const Geom &g)
 {
-    return (size_t)kNReg * hist_stride(g.nb) * sizeof(double) +
-           (size_t)(kValueThreads / kWave) * 3 * g.c1n * sizeof(double);
+    return (size_t)g.nb * 3 * kXN * kHS * sizeof(double) + (size_t)(kValueThreads / kWave) * 3 * g.c1n * sizeof(double);
 }
 
 // Wave-uniform minimum: butterfly inside each 16-lane row (DPP), then the
@@ -405,6 +417,18 @@ __device__ __forceinline__ int wave_min_dpp(int v)
 
 __device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Wave-uniform bitwise OR, with the same DPP steps as wave_min_dpp.
+__device__ __forceinline__ unsigned wave_or_dpp(unsigned v)
+{
+    v |= (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xf, 0xf, false);
+    v |= (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xf, 0xf, false);
+    v |= (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x124, 0xf, 0xf, false);
+    v |= (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x128, 0xf, 0xf, false);
+    const unsigned r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const unsigned r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return (r0 | r1) | (r2 | r3);
+}
+
 // Per-voxel quantities of the value pass.
 struct VoxA {
     int k;          // A-bin (lower tap)
@@ -412,42 +436,43 @@ struct VoxA {
     float wxv[15];  // x-node weight (5 nodes) times (1, m1(B), m2(B))
 };
 
-// Window slot weight of a voxel: a0 on slot o, a1 on slot o + 1.
-__device__ __forceinline__ float slot_w(bool in, int o, int w, float a0, float a1)
+// One bin window of the value pass: four A-bins b[0..3] (any four of the bins
+// the row's taps touch, ascending; unused slots hold a bin above L).  Each of
+// the lane's two voxels puts weight a0 on the slot of bin k and a1 on the
+// slot of bin k + 1 when those bins are in the window; the wave sums 4 slots
+// x 15 (x-node, moment) values across lanes and each lane spreads one total
+// over the 16 (y, z) regions of its column with FP64 LDS atomics.  A voxel
+// outside the row has k < -1 and matches no slot.
+__device__ __forceinline__ void value_window(double *H, int L, const int (&b)[kWin], const VoxA (&v)[kSlots],
+                                             const float (&wyz)[16], int lane)
 {
-    return in ? ((o == w) ? a0 : ((o == w - 1) ? a1 : 0.0f)) : 0.0f;
-}
-
-// One bin window of the value pass over the lane's two voxels: their taps go
-// to window slots (bins kbase + o, kbase + o + 1); the wave sums 4 slots x 15
-// (x-node, moment) values across lanes and each lane spreads one total over
-// the 16 (y, z) regions of its column with FP64 LDS atomics.
-__device__ __forceinline__ void value_window(double *H, int rs, int L, int kbase, const VoxA (&v)[kSlots],
-                                             const bool (&in)[kSlots], const float (&wyz)[16], int lane)
-{
+    float t[kSlots][kWin];
+#pragma unroll
+    for (int sl = 0; sl < kSlots; ++sl)
+#pragma unroll
+        for (int w = 0; w < kWin; ++w)
+            t[sl][w] = (v[sl].k == b[w]) ? v[sl].a0 : ((v[sl].k + 1 == b[w]) ? v[sl].a1 : 0.0f);
     float V[64];
 #pragma unroll
-    for (int w = 0; w < kWin; ++w) {
-        const float t0 = slot_w(in[0], v[0].k - kbase, w, v[0].a0, v[0].a1);
-        const float t1 = slot_w(in[1], v[1].k - kbase, w, v[1].a0, v[1].a1);
+    for (int w = 0; w < kWin; ++w)
 #pragma unroll
-        for (int q = 0; q < 15; ++q) V[w * 15 + q] = fmaf(t1, v[1].wxv[q], t0 * v[0].wxv[q]);
-    }
+        for (int q = 0; q < 15; ++q) V[w * 15 + q] = fmaf(t[1][w], v[1].wxv[q], t[0][w] * v[0].wxv[q]);
 #pragma unroll
     for (int q = kWin * 15; q < 64; ++q) V[q] = 0.0f;
     const float T = wave_transpose_sum(V, lane);
     if (lane < kWin * 15 && T != 0.0f) {
         const int w = lane / 15, q = lane - 15 * w, i = q / 3, m = q - 3 * i;
-        const int a = kbase + w;
+        const int a = w == 0 ? b[0] : (w == 1 ? b[1] : (w == 2 ? b[2] : b[3]));
         if (a <= L) {
-            double *h = H + i * rs + a * 3 + m;
+            double *h = H + ((a * 3 + m) * kXN + i) * kHS;
 #pragma unroll
-            for (int jk = 0; jk < 16; ++jk) atomicAdd(h + jk * kXN * rs, (double)(T * wyz[jk]));
+            for (int jk = 0; jk < 16; ++jk) atomicAdd(h + jk, (double)(T * wyz[jk]));
         }
     }
 }
 
-template <int FDT, int MDT>
+// DISP 0: displacements are FFD coefficients (eq 17); DISP 1: a dense field.
+template <int FDT, int MDT, int DISP>
 __global__ void __launch_bounds__(kValueThreads)
 k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, BatchArgs args, unsigned char *ws)
 {
@@ -458,9 +483,9 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batc
     const void *__restrict__ moving = args.p[it.prob].moving;
     const float *__restrict__ ffd = args.p[it.prob].ffd;
     double *__restrict__ moments = reinterpret_cast<double *>(ws + g.ws.moments);
-    const int nb = g.nb, L = nb - 1, rs = hist_stride(nb);
-    double *H = reinterpret_cast<double *>(smem);     // [16 (y,z)][5 x][rs]: region (i, j, k) at ((k*4+j)*5+i)*rs
-    const int nH = kNReg * rs;
+    const int nb = g.nb, L = nb - 1;
+    double *H = reinterpret_cast<double *>(smem);     // [nb][3][5][kHS], see kHS
+    const int nH = nb * 3 * kXN * kHS;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
@@ -473,7 +498,8 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batc
     const int xs = it.x0, xe = it.x1;                    // xe - xs <= 64 kSlots
     for (int row = wave; row < ny * nz; row += nwaves) {
         const int y = it.y0 + row % ny, z = it.z0 + row / ny;
-        const int px_lo = ffd_c1(g, ffd, xs, xe, y, z, c1, lane);
+        int px_lo = 0;
+        if (DISP == 0) px_lo = ffd_c1(g, ffd, xs, xe, y, z, c1, lane);
         wave_sync();
         VoxA v[kSlots];
         bool pend[kSlots];
@@ -483,7 +509,8 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batc
             pend[sl] = x < xe;
             const int xc = pend[sl] ? x : xe - 1;
             double u[3];
-            ffd_u(g, c1, px_lo, xc, u);
+            if (DISP == 0) ffd_u(g, c1, px_lo, xc, u);
+            else dense_u(g, ffd, xc, y, z, u);
             double sm = sample_moving<MDT>(g, moving, xc, y, z, u, nullptr);
             sm = fmin(fmax(sm, 0.0), (double)L);
             const float sf = ld_int<FDT>(fixed, ((size_t)z * g.nf[1] + y) * g.nf[0] + xc);
@@ -493,7 +520,7 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batc
             parzen(sf, L, kF, tF, f0w, f1w);
             const int kB = g.role ? kM : kF;
             const float b1w = g.role ? m1w : f1w;
-            v[sl].k = g.role ? kF : kM;
+            v[sl].k = pend[sl] ? (g.role ? kF : kM) : -8;
             v[sl].a0 = g.role ? f0w : m0w;
             v[sl].a1 = g.role ? f1w : m1w;
             const float m1 = (float)kB + b1w;
@@ -519,40 +546,31 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batc
 #pragma unroll
             for (int j = 0; j < 4; ++j) wyz[k * 4 + j] = wyv[j] * wzv[k];
 
-        // bin windows, two per pass: A-bins [kmin, kmin + 2] of the pending taps
-        constexpr int BIG = 0x7fffffff;
-        for (int pass = 0; pass <= 2 * nb; ++pass) {
-            int k1 = wave_min_dpp(min(pend[0] ? v[0].k : BIG, pend[1] ? v[1].k : BIG));
-            if (k1 == BIG) break;
-            bool in1[kSlots], rest[kSlots], in2[kSlots];
+        // the A-bins the row's taps touch (a wave-uniform 64-bit set), four per window
+        unsigned long long mine = 0ull;
 #pragma unroll
-            for (int sl = 0; sl < kSlots; ++sl) in1[sl] = pend[sl] && v[sl].k >= k1 && v[sl].k - k1 <= kWin - 2;
-            if (wave_ballot(in1[0] || in1[1]) == 0ull) {      // never stall: take the first pending lane
-                const int key = min(pend[0] ? v[0].k : BIG, pend[1] ? v[1].k : BIG);
-                k1 = __builtin_amdgcn_readlane(key, (int)__builtin_ctzll(wave_ballot(key != BIG)));
+        for (int sl = 0; sl < kSlots; ++sl)
+            if (pend[sl]) mine |= 3ull << v[sl].k;
+        unsigned long long bins = (unsigned long long)wave_or_dpp((unsigned)(mine >> 32)) << 32 |
+                                  wave_or_dpp((unsigned)mine);
+        while (bins != 0ull) {
+            int b[kWin];
 #pragma unroll
-                for (int sl = 0; sl < kSlots; ++sl) in1[sl] = pend[sl] && v[sl].k >= k1 && v[sl].k - k1 <= kWin - 2;
+            for (int w = 0; w < kWin; ++w) {
+                b[w] = bins ? (int)__builtin_ctzll(bins) : 1 << 20;
+                bins &= bins - 1;
             }
-#pragma unroll
-            for (int sl = 0; sl < kSlots; ++sl) rest[sl] = pend[sl] && !in1[sl];
-            const int k2 = wave_min_dpp(min(rest[0] ? v[0].k : BIG, rest[1] ? v[1].k : BIG));
-#pragma unroll
-            for (int sl = 0; sl < kSlots; ++sl)
-                in2[sl] = rest[sl] && k2 != BIG && v[sl].k >= k2 && v[sl].k - k2 <= kWin - 2;
-            value_window(H, rs, L, k1, v, in1, wyz, lane);
-            if (k2 != BIG) value_window(H, rs, L, k2, v, in2, wyz, lane);
-#pragma unroll
-            for (int sl = 0; sl < kSlots; ++sl) pend[sl] = rest[sl] && !in2[sl];
+            value_window(H, L, b, v, wyz, lane);
         }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nH; e += blockDim.x) {
         const double val = H[e];
-        if (val != 0.0) {
-            const int rl = e / rs, rem = e - rl * rs;
-            const int a = rem / 3, m = rem - 3 * a;
-            const int i = rl % kXN, jk = rl / kXN, j = jk & 3, k = jk >> 2;
-            if (a < nb && it.cx + i < g.K[0]) {
+        const int idx = e / kHS, jk = e - idx * kHS;
+        if (val != 0.0 && jk < 16) {
+            const int am = idx / kXN, i = idx - am * kXN, a = am / 3, m = am - 3 * a;
+            const int j = jk & 3, k = jk >> 2;
+            if (it.cx + i < g.K[0]) {
                 const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
                 unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], val);
             }
@@ -560,17 +578,17 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batc
     }
 }
 
-#define SRWCR_DISPATCH_DT(KERNEL, FDT_V, MDT_V, ...)                                                   \
+#define SRWCR_DISPATCH_DT(KERNEL, FDT_V, MDT_V, D, ...)                                                \
     do {                                                                                                 \
-        if ((FDT_V) == 0 && (MDT_V) == 0) hipLaunchKernelGGL((KERNEL<0, 0>), __VA_ARGS__);               \
-        else if ((FDT_V) == 0 && (MDT_V) == 1) hipLaunchKernelGGL((KERNEL<0, 1>), __VA_ARGS__);          \
-        else if ((FDT_V) == 0 && (MDT_V) == 2) hipLaunchKernelGGL((KERNEL<0, 2>), __VA_ARGS__);          \
-        else if ((FDT_V) == 1 && (MDT_V) == 0) hipLaunchKernelGGL((KERNEL<1, 0>), __VA_ARGS__);          \
-        else if ((FDT_V) == 1 && (MDT_V) == 1) hipLaunchKernelGGL((KERNEL<1, 1>), __VA_ARGS__);          \
-        else if ((FDT_V) == 1 && (MDT_V) == 2) hipLaunchKernelGGL((KERNEL<1, 2>), __VA_ARGS__);          \
-        else if ((FDT_V) == 2 && (MDT_V) == 0) hipLaunchKernelGGL((KERNEL<2, 0>), __VA_ARGS__);          \
-        else if ((FDT_V) == 2 && (MDT_V) == 1) hipLaunchKernelGGL((KERNEL<2, 1>), __VA_ARGS__);          \
-        else hipLaunchKernelGGL((KERNEL<2, 2>), __VA_ARGS__);                                           \
+        if ((FDT_V) == 0 && (MDT_V) == 0) hipLaunchKernelGGL((KERNEL<0, 0, D>), __VA_ARGS__);            \
+        else if ((FDT_V) == 0 && (MDT_V) == 1) hipLaunchKernelGGL((KERNEL<0, 1, D>), __VA_ARGS__);       \
+        else if ((FDT_V) == 0 && (MDT_V) == 2) hipLaunchKernelGGL((KERNEL<0, 2, D>), __VA_ARGS__);       \
+        else if ((FDT_V) == 1 && (MDT_V) == 0) hipLaunchKernelGGL((KERNEL<1, 0, D>), __VA_ARGS__);       \
+        else if ((FDT_V) == 1 && (MDT_V) == 1) hipLaunchKernelGGL((KERNEL<1, 1, D>), __VA_ARGS__);       \
+        else if ((FDT_V) == 1 && (MDT_V) == 2) hipLaunchKernelGGL((KERNEL<1, 2, D>), __VA_ARGS__);       \
+        else if ((FDT_V) == 2 && (MDT_V) == 0) hipLaunchKernelGGL((KERNEL<2, 0, D>), __VA_ARGS__);       \
+        else if ((FDT_V) == 2 && (MDT_V) == 1) hipLaunchKernelGGL((KERNEL<2, 1, D>), __VA_ARGS__);       \
+        else hipLaunchKernelGGL((KERNEL<2, 2, D>), __VA_ARGS__);                                        \
     } while (0)
 
 template <typename F>
@@ -580,11 +598,16 @@ static hipError_t set_lds(F *kernel, size_t bytes)
                                (int)bytes);
 }
 
-hipError_t launch_value(const Geom *geoms, int fdt, int mdt, const WorkItem *items, int nitems, const BatchArgs &args,
-                        unsigned char *ws, size_t lds_bytes, hipStream_t s)
+hipError_t launch_value(const Geom *geoms, int fdt, int mdt, int dense, const WorkItem *items, int nitems,
+                        const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
-    SRWCR_DISPATCH_DT(k_value, fdt, mdt, dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args, ws);
+    if (dense)
+        SRWCR_DISPATCH_DT(k_value, fdt, mdt, 1, dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args,
+                          ws);
+    else
+        SRWCR_DISPATCH_DT(k_value, fdt, mdt, 0, dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args,
+                          ws);
     return hipGetLastError();
 }
 
@@ -699,7 +722,8 @@ size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz)
     const size_t tab = (size_t)kNReg * tab_stride(g.nb) * sizeof(float) + kNReg * sizeof(float);
     const size_t G = (size_t)gnx * gny * gnz * 3 * sizeof(double);
     const size_t scratch = (size_t)(kGradThreads / kWave) * g.gscr * sizeof(float);
-    return G + tab + scratch;
+    const size_t bxw = (size_t)g.xw * sizeof(float4);
+    return bxw + G + tab + scratch;
 }
 
 // Per-voxel quantities of the gradient pass.
@@ -710,7 +734,9 @@ struct VoxG {
     float dm[3];      // dM/dy (FP32)
 };
 
-template <int FDT, int MDT, int ROLE>
+// DISP 0: scatter dD/dT to the FFD nodes (eq 17) into the workspace
+// accumulators; DISP 1: write dD/du(x) of a dense field to args.p[].grad.
+template <int FDT, int MDT, int ROLE, int DISP>
 __global__ void __launch_bounds__(kGradThreads)
 k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, BatchArgs args, unsigned char *ws)
 {
@@ -725,7 +751,8 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     double *__restrict__ grad = reinterpret_cast<double *>(ws + g.ws.grad);
     const int nb = g.nb, L = nb - 1, ts = tab_stride(nb);
     const int nG = it.gnx * it.gny * it.gnz * 3;
-    double *G = reinterpret_cast<double *>(smem);                       // [gnz][gny][gnx][3]
+    float4 *bxw = reinterpret_cast<float4 *>(smem);                     // FFD x weights of the item's x range
+    double *G = reinterpret_cast<double *>(bxw + g.xw);                 // [gnz][gny][gnx][3]
     float *tab = reinterpret_cast<float *>(G + nG);                      // [80 regions][ts]: (a, c) at a*3 + c
     float *alph = tab + kNReg * ts;                                      // [80]
     const int lane = threadIdx.x & (kWave - 1);
@@ -733,7 +760,12 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     const int nwaves = blockDim.x >> 6;
     float *scr = alph + kNReg + wave * g.gscr;
 
-    for (int i = threadIdx.x; i < nG; i += blockDim.x) G[i] = 0.0;
+    if (DISP == 0)
+        for (int i = threadIdx.x; i < nG; i += blockDim.x) G[i] = 0.0;
+    for (int i = threadIdx.x; DISP == 0 && i < it.x1 - it.x0; i += blockDim.x) {
+        const double4 b = g.ffd_w[0][it.x0 + i];
+        bxw[i] = make_float4((float)b.x, (float)b.y, (float)b.z, (float)b.w);
+    }
     for (int i = threadIdx.x; i < kNReg * nb; i += blockDim.x) {
         const int rl = i / nb, a = i - rl * nb;
         const int ii = rl % kXN, jk = rl / kXN, jj = jk & 3, kk = jk >> 2;
@@ -758,7 +790,8 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     for (int row = wave; row < ny * nz; row += nwaves) {
         const int y = it.y0 + row % ny, z = it.z0 + row / ny;
         double *c1 = reinterpret_cast<double *>(scr);
-        const int px_lo = ffd_c1(g, ffd, xs, xe, y, z, c1, lane);
+        int px_lo = 0;
+        if (DISP == 0) px_lo = ffd_c1(g, ffd, xs, xe, y, z, c1, lane);
         wave_sync();
         VoxG v[kSlots];
         bool pend[kSlots];
@@ -768,7 +801,8 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             pend[sl] = x < xe;
             const int xc = pend[sl] ? x : xe - 1;
             double u[3], dm[3];
-            ffd_u(g, c1, px_lo, xc, u);
+            if (DISP == 0) ffd_u(g, c1, px_lo, xc, u);
+            else dense_u(g, ffd, xc, y, z, u);
             double sm = sample_moving<MDT>(g, moving, xc, y, z, u, dm);
             sm = fmin(fmax(sm, 0.0), (double)L);
             const float sf = ld_int<FDT>(fixed, ((size_t)z * g.nf[1] + y) * g.nf[0] + xc);
@@ -892,9 +926,22 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             for (int sl = 0; sl < kSlots; ++sl) pend[sl] = pend[sl] && !inw[sl];
         }
 
-        // q = dD/ds * dM/dy * dy/dT  (eq 16), then the scatter to the control
-        // points (eq 17): per FFD cell p of the row the four moments
-        // M[p][l][e] = sum_{x in p} beta_l(eta_x) q_e(x) ...
+        // q = dD/ds * dM/dy * dy/dT  (eq 16): a dense field's gradient is q itself
+        if (DISP == 1) {
+            float *out = args.p[it.prob].grad;
+            const size_t nv = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
+            const size_t rowb = ((size_t)z * g.nf[1] + y) * g.nf[0];
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl)
+                if (xs + sl * kWave + lane < xe) {         // the windows have cleared pend[]
+                    const size_t vi = rowb + xs + sl * kWave + lane;
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) out[e * nv + vi] = gs[sl] * v[sl].dm[e] * g.ratio[e];
+                }
+            continue;
+        }
+        // ... then the scatter to the control points (eq 17): per FFD cell p of
+        // the row the four moments M[p][l][e] = sum_{x in p} beta_l(eta_x) q_e(x) ...
         const int dx = g.delta[0];
         const int px_hi = g.ffd_p[0][xe - 1];
         const int np = px_hi - px_lo + 1, nn = np + 3;
@@ -912,11 +959,11 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             float m0 = 0.0f, m1_ = 0.0f, m2_ = 0.0f, m3 = 0.0f;
             for (int xx = xa; xx < xb; ++xx) {
                 const float q = qb[(xx - xs) * 3 + e];
-                const double4 b = g.ffd_w[0][xx];
-                m0 = fmaf((float)b.x, q, m0);
-                m1_ = fmaf((float)b.y, q, m1_);
-                m2_ = fmaf((float)b.z, q, m2_);
-                m3 = fmaf((float)b.w, q, m3);
+                const float4 b = bxw[xx - xs];
+                m0 = fmaf(b.x, q, m0);
+                m1_ = fmaf(b.y, q, m1_);
+                m2_ = fmaf(b.z, q, m2_);
+                m3 = fmaf(b.w, q, m3);
             }
             cm[(p * 4 + 0) * 3 + e] = m0;
             cm[(p * 4 + 1) * 3 + e] = m1_;
@@ -950,6 +997,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         }
         wave_sync();
     }
+    if (DISP == 1) return;
     __syncthreads();
     const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
     for (int i = threadIdx.x; i < nG; i += blockDim.x) {
@@ -963,22 +1011,26 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     }
 }
 
-hipError_t launch_grad(const Geom *geoms, int fdt, int mdt, int role, const WorkItem *items, int nitems,
+hipError_t launch_grad(const Geom *geoms, int fdt, int mdt, int role, int dense, const WorkItem *items, int nitems,
                        const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
+#define SRWCR_GRAD_R(F, M, D)                                                                                  \
+    if (role)                                                                                                  \
+        hipLaunchKernelGGL((k_grad<F, M, 1, D>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, geoms, items,  \
+                           args, ws);                                                                          \
+    else                                                                                                       \
+        hipLaunchKernelGGL((k_grad<F, M, 0, D>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, geoms, items,  \
+                           args, ws);
 #define SRWCR_GRAD(F, M)                                                                                      \
     if (fdt == F && mdt == M) {                                                                               \
-        if (role)                                                                                             \
-            hipLaunchKernelGGL((k_grad<F, M, 1>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, geoms, items, \
-                               args, ws);                                                                     \
-        else                                                                                                  \
-            hipLaunchKernelGGL((k_grad<F, M, 0>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, geoms, items, \
-                               args, ws);                                                                     \
+        if (dense) { SRWCR_GRAD_R(F, M, 1) }                                                                  \
+        else { SRWCR_GRAD_R(F, M, 0) }                                                                        \
     }
     SRWCR_GRAD(0, 0) SRWCR_GRAD(0, 1) SRWCR_GRAD(0, 2) SRWCR_GRAD(1, 0) SRWCR_GRAD(1, 1) SRWCR_GRAD(1, 2)
     SRWCR_GRAD(2, 0) SRWCR_GRAD(2, 1) SRWCR_GRAD(2, 2)
 #undef SRWCR_GRAD
+#undef SRWCR_GRAD_R
     return hipGetLastError();
 }
 
@@ -996,9 +1048,12 @@ hipError_t prepare_kernels()
     if (e != hipSuccess) return e;
     const size_t b = (size_t)max_lds;
 #define SRWCR_SET(F, M)                                                         \
-    if (e == hipSuccess) e = set_lds(k_value<F, M>, b);                         \
-    if (e == hipSuccess) e = set_lds(k_grad<F, M, 0>, b);                       \
-    if (e == hipSuccess) e = set_lds(k_grad<F, M, 1>, b);
+    if (e == hipSuccess) e = set_lds(k_value<F, M, 0>, b);                      \
+    if (e == hipSuccess) e = set_lds(k_value<F, M, 1>, b);                      \
+    if (e == hipSuccess) e = set_lds(k_grad<F, M, 0, 0>, b);                    \
+    if (e == hipSuccess) e = set_lds(k_grad<F, M, 1, 0>, b);                    \
+    if (e == hipSuccess) e = set_lds(k_grad<F, M, 0, 1>, b);                    \
+    if (e == hipSuccess) e = set_lds(k_grad<F, M, 1, 1>, b);
     SRWCR_SET(0, 0) SRWCR_SET(0, 1) SRWCR_SET(0, 2) SRWCR_SET(1, 0) SRWCR_SET(1, 1) SRWCR_SET(1, 2)
     SRWCR_SET(2, 0) SRWCR_SET(2, 1) SRWCR_SET(2, 2)
 #undef SRWCR_SET

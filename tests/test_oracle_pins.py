@@ -381,6 +381,68 @@ def test_gradient_central_differences_16cube(orc, role):
     assert rel < 1e-4, rel
 
 
+# ------------------------------------------- dense displacement field
+def _dense_from_ffd(orc, p, ffd):
+    nx, ny, nz = p.fixed_dims
+    u = np.zeros((3, nz, ny, nx), dtype=np.float64)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                u[:, z, y, x] = orc.ffd_T(p, ffd, x, y, z) - (x, y, z)
+    return u.astype(np.float32)
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_dense_field_chain_rule_to_ffd(orc, role):
+    """A dense field sampled from an FFD gives the FFD's D, and eq 17 as the
+    adjoint, sum_x beta_c(x) dD/du(x), gives the FFD gradient (beta from the
+    centred cubic B-spline kernel)."""
+    fr, mr = synth.smooth_pair((13, 12, 11), k=4 + role)
+    nb = 24
+    f = orc.normalize(fr, fr.min(), fr.max(), nb)
+    m = orc.normalize(mr, mr.min(), mr.max(), nb)
+    p = P(orc, (13, 12, 11), nb=nb, K=(4, 4, 4), d=(4, 4, 4), role=role)
+    pd = orc.Problem(p.fixed_dims, p.moving_dims, nb, p.spatial_bins, p.ctrl_spacing, role, dense=True)
+    ffd = synth.random_ffd(p.ctrl_dims, 0.8, 11)
+    u = _dense_from_ffd(orc, p, ffd)
+    D, g = orc.gradient(p, f, m, ffd)
+    Dd, gd = orc.gradient(pd, f, m, u)
+    assert gd.shape == (3, 11, 12, 13)
+    assert abs(Dd - D) <= 1e-6 * D                     # u rounded to float32
+    nx, ny, nz = p.fixed_dims
+    ncx, ncy, ncz = p.ctrl_dims
+    gc = np.zeros_like(g)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                pc = (x // 4, y // 4, z // 4)
+                for n in range(4):
+                    for mm in range(4):
+                        for l in range(4):
+                            b = (cubic_bspline_kernel(x / 4 - (pc[0] + l - 1)) * cubic_bspline_kernel(y / 4 - (pc[1] + mm - 1))
+                                 * cubic_bspline_kernel(z / 4 - (pc[2] + n - 1)))
+                            gc[:, pc[2] + n, pc[1] + mm, pc[0] + l] += b * gd[:, z, y, x]
+    assert np.linalg.norm(gc - g) <= 1e-4 * np.linalg.norm(g)
+
+
+def test_dense_gradient_central_differences(orc):
+    """dD/du(x) of a dense field against central differences of D (h = 1e-3
+    voxel) at voxels away from the grid edges."""
+    fr, mr = synth.smooth_pair((14, 13, 12), k=6)
+    nb = 24
+    f = orc.normalize(fr, fr.min(), fr.max(), nb)
+    m = orc.normalize(mr, mr.min(), mr.max(), nb)
+    pd = orc.Problem((14, 13, 12), (14, 13, 12), nb, (4, 4, 4), (4, 4, 4), 0, dense=True)
+    rng = np.random.default_rng(12)
+    u = rng.normal(0.0, 0.7, size=(3, 12, 13, 14)).astype(np.float32)
+    D, g = orc.gradient(pd, f, m, u)
+    pts = [(int(rng.integers(3)), int(rng.integers(2, 10)), int(rng.integers(2, 11)), int(rng.integers(2, 12)))
+           for _ in range(40)]
+    fd = orc.fd_control_points(pd, f, m, u, pts, 1e-3)
+    an = np.array([g[p_] for p_ in pts])
+    assert np.linalg.norm(fd - an) <= 1e-3 * np.linalg.norm(an), (np.linalg.norm(fd - an) / np.linalg.norm(an))
+
+
 # ------------------------------------------------ known stationary points
 def test_zero_gradient_separated_levels_role_A(orc):
     """(Z-A): role A, piecewise-constant labels on non-integer bin positions at
