@@ -113,7 +113,8 @@ def main():
     # dominant kernel and its roofline (algorithmic bytes: F and M read once per pass)
     bytes_f = {"f32": 4, "f16": 2, "bf16": 2}[args.dtype]
     alg_bytes = bytes_f * (nvox + int(np.prod(w.moving_dims)))
-    kern = {"srwcr_value_pass": prof["value"] / prof["calls"], "srwcr_grad_pass": prof["grad"] / prof["calls"]}
+    kern = {"srwcr_warp_pass": prof["warp"] / prof["calls"], "srwcr_value_pass": prof["value"] / prof["calls"],
+            "srwcr_grad_pass": prof["grad"] / prof["calls"]}
     dom = max(kern, key=kern.get)
     achieved = alg_bytes / (kern[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -216,11 +216,11 @@ int srwcr_plan_info(const srwcr_plan *plan, int32_t *n_items, int32_t *value_lds
  * srwcr_profile(plan, 1) starts a session (up to 4096 calls are recorded, the
  * first call creates the events), srwcr_profile(plan, 0) stops recording.
  * srwcr_profile_read synchronises the recorded events and returns the summed
- * milliseconds of the five phases -- zeroing, value pass, finalisation,
- * gradient pass, gradient output -- and the number of calls recorded.  Not
- * thread-safe: profile one stream at a time. */
+ * milliseconds of the six phases -- zeroing, warp pass, value pass,
+ * finalisation, gradient pass, gradient output -- and the number of calls
+ * recorded.  Not thread-safe: profile one stream at a time. */
 int srwcr_profile(const srwcr_plan *plan, int32_t enable);
-int srwcr_profile_read(const srwcr_plan *plan, double ms[5], int32_t *calls);
+int srwcr_profile_read(const srwcr_plan *plan, double ms[6], int32_t *calls);
 
 /* Thread-local description of the last failure on this thread. */
 const char *srwcr_last_error(void);

@@ -197,10 +197,10 @@ class Plan:
 
     def profile_read(self) -> dict:
         """Summed milliseconds per phase of the grad() calls recorded so far."""
-        ms = (ctypes.c_double * 5)()
+        ms = (ctypes.c_double * 6)()
         n = ctypes.c_int32()
         _lib.check(_lib.load().srwcr_profile_read(self._h, ms, ctypes.byref(n)))
-        names = ["zero", "value", "finalize", "grad", "grad_out"]
+        names = ["zero", "warp", "value", "finalize", "grad", "grad_out"]
         return {"calls": n.value, **{k: ms[i] for i, k in enumerate(names)}}
 
     def debug_moments(self, fixed, moving, ffd):

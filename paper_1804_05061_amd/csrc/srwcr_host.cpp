@@ -88,7 +88,7 @@ struct srwcr_plan {
     WorkItem *items = nullptr;
     std::vector<WorkItem> items_host;
     int nitems = 0;
-    size_t value_lds = 0, grad_lds = 0;
+    size_t value_lds = 0, grad_lds = 0, prep_lds = 0;
     WsLayout ws;
     int device = 0;
     // diagnostics: per-phase HIP events recorded by srwcr_grad while profiling is on
@@ -99,7 +99,7 @@ struct srwcr_plan {
 };
 
 namespace {
-constexpr int kPhases = 5;            // zero, value, finalise, gradient, gradient output
+constexpr int kPhases = 6;            // zero, warp, value, finalise, gradient, gradient output
 constexpr size_t kProfCalls = 4096;   // calls recorded per profiling session
 
 // record event `k` of the current profiled call (no-op when profiling is off)
@@ -232,10 +232,11 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         g.c1n = (g.xw - 1) / g.delta[0] + 5;
         {
             const int np_max = (g.xw - 1) / g.delta[0] + 2;
-            int scr = std::max(6 * g.c1n, std::max(64, 3 * kSlots * kWave + 12 * np_max));
+            int scr = std::max(64, 3 * kSlots * kWave + 12 * np_max);
             g.gscr = (scr + 3) / 4 * 4;
         }
         P->value_lds = value_lds_bytes(g);
+        P->prep_lds = prep_lds_bytes(g);
         if (P->value_lds > (size_t)max_lds) {
             st = fail(SRWCR_E_UNSUPPORTED, "value pass needs %zu B of LDS, device allows %d", P->value_lds, max_lds);
             goto bad;
@@ -345,6 +346,12 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         off = align_up(off, 256);
         w.alpha = off;
         off += (size_t)g.R * sizeof(float);
+        off = align_up(off, 256);
+        const size_t nvox = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
+        w.kt = off;
+        off = align_up(off + nvox * sizeof(PrepKT), 256);
+        w.dm = off;
+        off += 3 * nvox * sizeof(float);
         w.total = align_up(off, 256);
         g.ws = w;
         void *d;
@@ -427,7 +434,9 @@ static BatchArgs one_problem(const void *fixed, const void *moving, const float 
     return a;
 }
 
-static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, unsigned char *ws, hipStream_t s)
+// zero -> warp pass -> value pass -> finalise (phases 0..3 of the profile)
+static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, int with_grad, unsigned char *ws,
+                     hipStream_t s)
 {
     const Geom &g = P->g;
     double *moments = (double *)(ws + P->ws.moments);
@@ -435,11 +444,13 @@ static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, unsi
     prof_mark(P, 0, s);
     HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
     prof_mark(P, 1, s);
-    HIP_TRY(launch_value(P->geom_dev, g.fdt, g.mdt, dense, P->items, P->nitems, args, ws, P->value_lds, s),
-            "value launch");
+    HIP_TRY(launch_prep(P->geom_dev, g.mdt, dense, with_grad, P->items, P->nitems, args, ws, P->prep_lds, s),
+            "warp launch");
     prof_mark(P, 2, s);
-    HIP_TRY(launch_finalize(P->geom_dev, 1, g.R, args, ws, s), "finalize launch");
+    HIP_TRY(launch_value(P->geom_dev, g.fdt, P->items, P->nitems, args, ws, P->value_lds, s), "value launch");
     prof_mark(P, 3, s);
+    HIP_TRY(launch_finalize(P->geom_dev, 1, g.R, args, ws, s), "finalize launch");
+    prof_mark(P, 4, s);
     return SRWCR_OK;
 }
 
@@ -449,7 +460,7 @@ int srwcr_eval(const srwcr_plan *plan, const void *fixed, const void *moving, co
     int st = check_call(plan, fixed, moving, ffd, workspace, workspace_bytes);
     if (st) return st;
     if (!d_value) return fail(SRWCR_E_INVALID_ARG, "d_value is NULL");
-    return run_value(plan, one_problem(fixed, moving, ffd, d_value, nullptr), 0, (unsigned char *)workspace,
+    return run_value(plan, one_problem(fixed, moving, ffd, d_value, nullptr), 0, 0, (unsigned char *)workspace,
                      (hipStream_t)stream);
 }
 
@@ -459,7 +470,7 @@ int srwcr_eval_dense(const srwcr_plan *plan, const void *fixed, const void *movi
     int st = check_call(plan, fixed, moving, field, workspace, workspace_bytes);
     if (st) return st;
     if (!d_value) return fail(SRWCR_E_INVALID_ARG, "d_value is NULL");
-    return run_value(plan, one_problem(fixed, moving, field, d_value, nullptr), 1, (unsigned char *)workspace,
+    return run_value(plan, one_problem(fixed, moving, field, d_value, nullptr), 1, 0, (unsigned char *)workspace,
                      (hipStream_t)stream);
 }
 
@@ -472,16 +483,15 @@ int srwcr_grad(const srwcr_plan *plan, const void *fixed, const void *moving, co
     unsigned char *ws = (unsigned char *)workspace;
     hipStream_t s = (hipStream_t)stream;
     const BatchArgs args = one_problem(fixed, moving, ffd, d_value, d_grad);
-    st = run_value(plan, args, 0, ws, s);
+    st = run_value(plan, args, 0, 1, ws, s);
     if (st) return st;
     const Geom &g = plan->g;
-    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.mdt, g.role, 0, plan->items, plan->nitems, args, ws, plan->grad_lds,
-                        s),
+    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.role, 0, plan->items, plan->nitems, args, ws, plan->grad_lds, s),
             "gradient launch");
-    prof_mark(plan, 4, s);
+    prof_mark(plan, 5, s);
     const size_t n = 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2];
     HIP_TRY(launch_grad_out(plan->geom_dev, 1, n, args, ws, s), "gradient output launch");
-    prof_mark(plan, 5, s);
+    prof_mark(plan, 6, s);
     if (plan->profiling && (size_t)(plan->prof_calls + 1) * (kPhases + 1) <= plan->ev_pool.size()) ++plan->prof_calls;
     return SRWCR_OK;
 }
@@ -495,11 +505,10 @@ int srwcr_grad_dense(const srwcr_plan *plan, const void *fixed, const void *movi
     unsigned char *ws = (unsigned char *)workspace;
     hipStream_t s = (hipStream_t)stream;
     const BatchArgs args = one_problem(fixed, moving, field, d_value, d_grad);
-    st = run_value(plan, args, 1, ws, s);
+    st = run_value(plan, args, 1, 1, ws, s);
     if (st) return st;
     const Geom &g = plan->g;
-    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.mdt, g.role, 1, plan->items, plan->nitems, args, ws, plan->grad_lds,
-                        s),
+    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.role, 1, plan->items, plan->nitems, args, ws, plan->grad_lds, s),
             "gradient launch");
     return SRWCR_OK;
 }
@@ -523,8 +532,10 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
     const size_t nzero = (plan->ws.counter + sizeof(double) - plan->ws.moments) / sizeof(double);
     HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
     const Geom &g = plan->g;
-    HIP_TRY(launch_value(plan->geom_dev, g.fdt, g.mdt, 0, plan->items, plan->nitems,
-                         one_problem(fixed, moving, ffd, nullptr, nullptr), ws, plan->value_lds, s),
+    const BatchArgs args = one_problem(fixed, moving, ffd, nullptr, nullptr);
+    HIP_TRY(launch_prep(plan->geom_dev, g.mdt, 0, 0, plan->items, plan->nitems, args, ws, plan->prep_lds, s),
+            "warp launch");
+    HIP_TRY(launch_value(plan->geom_dev, g.fdt, plan->items, plan->nitems, args, ws, plan->value_lds, s),
             "value launch");
     const size_t bytes = (size_t)plan->g.R * plan->g.nb * 3 * sizeof(double);
     HIP_TRY(hipMemcpyAsync(d_moments, moments, bytes, hipMemcpyDeviceToDevice, s), "moments copy");
@@ -552,7 +563,7 @@ int srwcr_profile(const srwcr_plan *plan, int32_t enable)
     return SRWCR_OK;
 }
 
-int srwcr_profile_read(const srwcr_plan *plan, double ms[5], int32_t *calls)
+int srwcr_profile_read(const srwcr_plan *plan, double ms[6], int32_t *calls)
 {
     if (!plan || !ms) return fail(SRWCR_E_INVALID_ARG, "NULL argument");
     for (int k = 0; k < kPhases; ++k) ms[k] = 0.0;
@@ -577,7 +588,7 @@ struct srwcr_batch {
     Geom *geoms_dev = nullptr;
     WorkItem *items_dev = nullptr;
     int nitems = 0;
-    size_t value_lds = 0, grad_lds = 0, ws_total = 0, zero_bytes = 0, max_params = 0;
+    size_t value_lds = 0, grad_lds = 0, prep_lds = 0, ws_total = 0, zero_bytes = 0, max_params = 0;
     int max_regions = 0;
 };
 
@@ -626,6 +637,7 @@ int srwcr_batch_create(int32_t n, const srwcr_plan *const *plans, srwcr_batch **
         b->max_regions = std::max(b->max_regions, g.R);
         b->max_params = std::max(b->max_params, 3 * ncell);
         b->value_lds = std::max(b->value_lds, plans[p]->value_lds);
+        b->prep_lds = std::max(b->prep_lds, plans[p]->prep_lds);
         b->grad_lds = std::max(b->grad_lds, plans[p]->grad_lds);
     }
     b->zero_bytes = off;
@@ -638,6 +650,11 @@ int srwcr_batch_create(int32_t n, const srwcr_plan *const *plans, srwcr_batch **
         off = align_up(off + (size_t)g.R * g.nb * 4 * sizeof(float), 256);
         w.alpha = off;
         off = align_up(off + (size_t)g.R * sizeof(float), 256);
+        const size_t nvox = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
+        w.kt = off;
+        off = align_up(off + nvox * sizeof(PrepKT), 256);
+        w.dm = off;
+        off = align_up(off + 3 * nvox * sizeof(float), 256);
         w.total = 0;
     }
     b->ws_total = off;
@@ -686,10 +703,10 @@ int srwcr_grad_batched(const srwcr_batch *b, const srwcr_batch_item *items, void
     unsigned char *ws = (unsigned char *)workspace;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_zero((double *)ws, b->zero_bytes / sizeof(double), s), "zero launch");
-    HIP_TRY(launch_value(b->geoms_dev, b->fdt, b->mdt, 0, b->items_dev, b->nitems, args, ws, b->value_lds, s),
-            "value launch");
+    HIP_TRY(launch_prep(b->geoms_dev, b->mdt, 0, 1, b->items_dev, b->nitems, args, ws, b->prep_lds, s), "warp launch");
+    HIP_TRY(launch_value(b->geoms_dev, b->fdt, b->items_dev, b->nitems, args, ws, b->value_lds, s), "value launch");
     HIP_TRY(launch_finalize(b->geoms_dev, n, b->max_regions, args, ws, s), "finalize launch");
-    HIP_TRY(launch_grad(b->geoms_dev, b->fdt, b->mdt, b->role, 0, b->items_dev, b->nitems, args, ws, b->grad_lds, s),
+    HIP_TRY(launch_grad(b->geoms_dev, b->fdt, b->role, 0, b->items_dev, b->nitems, args, ws, b->grad_lds, s),
             "gradient launch");
     HIP_TRY(launch_grad_out(b->geoms_dev, n, b->max_params, args, ws, s), "gradient output launch");
     return SRWCR_OK;

@@ -39,7 +39,16 @@ struct WsLayout {
     size_t alpha;      // float  [R]          role B: CR_r / (sigma_r^2 Z)
     size_t grad;       // double [3][nc]      gradient accumulators
     size_t counter;    // unsigned            finalise ticket
+    size_t kt;         // PrepKT [nvox]       warped moving bin and in-bin position per fixed voxel
+    size_t dm;         // float  [3][nvox]    dM/dy at the warped position (gradient calls)
     size_t total;
+};
+
+// One fixed voxel's warped moving sample s, as the value and gradient passes
+// use it: bin k = min(floor(s), L - 1) decided in FP64, t = s - k in FP32.
+struct PrepKT {
+    float t;
+    int k;
 };
 
 // Per-call device pointers of one problem, passed by value in the kernel
@@ -81,7 +90,7 @@ struct Geom {
     const double *mv_frac[3];  // (x + 1/2) M / N - 1/2 - base
     double ratio_d[3];         // nm / nf per axis
     int xw;                    // x-width of the work items (64 or 128 voxels)
-    int c1n;                   // FFD x-nodes an item row touches at most: (xw - 1) / delta + 5
+    int c1n;                   // FFD x-nodes an item row touches at most: (xw - 1) / delta + 5 (warp pass)
     int gscr;                  // floats of per-wave scratch in the gradient pass
     WsLayout ws;               // this problem's slots in the workspace of a launch
 };
@@ -92,11 +101,13 @@ hipError_t launch_zero(double *p, size_t n, hipStream_t s);
 hipError_t launch_normalize(const float *in, int64_t n, float lo, float scale, float L, void *out, int dt,
                             hipStream_t s);
 hipError_t launch_minmax(const float *in, int64_t n, float *partial, int nblocks, hipStream_t s);
-hipError_t launch_value(const Geom *geoms, int fdt, int mdt, int dense, const WorkItem *items, int nitems,
-                        const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s);
+hipError_t launch_prep(const Geom *geoms, int mdt, int dense, int with_grad, const WorkItem *items, int nitems,
+                       const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s);
+hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *items, int nitems, const BatchArgs &args,
+                        unsigned char *ws, size_t lds_bytes, hipStream_t s);
 hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const BatchArgs &args, unsigned char *ws,
                            hipStream_t s);
-hipError_t launch_grad(const Geom *geoms, int fdt, int mdt, int role, int dense, const WorkItem *items, int nitems,
+hipError_t launch_grad(const Geom *geoms, int fdt, int role, int dense, const WorkItem *items, int nitems,
                        const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s);
 hipError_t launch_grad_out(const Geom *geoms, int nprob, size_t max_params, const BatchArgs &args, unsigned char *ws,
                            hipStream_t s);
@@ -104,6 +115,7 @@ hipError_t launch_warp(const Geom &g, const void *moving, const float *ffd, floa
 hipError_t launch_downsample(const float *in, int nx, int ny, int nz, float *out, int ox, int oy, int oz,
                              hipStream_t s);
 hipError_t prepare_kernels();   // once per device: LDS limits of the value and gradient kernels
+size_t prep_lds_bytes(const Geom &g);
 size_t value_lds_bytes(const Geom &g);
 size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz);
 

@@ -48,6 +48,72 @@ __device__ __forceinline__ float ld_int(const void *p, size_t i)
     }
 }
 
+// Read of a per-axis table through a global-address-space pointer.  The
+// tables are reached through generic pointers held in Geom, which the
+// compiler would load with FLAT instructions; waiting for a FLAT load also
+// waits for every pending LDS operation of the wave (FLAT may address LDS),
+// so each row would stall until the previous row's LDS atomics drained.
+template <typename T>
+__device__ __forceinline__ T gld(const T *p, size_t i)
+{
+    return ((const __attribute__((address_space(1))) T *)p)[i];
+}
+__device__ __forceinline__ float4 gld(const float4 *p, size_t i)
+{
+    const __attribute__((address_space(1))) float *q = (const __attribute__((address_space(1))) float *)p + 4 * i;
+    return make_float4(q[0], q[1], q[2], q[3]);
+}
+__device__ __forceinline__ double4 gld(const double4 *p, size_t i)
+{
+    const __attribute__((address_space(1))) double *q = (const __attribute__((address_space(1))) double *)p + 4 * i;
+    return make_double4(q[0], q[1], q[2], q[3]);
+}
+
+// Per-row values that are the same for the whole wave, fetched with vector
+// loads by a few lanes and broadcast with readlane.  As scalar loads they
+// would share the LDS wait counter, and waiting for them would also wait for
+// the wave's pending LDS atomics.
+__device__ __forceinline__ float bcast(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ __forceinline__ int bcast(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// The 4 + 4 spatial weights of rows y and z (eq 8).  Table pointers are
+// passed in (hoisted out of the row loops, where the compiler would reload
+// them from Geom with scalar loads).
+__device__ __forceinline__ void row_sp_weights(const float4 *spw_y, const float4 *spw_z, int y, int z, int lane,
+                                               float (&wy)[4], float (&wz)[4])
+{
+    const float *ty = reinterpret_cast<const float *>(spw_y), *tz = reinterpret_cast<const float *>(spw_z);
+    float v = 0.0f;
+    if (lane < 4) v = gld(ty, 4 * (size_t)y + lane);
+    else if (lane < 8) v = gld(tz, 4 * (size_t)z + lane - 4);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        wy[j] = bcast(v, j);
+        wz[j] = bcast(v, 4 + j);
+    }
+}
+
+// FFD cells and weights of rows y and z (eq 17), the weights rounded to FP32.
+__device__ __forceinline__ void row_ffd_weights(const double4 *fw_y, const double4 *fw_z, const int *fp_y,
+                                                const int *fp_z, int y, int z, int lane, int &py, int &pz,
+                                                float (&by)[4], float (&bz)[4])
+{
+    const double *ty = reinterpret_cast<const double *>(fw_y), *tz = reinterpret_cast<const double *>(fw_z);
+    float v = 0.0f;
+    int c = 0;
+    if (lane < 4) v = (float)gld(ty, 4 * (size_t)y + lane);
+    else if (lane < 8) v = (float)gld(tz, 4 * (size_t)z + lane - 4);
+    else if (lane == 8) c = gld(fp_y, y);
+    else if (lane == 9) c = gld(fp_z, z);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        by[j] = bcast(v, j);
+        bz[j] = bcast(v, 4 + j);
+    }
+    py = bcast(c, 8);
+    pz = bcast(c, 9);
+}
+
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -150,9 +216,9 @@ __device__ __forceinline__ float parzen_dw0(float t) { return (t < 0.5f) ? -0.1f
 __device__ __forceinline__ void ffd_row(const Geom &g, const float *__restrict__ ffd, int xs, int xe, int y, int z,
                                         int xc, double *c1, int lane, double u[3])
 {
-    const int py = g.ffd_p[1][y], pz = g.ffd_p[2][z];
-    const double4 by = g.ffd_w[1][y], bz = g.ffd_w[2][z];
-    const int px_lo = g.ffd_p[0][xs], px_hi = g.ffd_p[0][xe - 1];
+    const int py = gld(g.ffd_p[1], y), pz = gld(g.ffd_p[2], z);
+    const double4 by = gld(g.ffd_w[1], y), bz = gld(g.ffd_w[2], z);
+    const int px_lo = gld(g.ffd_p[0], xs), px_hi = gld(g.ffd_p[0], xe - 1);
     const int nn = px_hi - px_lo + 4;
     const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
     const double wy[4] = {by.x, by.y, by.z, by.w}, wz[4] = {bz.x, bz.y, bz.z, bz.w};
@@ -170,8 +236,8 @@ __device__ __forceinline__ void ffd_row(const Geom &g, const float *__restrict__
         c1[e * kMaxNodeSeg + n] = acc;
     }
     wave_sync();
-    const int px = g.ffd_p[0][xc] - px_lo;
-    const double4 bx = g.ffd_w[0][xc];
+    const int px = gld(g.ffd_p[0], xc) - px_lo;
+    const double4 bx = gld(g.ffd_w[0], xc);
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         const double *c = c1 + e * kMaxNodeSeg + px;
@@ -186,9 +252,9 @@ __device__ __forceinline__ void ffd_row(const Geom &g, const float *__restrict__
 __device__ __forceinline__ int ffd_c1(const Geom &g, const float *__restrict__ ffd, int xs, int xe, int y, int z,
                                       double *c1, int lane)
 {
-    const int py = g.ffd_p[1][y], pz = g.ffd_p[2][z];
-    const double4 by = g.ffd_w[1][y], bz = g.ffd_w[2][z];
-    const int px_lo = g.ffd_p[0][xs], px_hi = g.ffd_p[0][xe - 1];
+    const int py = gld(g.ffd_p[1], y), pz = gld(g.ffd_p[2], z);
+    const double4 by = gld(g.ffd_w[1], y), bz = gld(g.ffd_w[2], z);
+    const int px_lo = gld(g.ffd_p[0], xs), px_hi = gld(g.ffd_p[0], xe - 1);
     const int nn = px_hi - px_lo + 4;
     const unsigned sy = (unsigned)g.nc[0], sz = (unsigned)g.nc[0] * g.nc[1], ncell = sz * g.nc[2];
     const double wy[4] = {by.x, by.y, by.z, by.w}, wz[4] = {bz.x, bz.y, bz.z, bz.w};
@@ -211,8 +277,8 @@ __device__ __forceinline__ int ffd_c1(const Geom &g, const float *__restrict__ f
 // Displacement of voxel xc from the row coefficients (four x weights).
 __device__ __forceinline__ void ffd_u(const Geom &g, const double *c1, int px_lo, int xc, double u[3])
 {
-    const int px = g.ffd_p[0][xc] - px_lo;
-    const double4 bx = g.ffd_w[0][xc];
+    const int px = gld(g.ffd_p[0], xc) - px_lo;
+    const double4 bx = gld(g.ffd_w[0], xc);
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         const double *c = c1 + e * g.c1n + px;
@@ -251,8 +317,8 @@ __device__ __forceinline__ double sample_moving(const Geom &g, const void *__res
             b = coord[e];
             t = u[e];
         } else {
-            b = g.mv_base[e][coord[e]];
-            t = fma(u[e], g.ratio_d[e], g.mv_frac[e][coord[e]]);
+            b = gld(g.mv_base[e], coord[e]);
+            t = fma(u[e], g.ratio_d[e], gld(g.mv_frac[e], coord[e]));
         }
         const double ft = floor(t);
         int i = b + (int)ft;
@@ -288,17 +354,11 @@ __device__ __forceinline__ double sample_moving(const Geom &g, const void *__res
     return val;
 }
 
-// Parzen taps of a warped FP64 sample: the bin is decided in FP64, the
-// in-bin position is then rounded to FP32.
-__device__ __forceinline__ void parzen_d(double s, int L, int &k, float &t, float &w0, float &w1)
+// Tap weights h(t), 1 - h(t) of an in-bin position t (eq 5), in FP32.
+__device__ __forceinline__ void parzen_w(float t, float &w0, float &w1)
 {
-    int kk = (int)s;                         // s >= 0
-    if (kk > L - 1) kk = L - 1;
-    const float tt = (float)(s - (double)kk);
-    float w = (tt < 0.5f) ? 1.0f - tt * (0.1f + 1.8f * tt) : 1.9f - tt * (3.7f - 1.8f * tt);
+    float w = (t < 0.5f) ? 1.0f - t * (0.1f + 1.8f * t) : 1.9f - t * (3.7f - 1.8f * t);
     w = fminf(fmaxf(w, 0.0f), 1.0f);
-    k = kk;
-    t = tt;
     w0 = w;
     w1 = 1.0f - w;
 }
@@ -388,6 +448,79 @@ hipError_t launch_minmax(const float *in, int64_t n, float *partial, int nblocks
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------- warp pass
+// The warp T (FFD of eq 17, or x + u(x) for a dense field) and the trilinear
+// sample of the moving image, once per call, in FP64: per fixed voxel the
+// moving bin k = min(floor(s), L - 1) decided in FP64 and the in-bin position
+// t = s - k rounded to FP32, plus dM/dy (FP32) when a gradient follows.  The
+// value and gradient passes read these (coalesced) instead of repeating the
+// dependent FFD loads and gathers.  One wave per item row, as in those passes.
+size_t prep_lds_bytes(const Geom &g) { return (size_t)(kValueThreads / kWave) * 3 * g.c1n * sizeof(double); }
+
+template <int MDT, int DISP, int GRAD>
+__global__ void __launch_bounds__(kValueThreads)
+k_prep(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, BatchArgs args, unsigned char *ws)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const WorkItem it = items[blockIdx.x];
+    const Geom &g = geoms[it.prob];
+    const void *__restrict__ moving = args.p[it.prob].moving;
+    const float *__restrict__ ffd = args.p[it.prob].ffd;
+    PrepKT *__restrict__ kt = reinterpret_cast<PrepKT *>(ws + g.ws.kt);
+    float *__restrict__ dmo = reinterpret_cast<float *>(ws + g.ws.dm);
+    const int L = g.nb - 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwaves = blockDim.x >> 6;
+    double *c1 = reinterpret_cast<double *>(smem) + wave * 3 * g.c1n;
+    const size_t nv = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
+    const int ny = it.y1 - it.y0, nz = it.z1 - it.z0;
+    const int xs = it.x0, xe = it.x1;
+    for (int row = wave; row < ny * nz; row += nwaves) {
+        const int y = it.y0 + row % ny, z = it.z0 + row / ny;
+        int px_lo = 0;
+        if (DISP == 0) px_lo = ffd_c1(g, ffd, xs, xe, y, z, c1, lane);
+        wave_sync();
+        const size_t rowb = ((size_t)z * g.nf[1] + y) * g.nf[0];
+#pragma unroll
+        for (int sl = 0; sl < kSlots; ++sl) {
+            const int x = xs + sl * kWave + lane;
+            if (x < xe) {
+                double u[3], dm[3];
+                if (DISP == 0) ffd_u(g, c1, px_lo, x, u);
+                else dense_u(g, ffd, x, y, z, u);
+                double sm = sample_moving<MDT>(g, moving, x, y, z, u, GRAD ? dm : nullptr);
+                sm = fmin(fmax(sm, 0.0), (double)L);
+                int kk = (int)sm;                        // sm >= 0
+                if (kk > L - 1) kk = L - 1;
+                kt[rowb + x] = PrepKT{(float)(sm - (double)kk), kk};
+                if (GRAD) {
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) dmo[e * nv + rowb + x] = (float)dm[e];
+                }
+            }
+        }
+        wave_sync();                                     // c1 is rewritten by the next row
+    }
+}
+
+#define SRWCR_PREP(M, D, G)                                                                                  \
+    hipLaunchKernelGGL((k_prep<M, D, G>), dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args, ws)
+
+hipError_t launch_prep(const Geom *geoms, int mdt, int dense, int with_grad, const WorkItem *items, int nitems,
+                       const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+#define SRWCR_PREP_M(M)                                                                                      \
+    if (mdt == M) {                                                                                          \
+        if (dense) { if (with_grad) SRWCR_PREP(M, 1, 1); else SRWCR_PREP(M, 1, 0); }                         \
+        else { if (with_grad) SRWCR_PREP(M, 0, 1); else SRWCR_PREP(M, 0, 0); }                               \
+    }
+    SRWCR_PREP_M(0) SRWCR_PREP_M(1) SRWCR_PREP_M(2)
+#undef SRWCR_PREP_M
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ value pass
 // Item histogram layout: H[((a * 3 + m) * 5 + i) * kHS + jk] holds moment m of
 // A-bin a in region (i, j, k) of the item's 5 x 4 x 4 block, jk = 4 k + j.
@@ -397,10 +530,7 @@ hipError_t launch_minmax(const float *in, int64_t n, float *partial, int nblocks
 // atomic touches each bank at most twice.
 constexpr int kHS = 17;
 
-size_t value_lds_bytes(const Geom &g)
-{
-    return (size_t)g.nb * 3 * kXN * kHS * sizeof(double) + (size_t)(kValueThreads / kWave) * 3 * g.c1n * sizeof(double);
-}
+size_t value_lds_bytes(const Geom &g) { return (size_t)g.nb * 3 * kXN * kHS * sizeof(double); }
 
 // Wave-uniform minimum: butterfly inside each 16-lane row (DPP), then the
 // four row results through scalar reads.
@@ -471,8 +601,8 @@ __device__ __forceinline__ void value_window(double *H, int L, const int (&b)[kW
     }
 }
 
-// DISP 0: displacements are FFD coefficients (eq 17); DISP 1: a dense field.
-template <int FDT, int MDT, int DISP>
+// Reads the warp pass's per-voxel moving bins (k_prep) and the fixed image.
+template <int FDT>
 __global__ void __launch_bounds__(kValueThreads)
 k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, BatchArgs args, unsigned char *ws)
 {
@@ -480,16 +610,17 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batc
     const WorkItem it = items[blockIdx.x];
     const Geom &g = geoms[it.prob];
     const void *__restrict__ fixed = args.p[it.prob].fixed;
-    const void *__restrict__ moving = args.p[it.prob].moving;
-    const float *__restrict__ ffd = args.p[it.prob].ffd;
+    const PrepKT *__restrict__ kt = reinterpret_cast<const PrepKT *>(ws + g.ws.kt);
     double *__restrict__ moments = reinterpret_cast<double *>(ws + g.ws.moments);
+    const float4 *spw_x = g.sp_w[0], *spw_y = g.sp_w[1], *spw_z = g.sp_w[2];
+    const int *spc_x = g.sp_cell[0];
+    const int role = g.role, nfx = g.nf[0], nfy = g.nf[1];
     const int nb = g.nb, L = nb - 1;
     double *H = reinterpret_cast<double *>(smem);     // [nb][3][5][kHS], see kHS
     const int nH = nb * 3 * kXN * kHS;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
-    double *c1 = H + nH + wave * 3 * g.c1n;
 
     for (int i = threadIdx.x; i < nH; i += blockDim.x) H[i] = 0.0;
     __syncthreads();
@@ -498,9 +629,7 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batc
     const int xs = it.x0, xe = it.x1;                    // xe - xs <= 64 kSlots
     for (int row = wave; row < ny * nz; row += nwaves) {
         const int y = it.y0 + row % ny, z = it.z0 + row / ny;
-        int px_lo = 0;
-        if (DISP == 0) px_lo = ffd_c1(g, ffd, xs, xe, y, z, c1, lane);
-        wave_sync();
+        const size_t rowb = ((size_t)z * nfy + y) * nfx;
         VoxA v[kSlots];
         bool pend[kSlots];
 #pragma unroll
@@ -508,26 +637,23 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batc
             const int x = xs + sl * kWave + lane;
             pend[sl] = x < xe;
             const int xc = pend[sl] ? x : xe - 1;
-            double u[3];
-            if (DISP == 0) ffd_u(g, c1, px_lo, xc, u);
-            else dense_u(g, ffd, xc, y, z, u);
-            double sm = sample_moving<MDT>(g, moving, xc, y, z, u, nullptr);
-            sm = fmin(fmax(sm, 0.0), (double)L);
-            const float sf = ld_int<FDT>(fixed, ((size_t)z * g.nf[1] + y) * g.nf[0] + xc);
-            int kM, kF;
-            float tM, tF, m0w, m1w, f0w, f1w;
-            parzen_d(sm, L, kM, tM, m0w, m1w);
+            const PrepKT pk = kt[rowb + xc];
+            const float sf = ld_int<FDT>(fixed, rowb + xc);
+            int kF;
+            float tF, m0w, m1w, f0w, f1w;
+            const int kM = pk.k;
+            parzen_w(pk.t, m0w, m1w);
             parzen(sf, L, kF, tF, f0w, f1w);
-            const int kB = g.role ? kM : kF;
-            const float b1w = g.role ? m1w : f1w;
-            v[sl].k = pend[sl] ? (g.role ? kF : kM) : -8;
-            v[sl].a0 = g.role ? f0w : m0w;
-            v[sl].a1 = g.role ? f1w : m1w;
+            const int kB = role ? kM : kF;
+            const float b1w = role ? m1w : f1w;
+            v[sl].k = pend[sl] ? (role ? kF : kM) : -8;
+            v[sl].a0 = role ? f0w : m0w;
+            v[sl].a1 = role ? f1w : m1w;
             const float m1 = (float)kB + b1w;
             const float m2 = fmaf((float)(2 * kB + 1), b1w, (float)(kB * kB));
             // x weights on the item's 5 x-nodes (the voxel's cell is it.cx or it.cx + 1)
-            const float4 wx4 = g.sp_w[0][xc];
-            const int ox = g.sp_cell[0][xc] - it.cx;
+            const float4 wx4 = gld(spw_x, xc);
+            const int ox = gld(spc_x, xc) - it.cx;
             const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
 #pragma unroll
             for (int n = 0; n < kXN; ++n) {
@@ -537,9 +663,8 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batc
                 v[sl].wxv[3 * n + 2] = wn * m2;
             }
         }
-        wave_sync();                                   // c1 is rewritten by the next row
-        const float4 wy4 = g.sp_w[1][y], wz4 = g.sp_w[2][z];
-        const float wyv[4] = {wy4.x, wy4.y, wy4.z, wy4.w}, wzv[4] = {wz4.x, wz4.y, wz4.z, wz4.w};
+        float wyv[4], wzv[4];
+        row_sp_weights(spw_y, spw_z, y, z, lane, wyv, wzv);
         float wyz[16];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -578,19 +703,6 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batc
     }
 }
 
-#define SRWCR_DISPATCH_DT(KERNEL, FDT_V, MDT_V, D, ...)                                                \
-    do {                                                                                                 \
-        if ((FDT_V) == 0 && (MDT_V) == 0) hipLaunchKernelGGL((KERNEL<0, 0, D>), __VA_ARGS__);            \
-        else if ((FDT_V) == 0 && (MDT_V) == 1) hipLaunchKernelGGL((KERNEL<0, 1, D>), __VA_ARGS__);       \
-        else if ((FDT_V) == 0 && (MDT_V) == 2) hipLaunchKernelGGL((KERNEL<0, 2, D>), __VA_ARGS__);       \
-        else if ((FDT_V) == 1 && (MDT_V) == 0) hipLaunchKernelGGL((KERNEL<1, 0, D>), __VA_ARGS__);       \
-        else if ((FDT_V) == 1 && (MDT_V) == 1) hipLaunchKernelGGL((KERNEL<1, 1, D>), __VA_ARGS__);       \
-        else if ((FDT_V) == 1 && (MDT_V) == 2) hipLaunchKernelGGL((KERNEL<1, 2, D>), __VA_ARGS__);       \
-        else if ((FDT_V) == 2 && (MDT_V) == 0) hipLaunchKernelGGL((KERNEL<2, 0, D>), __VA_ARGS__);       \
-        else if ((FDT_V) == 2 && (MDT_V) == 1) hipLaunchKernelGGL((KERNEL<2, 1, D>), __VA_ARGS__);       \
-        else hipLaunchKernelGGL((KERNEL<2, 2, D>), __VA_ARGS__);                                        \
-    } while (0)
-
 template <typename F>
 static hipError_t set_lds(F *kernel, size_t bytes)
 {
@@ -598,16 +710,13 @@ static hipError_t set_lds(F *kernel, size_t bytes)
                                (int)bytes);
 }
 
-hipError_t launch_value(const Geom *geoms, int fdt, int mdt, int dense, const WorkItem *items, int nitems,
-                        const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s)
+hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *items, int nitems, const BatchArgs &args,
+                        unsigned char *ws, size_t lds_bytes, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
-    if (dense)
-        SRWCR_DISPATCH_DT(k_value, fdt, mdt, 1, dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args,
-                          ws);
-    else
-        SRWCR_DISPATCH_DT(k_value, fdt, mdt, 0, dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args,
-                          ws);
+    if (fdt == 0) hipLaunchKernelGGL((k_value<0>), dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args, ws);
+    else if (fdt == 1) hipLaunchKernelGGL((k_value<1>), dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args, ws);
+    else hipLaunchKernelGGL((k_value<2>), dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args, ws);
     return hipGetLastError();
 }
 
@@ -736,7 +845,7 @@ struct VoxG {
 
 // DISP 0: scatter dD/dT to the FFD nodes (eq 17) into the workspace
 // accumulators; DISP 1: write dD/du(x) of a dense field to args.p[].grad.
-template <int FDT, int MDT, int ROLE, int DISP>
+template <int FDT, int ROLE, int DISP>
 __global__ void __launch_bounds__(kGradThreads)
 k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, BatchArgs args, unsigned char *ws)
 {
@@ -744,11 +853,17 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     const WorkItem it = items[blockIdx.x];
     const Geom &g = geoms[it.prob];
     const void *__restrict__ fixed = args.p[it.prob].fixed;
-    const void *__restrict__ moving = args.p[it.prob].moving;
-    const float *__restrict__ ffd = args.p[it.prob].ffd;
+    const PrepKT *__restrict__ kt = reinterpret_cast<const PrepKT *>(ws + g.ws.kt);
+    const float *__restrict__ dmi = reinterpret_cast<const float *>(ws + g.ws.dm);
+    const size_t nvox = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
     const float *__restrict__ tables = reinterpret_cast<const float *>(ws + g.ws.tables);
     const float *__restrict__ alpha = reinterpret_cast<const float *>(ws + g.ws.alpha);
     double *__restrict__ grad = reinterpret_cast<double *>(ws + g.ws.grad);
+    const float4 *spw_x = g.sp_w[0], *spw_y = g.sp_w[1], *spw_z = g.sp_w[2];
+    const int *spc_x = g.sp_cell[0], *fp_x = g.ffd_p[0], *fp_y = g.ffd_p[1], *fp_z = g.ffd_p[2];
+    const double4 *fw_y = g.ffd_w[1], *fw_z = g.ffd_w[2];
+    const int nfx = g.nf[0], nfy = g.nf[1], dx = g.delta[0];
+    const float ratio[3] = {g.ratio[0], g.ratio[1], g.ratio[2]};
     const int nb = g.nb, L = nb - 1, ts = tab_stride(nb);
     const int nG = it.gnx * it.gny * it.gnz * 3;
     float4 *bxw = reinterpret_cast<float4 *>(smem);                     // FFD x weights of the item's x range
@@ -763,7 +878,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     if (DISP == 0)
         for (int i = threadIdx.x; i < nG; i += blockDim.x) G[i] = 0.0;
     for (int i = threadIdx.x; DISP == 0 && i < it.x1 - it.x0; i += blockDim.x) {
-        const double4 b = g.ffd_w[0][it.x0 + i];
+        const double4 b = gld(g.ffd_w[0], it.x0 + i);
         bxw[i] = make_float4((float)b.x, (float)b.y, (float)b.z, (float)b.w);
     }
     for (int i = threadIdx.x; i < kNReg * nb; i += blockDim.x) {
@@ -789,10 +904,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     const int xs = it.x0, xe = it.x1;
     for (int row = wave; row < ny * nz; row += nwaves) {
         const int y = it.y0 + row % ny, z = it.z0 + row / ny;
-        double *c1 = reinterpret_cast<double *>(scr);
-        int px_lo = 0;
-        if (DISP == 0) px_lo = ffd_c1(g, ffd, xs, xe, y, z, c1, lane);
-        wave_sync();
+        const size_t rowb = ((size_t)z * nfy + y) * nfx;
         VoxG v[kSlots];
         bool pend[kSlots];
 #pragma unroll
@@ -800,15 +912,13 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             const int x = xs + sl * kWave + lane;
             pend[sl] = x < xe;
             const int xc = pend[sl] ? x : xe - 1;
-            double u[3], dm[3];
-            if (DISP == 0) ffd_u(g, c1, px_lo, xc, u);
-            else dense_u(g, ffd, xc, y, z, u);
-            double sm = sample_moving<MDT>(g, moving, xc, y, z, u, dm);
-            sm = fmin(fmax(sm, 0.0), (double)L);
-            const float sf = ld_int<FDT>(fixed, ((size_t)z * g.nf[1] + y) * g.nf[0] + xc);
-            int kM, kF;
-            float tM, tF, m0w, m1w, f0w, f1w;
-            parzen_d(sm, L, kM, tM, m0w, m1w);
+            const PrepKT pk = kt[rowb + xc];
+            const float sf = ld_int<FDT>(fixed, rowb + xc);
+            int kF;
+            float tF, m0w, m1w, f0w, f1w;
+            const int kM = pk.k;
+            const float tM = pk.t;
+            parzen_w(tM, m0w, m1w);
             parzen(sf, L, kF, tF, f0w, f1w);
             v[sl].kA = ROLE ? kF : kM;
             v[sl].kB = ROLE ? kM : kF;
@@ -817,17 +927,16 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             v[sl].a0 = ROLE ? f0w : m0w;
             v[sl].a1 = ROLE ? f1w : m1w;
             v[sl].m1 = (float)v[sl].kB + (ROLE ? m1w : f1w);
-            const float4 wx4 = g.sp_w[0][xc];
-            const int ox = g.sp_cell[0][xc] - it.cx;
+            const float4 wx4 = gld(spw_x, xc);
+            const int ox = gld(spc_x, xc) - it.cx;
             const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
 #pragma unroll
             for (int n = 0; n < kXN; ++n) v[sl].wx5[n] = (n - ox >= 0 && n - ox < 4) ? wl[(n - ox) & 3] : 0.0f;
 #pragma unroll
-            for (int e = 0; e < 3; ++e) v[sl].dm[e] = (float)dm[e];
+            for (int e = 0; e < 3; ++e) v[sl].dm[e] = dmi[e * nvox + rowb + xc];
         }
-        wave_sync();                                   // scratch is reused below
-        const float4 wy4 = g.sp_w[1][y], wz4 = g.sp_w[2][z];
-        const float wyv[4] = {wy4.x, wy4.y, wy4.z, wy4.w}, wzv[4] = {wz4.x, wz4.y, wz4.z, wz4.w};
+        float wyv[4], wzv[4];
+        row_sp_weights(spw_y, spw_z, y, z, lane, wyv, wzv);
 
         // dD/ds_M: the region tables interpolated by w(r, x) = wx wy wz through
         // window row tables T_row[i][slot] = sum_jk wy_j wz_k T[(i, j, k)][kmin + slot]
@@ -929,21 +1038,21 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         // q = dD/ds * dM/dy * dy/dT  (eq 16): a dense field's gradient is q itself
         if (DISP == 1) {
             float *out = args.p[it.prob].grad;
-            const size_t nv = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
-            const size_t rowb = ((size_t)z * g.nf[1] + y) * g.nf[0];
 #pragma unroll
             for (int sl = 0; sl < kSlots; ++sl)
                 if (xs + sl * kWave + lane < xe) {         // the windows have cleared pend[]
                     const size_t vi = rowb + xs + sl * kWave + lane;
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) out[e * nv + vi] = gs[sl] * v[sl].dm[e] * g.ratio[e];
+                    for (int e = 0; e < 3; ++e) out[e * nvox + vi] = gs[sl] * v[sl].dm[e] * ratio[e];
                 }
             continue;
         }
         // ... then the scatter to the control points (eq 17): per FFD cell p of
         // the row the four moments M[p][l][e] = sum_{x in p} beta_l(eta_x) q_e(x) ...
-        const int dx = g.delta[0];
-        const int px_hi = g.ffd_p[0][xe - 1];
+        int pxc = 0;                                                 // vector loads, see row_sp_weights
+        if (lane == 0) pxc = gld(fp_x, xs);
+        else if (lane == 1) pxc = gld(fp_x, xe - 1);
+        const int px_lo = bcast(pxc, 0), px_hi = bcast(pxc, 1);
         const int np = px_hi - px_lo + 1, nn = np + 3;
         float *qb = scr;                                             // [128][3]
         float *cm = scr + 3 * kSlots * kWave;                        // [np][4][3]
@@ -951,7 +1060,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         for (int sl = 0; sl < kSlots; ++sl)
 #pragma unroll
             for (int e = 0; e < 3; ++e)
-                qb[(sl * kWave + lane) * 3 + e] = gs[sl] * v[sl].dm[e] * g.ratio[e];
+                qb[(sl * kWave + lane) * 3 + e] = gs[sl] * v[sl].dm[e] * ratio[e];
         wave_sync();
         for (int t = lane; t < np * 3; t += kWave) {
             const int p = t / 3, e = t - 3 * p;
@@ -972,10 +1081,9 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         }
         wave_sync();
         // ... node sums R1[n][e] = sum_l M[n - l][l][e], then the 16 (y, z) node weights
-        const int py = g.ffd_p[1][y], pz = g.ffd_p[2][z];
-        const double4 by = g.ffd_w[1][y], bz = g.ffd_w[2][z];
-        const float byv[4] = {(float)by.x, (float)by.y, (float)by.z, (float)by.w};
-        const float bzv[4] = {(float)bz.x, (float)bz.y, (float)bz.z, (float)bz.w};
+        int py, pz;
+        float byv[4], bzv[4];
+        row_ffd_weights(fw_y, fw_z, fp_y, fp_z, y, z, lane, py, pz, byv, bzv);
         for (int t = lane; t < nn * 3; t += kWave) {
             const int n = t / 3, e = t - 3 * n;
             float r1 = 0.0f;
@@ -1011,26 +1119,17 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     }
 }
 
-hipError_t launch_grad(const Geom *geoms, int fdt, int mdt, int role, int dense, const WorkItem *items, int nitems,
+hipError_t launch_grad(const Geom *geoms, int fdt, int role, int dense, const WorkItem *items, int nitems,
                        const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
-#define SRWCR_GRAD_R(F, M, D)                                                                                  \
-    if (role)                                                                                                  \
-        hipLaunchKernelGGL((k_grad<F, M, 1, D>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, geoms, items,  \
-                           args, ws);                                                                          \
-    else                                                                                                       \
-        hipLaunchKernelGGL((k_grad<F, M, 0, D>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, geoms, items,  \
-                           args, ws);
-#define SRWCR_GRAD(F, M)                                                                                      \
-    if (fdt == F && mdt == M) {                                                                               \
-        if (dense) { SRWCR_GRAD_R(F, M, 1) }                                                                  \
-        else { SRWCR_GRAD_R(F, M, 0) }                                                                        \
-    }
-    SRWCR_GRAD(0, 0) SRWCR_GRAD(0, 1) SRWCR_GRAD(0, 2) SRWCR_GRAD(1, 0) SRWCR_GRAD(1, 1) SRWCR_GRAD(1, 2)
-    SRWCR_GRAD(2, 0) SRWCR_GRAD(2, 1) SRWCR_GRAD(2, 2)
+#define SRWCR_GRAD(F, R, D)                                                                                     \
+    if (fdt == F && role == R && dense == D)                                                                    \
+        hipLaunchKernelGGL((k_grad<F, R, D>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, geoms, items, args, ws);
+    SRWCR_GRAD(0, 0, 0) SRWCR_GRAD(0, 0, 1) SRWCR_GRAD(0, 1, 0) SRWCR_GRAD(0, 1, 1)
+    SRWCR_GRAD(1, 0, 0) SRWCR_GRAD(1, 0, 1) SRWCR_GRAD(1, 1, 0) SRWCR_GRAD(1, 1, 1)
+    SRWCR_GRAD(2, 0, 0) SRWCR_GRAD(2, 0, 1) SRWCR_GRAD(2, 1, 0) SRWCR_GRAD(2, 1, 1)
 #undef SRWCR_GRAD
-#undef SRWCR_GRAD_R
     return hipGetLastError();
 }
 
@@ -1047,15 +1146,20 @@ hipError_t prepare_kernels()
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return e;
     const size_t b = (size_t)max_lds;
-#define SRWCR_SET(F, M)                                                         \
-    if (e == hipSuccess) e = set_lds(k_value<F, M, 0>, b);                      \
-    if (e == hipSuccess) e = set_lds(k_value<F, M, 1>, b);                      \
-    if (e == hipSuccess) e = set_lds(k_grad<F, M, 0, 0>, b);                    \
-    if (e == hipSuccess) e = set_lds(k_grad<F, M, 1, 0>, b);                    \
-    if (e == hipSuccess) e = set_lds(k_grad<F, M, 0, 1>, b);                    \
-    if (e == hipSuccess) e = set_lds(k_grad<F, M, 1, 1>, b);
-    SRWCR_SET(0, 0) SRWCR_SET(0, 1) SRWCR_SET(0, 2) SRWCR_SET(1, 0) SRWCR_SET(1, 1) SRWCR_SET(1, 2)
-    SRWCR_SET(2, 0) SRWCR_SET(2, 1) SRWCR_SET(2, 2)
+#define SRWCR_SET(T)                                                                \
+    if (e == hipSuccess) e = set_lds(T<0>, b);                                      \
+    if (e == hipSuccess) e = set_lds(T<1>, b);                                      \
+    if (e == hipSuccess) e = set_lds(T<2>, b);
+    SRWCR_SET(k_value)
+#undef SRWCR_SET
+#define SRWCR_SET(A, B)                                                             \
+    if (e == hipSuccess) e = set_lds(k_grad<0, A, B>, b);                           \
+    if (e == hipSuccess) e = set_lds(k_grad<1, A, B>, b);                           \
+    if (e == hipSuccess) e = set_lds(k_grad<2, A, B>, b);                           \
+    if (e == hipSuccess) e = set_lds(k_prep<0, A, B>, b);                           \
+    if (e == hipSuccess) e = set_lds(k_prep<1, A, B>, b);                           \
+    if (e == hipSuccess) e = set_lds(k_prep<2, A, B>, b);
+    SRWCR_SET(0, 0) SRWCR_SET(0, 1) SRWCR_SET(1, 0) SRWCR_SET(1, 1)
 #undef SRWCR_SET
     if (e == hipSuccess && dev < 64) done[dev] = true;
     return e;
