@@ -85,9 +85,15 @@ struct srwcr_plan {
     Geom g;
     Geom *geom_dev = nullptr;     // g on the device (kernels read it through a one-problem array)
     std::vector<void *> dev_allocs;
-    WorkItem *items = nullptr;
+    WorkItem *items = nullptr;           // warp and gradient passes: boxes sized for the LDS node block
     std::vector<WorkItem> items_host;
     int nitems = 0;
+    WorkItem *vblocks = nullptr;         // value pass: whole region blocks, rows listed block by block
+    int *vrow = nullptr;                 // first row of each block, then the total
+    std::vector<WorkItem> vblocks_host;
+    std::vector<int> vrow_host;
+    int nvblocks = 0;
+    int nwg = 0;                         // persistent value-pass workgroups (one per compute unit)
     size_t value_lds = 0, grad_lds = 0, prep_lds = 0;
     WsLayout ws;
     int device = 0;
@@ -321,6 +327,39 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         }
         P->nitems = (int)items.size();
         P->items_host = items;
+        // value-pass blocks: an x-chunk by one spatial cell in y and z
+        {
+            std::vector<WorkItem> vb;
+            std::vector<int> vr(1, 0);
+            const auto xch = x_chunks(g.xw);
+            for (int cz = 0; cz < g.K[2] - 3; ++cz) {
+                if (lo[2][cz] < 0) continue;
+                for (int cy = 0; cy < g.K[1] - 3; ++cy) {
+                    if (lo[1][cy] < 0) continue;
+                    for (const auto &xr : xch) {
+                        WorkItem w{};
+                        w.x0 = xr.first; w.x1 = xr.second;
+                        w.y0 = lo[1][cy]; w.y1 = hi[1][cy];
+                        w.z0 = lo[2][cz]; w.z1 = hi[2][cz];
+                        w.cx = cells[0][w.x0]; w.cy = cy; w.cz = cz;
+                        vb.push_back(w);
+                        vr.push_back(vr.back() + (w.y1 - w.y0) * (w.z1 - w.z0));
+                    }
+                }
+            }
+            P->vblocks_host = vb;
+            P->vrow_host = vr;
+            P->nvblocks = (int)vb.size();
+            void *dv;
+            if ((st = upload(vb.data(), vb.size() * sizeof(WorkItem), &dv))) goto bad;
+            P->vblocks = (WorkItem *)dv;
+            if ((st = upload(vr.data(), vr.size() * sizeof(int), &dv))) goto bad;
+            P->vrow = (int *)dv;
+            int ncu = 0;
+            he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+            if (he != hipSuccess) { st = hip_fail(he, "hipDeviceGetAttribute(compute units)"); goto bad; }
+            P->nwg = std::max(1, std::min(ncu, vr.back()));
+        }
         void *d;
         if ((st = upload(items.data(), items.size() * sizeof(WorkItem), &d))) goto bad;
         P->items = (WorkItem *)d;
@@ -447,7 +486,8 @@ static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, int 
     HIP_TRY(launch_prep(P->geom_dev, g.mdt, dense, with_grad, P->items, P->nitems, args, ws, P->prep_lds, s),
             "warp launch");
     prof_mark(P, 2, s);
-    HIP_TRY(launch_value(P->geom_dev, g.fdt, P->items, P->nitems, args, ws, P->value_lds, s), "value launch");
+    HIP_TRY(launch_value(P->geom_dev, g.fdt, P->vblocks, P->vrow, P->nvblocks, P->nwg, args, ws, P->value_lds, s),
+            "value launch");
     prof_mark(P, 3, s);
     HIP_TRY(launch_finalize(P->geom_dev, 1, g.R, args, ws, s), "finalize launch");
     prof_mark(P, 4, s);
@@ -535,7 +575,8 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
     const BatchArgs args = one_problem(fixed, moving, ffd, nullptr, nullptr);
     HIP_TRY(launch_prep(plan->geom_dev, g.mdt, 0, 0, plan->items, plan->nitems, args, ws, plan->prep_lds, s),
             "warp launch");
-    HIP_TRY(launch_value(plan->geom_dev, g.fdt, plan->items, plan->nitems, args, ws, plan->value_lds, s),
+    HIP_TRY(launch_value(plan->geom_dev, g.fdt, plan->vblocks, plan->vrow, plan->nvblocks, plan->nwg, args, ws,
+                         plan->value_lds, s),
             "value launch");
     const size_t bytes = (size_t)plan->g.R * plan->g.nb * 3 * sizeof(double);
     HIP_TRY(hipMemcpyAsync(d_moments, moments, bytes, hipMemcpyDeviceToDevice, s), "moments copy");
@@ -588,6 +629,9 @@ struct srwcr_batch {
     Geom *geoms_dev = nullptr;
     WorkItem *items_dev = nullptr;
     int nitems = 0;
+    WorkItem *vblocks_dev = nullptr;
+    int *vrow_dev = nullptr;
+    int nvblocks = 0, nwg = 0;
     size_t value_lds = 0, grad_lds = 0, prep_lds = 0, ws_total = 0, zero_bytes = 0, max_params = 0;
     int max_regions = 0;
 };
@@ -597,6 +641,8 @@ void srwcr_batch_destroy(srwcr_batch *b)
     if (!b) return;
     if (b->geoms_dev) (void)hipFree(b->geoms_dev);
     if (b->items_dev) (void)hipFree(b->items_dev);
+    if (b->vblocks_dev) (void)hipFree(b->vblocks_dev);
+    if (b->vrow_dev) (void)hipFree(b->vrow_dev);
     delete b;
 }
 
@@ -668,11 +714,29 @@ int srwcr_batch_create(int32_t n, const srwcr_plan *const *plans, srwcr_batch **
     auto vox = [](const WorkItem &w) { return (long)(w.x1 - w.x0) * (w.y1 - w.y0) * (w.z1 - w.z0); };
     std::stable_sort(items.begin(), items.end(), [&](const WorkItem &a, const WorkItem &c) { return vox(a) > vox(c); });
     b->nitems = (int)items.size();
+    // value-pass blocks of every problem, one row list
+    std::vector<WorkItem> vb;
+    std::vector<int> vr(1, 0);
+    for (int p = 0; p < n; ++p)
+        for (size_t i = 0; i < plans[p]->vblocks_host.size(); ++i) {
+            WorkItem w = plans[p]->vblocks_host[i];
+            w.prob = p;
+            vb.push_back(w);
+            vr.push_back(vr.back() + (plans[p]->vrow_host[i + 1] - plans[p]->vrow_host[i]));
+        }
+    b->nvblocks = (int)vb.size();
+    int nwg_max = 0;
+    for (int p = 0; p < n; ++p) nwg_max = std::max(nwg_max, plans[p]->nwg);
+    b->nwg = std::max(1, std::min(nwg_max, vr.back()));
     hipError_t e = hipMalloc(&b->geoms_dev, n * sizeof(Geom));
     if (e == hipSuccess) e = hipMemcpy(b->geoms_dev, geoms.data(), n * sizeof(Geom), hipMemcpyHostToDevice);
     if (e == hipSuccess && !items.empty()) e = hipMalloc(&b->items_dev, items.size() * sizeof(WorkItem));
     if (e == hipSuccess && !items.empty())
         e = hipMemcpy(b->items_dev, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&b->vblocks_dev, vb.size() * sizeof(WorkItem));
+    if (e == hipSuccess) e = hipMemcpy(b->vblocks_dev, vb.data(), vb.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&b->vrow_dev, vr.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMemcpy(b->vrow_dev, vr.data(), vr.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         srwcr_batch_destroy(b);
         return hip_fail(e, "batch tables");
@@ -704,7 +768,9 @@ int srwcr_grad_batched(const srwcr_batch *b, const srwcr_batch_item *items, void
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_zero((double *)ws, b->zero_bytes / sizeof(double), s), "zero launch");
     HIP_TRY(launch_prep(b->geoms_dev, b->mdt, 0, 1, b->items_dev, b->nitems, args, ws, b->prep_lds, s), "warp launch");
-    HIP_TRY(launch_value(b->geoms_dev, b->fdt, b->items_dev, b->nitems, args, ws, b->value_lds, s), "value launch");
+    HIP_TRY(launch_value(b->geoms_dev, b->fdt, b->vblocks_dev, b->vrow_dev, b->nvblocks, b->nwg, args, ws,
+                         b->value_lds, s),
+            "value launch");
     HIP_TRY(launch_finalize(b->geoms_dev, n, b->max_regions, args, ws, s), "finalize launch");
     HIP_TRY(launch_grad(b->geoms_dev, b->fdt, b->role, 0, b->items_dev, b->nitems, args, ws, b->grad_lds, s),
             "gradient launch");

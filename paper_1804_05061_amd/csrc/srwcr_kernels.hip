@@ -601,105 +601,130 @@ __device__ __forceinline__ void value_window(double *H, int L, const int (&b)[kW
     }
 }
 
-// Reads the warp pass's per-voxel moving bins (k_prep) and the fixed image.
+// Value pass.  Schedule: one persistent workgroup per compute unit (the FP64
+// histogram of a 5 x 4 x 4 region block fills most of its LDS).  The item
+// rows of all region blocks (an x-chunk of at most two spatial cells by one
+// cell in y and z) form one list ordered by block; workgroup w takes rows
+// [w T / G, (w + 1) T / G) of the T rows, accumulates them in LDS and merges
+// the histogram into the global moments (FP64 atomics) only when its range
+// leaves a block, so that each block is flushed about once per workgroup that
+// touches it rather than once per small item.  The rows of one block are
+// dealt to the waves round-robin.  Reads the warp pass's per-voxel moving bins
+// (k_prep) and the fixed image.
 template <int FDT>
 __global__ void __launch_bounds__(kValueThreads)
-k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, BatchArgs args, unsigned char *ws)
+k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, const int *__restrict__ row_start,
+        int nblocks, int lds_doubles, BatchArgs args, unsigned char *ws)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const WorkItem it = items[blockIdx.x];
-    const Geom &g = geoms[it.prob];
-    const void *__restrict__ fixed = args.p[it.prob].fixed;
-    const PrepKT *__restrict__ kt = reinterpret_cast<const PrepKT *>(ws + g.ws.kt);
-    double *__restrict__ moments = reinterpret_cast<double *>(ws + g.ws.moments);
-    const float4 *spw_x = g.sp_w[0], *spw_y = g.sp_w[1], *spw_z = g.sp_w[2];
-    const int *spc_x = g.sp_cell[0];
-    const int role = g.role, nfx = g.nf[0], nfy = g.nf[1];
-    const int nb = g.nb, L = nb - 1;
     double *H = reinterpret_cast<double *>(smem);     // [nb][3][5][kHS], see kHS
-    const int nH = nb * 3 * kXN * kHS;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
+    const long total = row_start[nblocks];
+    long r0 = (long)blockIdx.x * total / gridDim.x;
+    const long r1 = (long)(blockIdx.x + 1) * total / gridDim.x;
+    int bi = 0;
+    while (bi + 1 < nblocks && row_start[bi + 1] <= r0) ++bi;
 
-    for (int i = threadIdx.x; i < nH; i += blockDim.x) H[i] = 0.0;
+    for (int i = threadIdx.x; i < lds_doubles; i += blockDim.x) H[i] = 0.0;
     __syncthreads();
 
-    const int ny = it.y1 - it.y0, nz = it.z1 - it.z0;
-    const int xs = it.x0, xe = it.x1;                    // xe - xs <= 64 kSlots
-    for (int row = wave; row < ny * nz; row += nwaves) {
-        const int y = it.y0 + row % ny, z = it.z0 + row / ny;
-        const size_t rowb = ((size_t)z * nfy + y) * nfx;
-        VoxA v[kSlots];
-        bool pend[kSlots];
+    while (r0 < r1) {
+        const WorkItem it = blocks[bi];
+        const long bstart = row_start[bi];
+        const long bend = min(r1, (long)row_start[bi + 1]);
+        const Geom &g = geoms[it.prob];
+        const void *__restrict__ fixed = args.p[it.prob].fixed;
+        const PrepKT *__restrict__ kt = reinterpret_cast<const PrepKT *>(ws + g.ws.kt);
+        double *__restrict__ moments = reinterpret_cast<double *>(ws + g.ws.moments);
+        const float4 *spw_x = g.sp_w[0], *spw_y = g.sp_w[1], *spw_z = g.sp_w[2];
+        const int *spc_x = g.sp_cell[0];
+        const int role = g.role, nfx = g.nf[0], nfy = g.nf[1];
+        const int nb = g.nb, L = nb - 1;
+        const int nH = nb * 3 * kXN * kHS;
+        const int ny = it.y1 - it.y0;
+        const int xs = it.x0, xe = it.x1;                // xe - xs <= 64 kSlots
+        for (long r = r0 + wave; r < bend; r += nwaves) {
+            const int row = (int)(r - bstart);
+            const int y = it.y0 + row % ny, z = it.z0 + row / ny;
+            const size_t rowb = ((size_t)z * nfy + y) * nfx;
+            VoxA v[kSlots];
+            bool pend[kSlots];
 #pragma unroll
-        for (int sl = 0; sl < kSlots; ++sl) {
-            const int x = xs + sl * kWave + lane;
-            pend[sl] = x < xe;
-            const int xc = pend[sl] ? x : xe - 1;
-            const PrepKT pk = kt[rowb + xc];
-            const float sf = ld_int<FDT>(fixed, rowb + xc);
-            int kF;
-            float tF, m0w, m1w, f0w, f1w;
-            const int kM = pk.k;
-            parzen_w(pk.t, m0w, m1w);
-            parzen(sf, L, kF, tF, f0w, f1w);
-            const int kB = role ? kM : kF;
-            const float b1w = role ? m1w : f1w;
-            v[sl].k = pend[sl] ? (role ? kF : kM) : -8;
-            v[sl].a0 = role ? f0w : m0w;
-            v[sl].a1 = role ? f1w : m1w;
-            const float m1 = (float)kB + b1w;
-            const float m2 = fmaf((float)(2 * kB + 1), b1w, (float)(kB * kB));
-            // x weights on the item's 5 x-nodes (the voxel's cell is it.cx or it.cx + 1)
-            const float4 wx4 = gld(spw_x, xc);
-            const int ox = gld(spc_x, xc) - it.cx;
-            const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
+            for (int sl = 0; sl < kSlots; ++sl) {
+                const int x = xs + sl * kWave + lane;
+                pend[sl] = x < xe;
+                const int xc = pend[sl] ? x : xe - 1;
+                const PrepKT pk = kt[rowb + xc];
+                const float sf = ld_int<FDT>(fixed, rowb + xc);
+                int kF;
+                float tF, m0w, m1w, f0w, f1w;
+                const int kM = pk.k;
+                parzen_w(pk.t, m0w, m1w);
+                parzen(sf, L, kF, tF, f0w, f1w);
+                const int kB = role ? kM : kF;
+                const float b1w = role ? m1w : f1w;
+                v[sl].k = pend[sl] ? (role ? kF : kM) : -8;
+                v[sl].a0 = role ? f0w : m0w;
+                v[sl].a1 = role ? f1w : m1w;
+                const float m1 = (float)kB + b1w;
+                const float m2 = fmaf((float)(2 * kB + 1), b1w, (float)(kB * kB));
+                // x weights on the item's 5 x-nodes (the voxel's cell is it.cx or it.cx + 1)
+                const float4 wx4 = gld(spw_x, xc);
+                const int ox = gld(spc_x, xc) - it.cx;
+                const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
 #pragma unroll
-            for (int n = 0; n < kXN; ++n) {
-                const float wn = (n - ox >= 0 && n - ox < 4) ? wl[(n - ox) & 3] : 0.0f;
-                v[sl].wxv[3 * n + 0] = wn;
-                v[sl].wxv[3 * n + 1] = wn * m1;
-                v[sl].wxv[3 * n + 2] = wn * m2;
+                for (int n = 0; n < kXN; ++n) {
+                    const float wn = (n - ox >= 0 && n - ox < 4) ? wl[(n - ox) & 3] : 0.0f;
+                    v[sl].wxv[3 * n + 0] = wn;
+                    v[sl].wxv[3 * n + 1] = wn * m1;
+                    v[sl].wxv[3 * n + 2] = wn * m2;
+                }
             }
-        }
-        float wyv[4], wzv[4];
-        row_sp_weights(spw_y, spw_z, y, z, lane, wyv, wzv);
-        float wyz[16];
+            float wyv[4], wzv[4];
+            row_sp_weights(spw_y, spw_z, y, z, lane, wyv, wzv);
+            float wyz[16];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+            for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) wyz[k * 4 + j] = wyv[j] * wzv[k];
+                for (int j = 0; j < 4; ++j) wyz[k * 4 + j] = wyv[j] * wzv[k];
 
-        // the A-bins the row's taps touch (a wave-uniform 64-bit set), four per window
-        unsigned long long mine = 0ull;
+            // the A-bins the row's taps touch (a wave-uniform 64-bit set), four per window
+            unsigned long long mine = 0ull;
 #pragma unroll
-        for (int sl = 0; sl < kSlots; ++sl)
-            if (pend[sl]) mine |= 3ull << v[sl].k;
-        unsigned long long bins = (unsigned long long)wave_or_dpp((unsigned)(mine >> 32)) << 32 |
-                                  wave_or_dpp((unsigned)mine);
-        while (bins != 0ull) {
-            int b[kWin];
+            for (int sl = 0; sl < kSlots; ++sl)
+                if (pend[sl]) mine |= 3ull << v[sl].k;
+            unsigned long long bins = (unsigned long long)wave_or_dpp((unsigned)(mine >> 32)) << 32 |
+                                      wave_or_dpp((unsigned)mine);
+            while (bins != 0ull) {
+                int b[kWin];
 #pragma unroll
-            for (int w = 0; w < kWin; ++w) {
-                b[w] = bins ? (int)__builtin_ctzll(bins) : 1 << 20;
-                bins &= bins - 1;
-            }
-            value_window(H, L, b, v, wyz, lane);
-        }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nH; e += blockDim.x) {
-        const double val = H[e];
-        const int idx = e / kHS, jk = e - idx * kHS;
-        if (val != 0.0 && jk < 16) {
-            const int am = idx / kXN, i = idx - am * kXN, a = am / 3, m = am - 3 * a;
-            const int j = jk & 3, k = jk >> 2;
-            if (it.cx + i < g.K[0]) {
-                const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
-                unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], val);
+                for (int w = 0; w < kWin; ++w) {
+                    b[w] = bins ? (int)__builtin_ctzll(bins) : 1 << 20;
+                    bins &= bins - 1;
+                }
+                value_window(H, L, b, v, wyz, lane);
             }
         }
+        __syncthreads();
+        // merge into the global moments, clearing the histogram for the next block
+        for (int e = threadIdx.x; e < nH; e += blockDim.x) {
+            const double val = H[e];
+            const int idx = e / kHS, jk = e - idx * kHS;
+            if (val != 0.0) {
+                H[e] = 0.0;
+                const int am = idx / kXN, i = idx - am * kXN, a = am / 3, m = am - 3 * a;
+                const int j = jk & 3, k = jk >> 2;
+                if (jk < 16 && it.cx + i < g.K[0]) {
+                    const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
+                    unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], val);
+                }
+            }
+        }
+        __syncthreads();
+        r0 = bend;
+        ++bi;
     }
 }
 
@@ -710,13 +735,18 @@ static hipError_t set_lds(F *kernel, size_t bytes)
                                (int)bytes);
 }
 
-hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *items, int nitems, const BatchArgs &args,
-                        unsigned char *ws, size_t lds_bytes, hipStream_t s)
+hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *blocks, const int *row_start, int nblocks,
+                        int nwg, const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s)
 {
-    if (nitems <= 0) return hipSuccess;
-    if (fdt == 0) hipLaunchKernelGGL((k_value<0>), dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args, ws);
-    else if (fdt == 1) hipLaunchKernelGGL((k_value<1>), dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args, ws);
-    else hipLaunchKernelGGL((k_value<2>), dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args, ws);
+    if (nblocks <= 0 || nwg <= 0) return hipSuccess;
+    const int ld = (int)(lds_bytes / sizeof(double));
+#define SRWCR_VAL(F) \
+    hipLaunchKernelGGL((k_value<F>), dim3(nwg), dim3(kValueThreads), lds_bytes, s, geoms, blocks, row_start, nblocks, ld, \
+                       args, ws)
+    if (fdt == 0) SRWCR_VAL(0);
+    else if (fdt == 1) SRWCR_VAL(1);
+    else SRWCR_VAL(2);
+#undef SRWCR_VAL
     return hipGetLastError();
 }
 
