@@ -238,7 +238,7 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         g.c1n = (g.xw - 1) / g.delta[0] + 5;
         {
             const int np_max = (g.xw - 1) / g.delta[0] + 2;
-            int scr = std::max(64, 3 * kSlots * kWave + 12 * np_max);
+            int scr = std::max(64 + kMaxBins * 3 * kXN, 3 * kSlots * kWave + 12 * np_max);
             g.gscr = (scr + 3) / 4 * 4;
         }
         P->value_lds = value_lds_bytes(g);

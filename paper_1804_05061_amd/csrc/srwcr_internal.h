@@ -12,8 +12,6 @@ constexpr int kWave = 64;         // CDNA wavefront width
 constexpr int kXN = 5;            // x-nodes of a work item (its x-range spans at most two spatial cells)
 constexpr int kNReg = kXN * 16;   // regions of a work item: 5 (x) x 4 (y) x 4 (z)
 constexpr int kWin = 4;           // bin slots of one value-pass window (A-bins kmin .. kmin + 3)
-constexpr int kGWinA = 4;         // gradient-pass window, moving image as A (one slot per voxel)
-constexpr int kGWinB = 5;         // gradient-pass window, moving image as B (two slots per voxel)
 constexpr int kValueThreads = 768;
 constexpr int kGradThreads = 768;
 constexpr int kMaxNodeSeg = 68;   // FFD x-nodes one 64-voxel row segment can touch (delta >= 1)

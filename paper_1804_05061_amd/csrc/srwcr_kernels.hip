@@ -832,11 +832,19 @@ k_finalize(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
         region[4 * r + 2] = var;
         region[4 * r + 3] = cr;
         __threadfence();
-        const unsigned ticket = atomicAdd(counter, 1u);
-        if (ticket == (unsigned)g.R - 1) {
-            __threadfence();
-            double D = 0.0;
-            for (int q = 0; q < g.R; ++q) D += __hip_atomic_load(&region[4 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the last wave to finish sums the per-region terms: lane-strided partial
+    // sums, then the fixed wave reduction (the same order on every call)
+    unsigned ticket = 0u;
+    if (a == 0) ticket = atomicAdd(counter, 1u);
+    ticket = __builtin_amdgcn_readfirstlane(ticket);
+    if (ticket == (unsigned)g.R - 1) {
+        __threadfence();
+        double part = 0.0;
+        for (int q = a; q < g.R; q += kWave)
+            part += __hip_atomic_load(&region[4 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double D = wave_sum_d(part);
+        if (a == 0) {
             *d_value = D * g.inv_Z;
             *counter = 0u;
         }
@@ -968,102 +976,80 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         float wyv[4], wzv[4];
         row_sp_weights(spw_y, spw_z, y, z, lane, wyv, wzv);
 
-        // dD/ds_M: the region tables interpolated by w(r, x) = wx wy wz through
-        // window row tables T_row[i][slot] = sum_jk wy_j wz_k T[(i, j, k)][kmin + slot]
-        constexpr int BIG = 0x7fffffff;
+        // dD/ds_M: the region tables interpolated by w(r, x) = wx wy wz.  Row
+        // tables T_row[s][i][c] = sum_jk wy_j wz_k T[(i, j, k)][bin_s][c] are
+        // built for every bin s the row's voxels need (a wave-uniform 64-bit
+        // set: k_A, and k_A + 1 when the moving image is B), one entry per
+        // lane; each voxel then combines its bin's 5 x-node entries, found at
+        // slot popcount(bins below k_A).
         float gs[kSlots] = {0.0f, 0.0f};
-        float *rowt = scr;                                           // <= 64 floats
-        const int W = ROLE == 0 ? kGWinA : kGWinB - 1;             // voxels taken per window: o in [0, W - 1]
-        for (int pass = 0; pass <= 2 * nb; ++pass) {
-            int kmin = wave_min_dpp(min(pend[0] ? v[0].kA : BIG, pend[1] ? v[1].kA : BIG));
-            if (kmin == BIG) break;
-            bool inw[kSlots];
+        int *blist = reinterpret_cast<int *>(scr);                  // [64] the row's bins, ascending
+        float *rowt = scr + 64;                                      // [nd][NE]
+        constexpr int NE = ROLE == 0 ? kXN * 3 : kXN;
+        unsigned long long mine = 0ull;
 #pragma unroll
-            for (int sl = 0; sl < kSlots; ++sl) inw[sl] = pend[sl] && v[sl].kA >= kmin && v[sl].kA - kmin <= W - 1;
-            if (wave_ballot(inw[0] || inw[1]) == 0ull) {
-                const int key = min(pend[0] ? v[0].kA : BIG, pend[1] ? v[1].kA : BIG);
-                kmin = __builtin_amdgcn_readlane(key, (int)__builtin_ctzll(wave_ballot(key != BIG)));
+        for (int sl = 0; sl < kSlots; ++sl)
+            if (pend[sl]) mine |= (ROLE == 0 ? 1ull : 3ull) << v[sl].kA;
+        const unsigned long long bins = (unsigned long long)wave_or_dpp((unsigned)(mine >> 32)) << 32 |
+                                        wave_or_dpp((unsigned)mine);
+        const int nd = __builtin_popcountll(bins);
+        if ((bins >> lane) & 1ull) blist[__builtin_popcountll(bins & ((1ull << lane) - 1ull))] = lane;
+        wave_sync();
+        for (int e = lane; e < nd * NE; e += kWave) {
+            const int sb = e / NE, r = e - sb * NE;
+            const int a = blist[sb];
+            const int i = ROLE == 0 ? r / 3 : r, c = ROLE == 0 ? r - 3 * i : 0;
+            float acc = 0.0f;
+            if (a <= (ROLE == 0 ? L - 1 : L)) {
+                const float *tp = tab + i * ts + a * 3 + c;
 #pragma unroll
-                for (int sl = 0; sl < kSlots; ++sl)
-                    inw[sl] = pend[sl] && v[sl].kA >= kmin && v[sl].kA - kmin <= W - 1;
+                for (int kz = 0; kz < 4; ++kz)
+#pragma unroll
+                    for (int jy = 0; jy < 4; ++jy) acc = fmaf(wyv[jy] * wzv[kz], tp[(kz * 4 + jy) * kXN * ts], acc);
             }
-            if (ROLE == 0) {
-                if (lane < kXN * kGWinA * 3) {                       // (i, slot, c)
-                    const int i = lane / (kGWinA * 3), rem = lane - i * kGWinA * 3;
-                    const int sl = rem / 3, c = rem - 3 * sl;
-                    const int a = kmin + sl;
-                    float acc = 0.0f;
-                    if (a <= L - 1) {
-                        const float *tp = tab + i * ts + a * 3 + c;
-#pragma unroll
-                        for (int kz = 0; kz < 4; ++kz)
-#pragma unroll
-                            for (int jy = 0; jy < 4; ++jy)
-                                acc = fmaf(wyv[jy] * wzv[kz], tp[(kz * 4 + jy) * kXN * ts], acc);
-                    }
-                    rowt[lane] = acc;
-                }
-                wave_sync();
-#pragma unroll
-                for (int sl = 0; sl < kSlots; ++sl) {
-                    if (inw[sl]) {
-                        const int o = v[sl].kA - kmin;
-                        float C[3];
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            float acc = 0.0f;
-#pragma unroll
-                            for (int i = 0; i < kXN; ++i) acc = fmaf(v[sl].wx5[i], rowt[(i * kGWinA + o) * 3 + c], acc);
-                            C[c] = acc;
-                        }
-                        gs[sl] = parzen_dw0(v[sl].tA) * fmaf(fmaf(C[0], v[sl].m1, C[1]), v[sl].m1, C[2]);
-                    }
-                }
-            } else {
-                constexpr int NS = kGWinB;                           // slots kmin .. kmin + 4
-                if (lane < kXN * NS) {
-                    const int i = lane / NS, sl = lane - i * NS, a = kmin + sl;
-                    float acc = 0.0f;
-                    if (a <= L) {
-                        const float *tp = tab + i * ts + a * 3;
-#pragma unroll
-                        for (int kz = 0; kz < 4; ++kz)
-#pragma unroll
-                            for (int jy = 0; jy < 4; ++jy)
-                                acc = fmaf(wyv[jy] * wzv[kz], tp[(kz * 4 + jy) * kXN * ts], acc);
-                    }
-                    rowt[lane] = acc;
-                } else if (lane < kXN * NS + kXN) {
-                    const int i = lane - kXN * NS;
-                    float acc = 0.0f;
-#pragma unroll
-                    for (int kz = 0; kz < 4; ++kz)
-#pragma unroll
-                        for (int jy = 0; jy < 4; ++jy)
-                            acc = fmaf(wyv[jy] * wzv[kz], alph[(kz * 4 + jy) * kXN + i], acc);
-                    rowt[lane] = acc;
-                }
-                wave_sync();
-#pragma unroll
-                for (int sl = 0; sl < kSlots; ++sl) {
-                    if (inw[sl]) {
-                        const int o = v[sl].kA - kmin;
-                        const float k21 = (float)(2 * v[sl].kB + 1);
-                        float acc = 0.0f;
-#pragma unroll
-                        for (int i = 0; i < kXN; ++i) {
-                            const float t = k21 * rowt[kXN * NS + i] - v[sl].a0 * rowt[i * NS + o] -
-                                            v[sl].a1 * rowt[i * NS + o + 1];
-                            acc = fmaf(v[sl].wx5[i], t, acc);
-                        }
-                        gs[sl] = -parzen_dw0(v[sl].tB) * acc;          // d m1 / d s_B = -d w0 / d s
-                    }
-                }
-            }
-            wave_sync();
-#pragma unroll
-            for (int sl = 0; sl < kSlots; ++sl) pend[sl] = pend[sl] && !inw[sl];
+            rowt[e] = acc;
         }
+        float arow[kXN];                                             // moving is B: CR_r / (sigma_r^2 Z) per x-node
+        if (ROLE == 1) {
+            float al = 0.0f;
+            if (lane < kXN) {
+#pragma unroll
+                for (int kz = 0; kz < 4; ++kz)
+#pragma unroll
+                    for (int jy = 0; jy < 4; ++jy) al = fmaf(wyv[jy] * wzv[kz], alph[(kz * 4 + jy) * kXN + lane], al);
+            }
+#pragma unroll
+            for (int i = 0; i < kXN; ++i) arow[i] = bcast(al, i);
+        }
+        wave_sync();
+#pragma unroll
+        for (int sl = 0; sl < kSlots; ++sl) {
+            if (!pend[sl]) continue;
+            const int sb = __builtin_popcountll(bins & ((1ull << v[sl].kA) - 1ull));
+            if (ROLE == 0) {
+                const float *rt = rowt + sb * NE;
+                float C[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < kXN; ++i) acc = fmaf(v[sl].wx5[i], rt[i * 3 + c], acc);
+                    C[c] = acc;
+                }
+                gs[sl] = parzen_dw0(v[sl].tA) * fmaf(fmaf(C[0], v[sl].m1, C[1]), v[sl].m1, C[2]);
+            } else {
+                const float *r0 = rowt + sb * NE, *r1 = r0 + NE;        // bins k_A and k_A + 1 (adjacent in the set)
+                const float k21 = (float)(2 * v[sl].kB + 1);
+                float acc = 0.0f;
+#pragma unroll
+                for (int i = 0; i < kXN; ++i) {
+                    const float t = k21 * arow[i] - v[sl].a0 * r0[i] - v[sl].a1 * r1[i];
+                    acc = fmaf(v[sl].wx5[i], t, acc);
+                }
+                gs[sl] = -parzen_dw0(v[sl].tB) * acc;                   // d m1 / d s_B = -d w0 / d s
+            }
+        }
+        wave_sync();                                                 // the scatter reuses the scratch
 
         // q = dD/ds * dM/dy * dy/dT  (eq 16): a dense field's gradient is q itself
         if (DISP == 1) {
