@@ -483,7 +483,8 @@ static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, int 
     prof_mark(P, 0, s);
     HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
     prof_mark(P, 1, s);
-    HIP_TRY(launch_prep(P->geom_dev, g.mdt, dense, with_grad, P->items, P->nitems, args, ws, P->prep_lds, s),
+    HIP_TRY(launch_prep(P->geom_dev, g.mdt, dense, with_grad, P->vblocks, P->vrow, P->nvblocks, P->vrow_host.back(),
+                        args, ws, P->prep_lds, s),
             "warp launch");
     prof_mark(P, 2, s);
     HIP_TRY(launch_value(P->geom_dev, g.fdt, P->vblocks, P->vrow, P->nvblocks, P->nwg, args, ws, P->value_lds, s),
@@ -573,7 +574,8 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
     HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
     const Geom &g = plan->g;
     const BatchArgs args = one_problem(fixed, moving, ffd, nullptr, nullptr);
-    HIP_TRY(launch_prep(plan->geom_dev, g.mdt, 0, 0, plan->items, plan->nitems, args, ws, plan->prep_lds, s),
+    HIP_TRY(launch_prep(plan->geom_dev, g.mdt, 0, 0, plan->vblocks, plan->vrow, plan->nvblocks,
+                        plan->vrow_host.back(), args, ws, plan->prep_lds, s),
             "warp launch");
     HIP_TRY(launch_value(plan->geom_dev, g.fdt, plan->vblocks, plan->vrow, plan->nvblocks, plan->nwg, args, ws,
                          plan->value_lds, s),
@@ -632,6 +634,7 @@ struct srwcr_batch {
     WorkItem *vblocks_dev = nullptr;
     int *vrow_dev = nullptr;
     int nvblocks = 0, nwg = 0;
+    long nrows = 0;
     size_t value_lds = 0, grad_lds = 0, prep_lds = 0, ws_total = 0, zero_bytes = 0, max_params = 0;
     int max_regions = 0;
 };
@@ -725,6 +728,7 @@ int srwcr_batch_create(int32_t n, const srwcr_plan *const *plans, srwcr_batch **
             vr.push_back(vr.back() + (plans[p]->vrow_host[i + 1] - plans[p]->vrow_host[i]));
         }
     b->nvblocks = (int)vb.size();
+    b->nrows = vr.back();
     int nwg_max = 0;
     for (int p = 0; p < n; ++p) nwg_max = std::max(nwg_max, plans[p]->nwg);
     b->nwg = std::max(1, std::min(nwg_max, vr.back()));
@@ -767,7 +771,9 @@ int srwcr_grad_batched(const srwcr_batch *b, const srwcr_batch_item *items, void
     unsigned char *ws = (unsigned char *)workspace;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_zero((double *)ws, b->zero_bytes / sizeof(double), s), "zero launch");
-    HIP_TRY(launch_prep(b->geoms_dev, b->mdt, 0, 1, b->items_dev, b->nitems, args, ws, b->prep_lds, s), "warp launch");
+    HIP_TRY(launch_prep(b->geoms_dev, b->mdt, 0, 1, b->vblocks_dev, b->vrow_dev, b->nvblocks, b->nrows, args, ws,
+                        b->prep_lds, s),
+            "warp launch");
     HIP_TRY(launch_value(b->geoms_dev, b->fdt, b->vblocks_dev, b->vrow_dev, b->nvblocks, b->nwg, args, ws,
                          b->value_lds, s),
             "value launch");

@@ -99,8 +99,9 @@ hipError_t launch_zero(double *p, size_t n, hipStream_t s);
 hipError_t launch_normalize(const float *in, int64_t n, float lo, float scale, float L, void *out, int dt,
                             hipStream_t s);
 hipError_t launch_minmax(const float *in, int64_t n, float *partial, int nblocks, hipStream_t s);
-hipError_t launch_prep(const Geom *geoms, int mdt, int dense, int with_grad, const WorkItem *items, int nitems,
-                       const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s);
+hipError_t launch_prep(const Geom *geoms, int mdt, int dense, int with_grad, const WorkItem *blocks,
+                       const int *row_start, int nblocks, long nrows, const BatchArgs &args, unsigned char *ws,
+                       size_t lds_bytes, hipStream_t s);
 // Value pass over region blocks: row_start[b] = first row (in a list of all
 // blocks' rows) of block b, row_start[nblocks] = total; nwg persistent
 // workgroups share the rows evenly.

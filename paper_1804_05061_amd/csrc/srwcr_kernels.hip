@@ -457,12 +457,24 @@ hipError_t launch_minmax(const float *in, int64_t n, float *partial, int nblocks
 // dependent FFD loads and gathers.  One wave per item row, as in those passes.
 size_t prep_lds_bytes(const Geom &g) { return (size_t)(kValueThreads / kWave) * 3 * g.c1n * sizeof(double); }
 
+// Rows come from the value pass's block-ordered row list: wave w of
+// workgroup b takes row 12 b + w, so the grid is balanced to the row.
 template <int MDT, int DISP, int GRAD>
 __global__ void __launch_bounds__(kValueThreads)
-k_prep(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, BatchArgs args, unsigned char *ws)
+k_prep(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, const int *__restrict__ row_start,
+       int nblocks, BatchArgs args, unsigned char *ws)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const WorkItem it = items[blockIdx.x];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long r = (long)blockIdx.x * (kValueThreads / kWave) + wave;
+    if (r >= row_start[nblocks]) return;
+    int lo = 0, hi = nblocks - 1;                       // block of row r: row_start[lo] <= r < row_start[lo + 1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_start[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    const WorkItem it = blocks[lo];
     const Geom &g = geoms[it.prob];
     const void *__restrict__ moving = args.p[it.prob].moving;
     const float *__restrict__ ffd = args.p[it.prob].ffd;
@@ -470,13 +482,12 @@ k_prep(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     float *__restrict__ dmo = reinterpret_cast<float *>(ws + g.ws.dm);
     const int L = g.nb - 1;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nwaves = blockDim.x >> 6;
     double *c1 = reinterpret_cast<double *>(smem) + wave * 3 * g.c1n;
     const size_t nv = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
-    const int ny = it.y1 - it.y0, nz = it.z1 - it.z0;
+    const int ny = it.y1 - it.y0;
     const int xs = it.x0, xe = it.x1;
-    for (int row = wave; row < ny * nz; row += nwaves) {
+    {
+        const int row = (int)(r - row_start[lo]);
         const int y = it.y0 + row % ny, z = it.z0 + row / ny;
         int px_lo = 0;
         if (DISP == 0) px_lo = ffd_c1(g, ffd, xs, xe, y, z, c1, lane);
@@ -500,17 +511,19 @@ k_prep(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
                 }
             }
         }
-        wave_sync();                                     // c1 is rewritten by the next row
     }
 }
 
-#define SRWCR_PREP(M, D, G)                                                                                  \
-    hipLaunchKernelGGL((k_prep<M, D, G>), dim3(nitems), dim3(kValueThreads), lds_bytes, s, geoms, items, args, ws)
+#define SRWCR_PREP(M, D, G)                                                                                   \
+    hipLaunchKernelGGL((k_prep<M, D, G>), dim3(nwg), dim3(kValueThreads), lds_bytes, s, geoms, blocks, row_start, \
+                       nblocks, args, ws)
 
-hipError_t launch_prep(const Geom *geoms, int mdt, int dense, int with_grad, const WorkItem *items, int nitems,
-                       const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s)
+hipError_t launch_prep(const Geom *geoms, int mdt, int dense, int with_grad, const WorkItem *blocks,
+                       const int *row_start, int nblocks, long nrows, const BatchArgs &args, unsigned char *ws,
+                       size_t lds_bytes, hipStream_t s)
 {
-    if (nitems <= 0) return hipSuccess;
+    if (nblocks <= 0 || nrows <= 0) return hipSuccess;
+    const int nwg = (int)((nrows + kValueThreads / kWave - 1) / (kValueThreads / kWave));
 #define SRWCR_PREP_M(M)                                                                                      \
     if (mdt == M) {                                                                                          \
         if (dense) { if (with_grad) SRWCR_PREP(M, 1, 1); else SRWCR_PREP(M, 1, 0); }                         \
