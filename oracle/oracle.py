@@ -114,6 +114,8 @@ def lib():
         L.orc_value.argtypes = [pp, fp, fp, fp]
         L.orc_gradient.restype = ctypes.c_double
         L.orc_gradient.argtypes = [pp, fp, fp, fp, ctypes.c_int, dp, dp]
+        L.orc_raptor.restype = ctypes.c_double
+        L.orc_raptor.argtypes = [pp, fp, fp, fp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
         _lib = L
@@ -286,6 +288,33 @@ def gradient(P: Problem, fixed: np.ndarray, moving: np.ndarray, ffd: np.ndarray,
     D = lib().orc_gradient(ctypes.byref(P.c()), fxp, mp, fp, int(form), _f64(g),
                            _f64(dm) if dm is not None else None)
     return (D, g, dm) if want_dDdM else (D, g)
+
+
+def raptor(P: Problem, fixed: np.ndarray, moving: np.ndarray, disp: np.ndarray, patches,
+           want_grad: bool = False, want_dRds: bool = False):
+    """RaPTOR of eqs (13, 14) over boxcar patches (eq 6), patches = int array
+    [n, 6] of half-open boxes (x0, y0, z0, x1, y1, z1); linear window on A,
+    frequency moments of B.  Returns the value, plus dRaPTOR/d(displacement)
+    (FFD or dense layout as in gradient()) and dRaPTOR/ds_M per voxel when asked."""
+    fx, fxp = _f32(fixed)
+    m, mp = _f32(moving)
+    f, fp = _f32(disp)
+    pt = np.ascontiguousarray(patches, dtype=np.int32).reshape(-1, 6)
+    ptp = pt.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    nx, ny, nz = P.fixed_dims
+    ncx, ncy, ncz = P.ctrl_dims
+    g = None
+    if want_grad:
+        g = np.zeros((3, nz, ny, nx)) if P.dense else np.zeros((3, ncz, ncy, ncx))
+    d = np.zeros((nz, ny, nx)) if want_dRds else None
+    v = lib().orc_raptor(ctypes.byref(P.c()), fxp, mp, fp, ptp, len(pt), _f64(g) if g is not None else None,
+                         _f64(d) if d is not None else None)
+    out = [v]
+    if want_grad:
+        out.append(g)
+    if want_dRds:
+        out.append(d)
+    return out[0] if len(out) == 1 else tuple(out)
 
 
 def num_threads() -> int:

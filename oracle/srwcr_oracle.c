@@ -19,6 +19,8 @@
  *     and, as a second form, by eqs 18 / 20 built from dp/dM of eq 26
  *   - chain rule to the control points                      (eqs 16, 17)
  *   - or, for a dense displacement field, dD/du(x) per voxel  (eq 16)
+ *   - RaPTOR (boxcar patches, linear window, frequency moments) and its
+ *     gradient, the paper's comparison metric                (eqs 6, 13, 14)
  * The joint PDF is kept literally: R x (L+1) x (L+1) doubles.  Per voxel only
  * the bins where h (or h') can be non-zero are visited, which is exact.
  *
@@ -646,6 +648,131 @@ double orc_gradient(const orc_problem *P, const float *fix, const float *mov, co
     free(priv);
     free(st); free(pa); free(mua);
     return D;
+}
+
+/* ------------------------------------------------ RaPTOR, eqs (6), (13), (14)
+ * Boxcar patches (eq 6): patches[6 r .. 6 r + 5] = x0, y0, z0, x1, y1, z1, a
+ * half-open box on the fixed grid (clipped to it); N_r is its voxel count and
+ * N_p = n_patches.  A linear window h(t) = max(0, 1 - |t|) on the A-bins
+ * (eq 14); the B-side statistics are plain frequency moments of B (eq 13 and
+ * sigma_r^2 = E_r[B^2] - E_r[B]^2 over the patch).  A patch whose B variance
+ * is at most VAR_REL of E_r[B^2] contributes nothing.
+ * grad (optional): dRaPTOR/d(displacement) in the layout of orc_gradient
+ * (FFD coefficients, or a dense field when P->dense); dRds_out (optional):
+ * dRaPTOR/ds_M at every fixed voxel.  Returns RaPTOR. */
+static double h_lin(double t) { t = fabs(t); return t < 1.0 ? 1.0 - t : 0.0; }
+
+/* one-sided derivative of h_lin(a - s) in s: right derivative (left in the
+ * argument a - s), inward at the top of the range s = L */
+static double dh_lin_ds(double a, double s, int L)
+{
+    double k = a - s;                     /* argument of h */
+    int side = deriv_side(s, L);          /* -1: left derivative in k, +1: right */
+    if (side < 0) {                       /* approach k from below */
+        if (k > -1.0 && k <= 0.0) return -1.0;   /* h = 1 + k on (-1, 0]: dh/dk = 1, dk/ds = -1 */
+        if (k > 0.0 && k <= 1.0) return 1.0;     /* h = 1 - k on (0, 1]: dh/dk = -1 */
+        return 0.0;
+    }
+    if (k >= -1.0 && k < 0.0) return -1.0;
+    if (k >= 0.0 && k < 1.0) return 1.0;
+    return 0.0;
+}
+
+double orc_raptor(const orc_problem *P, const float *fix, const float *mov, const float *disp, const int *patches,
+                  int n_patches, double *grad, double *dRds_out)
+{
+    int nb = P->n_bins, L = nb - 1;
+    long nvox = (long)P->nf[0] * P->nf[1] * P->nf[2];
+    int nc[3];
+    orc_ctrl_dims(P, nc);
+    long ncell = P->dense ? nvox : (long)nc[0] * nc[1] * nc[2];
+    double *dRds = (double *)calloc((size_t)nvox, sizeof(double));
+    double *Pa = (double *)malloc(sizeof(double) * nb), *S1 = (double *)malloc(sizeof(double) * nb);
+    double value = 0.0;
+    for (int r = 0; r < n_patches; ++r) {
+        int b0[3], b1[3];
+        for (int e = 0; e < 3; ++e) {
+            b0[e] = patches[6 * r + e] < 0 ? 0 : patches[6 * r + e];
+            b1[e] = patches[6 * r + 3 + e] > P->nf[e] ? P->nf[e] : patches[6 * r + 3 + e];
+        }
+        if (b1[0] <= b0[0] || b1[1] <= b0[1] || b1[2] <= b0[2]) continue;
+        double N = (double)(b1[0] - b0[0]) * (b1[1] - b0[1]) * (b1[2] - b0[2]);
+        double sB = 0.0, sB2 = 0.0;
+        for (int a = 0; a < nb; ++a) Pa[a] = S1[a] = 0.0;
+        for (int z = b0[2]; z < b1[2]; ++z)
+            for (int y = b0[1]; y < b1[1]; ++y)
+                for (int x = b0[0]; x < b1[0]; ++x) {
+                    double A, B;
+                    voxel_AB(P, fix, mov, disp, x, y, z, &A, &B, NULL);
+                    sB += B;
+                    sB2 += B * B;
+                    for (int a = 0; a < nb; ++a) {     /* eq (14), every bin */
+                        double hw = h_lin(a - A);
+                        Pa[a] += hw;
+                        S1[a] += hw * B;
+                    }
+                }
+        double E1 = sB / N, E2 = sB2 / N, var = E2 - E1 * E1;
+        if (!(var > VAR_REL * E2)) continue;
+        double Q = 0.0;                               /* sum_a p_r(a) mu_r(a)^2 */
+        for (int a = 0; a < nb; ++a)
+            if (Pa[a] > 0.0) Q += (Pa[a] / N) * (S1[a] / Pa[a]) * (S1[a] / Pa[a]);
+        double T = (E2 - Q) / var;                    /* the patch's term of eq (13) */
+        value += T;
+        if (!grad && !dRds_out) continue;
+        /* derivative of T with respect to A(x) and B(x) for x in the patch */
+        for (int z = b0[2]; z < b1[2]; ++z)
+            for (int y = b0[1]; y < b1[1]; ++y)
+                for (int x = b0[0]; x < b1[0]; ++x) {
+                    double A, B;
+                    voxel_AB(P, fix, mov, disp, x, y, z, &A, &B, NULL);
+                    double dQ_dA = 0.0, dQ_dB = 0.0;
+                    for (int a = 0; a < nb; ++a) {
+                        double mu = Pa[a] > 0.0 ? S1[a] / Pa[a] : B;   /* empty bin: the one-sided limit */
+                        double d = dh_lin_ds(a, A, L);
+                        /* d(S1^2 / P)/dA = (2 mu B - mu^2) dh/dA */
+                        dQ_dA += d * (2.0 * mu * B - mu * mu) / N;
+                        dQ_dB += 2.0 * h_lin(a - A) * mu / N;
+                    }
+                    double dT_dA = -dQ_dA / var;
+                    double dvar_dB = 2.0 * B / N - 2.0 * E1 / N;
+                    double dT_dB = (2.0 * B / N - dQ_dB) / var - T / var * dvar_dB;
+                    long vi = ((long)z * P->nf[1] + y) * P->nf[0] + x;
+                    dRds[vi] += (P->role == 0 ? dT_dA : dT_dB);
+                }
+    }
+    value /= (double)n_patches;
+    for (long v = 0; v < nvox; ++v) dRds[v] /= (double)n_patches;
+    if (dRds_out) memcpy(dRds_out, dRds, sizeof(double) * nvox);
+    if (grad) {
+        memset(grad, 0, sizeof(double) * 3 * ncell);
+        for (int z = 0; z < P->nf[2]; ++z)
+            for (int y = 0; y < P->nf[1]; ++y)
+                for (int x = 0; x < P->nf[0]; ++x) {
+                    long vi = ((long)z * P->nf[1] + y) * P->nf[0] + x;
+                    double g = dRds[vi];
+                    if (g == 0.0) continue;
+                    double A, B, dsdT[3];
+                    voxel_AB(P, fix, mov, disp, x, y, z, &A, &B, dsdT);
+                    if (P->dense) {
+                        for (int e = 0; e < 3; ++e) grad[e * nvox + vi] = g * dsdT[e];
+                        continue;
+                    }
+                    int pc[3] = {x / P->delta[0], y / P->delta[1], z / P->delta[2]};
+                    double eta[3] = {(double)(x % P->delta[0]) / P->delta[0],
+                                     (double)(y % P->delta[1]) / P->delta[1],
+                                     (double)(z % P->delta[2]) / P->delta[2]};
+                    for (int n = 0; n < 4; ++n)
+                        for (int m = 0; m < 4; ++m)
+                            for (int l = 0; l < 4; ++l) {
+                                double b = orc_beta(l, eta[0]) * orc_beta(m, eta[1]) * orc_beta(n, eta[2]);
+                                long idx = ((long)(pc[2] + n) * nc[1] + (pc[1] + m)) * nc[0] + (pc[0] + l);
+                                for (int e = 0; e < 3; ++e) grad[e * ncell + idx] += g * dsdT[e] * b;
+                            }
+                }
+    }
+    free(dRds); free(Pa); free(S1);
+    return value;
 }
 
 /* number of threads the parallel loops use (reported by the CPU baseline) */
