@@ -104,8 +104,8 @@ int srwcr_eval(const srwcr_plan *plan, const void *fixed, const void *moving, co
                double *d_value, void *workspace, size_t workspace_bytes, void *stream);
 
 /* Value and gradient dD/d(displacement) (eqs 15-21): d_value as srwcr_eval,
- * d_grad a device float32 array shaped like ffd.  The warped intensities are
- * recomputed, never stored. */
+ * d_grad a device float32 array shaped like ffd.  The warped samples and
+ * their image gradients are kept in the workspace between the passes. */
 int srwcr_grad(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd,
                double *d_value, float *d_grad, void *workspace, size_t workspace_bytes, void *stream);
 
@@ -148,6 +148,46 @@ void srwcr_batch_destroy(srwcr_batch *batch);
 size_t srwcr_batch_workspace_bytes(const srwcr_batch *batch);
 int srwcr_grad_batched(const srwcr_batch *batch, const srwcr_batch_item *items, void *workspace,
                        size_t workspace_bytes, void *stream);
+
+/* RaPTOR, the patch-based correlation ratio that SRWCR reduces to with a
+ * boxcar spatial distribution (eq 6), a linear window h(t) = max(0, 1 - |t|)
+ * on the A-bins and frequency estimates of p_r(b) and sigma_r^2 (eqs 13, 14):
+ *   RaPTOR = (1/N_p) sum_r (E_r[B^2] - sum_a p_r(a) mu_r(a)^2) / sigma_r^2,
+ * p_r(a) = sum_{x in r} h(a - A(x)) / N_r, mu_r(a) its h-weighted mean of B,
+ * E_r and sigma_r^2 = E_r[B^2] - E_r[B]^2 plain means over the N_r voxels of
+ * patch r.  A and B, the roles, dtypes, warp (FFD or dense field) and the
+ * intensity bins are the plan's.  A patch whose B variance is at most 1e-5 of
+ * E_r[B^2] adds 0; an empty bin adds nothing.
+ *
+ * srwcr_patch: a half-open voxel box [x0, x1) x [y0, y1) x [z0, z1) on the
+ * fixed grid; it is clipped to the grid, and a patch that the clip empties
+ * still counts in N_p.  raptor_patches_create copies n (1 .. 2^24) host boxes
+ * to the device for `plan` (which must outlive the set) and returns
+ * SRWCR_E_INVALID_ARG for n out of range or NULL pointers, SRWCR_E_UNSUPPORTED
+ * for a fixed grid of 2^31 voxels or more.
+ *
+ * raptor_eval writes RaPTOR to the device double d_value; raptor_grad also
+ * writes d_grad (device float32): dRaPTOR/d(FFD displacement) in the layout
+ * of srwcr_grad's d_grad when dense = 0, or dRaPTOR/du(x) [3][nz][ny][nx] for
+ * a dense field (dense = 1, disp as in srwcr_grad_dense).  The derivative is
+ * the exact derivative of eq 13 with the one-sided window derivative of
+ * srwcr_grad; the paper states none.  The workspace (raptor_workspace_bytes,
+ * 0 for a set made for another plan) is the caller's; the calls only enqueue
+ * kernels on `stream` and allocate nothing. */
+typedef struct {
+    int32_t x0, y0, z0, x1, y1, z1;
+} srwcr_patch;
+typedef struct raptor_patches raptor_patches;
+
+int raptor_patches_create(const srwcr_plan *plan, const srwcr_patch *patches, int32_t n, raptor_patches **out);
+void raptor_patches_destroy(raptor_patches *patches);
+size_t raptor_workspace_bytes(const srwcr_plan *plan, const raptor_patches *patches);
+int raptor_eval(const srwcr_plan *plan, const raptor_patches *patches, const void *fixed, const void *moving,
+                const float *disp, int32_t dense, double *d_value, void *workspace, size_t workspace_bytes,
+                void *stream);
+int raptor_grad(const srwcr_plan *plan, const raptor_patches *patches, const void *fixed, const void *moving,
+                const float *disp, int32_t dense, double *d_value, float *d_grad, void *workspace,
+                size_t workspace_bytes, void *stream);
 
 /* Backward-warped moving volume on the fixed grid: out[x] = M(T(x)) with the
  * interpolation of srwcr_eval (Sec. II-F).  moving: normalised device volume in

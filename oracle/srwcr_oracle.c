@@ -686,92 +686,146 @@ double orc_raptor(const orc_problem *P, const float *fix, const float *mov, cons
     int nc[3];
     orc_ctrl_dims(P, nc);
     long ncell = P->dense ? nvox : (long)nc[0] * nc[1] * nc[2];
-    double *dRds = (double *)calloc((size_t)nvox, sizeof(double));
-    double *Pa = (double *)malloc(sizeof(double) * nb), *S1 = (double *)malloc(sizeof(double) * nb);
-    double value = 0.0;
+    int want = grad || dRds_out;
+    /* A(x), B(x) (and dM/dT) at every fixed voxel */
+    double *Av = (double *)malloc(sizeof(double) * nvox), *Bv = (double *)malloc(sizeof(double) * nvox);
+    double *dsdT = want ? (double *)malloc(sizeof(double) * 3 * nvox) : NULL;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < P->nf[2]; ++z)
+        for (int y = 0; y < P->nf[1]; ++y)
+            for (int x = 0; x < P->nf[0]; ++x) {
+                long vi = ((long)z * P->nf[1] + y) * P->nf[0] + x;
+                double d3[3];
+                voxel_AB(P, fix, mov, disp, x, y, z, &Av[vi], &Bv[vi], d3);
+                if (dsdT)
+                    for (int e = 0; e < 3; ++e) dsdT[3 * vi + e] = d3[e];
+            }
+    /* per patch: its box clipped to the grid, N_r, p_r(a) N_r, S1_a, E1, sigma^2, T_r */
+    int *box = (int *)malloc(sizeof(int) * 6 * (size_t)(n_patches > 0 ? n_patches : 1));
+    double *Pa = (double *)calloc((size_t)n_patches * nb + 1, sizeof(double));
+    double *S1 = (double *)calloc((size_t)n_patches * nb + 1, sizeof(double));
+    double *Nr = (double *)calloc((size_t)n_patches + 1, sizeof(double));
+    double *E1r = (double *)calloc((size_t)n_patches + 1, sizeof(double));
+    double *varr = (double *)calloc((size_t)n_patches + 1, sizeof(double));
+    double *Tr = (double *)calloc((size_t)n_patches + 1, sizeof(double));
+    int *ok = (int *)calloc((size_t)n_patches + 1, sizeof(int));
+#pragma omp parallel for schedule(dynamic, 4)
     for (int r = 0; r < n_patches; ++r) {
-        int b0[3], b1[3];
+        int *b = box + 6 * r;
         for (int e = 0; e < 3; ++e) {
-            b0[e] = patches[6 * r + e] < 0 ? 0 : patches[6 * r + e];
-            b1[e] = patches[6 * r + 3 + e] > P->nf[e] ? P->nf[e] : patches[6 * r + 3 + e];
+            b[e] = patches[6 * r + e] < 0 ? 0 : patches[6 * r + e];
+            b[3 + e] = patches[6 * r + 3 + e] > P->nf[e] ? P->nf[e] : patches[6 * r + 3 + e];
         }
-        if (b1[0] <= b0[0] || b1[1] <= b0[1] || b1[2] <= b0[2]) continue;
-        double N = (double)(b1[0] - b0[0]) * (b1[1] - b0[1]) * (b1[2] - b0[2]);
-        double sB = 0.0, sB2 = 0.0;
-        for (int a = 0; a < nb; ++a) Pa[a] = S1[a] = 0.0;
-        for (int z = b0[2]; z < b1[2]; ++z)
-            for (int y = b0[1]; y < b1[1]; ++y)
-                for (int x = b0[0]; x < b1[0]; ++x) {
-                    double A, B;
-                    voxel_AB(P, fix, mov, disp, x, y, z, &A, &B, NULL);
+        if (b[3] <= b[0] || b[4] <= b[1] || b[5] <= b[2]) continue;      /* clipped away: adds 0 */
+        double N = (double)(b[3] - b[0]) * (b[4] - b[1]) * (b[5] - b[2]);
+        double sB = 0.0, sB2 = 0.0, *pa = Pa + (long)r * nb, *s1 = S1 + (long)r * nb;
+        for (int z = b[2]; z < b[5]; ++z)
+            for (int y = b[1]; y < b[4]; ++y)
+                for (int x = b[0]; x < b[3]; ++x) {
+                    long vi = ((long)z * P->nf[1] + y) * P->nf[0] + x;
+                    double A = Av[vi], B = Bv[vi];
                     sB += B;
                     sB2 += B * B;
                     for (int a = 0; a < nb; ++a) {     /* eq (14), every bin */
                         double hw = h_lin(a - A);
-                        Pa[a] += hw;
-                        S1[a] += hw * B;
+                        pa[a] += hw;
+                        s1[a] += hw * B;
                     }
                 }
         double E1 = sB / N, E2 = sB2 / N, var = E2 - E1 * E1;
+        Nr[r] = N;
+        E1r[r] = E1;
+        varr[r] = var;
         if (!(var > VAR_REL * E2)) continue;
         double Q = 0.0;                               /* sum_a p_r(a) mu_r(a)^2 */
         for (int a = 0; a < nb; ++a)
-            if (Pa[a] > 0.0) Q += (Pa[a] / N) * (S1[a] / Pa[a]) * (S1[a] / Pa[a]);
-        double T = (E2 - Q) / var;                    /* the patch's term of eq (13) */
-        value += T;
-        if (!grad && !dRds_out) continue;
-        /* derivative of T with respect to A(x) and B(x) for x in the patch */
-        for (int z = b0[2]; z < b1[2]; ++z)
-            for (int y = b0[1]; y < b1[1]; ++y)
-                for (int x = b0[0]; x < b1[0]; ++x) {
-                    double A, B;
-                    voxel_AB(P, fix, mov, disp, x, y, z, &A, &B, NULL);
-                    double dQ_dA = 0.0, dQ_dB = 0.0;
-                    for (int a = 0; a < nb; ++a) {
-                        double mu = Pa[a] > 0.0 ? S1[a] / Pa[a] : B;   /* empty bin: the one-sided limit */
-                        double d = dh_lin_ds(a, A, L);
-                        /* d(S1^2 / P)/dA = (2 mu B - mu^2) dh/dA */
-                        dQ_dA += d * (2.0 * mu * B - mu * mu) / N;
-                        dQ_dB += 2.0 * h_lin(a - A) * mu / N;
-                    }
-                    double dT_dA = -dQ_dA / var;
-                    double dvar_dB = 2.0 * B / N - 2.0 * E1 / N;
-                    double dT_dB = (2.0 * B / N - dQ_dB) / var - T / var * dvar_dB;
-                    long vi = ((long)z * P->nf[1] + y) * P->nf[0] + x;
-                    dRds[vi] += (P->role == 0 ? dT_dA : dT_dB);
-                }
+            if (pa[a] > 0.0) Q += (pa[a] / N) * (s1[a] / pa[a]) * (s1[a] / pa[a]);
+        Tr[r] = (E2 - Q) / var;                       /* the patch's term of eq (13) */
+        ok[r] = 1;
     }
+    double value = 0.0;
+    for (int r = 0; r < n_patches; ++r) value += Tr[r];
     value /= (double)n_patches;
-    for (long v = 0; v < nvox; ++v) dRds[v] /= (double)n_patches;
-    if (dRds_out) memcpy(dRds_out, dRds, sizeof(double) * nvox);
-    if (grad) {
-        memset(grad, 0, sizeof(double) * 3 * ncell);
-        for (int z = 0; z < P->nf[2]; ++z)
-            for (int y = 0; y < P->nf[1]; ++y)
-                for (int x = 0; x < P->nf[0]; ++x) {
-                    long vi = ((long)z * P->nf[1] + y) * P->nf[0] + x;
-                    double g = dRds[vi];
-                    if (g == 0.0) continue;
-                    double A, B, dsdT[3];
-                    voxel_AB(P, fix, mov, disp, x, y, z, &A, &B, dsdT);
-                    if (P->dense) {
-                        for (int e = 0; e < 3; ++e) grad[e * nvox + vi] = g * dsdT[e];
-                        continue;
+    if (want) {
+        /* derivative of T_r with respect to A(x) and B(x) for x in patch r */
+        double *dRds = (double *)calloc((size_t)nvox, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int r = 0; r < n_patches; ++r) {
+            if (!ok[r]) continue;
+            const int *b = box + 6 * r;
+            double N = Nr[r], E1 = E1r[r], var = varr[r], T = Tr[r];
+            const double *pa = Pa + (long)r * nb, *s1 = S1 + (long)r * nb;
+            for (int z = b[2]; z < b[5]; ++z)
+                for (int y = b[1]; y < b[4]; ++y)
+                    for (int x = b[0]; x < b[3]; ++x) {
+                        long vi = ((long)z * P->nf[1] + y) * P->nf[0] + x;
+                        double A = Av[vi], B = Bv[vi];
+                        double dQ_dA = 0.0, dQ_dB = 0.0;
+                        for (int a = 0; a < nb; ++a) {
+                            double mu = pa[a] > 0.0 ? s1[a] / pa[a] : B;   /* empty bin: the one-sided limit */
+                            double d = dh_lin_ds(a, A, L);
+                            /* d(S1^2 / P)/dA = (2 mu B - mu^2) dh/dA */
+                            dQ_dA += d * (2.0 * mu * B - mu * mu) / N;
+                            dQ_dB += 2.0 * h_lin(a - A) * mu / N;
+                        }
+                        double dT_dA = -dQ_dA / var;
+                        double dvar_dB = 2.0 * B / N - 2.0 * E1 / N;
+                        double dT_dB = (2.0 * B / N - dQ_dB) / var - T / var * dvar_dB;
+                        double t = (P->role == 0 ? dT_dA : dT_dB) / (double)n_patches;
+#pragma omp atomic
+                        dRds[vi] += t;
                     }
-                    int pc[3] = {x / P->delta[0], y / P->delta[1], z / P->delta[2]};
-                    double eta[3] = {(double)(x % P->delta[0]) / P->delta[0],
-                                     (double)(y % P->delta[1]) / P->delta[1],
-                                     (double)(z % P->delta[2]) / P->delta[2]};
-                    for (int n = 0; n < 4; ++n)
-                        for (int m = 0; m < 4; ++m)
-                            for (int l = 0; l < 4; ++l) {
-                                double b = orc_beta(l, eta[0]) * orc_beta(m, eta[1]) * orc_beta(n, eta[2]);
-                                long idx = ((long)(pc[2] + n) * nc[1] + (pc[1] + m)) * nc[0] + (pc[0] + l);
-                                for (int e = 0; e < 3; ++e) grad[e * ncell + idx] += g * dsdT[e] * b;
+        }
+        if (dRds_out) memcpy(dRds_out, dRds, sizeof(double) * nvox);
+        if (grad) {
+            /* eq (16): the chain rule through dM/dT, then eq (17) to the FFD nodes */
+            memset(grad, 0, sizeof(double) * 3 * ncell);
+            int nthreads = 1;
+#ifdef _OPENMP
+            nthreads = omp_get_max_threads();
+#endif
+            double *priv = P->dense ? NULL : (double *)calloc((size_t)nthreads * 3 * ncell, sizeof(double));
+#pragma omp parallel
+            {
+                int tid = 0;
+#ifdef _OPENMP
+                tid = omp_get_thread_num();
+#endif
+                double *gg = P->dense ? grad : priv + (long)tid * 3 * ncell;
+#pragma omp for schedule(static)
+                for (int z = 0; z < P->nf[2]; ++z)
+                    for (int y = 0; y < P->nf[1]; ++y)
+                        for (int x = 0; x < P->nf[0]; ++x) {
+                            long vi = ((long)z * P->nf[1] + y) * P->nf[0] + x;
+                            double g = dRds[vi];
+                            const double *d3 = dsdT + 3 * vi;
+                            if (P->dense) {
+                                for (int e = 0; e < 3; ++e) gg[e * nvox + vi] = g * d3[e];
+                                continue;
                             }
-                }
+                            if (g == 0.0) continue;
+                            int pc[3] = {x / P->delta[0], y / P->delta[1], z / P->delta[2]};
+                            double eta[3] = {(double)(x % P->delta[0]) / P->delta[0],
+                                             (double)(y % P->delta[1]) / P->delta[1],
+                                             (double)(z % P->delta[2]) / P->delta[2]};
+                            for (int n = 0; n < 4; ++n)
+                                for (int m = 0; m < 4; ++m)
+                                    for (int l = 0; l < 4; ++l) {
+                                        double bw = orc_beta(l, eta[0]) * orc_beta(m, eta[1]) * orc_beta(n, eta[2]);
+                                        long idx = ((long)(pc[2] + n) * nc[1] + (pc[1] + m)) * nc[0] + (pc[0] + l);
+                                        for (int e = 0; e < 3; ++e) gg[e * ncell + idx] += g * d3[e] * bw;
+                                    }
+                        }
+            }
+            if (!P->dense)
+                for (int t = 0; t < nthreads; ++t)
+                    for (long c = 0; c < 3 * ncell; ++c) grad[c] += priv[(long)t * 3 * ncell + c];
+            free(priv);
+        }
+        free(dRds);
     }
-    free(dRds); free(Pa); free(S1);
+    free(Av); free(Bv); free(dsdT); free(box);
+    free(Pa); free(S1); free(Nr); free(E1r); free(varr); free(Tr); free(ok);
     return value;
 }
 

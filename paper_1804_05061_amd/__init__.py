@@ -24,7 +24,7 @@ _TORCH_DT = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
 _DT_OF = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
 
 __all__ = ["Problem", "Plan", "Batch", "normalize", "minmax", "register_lbfgs", "LbfgsOptions", "SrwcrError",
-           "MOVING_AS_A", "MOVING_AS_B", "F32", "F16", "BF16", "SRWCRLoss", "SRWCRDenseLoss"]
+           "MOVING_AS_A", "MOVING_AS_B", "F32", "F16", "BF16", "SRWCRLoss", "SRWCRDenseLoss", "RaptorPatches"]
 
 
 def _stream():
@@ -263,6 +263,68 @@ class Batch:
         _lib.check(_lib.load().srwcr_grad_batched(self._h, items, _ptr(self.workspace), self.workspace_bytes,
                                                   _stream()))
         return values, grads
+
+
+class RaptorPatches:
+    """RaPTOR (eqs 6, 13, 14) over a fixed set of boxcar patches on a plan:
+    `boxes` is an int array [n, 6] of half-open boxes (x0, y0, z0, x1, y1, z1)
+    on the fixed grid.  Holds the device patch tables and its own workspace;
+    the plan is kept alive by the set."""
+
+    def __init__(self, plan: Plan, boxes):
+        import numpy as np
+        b = np.ascontiguousarray(np.asarray(boxes, dtype=np.int32).reshape(-1, 6))
+        self.plan = plan
+        self.n = len(b)
+        arr = (_lib.SrwcrPatch * max(self.n, 1))()
+        for i, r in enumerate(b.tolist()):
+            arr[i] = _lib.SrwcrPatch(*r)
+        L = _lib.load()
+        with torch.cuda.device(plan.device):
+            h = ctypes.c_void_p()
+            _lib.check(L.raptor_patches_create(plan.handle, arr, self.n, ctypes.byref(h)))
+            self._h = h
+            self.workspace_bytes = int(L.raptor_workspace_bytes(plan.handle, h))
+            self.workspace = torch.zeros(self.workspace_bytes, dtype=torch.uint8, device=plan.device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().raptor_patches_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def _check(self, fixed, moving, disp, dense):
+        p = self.plan.problem
+        _need_cuda(fixed, "fixed", _TORCH_DT[p.fixed_dtype], p.fixed_shape)
+        _need_cuda(moving, "moving", _TORCH_DT[p.moving_dtype], p.moving_shape)
+        _need_cuda(disp, "disp", torch.float32, p.field_shape if dense else p.ffd_shape)
+
+    def eval(self, fixed, moving, disp, dense: bool = False, out=None):
+        """RaPTOR (eq 13) as a 0-dim float64 device tensor; disp is the FFD, or
+        a dense field [3][nz][ny][nx] when dense."""
+        self._check(fixed, moving, disp, dense)
+        if out is None:
+            out = torch.empty((), dtype=torch.float64, device=fixed.device)
+        _lib.check(_lib.load().raptor_eval(self.plan.handle, self._h, _ptr(fixed), _ptr(moving), _ptr(disp),
+                                           1 if dense else 0, _ptr(out), _ptr(self.workspace),
+                                           self.workspace_bytes, _stream()))
+        return out
+
+    def grad(self, fixed, moving, disp, dense: bool = False, value_out=None, grad_out=None):
+        """(RaPTOR, dRaPTOR/d disp), the gradient shaped like disp."""
+        self._check(fixed, moving, disp, dense)
+        p = self.plan.problem
+        if value_out is None:
+            value_out = torch.empty((), dtype=torch.float64, device=fixed.device)
+        if grad_out is None:
+            grad_out = torch.empty(p.field_shape if dense else p.ffd_shape, dtype=torch.float32, device=fixed.device)
+        _lib.check(_lib.load().raptor_grad(self.plan.handle, self._h, _ptr(fixed), _ptr(moving), _ptr(disp),
+                                           1 if dense else 0, _ptr(value_out), _ptr(grad_out),
+                                           _ptr(self.workspace), self.workspace_bytes, _stream()))
+        return value_out, grad_out
 
 
 def normalize(raw: torch.Tensor, lo: float, hi: float, n_bins: int, dtype=torch.float32) -> torch.Tensor:

@@ -17,7 +17,8 @@ EXPORTED = ["srwcr_ctrl_dims", "srwcr_plan_create", "srwcr_plan_destroy", "srwcr
             "srwcr_lbfgs_default_opts", "register_lbfgs", "srwcr_debug_moments", "srwcr_plan_info",
             "srwcr_profile", "srwcr_profile_read", "srwcr_refine_ffd", "srwcr_bending_energy",
             "srwcr_eval_dense", "srwcr_grad_dense", "srwcr_batch_create", "srwcr_batch_destroy", "srwcr_batch_workspace_bytes", "srwcr_grad_batched",
-            "srwcr_last_error"]
+            "raptor_patches_create", "raptor_patches_destroy", "raptor_workspace_bytes", "raptor_eval",
+            "raptor_grad", "srwcr_last_error"]
 
 MAX_BATCH = 32
 
@@ -43,6 +44,11 @@ class SrwcrLbfgsReport(ctypes.Structure):
 class SrwcrBatchItem(ctypes.Structure):
     _fields_ = [("fixed", ctypes.c_void_p), ("moving", ctypes.c_void_p), ("ffd", ctypes.c_void_p),
                 ("d_value", ctypes.c_void_p), ("d_grad", ctypes.c_void_p)]
+
+
+class SrwcrPatch(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_int32), ("y0", ctypes.c_int32), ("z0", ctypes.c_int32),
+                ("x1", ctypes.c_int32), ("y1", ctypes.c_int32), ("z1", ctypes.c_int32)]
 
 
 class SrwcrError(RuntimeError):
@@ -89,6 +95,11 @@ def load() -> ctypes.CDLL:
         "srwcr_batch_destroy": (None, [vp]),
         "srwcr_batch_workspace_bytes": (sz, [vp]),
         "srwcr_grad_batched": (ctypes.c_int, [vp, ctypes.POINTER(SrwcrBatchItem), vp, sz, vp]),
+        "raptor_patches_create": (ctypes.c_int, [vp, ctypes.POINTER(SrwcrPatch), i32, ctypes.POINTER(vp)]),
+        "raptor_patches_destroy": (None, [vp]),
+        "raptor_workspace_bytes": (sz, [vp, vp]),
+        "raptor_eval": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, vp, vp, sz, vp]),
+        "raptor_grad": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]),
         "srwcr_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

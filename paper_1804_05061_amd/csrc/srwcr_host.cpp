@@ -392,6 +392,7 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         w.dm = off;
         off += 3 * nvox * sizeof(float);
         w.total = align_up(off, 256);
+        w.rds = w.total;
         g.ws = w;
         void *d;
         if ((st = upload(&g, sizeof(Geom), &d))) goto bad;
@@ -782,6 +783,163 @@ int srwcr_grad_batched(const srwcr_batch *b, const srwcr_batch_item *items, void
             "gradient launch");
     HIP_TRY(launch_grad_out(b->geoms_dev, n, b->max_params, args, ws, s), "gradient output launch");
     return SRWCR_OK;
+}
+
+// ------------------------------------------------------------------- RaPTOR
+struct raptor_patches {
+    const srwcr_plan *plan = nullptr;        // the plan the set was made for (not owned)
+    int npatch = 0, npieces = 0;
+    RaptorPatch *patches_dev = nullptr;
+    RaptorPiece *pieces_dev = nullptr;
+    // workspace offsets beyond the plan's SRWCR slots (rds starts at ws.total)
+    size_t stats = 0, ticket = 0, tval = 0, mu = 0, scal = 0, total = 0;
+};
+
+namespace {
+constexpr int kRaptorPiece = 2048;           // voxels of one workgroup of the RaPTOR passes
+constexpr int kRaptorMaxPatches = 1 << 24;
+}  // namespace
+
+void raptor_patches_destroy(raptor_patches *pt)
+{
+    if (!pt) return;
+    if (pt->patches_dev) (void)hipFree(pt->patches_dev);
+    if (pt->pieces_dev) (void)hipFree(pt->pieces_dev);
+    delete pt;
+}
+
+int raptor_patches_create(const srwcr_plan *plan, const srwcr_patch *patches, int32_t n, raptor_patches **out)
+{
+    if (!out) return fail(SRWCR_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!plan || !patches) return fail(SRWCR_E_INVALID_ARG, "NULL plan or patches");
+    if (n < 1 || n > kRaptorMaxPatches)
+        return fail(SRWCR_E_INVALID_ARG, "%d patches outside 1..%d", n, kRaptorMaxPatches);
+    const Geom &g = plan->g;
+    if ((double)g.nf[0] * g.nf[1] * g.nf[2] >= 2147483648.0)
+        return fail(SRWCR_E_UNSUPPORTED, "RaPTOR needs a fixed grid of fewer than 2^31 voxels");
+    std::vector<RaptorPatch> pv(n);
+    std::vector<RaptorPiece> pc;
+    for (int r = 0; r < n; ++r) {
+        const srwcr_patch &q = patches[r];
+        const int lo[3] = {q.x0, q.y0, q.z0}, hi[3] = {q.x1, q.y1, q.z1};
+        int b0[3], ext[3];
+        bool empty = false;
+        for (int e = 0; e < 3; ++e) {
+            b0[e] = std::max(lo[e], 0);
+            const int b1 = std::min(hi[e], g.nf[e]);
+            ext[e] = b1 - b0[e];
+            if (ext[e] <= 0) empty = true;
+        }
+        RaptorPatch &P = pv[r];
+        P = RaptorPatch{b0[0], b0[1], b0[2], 0, 0, 0, 0, 0};
+        if (empty) continue;                // counts in N_p, adds nothing (clipped away)
+        P.nx = ext[0];
+        P.ny = ext[1];
+        P.nz = ext[2];
+        P.n = ext[0] * ext[1] * ext[2];     // < 2^31: inside the grid
+        for (int st = 0; st < P.n; st += kRaptorPiece) pc.push_back(RaptorPiece{r, st, std::min(kRaptorPiece, P.n - st), 0});
+    }
+    raptor_patches *pt = new raptor_patches();
+    pt->plan = plan;
+    pt->npatch = n;
+    pt->npieces = (int)pc.size();
+    hipError_t e = hipMalloc(&pt->patches_dev, pv.size() * sizeof(RaptorPatch));
+    if (e == hipSuccess) e = hipMemcpy(pt->patches_dev, pv.data(), pv.size() * sizeof(RaptorPatch), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !pc.empty()) e = hipMalloc(&pt->pieces_dev, pc.size() * sizeof(RaptorPiece));
+    if (e == hipSuccess && !pc.empty())
+        e = hipMemcpy(pt->pieces_dev, pc.data(), pc.size() * sizeof(RaptorPiece), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        raptor_patches_destroy(pt);
+        return hip_fail(e, "RaPTOR patch tables");
+    }
+    // workspace: the plan's SRWCR slots, then rds [nvox] and the zeroed patch
+    // sums with the ticket, then the finalised tables
+    const size_t nvox = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
+    size_t off = plan->ws.rds + align_up(nvox * sizeof(float), 256);
+    pt->stats = off;
+    off += (size_t)n * (2 * g.nb + 3) * sizeof(double);
+    pt->ticket = off;
+    off = align_up(off + sizeof(double), 256);
+    pt->tval = off;
+    off = align_up(off + (size_t)n * sizeof(double), 256);
+    pt->mu = off;
+    off = align_up(off + (size_t)n * g.nb * sizeof(float2), 256);
+    pt->scal = off;
+    off = align_up(off + (size_t)n * sizeof(float4), 256);
+    pt->total = off;
+    *out = pt;
+    return SRWCR_OK;
+}
+
+size_t raptor_workspace_bytes(const srwcr_plan *plan, const raptor_patches *pt)
+{
+    return plan && pt && pt->plan == plan ? pt->total : 0;
+}
+
+static int run_raptor(const srwcr_plan *plan, const raptor_patches *pt, const void *fixed, const void *moving,
+                      const float *disp, int32_t dense, double *d_value, float *d_grad, void *workspace,
+                      size_t workspace_bytes, void *stream)
+{
+    if (!plan || !pt) return fail(SRWCR_E_INVALID_ARG, "NULL plan or patch set");
+    if (pt->plan != plan) return fail(SRWCR_E_INVALID_ARG, "the patch set was made for another plan");
+    if (!fixed || !moving || !disp) return fail(SRWCR_E_INVALID_ARG, "NULL volume or displacement pointer");
+    if (dense != 0 && dense != 1) return fail(SRWCR_E_INVALID_ARG, "dense = %d is neither 0 nor 1", dense);
+    if (!d_value) return fail(SRWCR_E_INVALID_ARG, "d_value is NULL");
+    if (!workspace) return fail(SRWCR_E_INVALID_ARG, "workspace is NULL");
+    if (workspace_bytes < pt->total)
+        return fail(SRWCR_E_WORKSPACE, "workspace has %zu B, RaPTOR needs %zu B", workspace_bytes, pt->total);
+    const Geom &g = plan->g;
+    unsigned char *ws = (unsigned char *)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    const bool with_grad = d_grad != nullptr;
+    const BatchArgs args = one_problem(fixed, moving, disp, d_value, d_grad);
+    RaptorArgs ra;
+    ra.patches = pt->patches_dev;
+    ra.pieces = pt->pieces_dev;
+    ra.npatch = pt->npatch;
+    ra.npieces = pt->npieces;
+    ra.stats = (double *)(ws + pt->stats);
+    ra.ticket = (unsigned *)(ws + pt->ticket);
+    ra.tval = (double *)(ws + pt->tval);
+    ra.mu = (float2 *)(ws + pt->mu);
+    ra.scal = (float4 *)(ws + pt->scal);
+    ra.rds = (float *)(ws + plan->ws.rds);
+    ra.value = d_value;
+    // zero: the patch sums and the ticket, and for a gradient rds and the FFD accumulators
+    const size_t zlo = with_grad ? plan->ws.rds : pt->stats;
+    HIP_TRY(launch_zero((double *)(ws + zlo), (pt->ticket + sizeof(double) - zlo) / sizeof(double), s), "zero launch");
+    if (with_grad && !dense)
+        HIP_TRY(launch_zero((double *)(ws + plan->ws.grad), 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2], s), "zero launch");
+    HIP_TRY(launch_prep(plan->geom_dev, g.mdt, dense, with_grad ? 1 : 0, plan->vblocks, plan->vrow, plan->nvblocks,
+                        plan->vrow_host.back(), args, ws, plan->prep_lds, s),
+            "warp launch");
+    HIP_TRY(launch_raptor_acc(plan->geom_dev, g.fdt, g.role, ra, args, ws, s), "RaPTOR accumulation launch");
+    HIP_TRY(launch_raptor_finalize(plan->geom_dev, ra, s), "RaPTOR finalize launch");
+    if (!with_grad) return SRWCR_OK;
+    HIP_TRY(launch_raptor_ds(plan->geom_dev, g.fdt, g.role, ra, args, ws, s), "RaPTOR derivative launch");
+    HIP_TRY(launch_grad(plan->geom_dev, 0, 2, dense, plan->items, plan->nitems, args, ws, plan->grad_lds, s),
+            "gradient launch");
+    if (!dense) {
+        const size_t n = 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2];
+        HIP_TRY(launch_grad_out(plan->geom_dev, 1, n, args, ws, s), "gradient output launch");
+    }
+    return SRWCR_OK;
+}
+
+int raptor_eval(const srwcr_plan *plan, const raptor_patches *patches, const void *fixed, const void *moving,
+                const float *disp, int32_t dense, double *d_value, void *workspace, size_t workspace_bytes,
+                void *stream)
+{
+    return run_raptor(plan, patches, fixed, moving, disp, dense, d_value, nullptr, workspace, workspace_bytes, stream);
+}
+
+int raptor_grad(const srwcr_plan *plan, const raptor_patches *patches, const void *fixed, const void *moving,
+                const float *disp, int32_t dense, double *d_value, float *d_grad, void *workspace,
+                size_t workspace_bytes, void *stream)
+{
+    if (!d_grad) return fail(SRWCR_E_INVALID_ARG, "d_grad is NULL");
+    return run_raptor(plan, patches, fixed, moving, disp, dense, d_value, d_grad, workspace, workspace_bytes, stream);
 }
 
 void srwcr_lbfgs_default_opts(srwcr_lbfgs_opts *o)

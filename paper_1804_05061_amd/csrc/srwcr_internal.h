@@ -39,7 +39,8 @@ struct WsLayout {
     size_t counter;    // unsigned            finalise ticket
     size_t kt;         // PrepKT [nvox]       warped moving bin and in-bin position per fixed voxel
     size_t dm;         // float  [3][nvox]    dM/dy at the warped position (gradient calls)
-    size_t total;
+    size_t total;      // end of the SRWCR slots
+    size_t rds;        // float  [nvox]       RaPTOR: dRaPTOR/ds_M per voxel (starts at `total`)
 };
 
 // One fixed voxel's warped moving sample s, as the value and gradient passes
@@ -93,6 +94,41 @@ struct Geom {
     WsLayout ws;               // this problem's slots in the workspace of a launch
 };
 
+// RaPTOR (eqs 6, 13, 14).  A patch clipped to the fixed grid: origin, extent
+// and voxel count (0 for a patch that lies outside the grid).
+struct RaptorPatch {
+    int x0, y0, z0;
+    int nx, ny, nz;
+    int n;
+    int pad;
+};
+
+// A run of consecutive voxels of one patch (x fastest, then y, then z),
+// the unit of one workgroup of the RaPTOR passes.
+struct RaptorPiece {
+    int patch;
+    int start;
+    int count;
+    int pad;
+};
+
+// Device slots of one RaPTOR call.  B enters the sums shifted by c_r, the
+// value of B at the patch's first voxel, which leaves eq 13 unchanged and
+// keeps the FP32 products small.
+struct RaptorArgs {
+    const RaptorPatch *patches;
+    const RaptorPiece *pieces;
+    int npatch;
+    int npieces;
+    double *stats;     // [npatch][2 nb + 2]: P_a, S1_a (a < nb), sum B', sum B'^2
+    unsigned *ticket;  // finalise ticket
+    double *tval;      // [npatch] the patch terms T_r
+    float2 *mu;        // [npatch][nb] (mu_r(a) - c_r, 1), or (0, 0) for an empty bin
+    float4 *scal;      // [npatch] (1 / (N_r sigma_r^2), or 0 for a skipped patch; T_r; E1 - c_r; c_r)
+    float *rds;        // [nvox] dRaPTOR/ds_M
+    double *value;     // RaPTOR
+};
+
 // Launchers (srwcr_kernels.hip).  `geoms` is a device array with one Geom per
 // problem; items carry their problem index; `ws` is the launch's workspace base.
 hipError_t launch_zero(double *p, size_t n, hipStream_t s);
@@ -113,6 +149,11 @@ hipError_t launch_grad(const Geom *geoms, int fdt, int role, int dense, const Wo
                        const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s);
 hipError_t launch_grad_out(const Geom *geoms, int nprob, size_t max_params, const BatchArgs &args, unsigned char *ws,
                            hipStream_t s);
+hipError_t launch_raptor_acc(const Geom *geoms, int fdt, int role, const RaptorArgs &ra, const BatchArgs &args,
+                             const unsigned char *ws, hipStream_t s);
+hipError_t launch_raptor_finalize(const Geom *geoms, const RaptorArgs &ra, hipStream_t s);
+hipError_t launch_raptor_ds(const Geom *geoms, int fdt, int role, const RaptorArgs &ra, const BatchArgs &args,
+                            const unsigned char *ws, hipStream_t s);
 hipError_t launch_warp(const Geom &g, const void *moving, const float *ffd, float *out, hipStream_t s);
 hipError_t launch_downsample(const float *in, int nx, int ny, int nz, float *out, int ox, int oy, int oz,
                              hipStream_t s);

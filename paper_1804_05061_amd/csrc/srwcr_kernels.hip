@@ -896,6 +896,9 @@ struct VoxG {
 
 // DISP 0: scatter dD/dT to the FFD nodes (eq 17) into the workspace
 // accumulators; DISP 1: write dD/du(x) of a dense field to args.p[].grad.
+// ROLE 0 / 1: dD/ds_M from the SRWCR region tables, moving image as A / B;
+// ROLE 2: dD/ds_M read per voxel from the workspace (RaPTOR), so only the
+// chain rule (eq 16) and the scatter run here.
 template <int FDT, int ROLE, int DISP>
 __global__ void __launch_bounds__(kGradThreads)
 k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, BatchArgs args, unsigned char *ws)
@@ -909,6 +912,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     const size_t nvox = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
     const float *__restrict__ tables = reinterpret_cast<const float *>(ws + g.ws.tables);
     const float *__restrict__ alpha = reinterpret_cast<const float *>(ws + g.ws.alpha);
+    const float *__restrict__ rds = reinterpret_cast<const float *>(ws + g.ws.rds);
     double *__restrict__ grad = reinterpret_cast<double *>(ws + g.ws.grad);
     const float4 *spw_x = g.sp_w[0], *spw_y = g.sp_w[1], *spw_z = g.sp_w[2];
     const int *spc_x = g.sp_cell[0], *fp_x = g.ffd_p[0], *fp_y = g.ffd_p[1], *fp_z = g.ffd_p[2];
@@ -932,7 +936,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         const double4 b = gld(g.ffd_w[0], it.x0 + i);
         bxw[i] = make_float4((float)b.x, (float)b.y, (float)b.z, (float)b.w);
     }
-    for (int i = threadIdx.x; i < kNReg * nb; i += blockDim.x) {
+    for (int i = threadIdx.x; ROLE < 2 && i < kNReg * nb; i += blockDim.x) {
         const int rl = i / nb, a = i - rl * nb;
         const int ii = rl % kXN, jk = rl / kXN, jj = jk & 3, kk = jk >> 2;
         float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f, al = 0.0f;
@@ -963,6 +967,12 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             const int x = xs + sl * kWave + lane;
             pend[sl] = x < xe;
             const int xc = pend[sl] ? x : xe - 1;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) v[sl].dm[e] = dmi[e * nvox + rowb + xc];
+            if constexpr (ROLE == 2) {
+                v[sl].tA = pend[sl] ? gld(rds, rowb + xc) : 0.0f;      // dD/ds_M of the voxel
+                continue;
+            }
             const PrepKT pk = kt[rowb + xc];
             const float sf = ld_int<FDT>(fixed, rowb + xc);
             int kF;
@@ -983,9 +993,12 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
 #pragma unroll
             for (int n = 0; n < kXN; ++n) v[sl].wx5[n] = (n - ox >= 0 && n - ox < 4) ? wl[(n - ox) & 3] : 0.0f;
-#pragma unroll
-            for (int e = 0; e < 3; ++e) v[sl].dm[e] = dmi[e * nvox + rowb + xc];
         }
+        float gs[kSlots] = {0.0f, 0.0f};
+        if constexpr (ROLE == 2) {
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) gs[sl] = v[sl].tA;
+        } else {
         float wyv[4], wzv[4];
         row_sp_weights(spw_y, spw_z, y, z, lane, wyv, wzv);
 
@@ -995,7 +1008,6 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         // set: k_A, and k_A + 1 when the moving image is B), one entry per
         // lane; each voxel then combines its bin's 5 x-node entries, found at
         // slot popcount(bins below k_A).
-        float gs[kSlots] = {0.0f, 0.0f};
         int *blist = reinterpret_cast<int *>(scr);                  // [64] the row's bins, ascending
         float *rowt = scr + 64;                                      // [nd][NE]
         constexpr int NE = ROLE == 0 ? kXN * 3 : kXN;
@@ -1063,6 +1075,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             }
         }
         wave_sync();                                                 // the scatter reuses the scratch
+        }
 
         // q = dD/ds * dM/dy * dy/dT  (eq 16): a dense field's gradient is q itself
         if (DISP == 1) {
@@ -1158,6 +1171,7 @@ hipError_t launch_grad(const Geom *geoms, int fdt, int role, int dense, const Wo
     SRWCR_GRAD(0, 0, 0) SRWCR_GRAD(0, 0, 1) SRWCR_GRAD(0, 1, 0) SRWCR_GRAD(0, 1, 1)
     SRWCR_GRAD(1, 0, 0) SRWCR_GRAD(1, 0, 1) SRWCR_GRAD(1, 1, 0) SRWCR_GRAD(1, 1, 1)
     SRWCR_GRAD(2, 0, 0) SRWCR_GRAD(2, 0, 1) SRWCR_GRAD(2, 1, 0) SRWCR_GRAD(2, 1, 1)
+    SRWCR_GRAD(0, 2, 0) SRWCR_GRAD(0, 2, 1)      // per-voxel dD/ds_M: the fixed image is not read
 #undef SRWCR_GRAD
     return hipGetLastError();
 }
@@ -1190,6 +1204,8 @@ hipError_t prepare_kernels()
     if (e == hipSuccess) e = set_lds(k_prep<2, A, B>, b);
     SRWCR_SET(0, 0) SRWCR_SET(0, 1) SRWCR_SET(1, 0) SRWCR_SET(1, 1)
 #undef SRWCR_SET
+    if (e == hipSuccess) e = set_lds(k_grad<0, 2, 0>, b);
+    if (e == hipSuccess) e = set_lds(k_grad<0, 2, 1>, b);
     if (e == hipSuccess && dev < 64) done[dev] = true;
     return e;
 }
@@ -1210,6 +1226,267 @@ hipError_t launch_grad_out(const Geom *geoms, int nprob, size_t max_params, cons
 {
     const int blocks = (int)std::min<size_t>((max_params + 255) / 256, 1024);
     hipLaunchKernelGGL(k_grad_out, dim3(blocks, nprob), dim3(256), 0, s, geoms, args, ws);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- RaPTOR
+// The patch-based correlation ratio of eqs (6, 13, 14): boxcar patches, a
+// linear window h(t) = max(0, 1 - |t|) on the A-bins and plain frequency
+// moments of B.  Per patch r the accumulation pass gathers
+//   P_a = sum h(a - A),  S1_a = sum h(a - A) B',  sum B',  sum B'^2
+// over its voxels, with B' = B - c_r and c_r the value of B at the patch's
+// first voxel (eq 13 is unchanged by the shift; it keeps the FP32 products
+// and the cancellation in E[B^2] - sum p mu^2 small).  One workgroup takes a
+// run of the patch's voxels; its waves take 64 voxels at a time, form the
+// wave-uniform set of A-bins they touch (two per voxel) and add, per bin,
+// the wave's sums of h and h B' to FP64 LDS slots; the slots are merged into
+// the patch's global sums once per workgroup.
+
+constexpr int kRaptorThreads = 256;
+
+// Wave-uniform FP32 sum: butterfly within each 16-lane row (DPP), then the
+// four row sums through readlane.  Must run with all lanes active.
+__device__ __forceinline__ float wave_sum_f(float v)
+{
+    v += dpp<0xB1>(v);     // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);     // quad_perm [2,3,0,1]
+    v += dpp<0x124>(v);    // row_ror:4
+    v += dpp<0x128>(v);    // row_ror:8
+    return (bcast(v, 0) + bcast(v, 16)) + (bcast(v, 32) + bcast(v, 48));
+}
+
+// B of one voxel as an integer part and a fraction: the moving sample's bin
+// and in-bin position (moving is B), or the fixed value (moving is A).
+template <int FDT, int ROLE>
+__device__ __forceinline__ void raptor_b(const PrepKT *__restrict__ kt, const void *__restrict__ fixed, size_t vi,
+                                         int &kb, float &tb)
+{
+    if constexpr (ROLE == 0) {
+        kb = 0;
+        tb = ld_int<FDT>(fixed, vi);
+    } else {
+        const PrepKT pk = kt[vi];
+        kb = pk.k;
+        tb = pk.t;
+    }
+}
+
+// Voxel `v` (0 .. n - 1) of a patch, x fastest: its fixed-grid index.
+__device__ __forceinline__ size_t raptor_voxel(const RaptorPatch &pt, int v, int nfx, int nfy)
+{
+    const int x = v % pt.nx, yz = v / pt.nx, y = yz % pt.ny, z = yz / pt.ny;
+    return ((size_t)(pt.z0 + z) * nfy + (pt.y0 + y)) * nfx + (pt.x0 + x);
+}
+
+// One voxel's A-bin k, in-bin position t (k = min(floor(A), L - 1)) and
+// shifted B' = (kb - ck) + (tb - ct).
+template <int FDT, int ROLE>
+__device__ __forceinline__ void raptor_ab(const PrepKT *__restrict__ kt, const void *__restrict__ fixed, size_t vi,
+                                          int L, int ck, float ct, int &kA, float &tA, float &Bs)
+{
+    int kb;
+    float tb;
+    raptor_b<FDT, ROLE>(kt, fixed, vi, kb, tb);
+    if constexpr (ROLE == 0) {
+        const PrepKT pk = kt[vi];
+        kA = pk.k;
+        tA = pk.t;
+    } else {
+        const float sf = ld_int<FDT>(fixed, vi);
+        kA = max(min((int)sf, L - 1), 0);                            // in range for any input
+        tA = sf - (float)kA;
+    }
+    Bs = (float)(kb - ck) + (tb - ct);
+}
+
+template <int FDT, int ROLE>
+__global__ void __launch_bounds__(kRaptorThreads)
+k_raptor_acc(const Geom *__restrict__ geoms, RaptorArgs ra, BatchArgs args, const unsigned char *ws)
+{
+    extern __shared__ double rsh[];                                   // [2 nb + 2]
+    const Geom &g = geoms[0];
+    const RaptorPiece pc = ra.pieces[blockIdx.x];
+    const RaptorPatch pt = ra.patches[pc.patch];
+    const int nb = g.nb, L = nb - 1, nst = 2 * nb + 3;
+    const PrepKT *__restrict__ kt = reinterpret_cast<const PrepKT *>(ws + g.ws.kt);
+    const void *__restrict__ fixed = args.p[0].fixed;
+    const int nfx = g.nf[0], nfy = g.nf[1];
+    for (int i = threadIdx.x; i < 2 * nb + 2; i += blockDim.x) rsh[i] = 0.0;
+    int ck;
+    float ct;
+    raptor_b<FDT, ROLE>(kt, fixed, raptor_voxel(pt, 0, nfx, nfy), ck, ct);
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int end = pc.start + pc.count;
+    double sb = 0.0, sb2 = 0.0;
+    for (int base = pc.start + wave * kWave; base < end; base += nwaves * kWave) {
+        const int v = base + lane;
+        const bool act = v < end;
+        int kA;
+        float tA, Bs;
+        raptor_ab<FDT, ROLE>(kt, fixed, raptor_voxel(pt, act ? v : base, nfx, nfy), L, ck, ct, kA, tA, Bs);
+        if (act) {
+            sb += (double)Bs;
+            sb2 += (double)Bs * (double)Bs;
+        }
+        const float h0 = act ? 1.0f - tA : 0.0f, h1 = act ? tA : 0.0f;
+        const unsigned long long mine = act ? 3ull << kA : 0ull;   // bins k_A, k_A + 1 (k_A <= L - 1 <= 62)
+        unsigned long long bins = (unsigned long long)wave_or_dpp((unsigned)(mine >> 32)) << 32 |
+                                  wave_or_dpp((unsigned)mine);
+        while (bins) {
+            const int a = __builtin_ctzll(bins);
+            bins &= bins - 1ull;
+            const float w = kA == a ? h0 : (kA + 1 == a ? h1 : 0.0f);
+            const float p = wave_sum_f(w), q = wave_sum_f(w * Bs);
+            if (lane == 0) {
+                atomicAdd(&rsh[a], (double)p);
+                atomicAdd(&rsh[nb + a], (double)q);
+            }
+        }
+    }
+    sb = wave_sum_d(sb);
+    sb2 = wave_sum_d(sb2);
+    if (lane == 0) {
+        atomicAdd(&rsh[2 * nb], sb);
+        atomicAdd(&rsh[2 * nb + 1], sb2);
+    }
+    __syncthreads();
+    double *st = ra.stats + (size_t)pc.patch * nst;
+    for (int i = threadIdx.x; i < 2 * nb + 2; i += blockDim.x)
+        if (rsh[i] != 0.0) unsafeAtomicAdd(&st[i], rsh[i]);
+    if (threadIdx.x == 0) st[2 * nb + 2] = (double)ck + (double)ct;   // c_r (every piece writes the same value)
+}
+
+// One wave per patch (lane = A-bin): the patch term
+//   T_r = (E[B'^2] - sum_a p_r(a) mu'_r(a)^2) / sigma_r^2,
+// mu'_r(a) = S1_a / P_a, and the tables of the derivative pass; the last wave
+// to finish writes RaPTOR = (1 / N_p) sum_r T_r, summed in patch order.
+__global__ void __launch_bounds__(kRaptorThreads) k_raptor_finalize(const Geom *__restrict__ geoms, RaptorArgs ra)
+{
+    const Geom &g = geoms[0];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int p = blockIdx.x * (kRaptorThreads / kWave) + (threadIdx.x >> 6);
+    if (p >= ra.npatch) return;
+    const int nb = g.nb, nst = 2 * nb + 3;
+    const double *st = ra.stats + (size_t)p * nst;
+    const double N = (double)ra.patches[p].n;
+    double P = 0.0, S = 0.0;
+    if (lane < nb) {
+        P = st[lane];
+        S = st[nb + lane];
+    }
+    const bool filled = P > 0.0;
+    const double mu = filled ? S / P : 0.0;
+    double T = 0.0, inv_nvar = 0.0, E1 = 0.0, c = 0.0;
+    const double Q = wave_sum_d(filled ? S * mu : 0.0);               // N sum_a p mu'^2
+    if (N > 0.0) {
+        c = st[2 * nb + 2];
+        E1 = st[2 * nb] / N;
+        const double E2s = st[2 * nb + 1] / N, var = E2s - E1 * E1;
+        const double E2 = E2s + c * (2.0 * E1 + c);                   // E[B^2] of the unshifted B
+        // a patch whose B is constant to 0.3 % (sigma^2 <= 1e-5 E[B^2]) is skipped
+        if (var > 1e-5 * E2) {
+            T = (E2s - Q / N) / var;
+            inv_nvar = 1.0 / (N * var);
+        }
+    }
+    if (lane < nb) ra.mu[(size_t)p * nb + lane] = make_float2((float)mu, filled ? 1.0f : 0.0f);
+    if (lane == 0) {
+        ra.scal[p] = make_float4((float)inv_nvar, (float)T, (float)E1, (float)c);
+        ra.tval[p] = T;
+        __threadfence();
+    }
+    unsigned ticket = 0u;
+    if (lane == 0) ticket = atomicAdd(ra.ticket, 1u);
+    ticket = __builtin_amdgcn_readfirstlane(ticket);
+    if (ticket == (unsigned)ra.npatch - 1) {
+        __threadfence();
+        double part = 0.0;
+        for (int q = lane; q < ra.npatch; q += kWave)
+            part += __hip_atomic_load(&ra.tval[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double R = wave_sum_d(part);
+        if (lane == 0) {
+            *ra.value = R / (double)ra.npatch;
+            *ra.ticket = 0u;
+        }
+    }
+}
+
+// Derivative pass: per patch voxel, dT_r/ds_M (the exact derivative of eq 13
+// with the one-sided window derivative), added over the patches that hold
+// the voxel into rds = dRaPTOR/ds_M.
+//   moving is A: dT/dA = ((B - mu(k+1))^2 - (B - mu(k))^2) / (N sigma^2),
+//   moving is B: dT/dB = 2 (B - sum_a h mu(a) - T (B - E1)) / (N sigma^2),
+// an empty bin's mu taken as the voxel's own B.
+template <int FDT, int ROLE>
+__global__ void __launch_bounds__(kRaptorThreads)
+k_raptor_ds(const Geom *__restrict__ geoms, RaptorArgs ra, BatchArgs args, const unsigned char *ws)
+{
+    extern __shared__ float2 rmu[];                                   // [nb]
+    const Geom &g = geoms[0];
+    const RaptorPiece pc = ra.pieces[blockIdx.x];
+    const float4 sc = ra.scal[pc.patch];
+    if (sc.x == 0.0f) return;                                         // skipped patch: no derivative
+    const RaptorPatch pt = ra.patches[pc.patch];
+    const int nb = g.nb, L = nb - 1;
+    const PrepKT *__restrict__ kt = reinterpret_cast<const PrepKT *>(ws + g.ws.kt);
+    const void *__restrict__ fixed = args.p[0].fixed;
+    const int nfx = g.nf[0], nfy = g.nf[1];
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) rmu[i] = ra.mu[(size_t)pc.patch * nb + i];
+    int ck;
+    float ct;
+    raptor_b<FDT, ROLE>(kt, fixed, raptor_voxel(pt, 0, nfx, nfy), ck, ct);
+    __syncthreads();
+    const float scale = sc.x / (float)ra.npatch;
+    const int end = pc.start + pc.count;
+    for (int v = pc.start + threadIdx.x; v < end; v += blockDim.x) {
+        const size_t vi = raptor_voxel(pt, v, nfx, nfy);
+        int kA;
+        float tA, Bs;
+        raptor_ab<FDT, ROLE>(kt, fixed, vi, L, ck, ct, kA, tA, Bs);
+        const float2 m0 = rmu[kA], m1 = rmu[kA + 1];
+        float d;
+        if constexpr (ROLE == 0) {
+            const float d0 = m0.y != 0.0f ? Bs - m0.x : 0.0f, d1 = m1.y != 0.0f ? Bs - m1.x : 0.0f;
+            d = (d1 - d0) * (d1 + d0);
+        } else {
+            const float hm = (1.0f - tA) * (m0.y != 0.0f ? m0.x : Bs) + tA * (m1.y != 0.0f ? m1.x : Bs);
+            d = 2.0f * (Bs - hm - sc.y * (Bs - sc.z));
+        }
+        unsafeAtomicAdd(&ra.rds[vi], scale * d);
+    }
+}
+
+hipError_t launch_raptor_acc(const Geom *geoms, int fdt, int role, const RaptorArgs &ra, const BatchArgs &args,
+                             const unsigned char *ws, hipStream_t s)
+{
+    if (ra.npieces <= 0) return hipSuccess;
+    const size_t lds = (size_t)(2 * kMaxBins + 2) * sizeof(double);
+#define RAPTOR_ACC(F, R)                                                                                       \
+    if (fdt == F && role == R)                                                                                 \
+        hipLaunchKernelGGL((k_raptor_acc<F, R>), dim3(ra.npieces), dim3(kRaptorThreads), lds, s, geoms, ra, args, ws);
+    RAPTOR_ACC(0, 0) RAPTOR_ACC(0, 1) RAPTOR_ACC(1, 0) RAPTOR_ACC(1, 1) RAPTOR_ACC(2, 0) RAPTOR_ACC(2, 1)
+#undef RAPTOR_ACC
+    return hipGetLastError();
+}
+
+hipError_t launch_raptor_finalize(const Geom *geoms, const RaptorArgs &ra, hipStream_t s)
+{
+    const int per = kRaptorThreads / kWave;
+    hipLaunchKernelGGL(k_raptor_finalize, dim3((ra.npatch + per - 1) / per), dim3(kRaptorThreads), 0, s, geoms, ra);
+    return hipGetLastError();
+}
+
+hipError_t launch_raptor_ds(const Geom *geoms, int fdt, int role, const RaptorArgs &ra, const BatchArgs &args,
+                            const unsigned char *ws, hipStream_t s)
+{
+    if (ra.npieces <= 0) return hipSuccess;
+    const size_t lds = (size_t)kMaxBins * sizeof(float2);
+#define RAPTOR_DS(F, R)                                                                                        \
+    if (fdt == F && role == R)                                                                                 \
+        hipLaunchKernelGGL((k_raptor_ds<F, R>), dim3(ra.npieces), dim3(kRaptorThreads), lds, s, geoms, ra, args, ws);
+    RAPTOR_DS(0, 0) RAPTOR_DS(0, 1) RAPTOR_DS(1, 0) RAPTOR_DS(1, 1) RAPTOR_DS(2, 0) RAPTOR_DS(2, 1)
+#undef RAPTOR_DS
     return hipGetLastError();
 }
 

@@ -343,3 +343,21 @@ def smooth_pair(shape, k=0, n_blobs=6):
         f += a * e
         g += b * np.exp(-((x - c[0] - 0.7) ** 2 + (y - c[1] + 0.4) ** 2 + (z - c[2]) ** 2) / (2 * s * s))
     return f.astype(np.float32), g.astype(np.float32)
+
+
+def raptor_patches(fixed_dims, side=17, coverage=1.0, k=0, extra_edge=True):
+    """Seeded RaPTOR patches: int32 [n, 6] half-open cubes (x0, y0, z0, x1,
+    y1, z1) of `side` voxels, centres uniform over the fixed grid (the boxes
+    reach past the border there and are clipped by the method), n chosen so
+    the patches hold `coverage` times the grid's voxel count.  With
+    extra_edge, two more boxes are appended: one wholly outside the grid and
+    one that covers it entirely."""
+    rng = rng_for(k, 11)
+    nx, ny, nz = fixed_dims
+    n = max(1, int(round(coverage * nx * ny * nz / side ** 3)))
+    c = np.stack([rng.integers(0, d, size=n) for d in (nx, ny, nz)], axis=1)
+    lo = c - side // 2
+    boxes = np.concatenate([lo, lo + side], axis=1)
+    if extra_edge:
+        boxes = np.concatenate([boxes, [[nx + 3, 0, 0, nx + 9, ny, nz], [-2, -2, -2, nx + 2, ny + 2, nz + 2]]])
+    return boxes.astype(np.int32)
