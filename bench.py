@@ -55,8 +55,9 @@ def parse():
     ap.add_argument("--cpu-slices", type=int, default=32, help="z-slices of the oracle sample")
     ap.add_argument("--cold", action="store_true", help="also time steps with the last-level cache flushed")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--workload", default="ct256", choices=["ct256", "breathing4d"],
-                    help="ct256: the headline single pair; breathing4d: 9 phase pairs x 3 levels, batched")
+    ap.add_argument("--workload", default="ct256", choices=["ct256", "breathing4d", "raptor256"],
+                    help="ct256: the headline single pair; breathing4d: 9 phase pairs x 3 levels, batched; "
+                         "raptor256: RaPTOR value+gradient over 17^3 patches of the ct256 pair")
     return ap.parse_args()
 
 
@@ -68,6 +69,8 @@ def main():
         sys.exit(2)
     if args.workload == "breathing4d":
         return bench_breathing4d(args)
+    if args.workload == "raptor256":
+        return bench_raptor256(args)
     import numpy as np
     import torch
 
@@ -262,6 +265,97 @@ def bench_breathing4d(args):
         "alg_gb_per_s": round(alg_bytes / (ms_graph * 1e-3) / 1e9, 2),
         "ms_sequential_27_calls": round(ms_seq, 5), "ms_batched_eager": round(ms_batch, 5),
         "ms_batched_graph": round(ms_graph, 5), "speedup_vs_sequential": round(ms_seq / ms_graph, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_raptor256(args):
+    """RaPTOR (eqs 6, 13, 14) value+gradient on the ct256 pair: 1709 random 17^3
+    patches (about one cover of the grid); FFD spacing 10, displacements
+    N(0, 1.5 vox), moving as A."""
+    import numpy as np
+    import torch
+
+    import paper_1804_05061_amd as S
+    from workloads import synth
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    w = synth.ct_phantom()
+    nb, K, delta = w.n_bins, w.spatial_bins, w.ctrl_spacing
+    print(f"[bench] workload {w.name} generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    prob = S.Problem(w.fixed_dims, w.moving_dims, nb, K, delta, S.MOVING_AS_A)
+    fr = torch.from_numpy(w.fixed).cuda()
+    mr = torch.from_numpy(w.moving).cuda()
+    flo, fhi = S.minmax(fr)
+    mlo, mhi = S.minmax(mr)
+    f = S.normalize(fr, flo, fhi, nb)
+    m = S.normalize(mr, mlo, mhi, nb)
+    ffd_np = synth.random_ffd(prob.ctrl_dims, 1.5, 43)
+    ffd = torch.from_numpy(ffd_np).cuda()
+    boxes = synth.raptor_patches(w.fixed_dims, side=17, coverage=1.0, k=44, extra_edge=False)
+    plan = S.Plan(prob)
+    rp = S.RaptorPatches(plan, boxes)
+    vbuf = torch.empty((), dtype=torch.float64, device="cuda")
+    gbuf = torch.empty(prob.ffd_shape, dtype=torch.float32, device="cuda")
+    nvox = int(np.prod(w.fixed_dims))
+    lo = np.maximum(boxes[:, :3], 0)
+    hi = np.minimum(boxes[:, 3:], np.array(w.fixed_dims))
+    patch_vox = int(np.prod(np.maximum(hi - lo, 0), axis=1).sum())
+
+    for _ in range(args.warmup):
+        rp.grad(f, m, ffd, value_out=vbuf, grad_out=gbuf)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        rp.grad(f, m, ffd, value_out=vbuf, grad_out=gbuf)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = rp.profile_read()
+    plan.profile(False)
+    ms_step = 1e3 * elapsed / args.steps
+    R = float(vbuf.item())
+    print(f"[bench] {args.steps} steps in {elapsed:.4f}s, RaPTOR={R:.10f}, phases(ms total)={prof}",
+          file=sys.stderr, flush=True)
+
+    # algorithmic bytes per launch of each kernel (its inputs read once, its outputs written once):
+    #   warp pass: M read once (4 B / moving voxel)
+    #   patch sums: the warped sample (8 B) and F (4 B) per patch voxel
+    #   derivative: the same 12 B plus the 4 B per-voxel sum per patch voxel
+    #   chain rule: the per-voxel sum (4 B) and dM/dy (12 B) per fixed voxel
+    alg = {"warp": 4 * int(np.prod(w.moving_dims)), "patch_sums": 12 * patch_vox, "derivative": 16 * patch_vox,
+           "chain_rule": 16 * nvox}
+    kern = {k: prof[k] / prof["calls"] for k in alg}
+    dom = max(kern, key=kern.get)
+    achieved = alg[dom] / (kern[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "alg_bytes_per_launch": alg[dom],
+                "mean_ms": round(kern[dom], 5),
+                "phase_ms": {k: round(v / prof["calls"], 5) for k, v in prof.items() if k != "calls"}}
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        fo = O.normalize(w.fixed, flo, fhi, nb)
+        mo = O.normalize(w.moving, mlo, mhi, nb)
+        Po = O.Problem(w.fixed_dims, w.moving_dims, nb, K, delta, 0)
+        a = time.perf_counter()
+        O.raptor(Po, fo, mo, ffd_np, boxes, want_grad=True)
+        dt_cpu = time.perf_counter() - a
+        cpu = {"value": round(nvox / dt_cpu, 1), "unit": "voxel-evals/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"the whole workload (value+gradient, {len(boxes)} patches), 1 run, {dt_cpu:.2f}s"}
+
+    line = {
+        "metric": "RaPTOR value+gradient voxel-evals/s at 256x256x128", "value": round(nvox / (ms_step * 1e-3), 1),
+        "unit": "voxel-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{w.name} CT-like phantom, f32 storage, {nb} bins, {len(boxes)} random 17^3 patches "
+                               f"({patch_vox} patch voxels), FFD spacing {delta[0]}, moving as A, Phi~N(0,1.5 vox)",
+                   "voxels": nvox, "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "RaPTOR": R,
     }
     print(json.dumps(line), flush=True)
 

@@ -258,7 +258,10 @@ int srwcr_plan_info(const srwcr_plan *plan, int32_t *n_items, int32_t *value_lds
  * srwcr_profile_read synchronises the recorded events and returns the summed
  * milliseconds of the six phases -- zeroing, warp pass, value pass,
  * finalisation, gradient pass, gradient output -- and the number of calls
- * recorded.  Not thread-safe: profile one stream at a time. */
+ * recorded.  raptor_grad calls on the plan are recorded too, with the phases
+ * zeroing, warp pass, patch sums, patch finalisation, per-voxel derivative,
+ * chain rule (gradient pass and output).  Not thread-safe: profile one
+ * stream and one kind of call at a time. */
 int srwcr_profile(const srwcr_plan *plan, int32_t enable);
 int srwcr_profile_read(const srwcr_plan *plan, double ms[6], int32_t *calls);
 

@@ -313,6 +313,15 @@ class RaptorPatches:
                                            self.workspace_bytes, _stream()))
         return out
 
+    def profile_read(self) -> dict:
+        """Summed milliseconds per phase of the grad() calls recorded since
+        plan.profile(True)."""
+        ms = (ctypes.c_double * 6)()
+        n = ctypes.c_int32()
+        _lib.check(_lib.load().srwcr_profile_read(self.plan.handle, ms, ctypes.byref(n)))
+        names = ["zero", "warp", "patch_sums", "patch_finalize", "derivative", "chain_rule"]
+        return {"calls": n.value, **{k: ms[i] for i, k in enumerate(names)}}
+
     def grad(self, fixed, moving, disp, dense: bool = False, value_out=None, grad_out=None):
         """(RaPTOR, dRaPTOR/d disp), the gradient shaped like disp."""
         self._check(fixed, moving, disp, dense)

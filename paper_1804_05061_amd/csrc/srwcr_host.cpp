@@ -792,7 +792,7 @@ struct raptor_patches {
     RaptorPatch *patches_dev = nullptr;
     RaptorPiece *pieces_dev = nullptr;
     // workspace offsets beyond the plan's SRWCR slots (rds starts at ws.total)
-    size_t stats = 0, ticket = 0, tval = 0, mu = 0, scal = 0, total = 0;
+    size_t stats = 0, stats_end = 0, tval = 0, mu = 0, scal = 0, total = 0;
 };
 
 namespace {
@@ -854,13 +854,13 @@ int raptor_patches_create(const srwcr_plan *plan, const srwcr_patch *patches, in
         return hip_fail(e, "RaPTOR patch tables");
     }
     // workspace: the plan's SRWCR slots, then rds [nvox] and the zeroed patch
-    // sums with the ticket, then the finalised tables
+    // sums, then the finalised tables
     const size_t nvox = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
     size_t off = plan->ws.rds + align_up(nvox * sizeof(float), 256);
     pt->stats = off;
     off += (size_t)n * (2 * g.nb + 3) * sizeof(double);
-    pt->ticket = off;
-    off = align_up(off + sizeof(double), 256);
+    pt->stats_end = off;
+    off = align_up(off, 256);
     pt->tval = off;
     off = align_up(off + (size_t)n * sizeof(double), 256);
     pt->mu = off;
@@ -900,30 +900,42 @@ static int run_raptor(const srwcr_plan *plan, const raptor_patches *pt, const vo
     ra.npatch = pt->npatch;
     ra.npieces = pt->npieces;
     ra.stats = (double *)(ws + pt->stats);
-    ra.ticket = (unsigned *)(ws + pt->ticket);
     ra.tval = (double *)(ws + pt->tval);
     ra.mu = (float2 *)(ws + pt->mu);
     ra.scal = (float4 *)(ws + pt->scal);
     ra.rds = (float *)(ws + plan->ws.rds);
     ra.value = d_value;
-    // zero: the patch sums and the ticket, and for a gradient rds and the FFD accumulators
+    // profiled gradient calls mark: zero, warp, patch sums, patch finalise,
+    // derivative, chain rule (gradient pass and output), end
+    auto mark = [&](int k) {
+        if (with_grad) prof_mark(plan, k, s);
+    };
+    // zero: the patch sums, and for a gradient rds and the FFD accumulators
     const size_t zlo = with_grad ? plan->ws.rds : pt->stats;
-    HIP_TRY(launch_zero((double *)(ws + zlo), (pt->ticket + sizeof(double) - zlo) / sizeof(double), s), "zero launch");
+    mark(0);
+    HIP_TRY(launch_zero((double *)(ws + zlo), (pt->stats_end - zlo) / sizeof(double), s), "zero launch");
     if (with_grad && !dense)
         HIP_TRY(launch_zero((double *)(ws + plan->ws.grad), 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2], s), "zero launch");
+    mark(1);
     HIP_TRY(launch_prep(plan->geom_dev, g.mdt, dense, with_grad ? 1 : 0, plan->vblocks, plan->vrow, plan->nvblocks,
                         plan->vrow_host.back(), args, ws, plan->prep_lds, s),
             "warp launch");
+    mark(2);
     HIP_TRY(launch_raptor_acc(plan->geom_dev, g.fdt, g.role, ra, args, ws, s), "RaPTOR accumulation launch");
+    mark(3);
     HIP_TRY(launch_raptor_finalize(plan->geom_dev, ra, s), "RaPTOR finalize launch");
     if (!with_grad) return SRWCR_OK;
+    mark(4);
     HIP_TRY(launch_raptor_ds(plan->geom_dev, g.fdt, g.role, ra, args, ws, s), "RaPTOR derivative launch");
+    mark(5);
     HIP_TRY(launch_grad(plan->geom_dev, 0, 2, dense, plan->items, plan->nitems, args, ws, plan->grad_lds, s),
             "gradient launch");
     if (!dense) {
         const size_t n = 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2];
         HIP_TRY(launch_grad_out(plan->geom_dev, 1, n, args, ws, s), "gradient output launch");
     }
+    mark(6);
+    if (plan->profiling && (size_t)(plan->prof_calls + 1) * (kPhases + 1) <= plan->ev_pool.size()) ++plan->prof_calls;
     return SRWCR_OK;
 }
 

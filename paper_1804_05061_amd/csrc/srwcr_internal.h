@@ -36,7 +36,7 @@ struct WsLayout {
     size_t tables;     // float  [R][nb][4]   gradient tables (role dependent)
     size_t alpha;      // float  [R]          role B: CR_r / (sigma_r^2 Z)
     size_t grad;       // double [3][nc]      gradient accumulators
-    size_t counter;    // unsigned            finalise ticket
+    size_t counter;    // 8 B                 end of the zeroed block (unused slot)
     size_t kt;         // PrepKT [nvox]       warped moving bin and in-bin position per fixed voxel
     size_t dm;         // float  [3][nvox]    dM/dy at the warped position (gradient calls)
     size_t total;      // end of the SRWCR slots
@@ -121,7 +121,6 @@ struct RaptorArgs {
     int npatch;
     int npieces;
     double *stats;     // [npatch][2 nb + 2]: P_a, S1_a (a < nb), sum B', sum B'^2
-    unsigned *ticket;  // finalise ticket
     double *tval;      // [npatch] the patch terms T_r
     float2 *mu;        // [npatch][nb] (mu_r(a) - c_r, 1), or (0, 0) for an empty bin
     float4 *scal;      // [npatch] (1 / (N_r sigma_r^2), or 0 for a skipped patch; T_r; E1 - c_r; c_r)

@@ -1,32 +1,37 @@
 // srwcr_kernels.hip -- gfx950 kernels for the SRWCR value and gradient
-// (Gong et al., arXiv 1804.05061).
+// (Gong et al., arXiv 1804.05061) and for RaPTOR, the patch-based metric it
+// reduces to (eqs 6, 13, 14).
 //
-// Work decomposition.  The fixed grid is cut into work items that each lie in
-// one spatial-bin cell, so every voxel of an item shares the same 4x4x4
-// regions (eq 7).  One workgroup takes one item; its waves take 64-voxel row
-// segments (lane = x).  Along a row the y and z weights of the regions and of
-// the FFD are wave-uniform, which makes both B-spline sums separable.
+// Work decomposition.  The fixed grid is cut into boxes that each lie in one
+// spatial-bin cell along y and z and at most two along x, so every voxel of a
+// box draws its 64 regions (eq 7) from one 5x4x4 block.  Waves take rows of up
+// to 128 voxels (two per lane); along a row the y and z weights of the regions
+// and of the FFD are wave-uniform, which makes both B-spline sums separable.
 //
-// Value pass (eqs 3, 5, 7, 17).  Per voxel: FFD displacement from per-row
-// contracted coefficients, trilinear sample of the moving image, two Parzen
-// taps of A and the Parzen moments m1, m2 of B.  The joint PDF is never
-// formed: summed over b, eq (3) only needs per (region, A-bin) the moments
-// P = sum w h(a - A), S1 = sum w h(a - A) m1(B), S2 = sum w h(a - A) m2(B).
-// A wave folds its 64 voxels into a 5-bin window x 4 x-nodes x 3 moments
-// (60 values) and sums them across lanes with a register transpose
-// (v_permlane32/16_swap and DPP), so no two lanes ever update the same LDS
-// address; each lane then spreads one total over the 16 (y, z) regions with
-// FP64 LDS atomics.  Lanes outside the window are taken in a further pass.
-// The item histogram is merged into the global FP64 moments once per item.
+// Warp pass (eqs 8, 17, Sec. II-F).  Per row: FFD displacement from
+// contracted coefficients in LDS (or a dense field), FP64 trilinear sample of
+// the moving image, its bin k and in-bin position t and, for gradient calls,
+// dM/dy, stored per voxel for the passes that follow.
+//
+// Value pass (eqs 3, 5, 7).  The joint PDF is never formed: summed over b,
+// eq (3) only needs per (region, A-bin) the moments P = sum w h(a - A),
+// S1 = sum w h(a - A) m1(B), S2 = sum w h(a - A) m2(B).  One persistent
+// workgroup per compute unit walks a share of the rows; a wave folds its
+// voxels into windows of four A-bins x 5 x-nodes x 3 moments, sums them
+// across lanes with a register transpose (v_permlane32/16_swap and DPP) and
+// spreads each total over the 16 (y, z) regions with FP64 LDS atomics; the
+// LDS histogram is merged into the global FP64 moments when the workgroup
+// leaves a region block.
 //
 // Finalisation (eqs 4, 9-12, 18-21) runs in FP64, one wave per region, and
-// writes D and per-region gradient tables (FP32, scaled by 1/(Z sigma_r^2)).
+// writes the per-region terms and gradient tables (FP32, scaled by
+// 1/(Z sigma_r^2)); a one-wave launch sums D in region order.
 //
-// Gradient pass (eqs 16-21).  Recomputes the warp (nothing per voxel is
-// stored), interpolates the region tables through the same separable weights
-// (window row-tables per wave), forms q = dD/ds * grad M * dy/dT per voxel and
-// scatters it to the FFD nodes: per-cell moments along x, then FP64 LDS
-// atomics over the 16 (y, z) node weights, merged globally once per item.
+// Gradient pass (eqs 16-21).  Interpolates the region tables through the
+// same separable weights (row tables per wave), forms q = dD/ds * grad M *
+// dy/dT per voxel and scatters it to the FFD nodes: per-cell moments along x,
+// then FP64 LDS atomics over the 16 (y, z) node weights, merged globally once
+// per box.  A dense field's gradient is q itself.
 #include "srwcr_internal.h"
 
 #include <hip/hip_bf16.h>
@@ -765,8 +770,8 @@ hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *blocks, cons
 
 // ---------------------------------------------------------- finalisation
 // One wave per region r (lane = intensity bin a).  region[4 r + 0..3] =
-// (U_r / sigma_r^2, p_r, sigma_r^2, CR_r); the last wave to finish sums the
-// per-region terms in region order and writes D = (1/Z) sum_r U_r / sigma_r^2.
+// (U_r / sigma_r^2, p_r, sigma_r^2, CR_r), and the region's gradient tables;
+// k_value_sum then writes D = (1/Z) sum_r U_r / sigma_r^2.
 __global__ void __launch_bounds__(64)
 k_finalize(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
 {
@@ -777,8 +782,6 @@ k_finalize(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
     double *region = reinterpret_cast<double *>(ws + g.ws.region);
     float *tables = reinterpret_cast<float *>(ws + g.ws.tables);
     float *alpha = reinterpret_cast<float *>(ws + g.ws.alpha);
-    unsigned *counter = reinterpret_cast<unsigned *>(ws + g.ws.counter);
-    double *d_value = args.p[blockIdx.y].value;
     double P = 0.0, S1 = 0.0, S2 = 0.0;
     if (a < nb) {
         const double *mp = moments + ((size_t)r * nb + a) * 3;
@@ -844,30 +847,37 @@ k_finalize(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
         region[4 * r + 1] = Pr;
         region[4 * r + 2] = var;
         region[4 * r + 3] = cr;
-        __threadfence();
     }
-    // the last wave to finish sums the per-region terms: lane-strided partial
-    // sums, then the fixed wave reduction (the same order on every call)
-    unsigned ticket = 0u;
-    if (a == 0) ticket = atomicAdd(counter, 1u);
-    ticket = __builtin_amdgcn_readfirstlane(ticket);
-    if (ticket == (unsigned)g.R - 1) {
-        __threadfence();
-        double part = 0.0;
-        for (int q = a; q < g.R; q += kWave)
-            part += __hip_atomic_load(&region[4 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double D = wave_sum_d(part);
-        if (a == 0) {
-            *d_value = D * g.inv_Z;
-            *counter = 0u;
-        }
+}
+
+// D = (1/Z) sum_r U_r / sigma_r^2 of problem blockIdx.x, summed in region
+// order (lane-strided partial sums, then the fixed wave reduction), one wave.
+// A launch of its own: it sees every region's term without a device-scope
+// fence in each finalising wave.
+__global__ void __launch_bounds__(kWave) k_value_sum(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
+{
+    const Geom &g = geoms[blockIdx.x];
+    const double *region = reinterpret_cast<const double *>(ws + g.ws.region);
+    const int lane = threadIdx.x;
+    double part = 0.0;
+    for (int q0 = lane; q0 < g.R; q0 += 8 * kWave) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = q0 + u * kWave < g.R ? region[4 * (q0 + u * kWave)] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) part += x[u];
     }
+    const double D = wave_sum_d(part);
+    if (lane == 0) *args.p[blockIdx.x].value = D * g.inv_Z;
 }
 
 hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const BatchArgs &args, unsigned char *ws,
                            hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize, dim3(max_regions, nprob), dim3(64), 0, s, geoms, args, ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_value_sum, dim3(nprob), dim3(kWave), 0, s, geoms, args, ws);
     return hipGetLastError();
 }
 
@@ -1271,12 +1281,42 @@ __device__ __forceinline__ void raptor_b(const PrepKT *__restrict__ kt, const vo
     }
 }
 
-// Voxel `v` (0 .. n - 1) of a patch, x fastest: its fixed-grid index.
-__device__ __forceinline__ size_t raptor_voxel(const RaptorPatch &pt, int v, int nfx, int nfy)
-{
-    const int x = v % pt.nx, yz = v / pt.nx, y = yz % pt.ny, z = yz / pt.ny;
-    return ((size_t)(pt.z0 + z) * nfy + (pt.y0 + y)) * nfx + (pt.x0 + x);
-}
+// A lane's position inside a patch box (x fastest), advanced by a fixed
+// stride without divisions: the stride is split once as sx + nx (sy + ny sz)
+// with sx < nx and sy < ny, so each step carries at most once per axis.
+struct PatchWalk {
+    int x, y, z, sx, sy, sz;
+
+    __device__ __forceinline__ void init(const RaptorPatch &pt, int v, int stride)
+    {
+        x = v % pt.nx;
+        const int yz = v / pt.nx;
+        y = yz % pt.ny;
+        z = yz / pt.ny;
+        sx = stride % pt.nx;
+        const int r = stride / pt.nx;
+        sy = r % pt.ny;
+        sz = r / pt.ny;
+    }
+    __device__ __forceinline__ void step(const RaptorPatch &pt)
+    {
+        x += sx;
+        y += sy;
+        z += sz;
+        if (x >= pt.nx) {
+            x -= pt.nx;
+            ++y;
+        }
+        if (y >= pt.ny) {
+            y -= pt.ny;
+            ++z;
+        }
+    }
+    __device__ __forceinline__ size_t index(const RaptorPatch &pt, int nfx, int nfy) const
+    {
+        return ((size_t)(pt.z0 + z) * nfy + (pt.y0 + y)) * nfx + (pt.x0 + x);
+    }
+};
 
 // One voxel's A-bin k, in-bin position t (k = min(floor(A), L - 1)) and
 // shifted B' = (kb - ck) + (tb - ct).
@@ -1299,6 +1339,15 @@ __device__ __forceinline__ void raptor_ab(const PrepKT *__restrict__ kt, const v
     Bs = (float)(kb - ck) + (tb - ct);
 }
 
+// The patch sums.  Each lane keeps FP32 sums for a window of kRWin
+// consecutive A-bins placed around the bin of the piece's first voxel; a
+// voxel whose two taps both fall in the window only updates its registers.
+// The others (a patch across a tissue boundary) take the exact per-bin path:
+// the wave-uniform set of their bins, one cross-lane sum of h and h B' per
+// bin, added to FP64 LDS slots.  The window sums are reduced across the wave
+// once per piece.
+constexpr int kRWin = 8;
+
 template <int FDT, int ROLE>
 __global__ void __launch_bounds__(kRaptorThreads)
 k_raptor_acc(const Geom *__restrict__ geoms, RaptorArgs ra, BatchArgs args, const unsigned char *ws)
@@ -1312,36 +1361,66 @@ k_raptor_acc(const Geom *__restrict__ geoms, RaptorArgs ra, BatchArgs args, cons
     const void *__restrict__ fixed = args.p[0].fixed;
     const int nfx = g.nf[0], nfy = g.nf[1];
     for (int i = threadIdx.x; i < 2 * nb + 2; i += blockDim.x) rsh[i] = 0.0;
-    int ck;
-    float ct;
-    raptor_b<FDT, ROLE>(kt, fixed, raptor_voxel(pt, 0, nfx, nfy), ck, ct);
-    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    int ck, wb;
+    float ct;
+    {
+        PatchWalk w0;
+        w0.init(pt, 0, 1);
+        const size_t v0 = w0.index(pt, nfx, nfy);
+        raptor_b<FDT, ROLE>(kt, fixed, v0, ck, ct);
+        int k0;
+        float t0, b0;
+        raptor_ab<FDT, ROLE>(kt, fixed, v0, L, ck, ct, k0, t0, b0);
+        wb = max(0, min(k0 - kRWin / 2 + 1, nb - kRWin));              // window bins wb .. wb + kRWin - 1
+    }
+    __syncthreads();
     const int end = pc.start + pc.count;
+    float accP[kRWin], accS[kRWin];
+#pragma unroll
+    for (int j = 0; j < kRWin; ++j) accP[j] = accS[j] = 0.0f;
     double sb = 0.0, sb2 = 0.0;
-    for (int base = pc.start + wave * kWave; base < end; base += nwaves * kWave) {
-        const int v = base + lane;
-        const bool act = v < end;
-        int kA;
-        float tA, Bs;
-        raptor_ab<FDT, ROLE>(kt, fixed, raptor_voxel(pt, act ? v : base, nfx, nfy), L, ck, ct, kA, tA, Bs);
+    PatchWalk pw;
+    pw.init(pt, min(pc.start + wave * kWave + lane, pt.n - 1), nwaves * kWave);
+    for (int base = pc.start + wave * kWave; base < end; base += nwaves * kWave, pw.step(pt)) {
+        const bool act = base + lane < end;
+        int kA = 0;
+        float tA = 0.0f, Bs = 0.0f;
+        if (act) raptor_ab<FDT, ROLE>(kt, fixed, pw.index(pt, nfx, nfy), L, ck, ct, kA, tA, Bs);
         if (act) {
             sb += (double)Bs;
             sb2 += (double)Bs * (double)Bs;
         }
-        const float h0 = act ? 1.0f - tA : 0.0f, h1 = act ? tA : 0.0f;
-        const unsigned long long mine = act ? 3ull << kA : 0ull;   // bins k_A, k_A + 1 (k_A <= L - 1 <= 62)
+        const int j0 = kA - wb;
+        const bool inw = act && j0 >= 0 && j0 <= kRWin - 2;
+        const float h0 = 1.0f - tA, h1 = tA;
+        const float wh0 = inw ? h0 : 0.0f, wh1 = inw ? h1 : 0.0f;
+#pragma unroll
+        for (int j = 0; j < kRWin; ++j) {
+            const float w = j == j0 ? wh0 : (j == j0 + 1 ? wh1 : 0.0f);
+            accP[j] += w;
+            accS[j] = fmaf(w, Bs, accS[j]);
+        }
+        const unsigned long long mine = act && !inw ? 3ull << kA : 0ull;   // k_A <= L - 1 <= 62
         unsigned long long bins = (unsigned long long)wave_or_dpp((unsigned)(mine >> 32)) << 32 |
                                   wave_or_dpp((unsigned)mine);
         while (bins) {
             const int a = __builtin_ctzll(bins);
             bins &= bins - 1ull;
-            const float w = kA == a ? h0 : (kA + 1 == a ? h1 : 0.0f);
+            const float w = inw || !act ? 0.0f : (kA == a ? h0 : (kA + 1 == a ? h1 : 0.0f));
             const float p = wave_sum_f(w), q = wave_sum_f(w * Bs);
             if (lane == 0) {
                 atomicAdd(&rsh[a], (double)p);
                 atomicAdd(&rsh[nb + a], (double)q);
             }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kRWin; ++j) {
+        const float p = wave_sum_f(accP[j]), q = wave_sum_f(accS[j]);
+        if (lane == 0 && wb + j <= L && (p != 0.0f || q != 0.0f)) {
+            atomicAdd(&rsh[wb + j], (double)p);
+            atomicAdd(&rsh[nb + wb + j], (double)q);
         }
     }
     sb = wave_sum_d(sb);
@@ -1359,8 +1438,10 @@ k_raptor_acc(const Geom *__restrict__ geoms, RaptorArgs ra, BatchArgs args, cons
 
 // One wave per patch (lane = A-bin): the patch term
 //   T_r = (E[B'^2] - sum_a p_r(a) mu'_r(a)^2) / sigma_r^2,
-// mu'_r(a) = S1_a / P_a, and the tables of the derivative pass; the last wave
-// to finish writes RaPTOR = (1 / N_p) sum_r T_r, summed in patch order.
+// mu'_r(a) = S1_a / P_a, and the tables of the derivative pass.  RaPTOR
+// itself is summed by k_raptor_value in the next launch, which sees every
+// T_r without a device-scope fence per wave (each such fence writes back the
+// compute unit's L2 slice, and 1700 of them cost more than the sums).
 __global__ void __launch_bounds__(kRaptorThreads) k_raptor_finalize(const Geom *__restrict__ geoms, RaptorArgs ra)
 {
     const Geom &g = geoms[0];
@@ -1394,22 +1475,24 @@ __global__ void __launch_bounds__(kRaptorThreads) k_raptor_finalize(const Geom *
     if (lane == 0) {
         ra.scal[p] = make_float4((float)inv_nvar, (float)T, (float)E1, (float)c);
         ra.tval[p] = T;
-        __threadfence();
     }
-    unsigned ticket = 0u;
-    if (lane == 0) ticket = atomicAdd(ra.ticket, 1u);
-    ticket = __builtin_amdgcn_readfirstlane(ticket);
-    if (ticket == (unsigned)ra.npatch - 1) {
-        __threadfence();
-        double part = 0.0;
-        for (int q = lane; q < ra.npatch; q += kWave)
-            part += __hip_atomic_load(&ra.tval[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double R = wave_sum_d(part);
-        if (lane == 0) {
-            *ra.value = R / (double)ra.npatch;
-            *ra.ticket = 0u;
-        }
+}
+
+// RaPTOR = (1 / N_p) sum_r T_r, summed in patch order (lane-strided partial
+// sums, then the fixed wave reduction), one wave.
+__global__ void __launch_bounds__(kWave) k_raptor_value(RaptorArgs ra)
+{
+    const int lane = threadIdx.x;
+    double part = 0.0;
+    for (int q0 = lane; q0 < ra.npatch; q0 += 8 * kWave) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = q0 + u * kWave < ra.npatch ? ra.tval[q0 + u * kWave] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) part += x[u];
     }
+    const double R = wave_sum_d(part);
+    if (lane == 0) *ra.value = R / (double)ra.npatch;
 }
 
 // Derivative pass: per patch voxel, dT_r/ds_M (the exact derivative of eq 13
@@ -1435,12 +1518,14 @@ k_raptor_ds(const Geom *__restrict__ geoms, RaptorArgs ra, BatchArgs args, const
     for (int i = threadIdx.x; i < nb; i += blockDim.x) rmu[i] = ra.mu[(size_t)pc.patch * nb + i];
     int ck;
     float ct;
-    raptor_b<FDT, ROLE>(kt, fixed, raptor_voxel(pt, 0, nfx, nfy), ck, ct);
+    raptor_b<FDT, ROLE>(kt, fixed, ((size_t)pt.z0 * nfy + pt.y0) * nfx + pt.x0, ck, ct);
     __syncthreads();
     const float scale = sc.x / (float)ra.npatch;
     const int end = pc.start + pc.count;
-    for (int v = pc.start + threadIdx.x; v < end; v += blockDim.x) {
-        const size_t vi = raptor_voxel(pt, v, nfx, nfy);
+    PatchWalk pw;
+    pw.init(pt, min(pc.start + (int)threadIdx.x, pt.n - 1), blockDim.x);
+    for (int v = pc.start + threadIdx.x; v < end; v += blockDim.x, pw.step(pt)) {
+        const size_t vi = pw.index(pt, nfx, nfy);
         int kA;
         float tA, Bs;
         raptor_ab<FDT, ROLE>(kt, fixed, vi, L, ck, ct, kA, tA, Bs);
@@ -1474,6 +1559,9 @@ hipError_t launch_raptor_finalize(const Geom *geoms, const RaptorArgs &ra, hipSt
 {
     const int per = kRaptorThreads / kWave;
     hipLaunchKernelGGL(k_raptor_finalize, dim3((ra.npatch + per - 1) / per), dim3(kRaptorThreads), 0, s, geoms, ra);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_raptor_value, dim3(1), dim3(kWave), 0, s, ra);
     return hipGetLastError();
 }
 

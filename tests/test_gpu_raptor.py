@@ -59,9 +59,11 @@ def test_raptor_matches_oracle(orc, role, dense):
     assert rel(g2.cpu().numpy(), gg) <= 1e-6
 
 
-def test_raptor_ct256_full_size(orc):
-    """256x256x128 CT phantom, 64 bins, ~1.0x coverage by 17^3 patches: value
-    and FFD gradient of the whole workload against the oracle."""
+@pytest.mark.parametrize("edge", [False, True])
+def test_raptor_ct256_full_size(orc, edge):
+    """256x256x128 CT phantom, 64 bins, ~1.0x coverage by 17^3 patches (the
+    benchmark's set; with `edge`, plus a patch outside the grid and one over
+    all of it): value and FFD gradient of the whole workload against the oracle."""
     import paper_1804_05061_amd as S
     w = synth.ct_phantom()
     fr, mr = w.fixed, w.moving
@@ -71,7 +73,7 @@ def test_raptor_ct256_full_size(orc):
     f = S.normalize(torch.from_numpy(fr).cuda(), flo, fhi, w.n_bins)
     m = S.normalize(torch.from_numpy(mr).cuda(), mlo, mhi, w.n_bins)
     ffd = synth.random_ffd(P.ctrl_dims, 1.5, 43)
-    boxes = synth.raptor_patches(w.fixed_dims, side=17, coverage=1.0, k=44)
+    boxes = synth.raptor_patches(w.fixed_dims, side=17, coverage=1.0, k=44, extra_edge=edge)
     plan = S.Plan(P)
     rp = S.RaptorPatches(plan, boxes)
     v, g = rp.grad(f, m, torch.from_numpy(ffd).cuda())
@@ -81,7 +83,7 @@ def test_raptor_ct256_full_size(orc):
     mo = orc.normalize(mr, mlo, mhi, w.n_bins)
     vr, gr = orc.raptor(Po, fo, mo, ffd, boxes, want_grad=True)
     gg = g.cpu().numpy().astype(np.float64)
-    print(f"raptor ct256 ({len(boxes)} patches): {float(v):.12f} oracle {vr:.12f} "
+    print(f"raptor ct256 edge={edge} ({len(boxes)} patches): {float(v):.12f} oracle {vr:.12f} "
           f"(rel {abs(float(v) - vr) / vr:.1e}); grad rel {rel(gg, gr):.2e}", flush=True)
     assert abs(float(v) - vr) <= 1e-5 * vr
     assert rel(gg, gr) <= 1e-4
