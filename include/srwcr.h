@@ -56,7 +56,9 @@ typedef struct {
     int32_t fixed_dims[3];     /* (nx, ny, nz) of F, each >= 2 */
     int32_t moving_dims[3];    /* (mx, my, mz) of M, each >= 2 */
     int32_t n_bins;            /* L_eps + 1 intensity bins, 2..64 (the paper uses 32) */
-    int32_t spatial_bins[3];   /* K cubic B-spline spatial bins per axis, each 4..64 */
+    int32_t spatial_bins[3];   /* K cubic B-spline spatial bins per axis, each 4..64; all three 0:
+                                  the regions are the FFD nodes (the paper's setting, Sec. II-C),
+                                  K = n_c per axis, node j at (j - 1) ctrl_spacing */
     int32_t ctrl_spacing[3];   /* FFD control spacing delta in fixed voxels, each >= 1 */
     int32_t role;              /* srwcr_role */
     int32_t fixed_dtype;       /* srwcr_dtype of the normalised fixed volume */

@@ -35,7 +35,7 @@ def build(force: bool = True) -> str:
 class _Problem(ctypes.Structure):
     _fields_ = [("nf", ctypes.c_int * 3), ("nm", ctypes.c_int * 3), ("n_bins", ctypes.c_int),
                 ("K", ctypes.c_int * 3), ("delta", ctypes.c_int * 3), ("role", ctypes.c_int),
-                ("dense", ctypes.c_int)]
+                ("dense", ctypes.c_int), ("at_nodes", ctypes.c_int)]
 
 
 @dataclass(frozen=True)
@@ -44,7 +44,8 @@ class Problem:
 
     role 0: the moving image plays A (the model image); role 1: it plays B
     (the estimated image) -- Sec. II-E / Table II.  spatial_bins == (1, 1, 1)
-    selects one constant region (a test-only special case).  dense: the
+    selects one constant region (a test-only special case); (0, 0, 0) puts
+    the regions on the FFD nodes, K = n_c per axis (the paper's setting, Sec. II-C).  dense: the
     displacements are a dense field u (3, nz, ny, nx) on the fixed grid,
     T(x) = x + u(x), instead of FFD coefficients."""
     fixed_dims: tuple   # (nx, ny, nz)
@@ -60,7 +61,8 @@ class Problem:
         p.nf[:] = list(self.fixed_dims)
         p.nm[:] = list(self.moving_dims)
         p.n_bins = self.n_bins
-        p.K[:] = list(self.spatial_bins)
+        p.K[:] = list(self.ctrl_dims if self.at_nodes else self.spatial_bins)
+        p.at_nodes = 1 if self.at_nodes else 0
         p.delta[:] = list(self.ctrl_spacing)
         p.role = self.role
         p.dense = 1 if self.dense else 0
@@ -73,7 +75,12 @@ class Problem:
 
     @property
     def n_regions(self) -> int:
-        return int(np.prod(self.spatial_bins))
+        return int(np.prod(self.ctrl_dims if self.at_nodes else self.spatial_bins))
+
+    @property
+    def at_nodes(self) -> bool:
+        """spatial_bins == (0, 0, 0): the regions are the FFD nodes (the paper's setting)."""
+        return tuple(self.spatial_bins) == (0, 0, 0)
 
 
 _lib = None
@@ -98,6 +105,8 @@ def lib():
         L.orc_normalize.argtypes = [fp, ctypes.c_long, ctypes.c_double, ctypes.c_double, ctypes.c_int, fp]
         L.orc_axis_region_weights.restype = None
         L.orc_axis_region_weights.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_axis_node_weights.restype = None
+        L.orc_axis_node_weights.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.orc_ffd_T.restype = None
         L.orc_ffd_T.argtypes = [pp, fp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.orc_sample.restype = ctypes.c_double
@@ -158,6 +167,14 @@ def axis_region_weights(x: int, N: int, K: int) -> np.ndarray:
     """Spatial weights of the K nodes of one axis at voxel x, eqs (7, 8)."""
     w = np.zeros(K, dtype=np.float64)
     lib().orc_axis_region_weights(int(x), int(N), int(K), _f64(w))
+    return w
+
+
+def axis_node_weights(x: int, delta: int, K: int) -> np.ndarray:
+    """Spatial weights of the K FFD-lattice nodes of one axis at voxel x (regions
+    at the control points, Sec. II-C)."""
+    w = np.zeros(K, dtype=np.float64)
+    lib().orc_axis_node_weights(int(x), int(delta), int(K), _f64(w))
     return w
 
 

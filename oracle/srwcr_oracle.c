@@ -57,6 +57,8 @@ typedef struct {
     int role;       /* 0: the moving image is A (model); 1: it is B (estimated) */
     int dense;      /* 0: displacements are FFD coefficients (eq 17); 1: a dense field
                        u[3][nz][ny][nx] on the fixed grid, T(x) = x + u(x) */
+    int at_nodes;   /* 1: the regions are the FFD nodes (the paper's setting, Sec. II-C):
+                       K = n_c per axis, spacing delta, cell floor(x / delta) */
 } orc_problem;
 
 #define VAR_REL 1e-5   /* degenerate region: sigma_r^2 <= VAR_REL * E_r[b^2] */
@@ -134,6 +136,23 @@ void orc_axis_region_weights(int x, int N, int K, double *w)
     if (c > K - 4) c = K - 4;
     double t = (double)(num - (long)c * (long)(N - 1)) / (double)(N - 1);
     for (int l = 0; l < 4; ++l) w[c + l] = orc_beta(l, t);
+}
+
+/* Weights of the K = n_c nodes of one axis when the regions sit on the FFD
+ * lattice (eq 7 with the control points of eq 17 as region centres): node
+ * c + l, c = floor(x / delta), carries beta_l((x mod delta) / delta). */
+void orc_axis_node_weights(int x, int delta, int K, double *w)
+{
+    for (int j = 0; j < K; ++j) w[j] = 0.0;
+    int c = x / delta;
+    double eta = (double)(x % delta) / delta;
+    for (int l = 0; l < 4; ++l) w[c + l] = orc_beta(l, eta);
+}
+
+static void axis_weights(const orc_problem *P, int e, int x, double *w)
+{
+    if (P->at_nodes) orc_axis_node_weights(x, P->delta[e], P->K[e], w);
+    else orc_axis_region_weights(x, P->nf[e], P->K[e], w);
 }
 
 /* ----------------------------------------------- T(x; Phi), eqs (8, 17)
@@ -315,11 +334,11 @@ void orc_joint_mass_box(const orc_problem *P, const float *fix, const float *mov
     double *wy = (double *)malloc(sizeof(double) * P->K[1]);
     double *wz = (double *)malloc(sizeof(double) * P->K[2]);
     for (int z = box[4]; z < box[5]; ++z) {
-        orc_axis_region_weights(z, P->nf[2], P->K[2], wz);
+        axis_weights(P, 2, z, wz);
         for (int y = box[2]; y < box[3]; ++y) {
-            orc_axis_region_weights(y, P->nf[1], P->K[1], wy);
+            axis_weights(P, 1, y, wy);
             for (int x = box[0]; x < box[1]; ++x) {
-                orc_axis_region_weights(x, P->nf[0], P->K[0], wx);
+                axis_weights(P, 0, x, wx);
                 voxel_mass(P, fix, mov, ffd, x, y, z, wx, wy, wz, q);
             }
         }
@@ -350,11 +369,11 @@ double orc_joint_pdf(const orc_problem *P, const float *fix, const float *mov, c
         double *wz = (double *)malloc(sizeof(double) * P->K[2]);
 #pragma omp for schedule(static)
         for (int z = 0; z < P->nf[2]; ++z) {
-            orc_axis_region_weights(z, P->nf[2], P->K[2], wz);
+            axis_weights(P, 2, z, wz);
             for (int y = 0; y < P->nf[1]; ++y) {
-                orc_axis_region_weights(y, P->nf[1], P->K[1], wy);
+                axis_weights(P, 1, y, wy);
                 for (int x = 0; x < P->nf[0]; ++x) {
-                    orc_axis_region_weights(x, P->nf[0], P->K[0], wx);
+                    axis_weights(P, 0, x, wx);
                     voxel_mass(P, fix, mov, ffd, x, y, z, wx, wy, wz, pp);
                 }
             }
@@ -610,11 +629,11 @@ double orc_gradient(const orc_problem *P, const float *fix, const float *mov, co
         double *wz = (double *)malloc(sizeof(double) * P->K[2]);
 #pragma omp for schedule(static)
         for (int z = 0; z < P->nf[2]; ++z) {
-            orc_axis_region_weights(z, P->nf[2], P->K[2], wz);
+            axis_weights(P, 2, z, wz);
             for (int y = 0; y < P->nf[1]; ++y) {
-                orc_axis_region_weights(y, P->nf[1], P->K[1], wy);
+                axis_weights(P, 1, y, wy);
                 for (int x = 0; x < P->nf[0]; ++x) {
-                    orc_axis_region_weights(x, P->nf[0], P->K[0], wx);
+                    axis_weights(P, 0, x, wx);
                     double A, B, dsdT[3];
                     voxel_AB(P, fix, mov, ffd, x, y, z, &A, &B, dsdT);
                     double g = dDdM_voxel(P, form, A, B, Z, wx, wy, wz, st, pa, mua);

@@ -95,6 +95,16 @@ class Problem:
         """Dense displacement field u[3][nz][ny][nx] on the fixed grid."""
         return (3,) + tuple(self.fixed_dims[::-1])
 
+    @property
+    def at_nodes(self) -> bool:
+        """spatial_bins (0, 0, 0): the regions are the FFD nodes (Sec. II-C)."""
+        return tuple(self.spatial_bins) == (0, 0, 0)
+
+    @property
+    def n_regions(self) -> int:
+        k = self.ctrl_dims if self.at_nodes else self.spatial_bins
+        return int(k[0]) * int(k[1]) * int(k[2])
+
 
 class Plan:
     """A plan (device tables and launch geometry) plus its own workspace."""
@@ -206,7 +216,7 @@ class Plan:
     def debug_moments(self, fixed, moving, ffd):
         """Raw (P, S1, S2) moment slots [R, n_bins, 3] of the value pass."""
         self._check_inputs(fixed, moving, ffd)
-        R = int(torch.tensor(self.problem.spatial_bins).prod())
+        R = self.problem.n_regions
         out = torch.empty((R, self.problem.n_bins, 3), dtype=torch.float64, device=fixed.device)
         _lib.check(_lib.load().srwcr_debug_moments(self._h, _ptr(fixed), _ptr(moving), _ptr(ffd), _ptr(out),
                                                    _ptr(self.workspace), self.workspace_bytes, _stream()))

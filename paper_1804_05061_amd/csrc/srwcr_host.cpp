@@ -48,12 +48,14 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int validate_problem(const srwcr_problem *p)
 {
     if (!p) return fail(SRWCR_E_INVALID_ARG, "problem is NULL");
+    const bool at_nodes = p->spatial_bins[0] == 0 && p->spatial_bins[1] == 0 && p->spatial_bins[2] == 0;
     for (int e = 0; e < 3; ++e) {
         if (p->fixed_dims[e] < 2 || p->moving_dims[e] < 2)
             return fail(SRWCR_E_INVALID_ARG, "grid axis %d must have at least 2 voxels (fixed %d, moving %d)", e,
                         p->fixed_dims[e], p->moving_dims[e]);
-        if (p->spatial_bins[e] < 4 || p->spatial_bins[e] > 64)
-            return fail(SRWCR_E_INVALID_ARG, "spatial_bins[%d] = %d outside 4..64", e, p->spatial_bins[e]);
+        if (!at_nodes && (p->spatial_bins[e] < 4 || p->spatial_bins[e] > 64))
+            return fail(SRWCR_E_INVALID_ARG, "spatial_bins[%d] = %d outside 4..64 (all three 0: regions at the FFD "
+                        "nodes)", e, p->spatial_bins[e]);
         if (p->ctrl_spacing[e] < 1)
             return fail(SRWCR_E_INVALID_ARG, "ctrl_spacing[%d] = %d must be >= 1", e, p->ctrl_spacing[e]);
         if ((int64_t)p->fixed_dims[e] > (1 << 20) || (int64_t)p->moving_dims[e] > (1 << 20))
@@ -147,6 +149,7 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
     *out = nullptr;
     int st = validate_problem(prob);
     if (st != SRWCR_OK) return st;
+    const bool at_nodes = prob->spatial_bins[0] == 0;   // validated: all three 0, regions at the FFD nodes
     srwcr_plan *P = new srwcr_plan();
     P->prob = *prob;
     Geom &g = P->g;
@@ -154,9 +157,9 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
     for (int e = 0; e < 3; ++e) {
         g.nf[e] = prob->fixed_dims[e];
         g.nm[e] = prob->moving_dims[e];
-        g.K[e] = prob->spatial_bins[e];
         g.delta[e] = prob->ctrl_spacing[e];
         g.nc[e] = (g.nf[e] - 1) / g.delta[e] + 4;
+        g.K[e] = at_nodes ? g.nc[e] : prob->spatial_bins[e];
         g.same_grid[e] = g.nm[e] == g.nf[e];
         g.ratio[e] = (float)((double)g.nm[e] / (double)g.nf[e]);
         g.ratio_d[e] = (double)g.nm[e] / (double)g.nf[e];
@@ -187,11 +190,19 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         std::vector<double4> ffd_w(N);
         std::vector<double> mv_frac(N);
         for (int x = 0; x < N; ++x) {
-            // spatial bins: node j at (j - 1) (N - 1) / (K - 3); integer cell arithmetic
-            const long num = (long)x * (K - 3);
-            int c = (int)(num / (N - 1));
-            if (c > K - 4) c = K - 4;
-            const double t = (double)(num - (long)c * (N - 1)) / (double)(N - 1);
+            // spatial bins: node j at (j - 1) (N - 1) / (K - 3), integer cell
+            // arithmetic; or, with the regions at the FFD nodes, node j at (j - 1) delta
+            int c;
+            double t;
+            if (at_nodes) {
+                c = x / g.delta[e];
+                t = (double)(x % g.delta[e]) / g.delta[e];
+            } else {
+                const long num = (long)x * (K - 3);
+                c = (int)(num / (N - 1));
+                if (c > K - 4) c = K - 4;
+                t = (double)(num - (long)c * (N - 1)) / (double)(N - 1);
+            }
             sp_cell[x] = c;
             sp_w[x] = make_float4((float)bspline_piece(0, t), (float)bspline_piece(1, t), (float)bspline_piece(2, t),
                                   (float)bspline_piece(3, t));

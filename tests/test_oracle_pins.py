@@ -512,3 +512,78 @@ def test_constant_estimated_image_closed_forms(orc, role):
         assert abs(D - expect) < 1e-12
         if expect == 0.0:
             assert np.abs(g).max() == 0.0
+
+
+# ------------------------- regions on the FFD nodes (the paper's setting)
+def test_node_weights_partition_and_interior_mass(orc):
+    """Regions at the control points (Sec. II-C, eq 7 with eq 17's lattice):
+    the weights of a voxel sum to 1, each is the centred cubic B-spline of
+    the voxel's distance to its node in units of delta, and over the integer
+    voxels of its whole support an interior node holds mass exactly delta."""
+    N, d = 41, 5
+    K = (N - 1) // d + 4
+    tot = np.zeros(K)
+    for x in range(N):
+        w = orc.axis_node_weights(x, d, K)
+        assert abs(w.sum() - 1.0) < 1e-15
+        for j in range(K):                         # stored node j sits at (j - 1) delta
+            assert abs(w[j] - cubic_bspline_kernel((x - (j - 1) * d) / d)) < 1e-15
+        tot += w
+    interior = range(3, N // d)                    # support ((j - 3) d, (j + 1) d) inside [0, N - 1]
+    assert len(interior) >= 4
+    for j in interior:
+        assert abs(tot[j] - d) < 1e-12, (j, tot[j])
+
+
+def test_node_regions_joint_pdf_marginal(orc):
+    """p(r) of eq (3) with regions at the FFD nodes: Z = |Omega| and interior
+    regions hold (delta^3 / Z) whatever the images."""
+    nx, ny, nz, d = 26, 27, 21, 5
+    p = orc.Problem((nx, ny, nz), (nx, ny, nz), 16, (0, 0, 0), (d, d, d), 0)
+    fr, mr = synth.smooth_pair((nz, ny, nx), k=21)
+    f = orc.normalize(fr, fr.min(), fr.max(), 16)
+    m = orc.normalize(mr, mr.min(), mr.max(), 16)
+    ffd = synth.random_ffd(p.ctrl_dims, 0.8, 22)
+    pdf, Z = orc.joint_pdf(p, f, m, ffd)
+    assert pdf.shape[0] == int(np.prod(p.ctrl_dims))
+    assert abs(Z - nx * ny * nz) < 1e-9
+    pr = pdf.sum(axis=(1, 2)).reshape(p.ctrl_dims[::-1]) * Z
+    ncx, ncy, ncz = p.ctrl_dims
+    inner = pr[3:nz // d, 3:ny // d, 3:nx // d]       # nodes whose whole support lies in the grid
+    assert inner.size > 0 and np.allclose(inner, d ** 3, atol=1e-9)
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_node_regions_D_zero_forms_and_gradient(orc, role):
+    """Regions at the FFD nodes: D = 0 for B = f(A) on bin centres, the four
+    value forms agree in [0, 1], and the gradient matches central differences."""
+    rng = np.random.default_rng(23 + role)
+    nx, ny, nz, nb = 13, 12, 11, 16
+    labels = rng.integers(0, nb, size=(nz, ny, nx))
+    A = labels.astype(np.float32)
+    B = rng.permutation(nb)[labels].astype(np.float32)
+    p = orc.Problem((nx, ny, nz), (nx, ny, nz), nb, (0, 0, 0), (4, 4, 4), role)
+    fixed, moving = (B, A) if role == 0 else (A, B)
+    assert abs(orc.value(p, fixed, moving, np.zeros((3,) + p.ctrl_dims[::-1], np.float32))) < 1e-14
+
+    fr, mr = synth.smooth_pair((14, 14, 14), k=24 + role)
+    nb = 24
+    f = orc.normalize(fr, fr.min(), fr.max(), nb)
+    m = orc.normalize(mr, mr.min(), mr.max(), nb)
+    p = orc.Problem((14, 14, 14), (14, 14, 14), nb, (0, 0, 0), (5, 5, 5), role)
+    ffd = synth.random_ffd(p.ctrl_dims, 0.8, 25 + role)
+    pdf, _ = orc.joint_pdf(p, f, m, ffd)
+    vals = [orc.srwcr_from_pdf(pdf, w) for w in range(4)]
+    assert max(vals) - min(vals) < 1e-13 and 0.0 <= vals[0] <= 1.0
+    D, g = orc.gradient(p, f, m, ffd)
+    idx = np.argsort(-np.abs(g).ravel())[:40]
+    fd = []
+    for i in idx:
+        fp_, fm_ = ffd.copy().ravel(), ffd.copy().ravel()
+        fp_[i] = np.float32(float(ffd.ravel()[i]) + 1e-4)
+        fm_[i] = np.float32(float(ffd.ravel()[i]) - 1e-4)
+        hh = float(fp_[i]) - float(fm_[i])
+        fd.append((orc.value(p, f, m, fp_.reshape(ffd.shape)) - orc.value(p, f, m, fm_.reshape(ffd.shape))) / hh)
+    fd = np.array(fd)
+    an = g.ravel()[idx]
+    assert np.linalg.norm(fd - an) <= 1e-4 * np.linalg.norm(an)
