@@ -123,6 +123,8 @@ def lib():
         L.orc_value.argtypes = [pp, fp, fp, fp]
         L.orc_gradient.restype = ctypes.c_double
         L.orc_gradient.argtypes = [pp, fp, fp, fp, ctypes.c_int, dp, dp]
+        L.orc_gradient_fixed.restype = ctypes.c_double
+        L.orc_gradient_fixed.argtypes = [pp, fp, fp, fp, ctypes.c_int, dp]
         L.orc_raptor.restype = ctypes.c_double
         L.orc_raptor.argtypes = [pp, fp, fp, fp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
@@ -305,6 +307,19 @@ def gradient(P: Problem, fixed: np.ndarray, moving: np.ndarray, ffd: np.ndarray,
     D = lib().orc_gradient(ctypes.byref(P.c()), fxp, mp, fp, int(form), _f64(g),
                            _f64(dm) if dm is not None else None)
     return (D, g, dm) if want_dDdM else (D, g)
+
+
+def gradient_fixed(P: Problem, fixed: np.ndarray, moving: np.ndarray, disp: np.ndarray, form: int = 0):
+    """(D, dD/ds_F[nz, ny, nx]): the derivative of D with respect to the
+    normalised fixed intensity at every voxel (eq 19 or 21 for the fixed
+    image's role; form 1: eqs 18/20 with 26)."""
+    fx, fxp = _f32(fixed)
+    m, mp = _f32(moving)
+    f, fp = _f32(disp)
+    nx, ny, nz = P.fixed_dims
+    g = np.zeros((nz, ny, nx))
+    D = lib().orc_gradient_fixed(ctypes.byref(P.c()), fxp, mp, fp, int(form), _f64(g))
+    return D, g
 
 
 def raptor(P: Problem, fixed: np.ndarray, moving: np.ndarray, disp: np.ndarray, patches,

@@ -669,6 +669,51 @@ double orc_gradient(const orc_problem *P, const float *fix, const float *mov, co
     return D;
 }
 
+/* dD/ds_F: the derivative of D with respect to the normalised fixed intensity
+ * at every fixed voxel (a dense field [nz][ny][nx]).  The fixed image is B
+ * when the moving image is A and A otherwise, so its derivative is eq (19)
+ * (form 0) or eqs (18), (26) (form 1) when it is B, and eq (21) or eqs (20),
+ * (26) when it is A; the per-voxel routine takes the formula from the role,
+ * so it runs on a copy of the problem with the role flipped while A and B
+ * keep their images.  Returns D. */
+double orc_gradient_fixed(const orc_problem *P, const float *fix, const float *mov, const float *disp, int form,
+                          double *dDdF)
+{
+    int R = n_regions(P), nb = P->n_bins;
+    double *p = (double *)malloc(sizeof(double) * (size_t)R * nb * nb);
+    double Z = orc_joint_pdf(P, fix, mov, disp, p);
+    double D = orc_srwcr_from_pdf(R, nb, p, 0);
+    region_stats *st = (region_stats *)malloc(sizeof(region_stats) * R);
+    double *pa = (double *)malloc(sizeof(double) * R * nb), *mua = (double *)malloc(sizeof(double) * R * nb);
+    region_statistics(R, nb, p, st, pa, mua);
+    free(p);
+    orc_problem Pf = *P;
+    Pf.role = 1 - P->role;
+#pragma omp parallel
+    {
+        double *wx = (double *)malloc(sizeof(double) * P->K[0]);
+        double *wy = (double *)malloc(sizeof(double) * P->K[1]);
+        double *wz = (double *)malloc(sizeof(double) * P->K[2]);
+#pragma omp for schedule(static)
+        for (int z = 0; z < P->nf[2]; ++z) {
+            axis_weights(P, 2, z, wz);
+            for (int y = 0; y < P->nf[1]; ++y) {
+                axis_weights(P, 1, y, wy);
+                for (int x = 0; x < P->nf[0]; ++x) {
+                    axis_weights(P, 0, x, wx);
+                    double A, B;
+                    voxel_AB(P, fix, mov, disp, x, y, z, &A, &B, NULL);
+                    long vi = ((long)z * P->nf[1] + y) * P->nf[0] + x;
+                    dDdF[vi] = dDdM_voxel(&Pf, form, A, B, Z, wx, wy, wz, st, pa, mua);
+                }
+            }
+        }
+        free(wx); free(wy); free(wz);
+    }
+    free(st); free(pa); free(mua);
+    return D;
+}
+
 /* ------------------------------------------------ RaPTOR, eqs (6), (13), (14)
  * Boxcar patches (eq 6): patches[6 r .. 6 r + 5] = x0, y0, z0, x1, y1, z1, a
  * half-open box on the fixed grid (clipped to it); N_r is its voxel count and

@@ -587,3 +587,49 @@ def test_node_regions_D_zero_forms_and_gradient(orc, role):
     fd = np.array(fd)
     an = g.ravel()[idx]
     assert np.linalg.norm(fd - an) <= 1e-4 * np.linalg.norm(an)
+
+
+# ------------------------------- derivative with respect to the fixed image
+@pytest.mark.parametrize("role", [0, 1])
+def test_fixed_image_gradient_central_differences(orc, role):
+    """dD/ds_F per voxel (eq 19 or 21 for the fixed image's role) against
+    central differences of D in single fixed voxels, and eqs 19/21 against
+    eqs 18/20 with (26)."""
+    fr, mr = synth.smooth_pair((12, 13, 14), k=30 + role)
+    nb = 24
+    f = orc.normalize(fr, fr.min(), fr.max(), nb)
+    m = orc.normalize(mr, mr.min(), mr.max(), nb)
+    p = P(orc, (14, 13, 12), nb=nb, K=(4, 4, 4), d=(5, 5, 5), role=role)
+    ffd = synth.random_ffd(p.ctrl_dims, 0.8, 31 + role)
+    D, g = orc.gradient_fixed(p, f, m, ffd)
+    D1, g1 = orc.gradient_fixed(p, f, m, ffd, form=1)
+    assert abs(D - orc.value(p, f, m, ffd)) < 1e-15 and abs(D1 - D) < 1e-15
+    assert np.abs(g1 - g).max() <= 1e-12 * np.abs(g).max()
+    idx = np.argsort(-np.abs(g).ravel())[:40]
+    fd = []
+    for i in idx:
+        fp_, fm_ = f.copy().ravel(), f.copy().ravel()
+        fp_[i] = np.float32(float(f.ravel()[i]) + 1e-3)
+        fm_[i] = np.float32(float(f.ravel()[i]) - 1e-3)
+        hh = float(fp_[i]) - float(fm_[i])
+        fd.append((orc.value(p, fp_.reshape(f.shape), m, ffd) - orc.value(p, fm_.reshape(f.shape), m, ffd)) / hh)
+    fd = np.array(fd)
+    an = g.ravel()[idx]
+    assert np.linalg.norm(fd - an) <= 1e-4 * np.linalg.norm(an), np.linalg.norm(fd - an) / np.linalg.norm(an)
+
+
+def test_fixed_image_gradient_is_the_swapped_moving_gradient(orc):
+    """With the identity warp and equal grids, the pair (fixed F, moving M,
+    moving as A) has the same A and B as (fixed M, moving F, moving as B), so
+    dD/ds_F of the first equals dD/ds_M of the second."""
+    fr, mr = synth.smooth_pair((12, 12, 12), k=33)
+    nb = 24
+    f = orc.normalize(fr, fr.min(), fr.max(), nb)
+    m = orc.normalize(mr, mr.min(), mr.max(), nb)
+    p0 = P(orc, (12, 12, 12), nb=nb, K=(4, 4, 4), d=(4, 4, 4), role=0)
+    p1 = P(orc, (12, 12, 12), nb=nb, K=(4, 4, 4), d=(4, 4, 4), role=1)
+    zero = np.zeros((3,) + p0.ctrl_dims[::-1], np.float32)
+    D0, gF = orc.gradient_fixed(p0, f, m, zero)
+    D1, _, gM = orc.gradient(p1, m, f, zero, want_dDdM=True)
+    assert abs(D0 - D1) < 1e-14
+    assert np.abs(gF - gM).max() <= 1e-12 * np.abs(gM).max()
