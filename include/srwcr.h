@@ -123,6 +123,18 @@ int srwcr_eval_dense(const srwcr_plan *plan, const void *fixed, const void *movi
 int srwcr_grad_dense(const srwcr_plan *plan, const void *fixed, const void *moving, const float *field,
                      double *d_value, float *d_grad, void *workspace, size_t workspace_bytes, void *stream);
 
+/* dD/ds_F: the derivative of D with respect to the normalised fixed intensity
+ * at every fixed voxel, written to d_grad_fixed, a device float32 volume of
+ * the fixed dims [nz][ny][nx] (it makes the fixed image a differentiable
+ * input too, e.g. a network's output).  The fixed image plays B when the
+ * moving image is A (eq 19) and A otherwise (eq 21), with the one-sided
+ * window derivatives of srwcr_grad; the derivative is with respect to the
+ * stored normalised value, so a caller that normalised raw intensities with
+ * srwcr_normalize multiplies by L / (hi - lo).  disp is the FFD (dense = 0)
+ * or a dense field [3][nz][ny][nx] (dense = 1); d_value receives D. */
+int srwcr_grad_fixed(const srwcr_plan *plan, const void *fixed, const void *moving, const float *disp, int32_t dense,
+                     double *d_value, float *d_grad_fixed, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Batched value + gradient over up to SRWCR_MAX_BATCH independent problems
  * (e.g. the phases of a 4-D series times the levels of their pyramids): one
  * launch per pass covers every problem, so small problems share the device

@@ -191,6 +191,23 @@ class Plan:
                                                 _stream()))
         return value_out, grad_out
 
+    def grad_fixed(self, fixed, moving, disp, dense: bool = False, value_out=None, grad_out=None):
+        """(D, dD/ds_F[nz][ny][nx]): the derivative with respect to the normalised
+        fixed intensity per voxel; disp is the FFD, or a dense field when dense."""
+        if dense:
+            self._check_dense(fixed, moving, disp)
+        else:
+            self._check_inputs(fixed, moving, disp)
+        if value_out is None:
+            value_out = torch.empty((), dtype=torch.float64, device=fixed.device)
+        if grad_out is None:
+            grad_out = torch.empty(self.problem.fixed_shape, dtype=torch.float32, device=fixed.device)
+        _need_cuda(grad_out, "grad_out", torch.float32, self.problem.fixed_shape)
+        _lib.check(_lib.load().srwcr_grad_fixed(self._h, _ptr(fixed), _ptr(moving), _ptr(disp), 1 if dense else 0,
+                                                _ptr(value_out), _ptr(grad_out), _ptr(self.workspace),
+                                                self.workspace_bytes, _stream()))
+        return value_out, grad_out
+
     def warp(self, moving, ffd, out=None):
         """Backward-warped moving volume on the fixed grid (float32)."""
         p = self.problem
@@ -401,38 +418,57 @@ def register_lbfgs(problem: Problem, fixed: torch.Tensor, moving: torch.Tensor, 
             "status": list(rep.status)}
 
 
-class SRWCRLoss(torch.autograd.Function):
-    """D = SRWCR as a differentiable function of the FFD displacements.
+def _fixed_grad(ctx, disp, fixed, moving, dense, grad_output):
+    """dD/d(normalised fixed) for a float32 fixed volume that requires grad."""
+    if not ctx.needs_input_grad[1]:
+        return None
+    _, gf = ctx.plan.grad_fixed(fixed.detach(), moving, disp, dense=dense)
+    return gf * grad_output.to(torch.float32)
 
-    forward runs srwcr_eval; backward re-runs srwcr_grad (the warped volume is
-    recomputed, never stored) and scales by grad_output."""
+
+class SRWCRLoss(torch.autograd.Function):
+    """D = SRWCR as a differentiable function of the FFD displacements (and of
+    the normalised fixed volume when it requires grad).
+
+    forward runs srwcr_eval; backward runs srwcr_grad (and srwcr_grad_fixed)
+    and scales by grad_output."""
 
     @staticmethod
     def forward(ctx, ffd, fixed, moving, plan):
         ctx.plan = plan
         ctx.save_for_backward(ffd, fixed, moving)
-        return plan.eval(fixed, moving, ffd.detach().contiguous()).clone()
+        return plan.eval(fixed.detach(), moving, ffd.detach().contiguous()).clone()
 
     @staticmethod
     def backward(ctx, grad_output):
         ffd, fixed, moving = ctx.saved_tensors
-        _, g = ctx.plan.grad(fixed, moving, ffd.detach().contiguous())
-        return (g * grad_output.to(torch.float32)), None, None, None
+        d = ffd.detach().contiguous()
+        g = None
+        if ctx.needs_input_grad[0]:
+            _, g = ctx.plan.grad(fixed.detach(), moving, d)
+            g = g * grad_output.to(torch.float32)
+        return g, _fixed_grad(ctx, d, fixed, moving, False, grad_output), None, None
 
 
 class SRWCRDenseLoss(torch.autograd.Function):
     """D = SRWCR as a differentiable function of a dense displacement field
     u[3][nz][ny][nx] (T(x) = x + u(x)), e.g. the output of a registration
-    network.  backward re-runs srwcr_grad_dense and scales by grad_output."""
+    network (and of the normalised fixed volume when it requires grad).
+    backward runs srwcr_grad_dense (and srwcr_grad_fixed) and scales by
+    grad_output."""
 
     @staticmethod
     def forward(ctx, field, fixed, moving, plan):
         ctx.plan = plan
         ctx.save_for_backward(field, fixed, moving)
-        return plan.eval_dense(fixed, moving, field.detach().contiguous()).clone()
+        return plan.eval_dense(fixed.detach(), moving, field.detach().contiguous()).clone()
 
     @staticmethod
     def backward(ctx, grad_output):
         field, fixed, moving = ctx.saved_tensors
-        _, g = ctx.plan.grad_dense(fixed, moving, field.detach().contiguous())
-        return (g * grad_output.to(torch.float32)), None, None, None
+        u = field.detach().contiguous()
+        g = None
+        if ctx.needs_input_grad[0]:
+            _, g = ctx.plan.grad_dense(fixed.detach(), moving, u)
+            g = g * grad_output.to(torch.float32)
+        return g, _fixed_grad(ctx, u, fixed, moving, True, grad_output), None, None

@@ -18,7 +18,7 @@ EXPORTED = ["srwcr_ctrl_dims", "srwcr_plan_create", "srwcr_plan_destroy", "srwcr
             "srwcr_profile", "srwcr_profile_read", "srwcr_refine_ffd", "srwcr_bending_energy",
             "srwcr_eval_dense", "srwcr_grad_dense", "srwcr_batch_create", "srwcr_batch_destroy", "srwcr_batch_workspace_bytes", "srwcr_grad_batched",
             "raptor_patches_create", "raptor_patches_destroy", "raptor_workspace_bytes", "raptor_eval",
-            "raptor_grad", "srwcr_last_error"]
+            "raptor_grad", "srwcr_grad_fixed", "srwcr_last_error"]
 
 MAX_BATCH = 32
 
@@ -100,6 +100,7 @@ def load() -> ctypes.CDLL:
         "raptor_workspace_bytes": (sz, [vp, vp]),
         "raptor_eval": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, vp, vp, sz, vp]),
         "raptor_grad": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]),
+        "srwcr_grad_fixed": (ctypes.c_int, [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]),
         "srwcr_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

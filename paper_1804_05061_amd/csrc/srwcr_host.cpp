@@ -96,6 +96,13 @@ struct srwcr_plan {
     std::vector<int> vrow_host;
     int nvblocks = 0;
     int nwg = 0;                         // persistent value-pass workgroups (one per compute unit)
+    // warp pass rows: the value blocks, or, when the spatial cells are narrower
+    // than a row (regions at the FFD nodes), x-chunks of a full row width over
+    // the whole y-z plane (the warp pass does not depend on the regions)
+    const WorkItem *wblocks = nullptr;
+    const int *wrow = nullptr;
+    std::vector<int> wrow_host;
+    int nwblocks = 0;
     size_t value_lds = 0, grad_lds = 0, prep_lds = 0;
     WsLayout ws;
     int device = 0;
@@ -370,6 +377,28 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
             he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
             if (he != hipSuccess) { st = hip_fail(he, "hipDeviceGetAttribute(compute units)"); goto bad; }
             P->nwg = std::max(1, std::min(ncu, vr.back()));
+            P->wblocks = P->vblocks;
+            P->wrow = P->vrow;
+            P->wrow_host = vr;
+            P->nwblocks = P->nvblocks;
+            if (at_nodes) {
+                std::vector<WorkItem> wb;
+                std::vector<int> wr(1, 0);
+                for (int x0 = 0; x0 < g.nf[0]; x0 += g.xw) {
+                    WorkItem w{};
+                    w.x0 = x0; w.x1 = std::min(g.nf[0], x0 + g.xw);
+                    w.y0 = 0; w.y1 = g.nf[1];
+                    w.z0 = 0; w.z1 = g.nf[2];
+                    wb.push_back(w);
+                    wr.push_back(wr.back() + g.nf[1] * g.nf[2]);
+                }
+                if ((st = upload(wb.data(), wb.size() * sizeof(WorkItem), &dv))) goto bad;
+                P->wblocks = (const WorkItem *)dv;
+                if ((st = upload(wr.data(), wr.size() * sizeof(int), &dv))) goto bad;
+                P->wrow = (const int *)dv;
+                P->wrow_host = wr;
+                P->nwblocks = (int)wb.size();
+            }
         }
         void *d;
         if ((st = upload(items.data(), items.size() * sizeof(WorkItem), &d))) goto bad;
@@ -495,7 +524,7 @@ static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, int 
     prof_mark(P, 0, s);
     HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
     prof_mark(P, 1, s);
-    HIP_TRY(launch_prep(P->geom_dev, g.mdt, dense, with_grad, P->vblocks, P->vrow, P->nvblocks, P->vrow_host.back(),
+    HIP_TRY(launch_prep(P->geom_dev, g.mdt, dense, with_grad, P->wblocks, P->wrow, P->nwblocks, P->wrow_host.back(),
                         args, ws, P->prep_lds, s),
             "warp launch");
     prof_mark(P, 2, s);
@@ -566,6 +595,24 @@ int srwcr_grad_dense(const srwcr_plan *plan, const void *fixed, const void *movi
     return SRWCR_OK;
 }
 
+int srwcr_grad_fixed(const srwcr_plan *plan, const void *fixed, const void *moving, const float *disp, int32_t dense,
+                     double *d_value, float *d_grad_fixed, void *workspace, size_t workspace_bytes, void *stream)
+{
+    int st = check_call(plan, fixed, moving, disp, workspace, workspace_bytes);
+    if (st) return st;
+    if (dense != 0 && dense != 1) return fail(SRWCR_E_INVALID_ARG, "dense = %d is neither 0 nor 1", dense);
+    if (!d_value || !d_grad_fixed) return fail(SRWCR_E_INVALID_ARG, "d_value or d_grad_fixed is NULL");
+    unsigned char *ws = (unsigned char *)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    const BatchArgs args = one_problem(fixed, moving, disp, d_value, d_grad_fixed);
+    st = run_value(plan, args, dense, 0, ws, s);
+    if (st) return st;
+    const Geom &g = plan->g;
+    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.role, 2, plan->items, plan->nitems, args, ws, plan->grad_lds, s),
+            "fixed-image adjoint launch");
+    return SRWCR_OK;
+}
+
 int ffd_warp(const srwcr_plan *plan, const void *moving, const float *ffd, float *out, void *stream)
 {
     if (!plan || !moving || !ffd || !out) return fail(SRWCR_E_INVALID_ARG, "NULL argument");
@@ -586,8 +633,8 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
     HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
     const Geom &g = plan->g;
     const BatchArgs args = one_problem(fixed, moving, ffd, nullptr, nullptr);
-    HIP_TRY(launch_prep(plan->geom_dev, g.mdt, 0, 0, plan->vblocks, plan->vrow, plan->nvblocks,
-                        plan->vrow_host.back(), args, ws, plan->prep_lds, s),
+    HIP_TRY(launch_prep(plan->geom_dev, g.mdt, 0, 0, plan->wblocks, plan->wrow, plan->nwblocks,
+                        plan->wrow_host.back(), args, ws, plan->prep_lds, s),
             "warp launch");
     HIP_TRY(launch_value(plan->geom_dev, g.fdt, plan->vblocks, plan->vrow, plan->nvblocks, plan->nwg, args, ws,
                          plan->value_lds, s),
@@ -928,8 +975,8 @@ static int run_raptor(const srwcr_plan *plan, const raptor_patches *pt, const vo
     if (with_grad && !dense)
         HIP_TRY(launch_zero((double *)(ws + plan->ws.grad), 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2], s), "zero launch");
     mark(1);
-    HIP_TRY(launch_prep(plan->geom_dev, g.mdt, dense, with_grad ? 1 : 0, plan->vblocks, plan->vrow, plan->nvblocks,
-                        plan->vrow_host.back(), args, ws, plan->prep_lds, s),
+    HIP_TRY(launch_prep(plan->geom_dev, g.mdt, dense, with_grad ? 1 : 0, plan->wblocks, plan->wrow, plan->nwblocks,
+                        plan->wrow_host.back(), args, ws, plan->prep_lds, s),
             "warp launch");
     mark(2);
     HIP_TRY(launch_raptor_acc(plan->geom_dev, g.fdt, g.role, ra, args, ws, s), "RaPTOR accumulation launch");

@@ -806,42 +806,46 @@ k_finalize(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
     const double omc = ok ? U / (Pr * var) : 0.0;       // 1 - CR_r
     const double cr = ok ? 1.0 - omc : 0.0;
     const double s = ok ? g.inv_Z / var : 0.0;
+    // Tables of both adjoints, each scaled by 1/(Z sigma_r^2): the image that
+    // plays B needs E'_a = 2 mu_r(a) - 2 (1 - CR_r) mu_r and alpha_r = CR_r; the
+    // image that plays A needs the coefficients (c2, c1, c0) of m1^2, m1, 1 in
+    // (m1 - mu(a))^2 - (m1 - mu(a+1))^2, an empty bin's square taken as 0.
+    // Slots per (r, a): moving is A: (c2, c1, c0, E'); moving is B:
+    // (E', c2, c1, c0) -- the moving image's adjoint first, the fixed image's
+    // after it.
     float *tp = tables + ((size_t)r * nb + a) * 4;
-    if (g.role == 1) {
-        // moving is B: E'_a = 2 mu_r(a) - 2 (1 - CR_r) mu_r, scaled by 1/(Z sigma^2)
-        if (a < nb) {
-            const double E = (filled ? 2.0 * mu_a : 0.0) - 2.0 * omc * mu_r;
-            tp[0] = (float)(s * E);
-            tp[1] = tp[2] = tp[3] = 0.0f;
+    const double mu_n = __shfl_down(mu_a, 1);
+    const int fill_n = __shfl_down(filled ? 1 : 0, 1);
+    if (a < nb) {
+        const double E = (filled ? 2.0 * mu_a : 0.0) - 2.0 * omc * mu_r;
+        double c2 = 0.0, c1 = 0.0, c0 = 0.0;
+        const bool f0 = filled, f1 = (a + 1 < nb) && fill_n;
+        if (f0 && f1) {
+            c1 = 2.0 * (mu_n - mu_a);
+            c0 = -(mu_n - mu_a) * (mu_n + mu_a);
+        } else if (f0) {
+            c2 = 1.0;
+            c1 = -2.0 * mu_a;
+            c0 = mu_a * mu_a;
+        } else if (f1) {
+            c2 = -1.0;
+            c1 = 2.0 * mu_n;
+            c0 = -mu_n * mu_n;
         }
-        if (a == 0) alpha[r] = (float)(s * cr);
-    } else {
-        // moving is A: coefficients of m1^2, m1, 1 in
-        // (m1 - mu(a))^2 - (m1 - mu(a+1))^2, an empty bin's square taken as 0
-        const double mu_n = __shfl_down(mu_a, 1);
-        const int fill_n = __shfl_down(filled ? 1 : 0, 1);
-        if (a < nb) {
-            double c2 = 0.0, c1 = 0.0, c0 = 0.0;
-            const bool f0 = filled, f1 = (a + 1 < nb) && fill_n;
-            if (f0 && f1) {
-                c1 = 2.0 * (mu_n - mu_a);
-                c0 = -(mu_n - mu_a) * (mu_n + mu_a);
-            } else if (f0) {
-                c2 = 1.0;
-                c1 = -2.0 * mu_a;
-                c0 = mu_a * mu_a;
-            } else if (f1) {
-                c2 = -1.0;
-                c1 = 2.0 * mu_n;
-                c0 = -mu_n * mu_n;
-            }
-            tp[0] = (float)(s * c2);
-            tp[1] = (float)(s * c1);
-            tp[2] = (float)(s * c0);
-            tp[3] = 0.0f;
+        const float tE = (float)(s * E), t2 = (float)(s * c2), t1 = (float)(s * c1), t0 = (float)(s * c0);
+        if (g.role == 1) {
+            tp[0] = tE;
+            tp[1] = t2;
+            tp[2] = t1;
+            tp[3] = t0;
+        } else {
+            tp[0] = t2;
+            tp[1] = t1;
+            tp[2] = t0;
+            tp[3] = tE;
         }
-        if (a == 0) alpha[r] = 0.0f;
     }
+    if (a == 0) alpha[r] = (float)(s * cr);
     if (a == 0) {
         region[4 * r + 0] = ok ? U / var : 0.0;
         region[4 * r + 1] = Pr;
@@ -905,10 +909,11 @@ struct VoxG {
 };
 
 // DISP 0: scatter dD/dT to the FFD nodes (eq 17) into the workspace
-// accumulators; DISP 1: write dD/du(x) of a dense field to args.p[].grad.
-// ROLE 0 / 1: dD/ds_M from the SRWCR region tables, moving image as A / B;
-// ROLE 2: dD/ds_M read per voxel from the workspace (RaPTOR), so only the
-// chain rule (eq 16) and the scatter run here.
+// accumulators; DISP 1: write dD/du(x) of a dense field to args.p[].grad;
+// DISP 2: write dD/ds_F, the fixed image's adjoint, per voxel to
+// args.p[].grad (no chain rule).  ROLE 0 / 1: the adjoints from the SRWCR
+// region tables, moving image as A / B; ROLE 2: dD/ds_M read per voxel from
+// the workspace (RaPTOR), so only the chain rule (eq 16) and the scatter run.
 template <int FDT, int ROLE, int DISP>
 __global__ void __launch_bounds__(kGradThreads)
 k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, BatchArgs args, unsigned char *ws)
@@ -939,6 +944,10 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
     float *scr = alph + kNReg + wave * g.gscr;
+    // the adjoint taken: of the image that plays A (eq 21) or B (eq 19), and
+    // where its tables sit in the four slots per (region, bin)
+    constexpr bool FA = DISP == 2 ? ROLE == 1 : ROLE == 0;
+    constexpr int CO = DISP == 2 ? (ROLE == 0 ? 3 : 1) : 0;
 
     if (DISP == 0)
         for (int i = threadIdx.x; i < nG; i += blockDim.x) G[i] = 0.0;
@@ -952,10 +961,12 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f, al = 0.0f;
         if (it.cx + ii < g.K[0]) {
             const int R = ((it.cz + kk) * g.K[1] + (it.cy + jj)) * g.K[0] + (it.cx + ii);
-            const float *tp = tables + ((size_t)R * nb + a) * 4;
+            const float *tp = tables + ((size_t)R * nb + a) * 4 + CO;
             t0 = tp[0];
-            t1 = tp[1];
-            t2 = tp[2];
+            if (FA) {
+                t1 = tp[1];
+                t2 = tp[2];
+            }
             al = alpha[R];
         }
         tab[rl * ts + a * 3 + 0] = t0;
@@ -978,7 +989,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             pend[sl] = x < xe;
             const int xc = pend[sl] ? x : xe - 1;
 #pragma unroll
-            for (int e = 0; e < 3; ++e) v[sl].dm[e] = dmi[e * nvox + rowb + xc];
+            for (int e = 0; DISP != 2 && e < 3; ++e) v[sl].dm[e] = dmi[e * nvox + rowb + xc];
             if constexpr (ROLE == 2) {
                 v[sl].tA = pend[sl] ? gld(rds, rowb + xc) : 0.0f;      // dD/ds_M of the voxel
                 continue;
@@ -1020,11 +1031,11 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         // slot popcount(bins below k_A).
         int *blist = reinterpret_cast<int *>(scr);                  // [64] the row's bins, ascending
         float *rowt = scr + 64;                                      // [nd][NE]
-        constexpr int NE = ROLE == 0 ? kXN * 3 : kXN;
+        constexpr int NE = FA ? kXN * 3 : kXN;
         unsigned long long mine = 0ull;
 #pragma unroll
         for (int sl = 0; sl < kSlots; ++sl)
-            if (pend[sl]) mine |= (ROLE == 0 ? 1ull : 3ull) << v[sl].kA;
+            if (pend[sl]) mine |= (FA ? 1ull : 3ull) << v[sl].kA;
         const unsigned long long bins = (unsigned long long)wave_or_dpp((unsigned)(mine >> 32)) << 32 |
                                         wave_or_dpp((unsigned)mine);
         const int nd = __builtin_popcountll(bins);
@@ -1033,9 +1044,9 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         for (int e = lane; e < nd * NE; e += kWave) {
             const int sb = e / NE, r = e - sb * NE;
             const int a = blist[sb];
-            const int i = ROLE == 0 ? r / 3 : r, c = ROLE == 0 ? r - 3 * i : 0;
+            const int i = FA ? r / 3 : r, c = FA ? r - 3 * i : 0;
             float acc = 0.0f;
-            if (a <= (ROLE == 0 ? L - 1 : L)) {
+            if (a <= (FA ? L - 1 : L)) {
                 const float *tp = tab + i * ts + a * 3 + c;
 #pragma unroll
                 for (int kz = 0; kz < 4; ++kz)
@@ -1044,8 +1055,8 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             }
             rowt[e] = acc;
         }
-        float arow[kXN];                                             // moving is B: CR_r / (sigma_r^2 Z) per x-node
-        if (ROLE == 1) {
+        float arow[kXN];                                             // B's adjoint: CR_r / (sigma_r^2 Z) per x-node
+        if (!FA) {
             float al = 0.0f;
             if (lane < kXN) {
 #pragma unroll
@@ -1061,7 +1072,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         for (int sl = 0; sl < kSlots; ++sl) {
             if (!pend[sl]) continue;
             const int sb = __builtin_popcountll(bins & ((1ull << v[sl].kA) - 1ull));
-            if (ROLE == 0) {
+            if (FA) {
                 const float *rt = rowt + sb * NE;
                 float C[3];
 #pragma unroll
@@ -1087,6 +1098,13 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         wave_sync();                                                 // the scatter reuses the scratch
         }
 
+        if (DISP == 2) {                                             // the fixed image's dD/ds_F
+            float *out = args.p[it.prob].grad;
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl)
+                if (xs + sl * kWave + lane < xe) out[rowb + xs + sl * kWave + lane] = gs[sl];
+            continue;
+        }
         // q = dD/ds * dM/dy * dy/dT  (eq 16): a dense field's gradient is q itself
         if (DISP == 1) {
             float *out = args.p[it.prob].grad;
@@ -1157,7 +1175,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         }
         wave_sync();
     }
-    if (DISP == 1) return;
+    if (DISP != 0) return;
     __syncthreads();
     const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
     for (int i = threadIdx.x; i < nG; i += blockDim.x) {
@@ -1182,6 +1200,8 @@ hipError_t launch_grad(const Geom *geoms, int fdt, int role, int dense, const Wo
     SRWCR_GRAD(1, 0, 0) SRWCR_GRAD(1, 0, 1) SRWCR_GRAD(1, 1, 0) SRWCR_GRAD(1, 1, 1)
     SRWCR_GRAD(2, 0, 0) SRWCR_GRAD(2, 0, 1) SRWCR_GRAD(2, 1, 0) SRWCR_GRAD(2, 1, 1)
     SRWCR_GRAD(0, 2, 0) SRWCR_GRAD(0, 2, 1)      // per-voxel dD/ds_M: the fixed image is not read
+    SRWCR_GRAD(0, 0, 2) SRWCR_GRAD(0, 1, 2) SRWCR_GRAD(1, 0, 2) SRWCR_GRAD(1, 1, 2)
+    SRWCR_GRAD(2, 0, 2) SRWCR_GRAD(2, 1, 2)
 #undef SRWCR_GRAD
     return hipGetLastError();
 }
@@ -1216,6 +1236,11 @@ hipError_t prepare_kernels()
 #undef SRWCR_SET
     if (e == hipSuccess) e = set_lds(k_grad<0, 2, 0>, b);
     if (e == hipSuccess) e = set_lds(k_grad<0, 2, 1>, b);
+#define SRWCR_SET(F)                                                                \
+    if (e == hipSuccess) e = set_lds(k_grad<F, 0, 2>, b);                           \
+    if (e == hipSuccess) e = set_lds(k_grad<F, 1, 2>, b);
+    SRWCR_SET(0) SRWCR_SET(1) SRWCR_SET(2)
+#undef SRWCR_SET
     if (e == hipSuccess && dev < 64) done[dev] = true;
     return e;
 }
