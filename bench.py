@@ -55,9 +55,10 @@ def parse():
     ap.add_argument("--cpu-slices", type=int, default=32, help="z-slices of the oracle sample")
     ap.add_argument("--cold", action="store_true", help="also time steps with the last-level cache flushed")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--workload", default="ct256", choices=["ct256", "breathing4d", "raptor256"],
-                    help="ct256: the headline single pair; breathing4d: 9 phase pairs x 3 levels, batched; "
-                         "raptor256: RaPTOR value+gradient over 17^3 patches of the ct256 pair")
+    ap.add_argument("--workload", default="ct256", choices=["ct256", "nodes256x99", "breathing4d", "raptor256"],
+                    help="ct256: the headline single pair; nodes256x99: the paper's own setting (regions at the "
+                         "FFD nodes, delta 5, 32 bins) on a 256x256x99 phantom; breathing4d: 9 phase pairs x 3 "
+                         "levels, batched; raptor256: RaPTOR value+gradient over 17^3 patches of the ct256 pair")
     return ap.parse_args()
 
 
@@ -79,8 +80,14 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.time()
-    w = synth.ct_phantom()
-    nb, K, delta = w.n_bins, w.spatial_bins, w.ctrl_spacing
+    nodes = args.workload == "nodes256x99"
+    if nodes:
+        # the paper's operating point: regions at the control points, delta 5, 32 bins, 256x256x99
+        w = synth.ct_phantom(shape=(99, 256, 256))
+        nb, K, delta, phi_sigma, phi_seed = 32, (0, 0, 0), (5, 5, 5), 1.5, 51
+    else:
+        w = synth.ct_phantom()
+        nb, K, delta, phi_sigma, phi_seed = w.n_bins, w.spatial_bins, w.ctrl_spacing, 2.0, 2
     print(f"[bench] workload {w.name} generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     dt = {"f32": (S.F32, torch.float32, "f32"), "f16": (S.F16, torch.float16, "f16"),
           "bf16": (S.BF16, torch.bfloat16, "bf16")}[args.dtype]
@@ -91,7 +98,7 @@ def main():
     mlo, mhi = S.minmax(mr)
     f = S.normalize(fr, flo, fhi, nb, dt[1])
     m = S.normalize(mr, mlo, mhi, nb, dt[1])
-    ffd_np = synth.random_ffd(prob.ctrl_dims, 2.0, 2)
+    ffd_np = synth.random_ffd(prob.ctrl_dims, phi_sigma, phi_seed)
     ffd = torch.from_numpy(ffd_np).cuda()
     plan = S.Plan(prob)
     vbuf = torch.empty((), dtype=torch.float64, device="cuda")
@@ -157,7 +164,7 @@ def main():
         fz, mz = np.ascontiguousarray(fo[:nz]), np.ascontiguousarray(mo[:nz])
         Pz = O.Problem((w.fixed_dims[0], w.fixed_dims[1], nz), (w.moving_dims[0], w.moving_dims[1], nz), nb, K,
                        delta, 0)
-        ffd_z = synth.random_ffd(Pz.ctrl_dims, 2.0, 2)
+        ffd_z = synth.random_ffd(Pz.ctrl_dims, phi_sigma, phi_seed)
         a = time.perf_counter()
         O.gradient(Pz, fz, mz, ffd_z)
         dt_cpu = time.perf_counter() - a
@@ -167,12 +174,23 @@ def main():
                          f"{dt_cpu:.2f}s"}
 
     value = nvox / (ms_step * 1e-3)
+    vs = None
+    if nodes:
+        metric = "SRWCR value+gradient voxel-evals/s at 256x256x99, regions at the FFD nodes"
+        regions = f"regions at the FFD nodes ({prob.n_regions} regions)"
+        # the paper's own figure for this setting and size: 851 ms (value) + 238 ms
+        # (derivatives) per iteration on a GTX 1060 (Table VIII); another machine,
+        # context only
+        vs = round(value / (nvox / 1.089), 2)
+    else:
+        metric = METRIC
+        regions = f"{K[0]}x{K[1]}x{K[2]} spatial bins"
     line = {
-        "metric": METRIC, "value": round(value, 1), "unit": "voxel-evals/s", "n_gpus": 1, "steps": args.steps,
+        "metric": metric, "value": round(value, 1), "unit": "voxel-evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": dt[2], "data": "synthetic",
-        "config": {"workload": f"{w.name} CT-like phantom, {dt[2]} storage, {nb} bins, {K[0]}x{K[1]}x{K[2]} "
-                               f"spatial bins, FFD spacing {delta[0]}, moving as A, Phi~N(0,2 vox)",
+        "vs_baseline": vs, "dtype": dt[2], "data": "synthetic",
+        "config": {"workload": f"{w.name} CT-like phantom, {dt[2]} storage, {nb} bins, {regions}, "
+                               f"FFD spacing {delta[0]}, moving as A, Phi~N(0,{phi_sigma} vox)",
                    "voxels": nvox, "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "D": D,
     }
