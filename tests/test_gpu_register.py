@@ -11,13 +11,15 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def test_register_lbfgs_recovers_displacement(orc):
+@pytest.mark.parametrize("spatial", [(4, 4, 4), (0, 0, 0)], ids=["K4", "nodes"])
+def test_register_lbfgs_recovers_displacement(orc, spatial):
+    """spatial (0, 0, 0): the regions sit on the FFD nodes at every level."""
     import paper_1804_05061_amd as S
     w = synth.ct_phantom(shape=(48, 64, 64), breathing=4.0, field_spacing=16, field_sigma=1.0, noise=20.0)
     nb = 32
     f = S.normalize(torch.from_numpy(w.fixed).cuda(), float(w.fixed.min()), float(w.fixed.max()), nb)
     m = S.normalize(torch.from_numpy(w.moving).cuda(), float(w.moving.min()), float(w.moving.max()), nb)
-    prob = S.Problem(w.fixed_dims, w.moving_dims, nb, (4, 4, 4), (8, 8, 8), S.MOVING_AS_A)
+    prob = S.Problem(w.fixed_dims, w.moving_dims, nb, spatial, (8, 8, 8), S.MOVING_AS_A)
     ffd = np.zeros(prob.ffd_shape, dtype=np.float32)
     opts = S.LbfgsOptions(levels=2, max_iter=(40, 40, 0), stall_window=10, bending_weight=0.0)
     rep = S.register_lbfgs(prob, f, m, ffd, opts)
@@ -40,5 +42,5 @@ def test_register_lbfgs_recovers_displacement(orc):
         err0.append(np.sum(target ** 2))
         err1.append(np.sum((d - target) ** 2))
     rmse0, rmse1 = np.sqrt(np.mean(err0)), np.sqrt(np.mean(err1))
-    print(f"edge displacement RMSE {rmse0:.3f} -> {rmse1:.3f} voxels", flush=True)
+    print(f"{spatial}: edge displacement RMSE {rmse0:.3f} -> {rmse1:.3f} voxels", flush=True)
     assert rmse1 < 0.8 * rmse0
