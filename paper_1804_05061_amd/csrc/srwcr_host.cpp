@@ -103,6 +103,16 @@ struct srwcr_plan {
     const int *wrow = nullptr;
     std::vector<int> wrow_host;
     int nwblocks = 0;
+    // staged value pass (when the staging slots fit): per workgroup its first
+    // block-visit id; per region the visits that hold it (CSR: reg_start, ent =
+    // visit * 80 + local region); waves per region of the merge
+    bool staged = false;
+    const int *visit_start = nullptr;
+    const int *reg_start = nullptr;
+    const int *ent = nullptr;
+    int merge_waves = 1;
+    size_t stage_visits = 0;
+    size_t staging_off = 0;
     size_t value_lds = 0, grad_lds = 0, prep_lds = 0;
     WsLayout ws;
     int device = 0;
@@ -377,6 +387,57 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
             he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
             if (he != hipSuccess) { st = hip_fail(he, "hipDeviceGetAttribute(compute units)"); goto bad; }
             P->nwg = std::max(1, std::min(ncu, vr.back()));
+            {
+                // the workgroups' block visits, as the value pass walks them: workgroup w
+                // takes rows [w T / G, (w + 1) T / G) and visits every block they touch
+                const long T = vr.back();
+                const int G = P->nwg;
+                std::vector<int> vstart(G + 1, 0), vblock;
+                for (int w = 0; w < G; ++w) {
+                    long r0 = (long)w * T / G;
+                    const long r1 = (long)(w + 1) * T / G;
+                    int bi = 0;
+                    while (bi + 1 < (int)vb.size() && vr[bi + 1] <= r0) ++bi;
+                    while (r0 < r1) {
+                        vblock.push_back(bi);
+                        r0 = std::min(r1, (long)vr[bi + 1]);
+                        ++bi;
+                    }
+                    vstart[w + 1] = (int)vblock.size();
+                }
+                const size_t V = vblock.size();
+                const size_t stage_bytes = V * (size_t)kNReg * g.nb * 3 * sizeof(double);
+                if (stage_bytes <= ((size_t)512 << 20) && V * kNReg < (size_t)INT32_MAX) {
+                    std::vector<std::vector<int>> per(g.R);
+                    for (size_t v = 0; v < V; ++v) {
+                        const WorkItem &b = vb[vblock[v]];
+                        for (int loc = 0; loc < kNReg; ++loc) {
+                            const int i = loc >> 4, jk = loc & 15, j = jk & 3, k = jk >> 2;
+                            if (b.cx + i >= g.K[0]) continue;
+                            const int R = ((b.cz + k) * g.K[1] + (b.cy + j)) * g.K[0] + (b.cx + i);
+                            per[R].push_back((int)(v * kNReg + loc));
+                        }
+                    }
+                    std::vector<int> rs(g.R + 1, 0), en;
+                    size_t emax = 0;
+                    for (int R = 0; R < g.R; ++R) {
+                        en.insert(en.end(), per[R].begin(), per[R].end());
+                        rs[R + 1] = (int)en.size();
+                        emax = std::max(emax, per[R].size());
+                    }
+                    if ((st = upload(vstart.data(), vstart.size() * sizeof(int), &dv))) goto bad;
+                    P->visit_start = (const int *)dv;
+                    if ((st = upload(rs.data(), rs.size() * sizeof(int), &dv))) goto bad;
+                    P->reg_start = (const int *)dv;
+                    if (!en.empty()) {
+                        if ((st = upload(en.data(), en.size() * sizeof(int), &dv))) goto bad;
+                        P->ent = (const int *)dv;
+                    }
+                    P->merge_waves = (int)std::max<size_t>(1, std::min<size_t>(16, (emax + 7) / 8));
+                    P->staged = !en.empty();
+                    P->stage_visits = V;
+                }
+            }
             P->wblocks = P->vblocks;
             P->wrow = P->vrow;
             P->wrow_host = vr;
@@ -406,7 +467,7 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
     }
 
     {
-        // workspace: zeroed block first (moments, gradient accumulators, ticket)
+        // workspace: zeroed block first (moments, gradient accumulators)
         WsLayout &w = P->ws;
         const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
         size_t off = 0;
@@ -431,6 +492,9 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         off = align_up(off + nvox * sizeof(PrepKT), 256);
         w.dm = off;
         off += 3 * nvox * sizeof(float);
+        off = align_up(off, 256);
+        P->staging_off = off;
+        if (P->staged) off += P->stage_visits * (size_t)kNReg * g.nb * 3 * sizeof(double);
         w.total = align_up(off, 256);
         w.rds = w.total;
         g.ws = w;
@@ -528,8 +592,13 @@ static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, int 
                         args, ws, P->prep_lds, s),
             "warp launch");
     prof_mark(P, 2, s);
-    HIP_TRY(launch_value(P->geom_dev, g.fdt, P->vblocks, P->vrow, P->nvblocks, P->nwg, args, ws, P->value_lds, s),
+    HIP_TRY(launch_value(P->geom_dev, g.fdt, P->vblocks, P->vrow, P->nvblocks, P->nwg, args, ws, P->value_lds, s,
+                         P->staged ? (double *)(ws + P->staging_off) : nullptr, P->visit_start),
             "value launch");
+    if (P->staged)
+        HIP_TRY(launch_merge(P->geom_dev, (const double *)(ws + P->staging_off), P->reg_start, P->ent, g.R, g.nb,
+                             P->merge_waves, ws, s),
+                "merge launch");
     prof_mark(P, 3, s);
     HIP_TRY(launch_finalize(P->geom_dev, 1, g.R, args, ws, s), "finalize launch");
     prof_mark(P, 4, s);
@@ -637,8 +706,13 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
                         plan->wrow_host.back(), args, ws, plan->prep_lds, s),
             "warp launch");
     HIP_TRY(launch_value(plan->geom_dev, g.fdt, plan->vblocks, plan->vrow, plan->nvblocks, plan->nwg, args, ws,
-                         plan->value_lds, s),
+                         plan->value_lds, s, plan->staged ? (double *)(ws + plan->staging_off) : nullptr,
+                         plan->visit_start),
             "value launch");
+    if (plan->staged)
+        HIP_TRY(launch_merge(plan->geom_dev, (const double *)(ws + plan->staging_off), plan->reg_start, plan->ent,
+                             g.R, g.nb, plan->merge_waves, ws, s),
+                "merge launch");
     const size_t bytes = (size_t)plan->g.R * plan->g.nb * 3 * sizeof(double);
     HIP_TRY(hipMemcpyAsync(d_moments, moments, bytes, hipMemcpyDeviceToDevice, s), "moments copy");
     return SRWCR_OK;
@@ -727,7 +801,7 @@ int srwcr_batch_create(int32_t n, const srwcr_plan *const *plans, srwcr_batch **
     b->fdt = plans[0]->g.fdt;
     b->mdt = plans[0]->g.mdt;
     b->role = plans[0]->g.role;
-    // workspace: every problem's zeroed block (moments, gradient, ticket) first, then the rest
+    // workspace: every problem's zeroed block (moments, gradient) first, then the rest
     std::vector<Geom> geoms(n);
     size_t off = 0;
     for (int p = 0; p < n; ++p) {

@@ -632,7 +632,8 @@ __device__ __forceinline__ void value_window(double *H, int L, const int (&b)[kW
 template <int FDT>
 __global__ void __launch_bounds__(kValueThreads)
 k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, const int *__restrict__ row_start,
-        int nblocks, int lds_doubles, BatchArgs args, unsigned char *ws)
+        int nblocks, int lds_doubles, BatchArgs args, unsigned char *ws, double *__restrict__ staging,
+        const int *__restrict__ visit_start)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     double *H = reinterpret_cast<double *>(smem);     // [nb][3][5][kHS], see kHS
@@ -648,6 +649,7 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
     for (int i = threadIdx.x; i < lds_doubles; i += blockDim.x) H[i] = 0.0;
     __syncthreads();
 
+    int visit = 0;                                       // blocks this workgroup has left so far
     while (r0 < r1) {
         const WorkItem it = blocks[bi];
         const long bstart = row_start[bi];
@@ -726,24 +728,97 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
             }
         }
         __syncthreads();
-        // merge into the global moments, clearing the histogram for the next block
-        for (int e = threadIdx.x; e < nH; e += blockDim.x) {
-            const double val = H[e];
-            const int idx = e / kHS, jk = e - idx * kHS;
-            if (val != 0.0) {
+        if (staging) {
+            // the histogram to this visit's staging slots, region-major ([80 local
+            // regions][nb][3]), in plain coalesced stores, clearing it for the next
+            // block; k_merge adds up the visits of each region in a fixed order
+            double *dst = staging + (size_t)(visit_start[blockIdx.x] + visit) * (kNReg * nb * 3);
+            const int n = kNReg * nb * 3, nb3 = nb * 3;
+            for (int o = threadIdx.x; o < n; o += blockDim.x) {
+                const int loc = o / nb3, rem = o - loc * nb3, a = rem / 3, m = rem - 3 * a;
+                const int e = ((a * 3 + m) * kXN + (loc >> 4)) * kHS + (loc & 15);
+                dst[o] = H[e];
                 H[e] = 0.0;
-                const int am = idx / kXN, i = idx - am * kXN, a = am / 3, m = am - 3 * a;
-                const int j = jk & 3, k = jk >> 2;
-                if (jk < 16 && it.cx + i < g.K[0]) {
-                    const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
-                    unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], val);
+            }
+        } else {
+            // merge into the global moments, clearing the histogram for the next block
+            for (int e = threadIdx.x; e < nH; e += blockDim.x) {
+                const double val = H[e];
+                const int idx = e / kHS, jk = e - idx * kHS;
+                if (val != 0.0) {
+                    H[e] = 0.0;
+                    const int am = idx / kXN, i = idx - am * kXN, a = am / 3, m = am - 3 * a;
+                    const int j = jk & 3, k = jk >> 2;
+                    if (jk < 16 && it.cx + i < g.K[0]) {
+                        const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
+                        unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], val);
+                    }
                 }
             }
         }
         __syncthreads();
         r0 = bend;
         ++bi;
+        ++visit;
     }
+}
+
+// Moments of region r from the staged value pass: the sum, in a fixed order,
+// of the staging slots of every visit whose block holds r (visits
+// ent[reg_start[r] ..], each entry visit * 80 + local region).  One workgroup
+// per region, 64 W threads: wave w takes entries w, w + W, ...; lane a < nb
+// the three moments of bin a; the W partial sums are added in wave order.
+__global__ void __launch_bounds__(1024)
+k_merge(const Geom *__restrict__ geoms, const double *__restrict__ staging, const int *__restrict__ reg_start,
+        const int *__restrict__ ent, unsigned char *ws)
+{
+    extern __shared__ double part[];                     // [W][nb][3]
+    const Geom &g = geoms[0];
+    double *__restrict__ moments = reinterpret_cast<double *>(ws + g.ws.moments);
+    const int r = blockIdx.x, nb = g.nb, lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    const int W = blockDim.x >> 6, nb3 = nb * 3;
+    const int e0 = reg_start[r], e1 = reg_start[r + 1];
+    double s[3] = {0.0, 0.0, 0.0};
+    if (lane < nb) {
+        int e = e0 + w;
+        for (; e + 3 * W < e1; e += 4 * W) {             // four entries in flight
+            double v[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double *p = staging + (size_t)ent[e + u * W] * nb3 + 3 * lane;
+#pragma unroll
+                for (int m = 0; m < 3; ++m) v[u][m] = p[m];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) s[m] += v[u][m];
+        }
+        for (; e < e1; e += W) {
+            const double *p = staging + (size_t)ent[e] * nb3 + 3 * lane;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) s[m] += p[m];
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) part[(w * nb + lane) * 3 + m] = s[m];
+    }
+    __syncthreads();
+    if (w == 0 && lane < nb) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            double t = 0.0;
+            for (int ww = 0; ww < W; ++ww) t += part[(ww * nb + lane) * 3 + m];
+            moments[((size_t)r * nb + lane) * 3 + m] = t;
+        }
+    }
+}
+
+hipError_t launch_merge(const Geom *geoms, const double *staging, const int *reg_start, const int *ent, int nregions,
+                        int nb, int waves, unsigned char *ws, hipStream_t s)
+{
+    const size_t lds = (size_t)waves * nb * 3 * sizeof(double);
+    hipLaunchKernelGGL(k_merge, dim3(nregions), dim3(waves * kWave), lds, s, geoms, staging, reg_start, ent, ws);
+    return hipGetLastError();
 }
 
 template <typename F>
@@ -754,13 +829,14 @@ static hipError_t set_lds(F *kernel, size_t bytes)
 }
 
 hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *blocks, const int *row_start, int nblocks,
-                        int nwg, const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s)
+                        int nwg, const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s,
+                        double *staging, const int *visit_start)
 {
     if (nblocks <= 0 || nwg <= 0) return hipSuccess;
     const int ld = (int)(lds_bytes / sizeof(double));
 #define SRWCR_VAL(F) \
     hipLaunchKernelGGL((k_value<F>), dim3(nwg), dim3(kValueThreads), lds_bytes, s, geoms, blocks, row_start, nblocks, ld, \
-                       args, ws)
+                       args, ws, staging, visit_start)
     if (fdt == 0) SRWCR_VAL(0);
     else if (fdt == 1) SRWCR_VAL(1);
     else SRWCR_VAL(2);
