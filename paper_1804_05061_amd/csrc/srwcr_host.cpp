@@ -80,6 +80,69 @@ double bspline_piece(int l, double t)
     }
 }
 
+// The staged value pass of a set of value blocks (blocks[i].prob = problem):
+// the block visits of the G persistent workgroups, as the value pass walks
+// them (workgroup w takes rows [w T / G, (w + 1) T / G) and visits every block
+// they touch), and, per region of every problem (problem by problem), the
+// visits that hold it as entries visit * 80 + local region.
+struct StagePlan {
+    std::vector<int> vstart;        // [G + 1] first visit id of each workgroup
+    std::vector<int> reg_start;     // [regions + 1]
+    std::vector<int> ent;
+    std::vector<int2> reg_id;       // (problem, region) per merged region
+    size_t visits = 0;
+    int waves = 1;                  // merge waves per region
+};
+
+StagePlan stage_plan(const std::vector<WorkItem> &vb, const std::vector<int> &vr, int G,
+                     const std::vector<const Geom *> &geoms)
+{
+    StagePlan sp;
+    const long T = vr.back();
+    sp.vstart.assign(G + 1, 0);
+    std::vector<int> vblock;
+    for (int w = 0; w < G; ++w) {
+        long r0 = (long)w * T / G;
+        const long r1 = (long)(w + 1) * T / G;
+        int bi = 0;
+        while (bi + 1 < (int)vb.size() && vr[bi + 1] <= r0) ++bi;
+        while (r0 < r1) {
+            vblock.push_back(bi);
+            r0 = std::min(r1, (long)vr[bi + 1]);
+            ++bi;
+        }
+        sp.vstart[w + 1] = (int)vblock.size();
+    }
+    sp.visits = vblock.size();
+    std::vector<int> base(geoms.size() + 1, 0);
+    for (size_t p = 0; p < geoms.size(); ++p) base[p + 1] = base[p] + geoms[p]->R;
+    std::vector<std::vector<int>> per(base.back());
+    for (size_t v = 0; v < sp.visits; ++v) {
+        const WorkItem &b = vb[vblock[v]];
+        const Geom &g = *geoms[b.prob];
+        for (int loc = 0; loc < kNReg; ++loc) {
+            const int i = loc >> 4, jk = loc & 15, j = jk & 3, k = jk >> 2;
+            if (b.cx + i >= g.K[0]) continue;
+            const int R = ((b.cz + k) * g.K[1] + (b.cy + j)) * g.K[0] + (b.cx + i);
+            per[base[b.prob] + R].push_back((int)(v * kNReg + loc));
+        }
+    }
+    sp.reg_start.assign(base.back() + 1, 0);
+    size_t emax = 0;
+    for (size_t p = 0; p < geoms.size(); ++p)
+        for (int R = 0; R < geoms[p]->R; ++R) {
+            const int q = base[p] + R;
+            sp.ent.insert(sp.ent.end(), per[q].begin(), per[q].end());
+            sp.reg_start[q + 1] = (int)sp.ent.size();
+            sp.reg_id.push_back(make_int2((int)p, R));
+            emax = std::max(emax, per[q].size());
+        }
+    sp.waves = (int)std::max<size_t>(1, std::min<size_t>(16, (emax + 7) / 8));
+    return sp;
+}
+
+constexpr size_t kStageLimit = (size_t)512 << 20;   // staging slots above this: atomic merge
+
 }  // namespace
 
 struct srwcr_plan {
@@ -388,54 +451,18 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
             if (he != hipSuccess) { st = hip_fail(he, "hipDeviceGetAttribute(compute units)"); goto bad; }
             P->nwg = std::max(1, std::min(ncu, vr.back()));
             {
-                // the workgroups' block visits, as the value pass walks them: workgroup w
-                // takes rows [w T / G, (w + 1) T / G) and visits every block they touch
-                const long T = vr.back();
-                const int G = P->nwg;
-                std::vector<int> vstart(G + 1, 0), vblock;
-                for (int w = 0; w < G; ++w) {
-                    long r0 = (long)w * T / G;
-                    const long r1 = (long)(w + 1) * T / G;
-                    int bi = 0;
-                    while (bi + 1 < (int)vb.size() && vr[bi + 1] <= r0) ++bi;
-                    while (r0 < r1) {
-                        vblock.push_back(bi);
-                        r0 = std::min(r1, (long)vr[bi + 1]);
-                        ++bi;
-                    }
-                    vstart[w + 1] = (int)vblock.size();
-                }
-                const size_t V = vblock.size();
-                const size_t stage_bytes = V * (size_t)kNReg * g.nb * 3 * sizeof(double);
-                if (stage_bytes <= ((size_t)512 << 20) && V * kNReg < (size_t)INT32_MAX) {
-                    std::vector<std::vector<int>> per(g.R);
-                    for (size_t v = 0; v < V; ++v) {
-                        const WorkItem &b = vb[vblock[v]];
-                        for (int loc = 0; loc < kNReg; ++loc) {
-                            const int i = loc >> 4, jk = loc & 15, j = jk & 3, k = jk >> 2;
-                            if (b.cx + i >= g.K[0]) continue;
-                            const int R = ((b.cz + k) * g.K[1] + (b.cy + j)) * g.K[0] + (b.cx + i);
-                            per[R].push_back((int)(v * kNReg + loc));
-                        }
-                    }
-                    std::vector<int> rs(g.R + 1, 0), en;
-                    size_t emax = 0;
-                    for (int R = 0; R < g.R; ++R) {
-                        en.insert(en.end(), per[R].begin(), per[R].end());
-                        rs[R + 1] = (int)en.size();
-                        emax = std::max(emax, per[R].size());
-                    }
-                    if ((st = upload(vstart.data(), vstart.size() * sizeof(int), &dv))) goto bad;
+                const StagePlan sp = stage_plan(vb, vr, P->nwg, {&g});
+                const size_t stage_bytes = sp.visits * (size_t)kNReg * g.nb * 3 * sizeof(double);
+                if (stage_bytes <= kStageLimit && sp.visits * kNReg < (size_t)INT32_MAX && !sp.ent.empty()) {
+                    if ((st = upload(sp.vstart.data(), sp.vstart.size() * sizeof(int), &dv))) goto bad;
                     P->visit_start = (const int *)dv;
-                    if ((st = upload(rs.data(), rs.size() * sizeof(int), &dv))) goto bad;
+                    if ((st = upload(sp.reg_start.data(), sp.reg_start.size() * sizeof(int), &dv))) goto bad;
                     P->reg_start = (const int *)dv;
-                    if (!en.empty()) {
-                        if ((st = upload(en.data(), en.size() * sizeof(int), &dv))) goto bad;
-                        P->ent = (const int *)dv;
-                    }
-                    P->merge_waves = (int)std::max<size_t>(1, std::min<size_t>(16, (emax + 7) / 8));
-                    P->staged = !en.empty();
-                    P->stage_visits = V;
+                    if ((st = upload(sp.ent.data(), sp.ent.size() * sizeof(int), &dv))) goto bad;
+                    P->ent = (const int *)dv;
+                    P->merge_waves = sp.waves;
+                    P->staged = true;
+                    P->stage_visits = sp.visits;
                 }
             }
             P->wblocks = P->vblocks;
@@ -592,12 +619,13 @@ static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, int 
                         args, ws, P->prep_lds, s),
             "warp launch");
     prof_mark(P, 2, s);
+    const long stride = (long)kNReg * g.nb * 3;
     HIP_TRY(launch_value(P->geom_dev, g.fdt, P->vblocks, P->vrow, P->nvblocks, P->nwg, args, ws, P->value_lds, s,
-                         P->staged ? (double *)(ws + P->staging_off) : nullptr, P->visit_start),
+                         P->staged ? (double *)(ws + P->staging_off) : nullptr, P->visit_start, stride),
             "value launch");
     if (P->staged)
-        HIP_TRY(launch_merge(P->geom_dev, (const double *)(ws + P->staging_off), P->reg_start, P->ent, g.R, g.nb,
-                             P->merge_waves, ws, s),
+        HIP_TRY(launch_merge(P->geom_dev, (const double *)(ws + P->staging_off), stride, P->reg_start, P->ent,
+                             nullptr, g.R, g.nb, P->merge_waves, ws, s),
                 "merge launch");
     prof_mark(P, 3, s);
     HIP_TRY(launch_finalize(P->geom_dev, 1, g.R, args, ws, s), "finalize launch");
@@ -705,13 +733,14 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
     HIP_TRY(launch_prep(plan->geom_dev, g.mdt, 0, 0, plan->wblocks, plan->wrow, plan->nwblocks,
                         plan->wrow_host.back(), args, ws, plan->prep_lds, s),
             "warp launch");
+    const long stride = (long)kNReg * g.nb * 3;
     HIP_TRY(launch_value(plan->geom_dev, g.fdt, plan->vblocks, plan->vrow, plan->nvblocks, plan->nwg, args, ws,
                          plan->value_lds, s, plan->staged ? (double *)(ws + plan->staging_off) : nullptr,
-                         plan->visit_start),
+                         plan->visit_start, stride),
             "value launch");
     if (plan->staged)
-        HIP_TRY(launch_merge(plan->geom_dev, (const double *)(ws + plan->staging_off), plan->reg_start, plan->ent,
-                             g.R, g.nb, plan->merge_waves, ws, s),
+        HIP_TRY(launch_merge(plan->geom_dev, (const double *)(ws + plan->staging_off), stride, plan->reg_start,
+                             plan->ent, nullptr, g.R, g.nb, plan->merge_waves, ws, s),
                 "merge launch");
     const size_t bytes = (size_t)plan->g.R * plan->g.nb * 3 * sizeof(double);
     HIP_TRY(hipMemcpyAsync(d_moments, moments, bytes, hipMemcpyDeviceToDevice, s), "moments copy");
@@ -770,6 +799,13 @@ struct srwcr_batch {
     long nrows = 0;
     size_t value_lds = 0, grad_lds = 0, prep_lds = 0, ws_total = 0, zero_bytes = 0, max_params = 0;
     int max_regions = 0;
+    // staged value pass (see stage_plan)
+    bool staged = false;
+    int *visit_start = nullptr, *reg_start = nullptr, *ent = nullptr;
+    int2 *reg_id = nullptr;
+    int nregions = 0, max_nb = 0, merge_waves = 1;
+    long stage_stride = 0;
+    size_t staging_off = 0;
 };
 
 void srwcr_batch_destroy(srwcr_batch *b)
@@ -779,6 +815,8 @@ void srwcr_batch_destroy(srwcr_batch *b)
     if (b->items_dev) (void)hipFree(b->items_dev);
     if (b->vblocks_dev) (void)hipFree(b->vblocks_dev);
     if (b->vrow_dev) (void)hipFree(b->vrow_dev);
+    for (void *p : {(void *)b->visit_start, (void *)b->reg_start, (void *)b->ent, (void *)b->reg_id})
+        if (p) (void)hipFree(p);
     delete b;
 }
 
@@ -874,6 +912,32 @@ int srwcr_batch_create(int32_t n, const srwcr_plan *const *plans, srwcr_batch **
     if (e == hipSuccess) e = hipMemcpy(b->vblocks_dev, vb.data(), vb.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&b->vrow_dev, vr.size() * sizeof(int));
     if (e == hipSuccess) e = hipMemcpy(b->vrow_dev, vr.data(), vr.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        // staged value pass over all problems' blocks, when its slots fit
+        std::vector<const Geom *> gp(n);
+        for (int p = 0; p < n; ++p) {
+            gp[p] = &plans[p]->g;
+            b->max_nb = std::max(b->max_nb, plans[p]->g.nb);
+        }
+        const StagePlan sp = stage_plan(vb, vr, b->nwg, gp);
+        b->stage_stride = (long)kNReg * b->max_nb * 3;
+        const size_t stage_bytes = sp.visits * (size_t)b->stage_stride * sizeof(double);
+        if (stage_bytes <= kStageLimit && sp.visits * kNReg < (size_t)INT32_MAX && !sp.ent.empty()) {
+            auto put = [&](const void *src, size_t bytes, void **dst) {
+                if (e == hipSuccess) e = hipMalloc(dst, bytes);
+                if (e == hipSuccess) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+            };
+            put(sp.vstart.data(), sp.vstart.size() * sizeof(int), (void **)&b->visit_start);
+            put(sp.reg_start.data(), sp.reg_start.size() * sizeof(int), (void **)&b->reg_start);
+            put(sp.ent.data(), sp.ent.size() * sizeof(int), (void **)&b->ent);
+            put(sp.reg_id.data(), sp.reg_id.size() * sizeof(int2), (void **)&b->reg_id);
+            b->nregions = (int)sp.reg_id.size();
+            b->merge_waves = sp.waves;
+            b->staging_off = align_up(b->ws_total, 256);
+            b->ws_total = align_up(b->staging_off + stage_bytes, 256);
+            b->staged = e == hipSuccess;
+        }
+    }
     if (e != hipSuccess) {
         srwcr_batch_destroy(b);
         return hip_fail(e, "batch tables");
@@ -907,9 +971,14 @@ int srwcr_grad_batched(const srwcr_batch *b, const srwcr_batch_item *items, void
     HIP_TRY(launch_prep(b->geoms_dev, b->mdt, 0, 1, b->vblocks_dev, b->vrow_dev, b->nvblocks, b->nrows, args, ws,
                         b->prep_lds, s),
             "warp launch");
+    double *staging = b->staged ? (double *)(ws + b->staging_off) : nullptr;
     HIP_TRY(launch_value(b->geoms_dev, b->fdt, b->vblocks_dev, b->vrow_dev, b->nvblocks, b->nwg, args, ws,
-                         b->value_lds, s),
+                         b->value_lds, s, staging, b->visit_start, b->stage_stride),
             "value launch");
+    if (b->staged)
+        HIP_TRY(launch_merge(b->geoms_dev, staging, b->stage_stride, b->reg_start, b->ent, b->reg_id, b->nregions,
+                             b->max_nb, b->merge_waves, ws, s),
+                "merge launch");
     HIP_TRY(launch_finalize(b->geoms_dev, n, b->max_regions, args, ws, s), "finalize launch");
     HIP_TRY(launch_grad(b->geoms_dev, b->fdt, b->role, 0, b->items_dev, b->nitems, args, ws, b->grad_lds, s),
             "gradient launch");

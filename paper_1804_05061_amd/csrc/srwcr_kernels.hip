@@ -633,7 +633,7 @@ template <int FDT>
 __global__ void __launch_bounds__(kValueThreads)
 k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, const int *__restrict__ row_start,
         int nblocks, int lds_doubles, BatchArgs args, unsigned char *ws, double *__restrict__ staging,
-        const int *__restrict__ visit_start)
+        const int *__restrict__ visit_start, long stage_stride)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     double *H = reinterpret_cast<double *>(smem);     // [nb][3][5][kHS], see kHS
@@ -732,7 +732,7 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
             // the histogram to this visit's staging slots, region-major ([80 local
             // regions][nb][3]), in plain coalesced stores, clearing it for the next
             // block; k_merge adds up the visits of each region in a fixed order
-            double *dst = staging + (size_t)(visit_start[blockIdx.x] + visit) * (kNReg * nb * 3);
+            double *dst = staging + (size_t)(visit_start[blockIdx.x] + visit) * stage_stride;
             const int n = kNReg * nb * 3, nb3 = nb * 3;
             for (int o = threadIdx.x; o < n; o += blockDim.x) {
                 const int loc = o / nb3, rem = o - loc * nb3, a = rem / 3, m = rem - 3 * a;
@@ -763,21 +763,30 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
     }
 }
 
-// Moments of region r from the staged value pass: the sum, in a fixed order,
-// of the staging slots of every visit whose block holds r (visits
-// ent[reg_start[r] ..], each entry visit * 80 + local region).  One workgroup
-// per region, 64 W threads: wave w takes entries w, w + W, ...; lane a < nb
-// the three moments of bin a; the W partial sums are added in wave order.
+// Moments of a region from the staged value pass: the sum, in a fixed order,
+// of the staging slots of every visit whose block holds it (visits
+// ent[reg_start[q] ..], each entry visit * 80 + local region; a visit's slots
+// start at visit * stage_stride).  Workgroup q takes region reg_id[q] =
+// (problem, region), or (0, q) without reg_id; 64 W threads: wave w takes
+// entries w, w + W, ...; lane a < nb the three moments of bin a; the W
+// partial sums are added in wave order.
 __global__ void __launch_bounds__(1024)
-k_merge(const Geom *__restrict__ geoms, const double *__restrict__ staging, const int *__restrict__ reg_start,
-        const int *__restrict__ ent, unsigned char *ws)
+k_merge(const Geom *__restrict__ geoms, const double *__restrict__ staging, long stage_stride,
+        const int *__restrict__ reg_start, const int *__restrict__ ent, const int2 *__restrict__ reg_id,
+        unsigned char *ws)
 {
     extern __shared__ double part[];                     // [W][nb][3]
-    const Geom &g = geoms[0];
+    const int q = blockIdx.x;
+    const int2 id = reg_id ? reg_id[q] : make_int2(0, q);
+    const Geom &g = geoms[id.x];
     double *__restrict__ moments = reinterpret_cast<double *>(ws + g.ws.moments);
-    const int r = blockIdx.x, nb = g.nb, lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    const int r = id.y, nb = g.nb, lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
     const int W = blockDim.x >> 6, nb3 = nb * 3;
-    const int e0 = reg_start[r], e1 = reg_start[r + 1];
+    const int e0 = reg_start[q], e1 = reg_start[q + 1];
+    auto slot = [&](int e) {
+        const int v = ent[e];
+        return staging + (size_t)(v / kNReg) * stage_stride + (size_t)(v % kNReg) * nb3 + 3 * lane;
+    };
     double s[3] = {0.0, 0.0, 0.0};
     if (lane < nb) {
         int e = e0 + w;
@@ -785,7 +794,7 @@ k_merge(const Geom *__restrict__ geoms, const double *__restrict__ staging, cons
             double v[4][3];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const double *p = staging + (size_t)ent[e + u * W] * nb3 + 3 * lane;
+                const double *p = slot(e + u * W);
 #pragma unroll
                 for (int m = 0; m < 3; ++m) v[u][m] = p[m];
             }
@@ -795,7 +804,7 @@ k_merge(const Geom *__restrict__ geoms, const double *__restrict__ staging, cons
                 for (int m = 0; m < 3; ++m) s[m] += v[u][m];
         }
         for (; e < e1; e += W) {
-            const double *p = staging + (size_t)ent[e] * nb3 + 3 * lane;
+            const double *p = slot(e);
 #pragma unroll
             for (int m = 0; m < 3; ++m) s[m] += p[m];
         }
@@ -813,11 +822,14 @@ k_merge(const Geom *__restrict__ geoms, const double *__restrict__ staging, cons
     }
 }
 
-hipError_t launch_merge(const Geom *geoms, const double *staging, const int *reg_start, const int *ent, int nregions,
-                        int nb, int waves, unsigned char *ws, hipStream_t s)
+hipError_t launch_merge(const Geom *geoms, const double *staging, long stage_stride, const int *reg_start,
+                        const int *ent, const int2 *reg_id, int nregions, int max_nb, int waves, unsigned char *ws,
+                        hipStream_t s)
 {
-    const size_t lds = (size_t)waves * nb * 3 * sizeof(double);
-    hipLaunchKernelGGL(k_merge, dim3(nregions), dim3(waves * kWave), lds, s, geoms, staging, reg_start, ent, ws);
+    if (nregions <= 0) return hipSuccess;
+    const size_t lds = (size_t)waves * max_nb * 3 * sizeof(double);
+    hipLaunchKernelGGL(k_merge, dim3(nregions), dim3(waves * kWave), lds, s, geoms, staging, stage_stride, reg_start,
+                       ent, reg_id, ws);
     return hipGetLastError();
 }
 
@@ -830,13 +842,13 @@ static hipError_t set_lds(F *kernel, size_t bytes)
 
 hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *blocks, const int *row_start, int nblocks,
                         int nwg, const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s,
-                        double *staging, const int *visit_start)
+                        double *staging, const int *visit_start, long stage_stride)
 {
     if (nblocks <= 0 || nwg <= 0) return hipSuccess;
     const int ld = (int)(lds_bytes / sizeof(double));
 #define SRWCR_VAL(F) \
     hipLaunchKernelGGL((k_value<F>), dim3(nwg), dim3(kValueThreads), lds_bytes, s, geoms, blocks, row_start, nblocks, ld, \
-                       args, ws, staging, visit_start)
+                       args, ws, staging, visit_start, stage_stride)
     if (fdt == 0) SRWCR_VAL(0);
     else if (fdt == 1) SRWCR_VAL(1);
     else SRWCR_VAL(2);
