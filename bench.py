@@ -31,12 +31,12 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1804_05061_amd", "csrc", "srwcr_kernel
 # (FETCH_SIZE, then WRITE_SIZE) over this benchmark, each scaled by what the
 # same counter reads for k_normalize, a copy of known size (32 MiB read,
 # 32 MiB written at 256x256x128 FP32): fetch x 2.00, write x 1.00.  Keyed by
-# the SHA-256 of the kernel source the counters were taken on, so the figure
-# is reported as null once the kernels change.
+# the SHA-256 of the kernel source the counters were taken on and by the
+# workload, so the figure is reported as null once the kernels change.
 TRAFFIC = {
-    ("8000a03b3411ab8425149a3b83caf26f2543112d3d3418df835ef6f9affcf8cd", "srwcr_value_pass", "f32"): {
-        "fetch_bytes": 100860931, "write_bytes": 90410496, "fetch_size_kib": 49287.6, "write_size_kib": 88291.5,
-        "scale_fetch": 1.9984, "scale_write": 1.0, "copy_kernel": "k_normalize, 32 MiB in, 32 MiB out"},
+    ("8917261e721e4b8fa8d7376f2652596d0e0a6c93e9dcfec397c7b67d8cee756b", "ct256", "srwcr_value_pass", "f32"): {
+        "fetch_bytes": 100852165, "write_bytes": 33300480, "fetch_size_kib": 49293.0, "write_size_kib": 32520.0,
+        "scale_fetch": 1.998, "scale_write": 1.0, "copy_kernel": "k_normalize, 32 MiB in, 32 MiB out"},
 }
 
 
@@ -136,7 +136,7 @@ def main():
                 "alg_bytes_per_launch": alg_bytes, "mean_ms": round(kern[dom], 5),
                 "phase_ms": {k: round(v / prof["calls"], 5) for k, v in prof.items() if k != "calls"}}
 
-    rec = TRAFFIC.get((kernel_source_sha(), dom, dt[2]))
+    rec = TRAFFIC.get((kernel_source_sha(), args.workload, dom, dt[2]))
     if rec is not None:
         roofline["traffic"] = rec["fetch_bytes"] + rec["write_bytes"]
         roofline["traffic_detail"] = rec

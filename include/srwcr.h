@@ -271,7 +271,8 @@ int srwcr_plan_info(const srwcr_plan *plan, int32_t *n_items, int32_t *value_lds
  * first call creates the events), srwcr_profile(plan, 0) stops recording.
  * srwcr_profile_read synchronises the recorded events and returns the summed
  * milliseconds of the six phases -- zeroing, warp pass, value pass,
- * finalisation, gradient pass, gradient output -- and the number of calls
+ * finalisation (with the merge of a staged value pass), gradient pass,
+ * gradient output -- and the number of calls
  * recorded.  raptor_grad calls on the plan are recorded too, with the phases
  * zeroing, warp pass, patch sums, patch finalisation, per-voxel derivative,
  * chain rule (gradient pass and output).  Not thread-safe: profile one

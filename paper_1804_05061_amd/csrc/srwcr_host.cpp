@@ -623,11 +623,11 @@ static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, int 
     HIP_TRY(launch_value(P->geom_dev, g.fdt, P->vblocks, P->vrow, P->nvblocks, P->nwg, args, ws, P->value_lds, s,
                          P->staged ? (double *)(ws + P->staging_off) : nullptr, P->visit_start, stride),
             "value launch");
+    prof_mark(P, 3, s);                     // the merge is timed with the finalisation
     if (P->staged)
         HIP_TRY(launch_merge(P->geom_dev, (const double *)(ws + P->staging_off), stride, P->reg_start, P->ent,
                              nullptr, g.R, g.nb, P->merge_waves, ws, s),
                 "merge launch");
-    prof_mark(P, 3, s);
     HIP_TRY(launch_finalize(P->geom_dev, 1, g.R, args, ws, s), "finalize launch");
     prof_mark(P, 4, s);
     return SRWCR_OK;

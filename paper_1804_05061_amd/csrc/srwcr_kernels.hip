@@ -942,25 +942,35 @@ k_finalize(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
     }
 }
 
-// D = (1/Z) sum_r U_r / sigma_r^2 of problem blockIdx.x, summed in region
-// order (lane-strided partial sums, then the fixed wave reduction), one wave.
-// A launch of its own: it sees every region's term without a device-scope
-// fence in each finalising wave.
-__global__ void __launch_bounds__(kWave) k_value_sum(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
+// D = (1/Z) sum_r U_r / sigma_r^2 of problem blockIdx.x, summed in a fixed
+// order: thread t adds regions t, t + 1024, ... in increasing order (eight
+// loads in flight), then a fixed tree over the 1024 partial sums.  A launch of
+// its own: it sees every region's term without a device-scope fence in each
+// finalising wave.
+constexpr int kSumThreads = 1024;
+
+__global__ void __launch_bounds__(kSumThreads)
+k_value_sum(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
 {
+    __shared__ double part[kSumThreads];
     const Geom &g = geoms[blockIdx.x];
     const double *region = reinterpret_cast<const double *>(ws + g.ws.region);
-    const int lane = threadIdx.x;
-    double part = 0.0;
-    for (int q0 = lane; q0 < g.R; q0 += 8 * kWave) {
+    const int t = threadIdx.x;
+    double acc = 0.0;
+    for (int q0 = t; q0 < g.R; q0 += 8 * kSumThreads) {
         double x[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = q0 + u * kWave < g.R ? region[4 * (q0 + u * kWave)] : 0.0;
+        for (int u = 0; u < 8; ++u) x[u] = q0 + u * kSumThreads < g.R ? region[4 * (q0 + u * kSumThreads)] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) part += x[u];
+        for (int u = 0; u < 8; ++u) acc += x[u];
     }
-    const double D = wave_sum_d(part);
-    if (lane == 0) *args.p[blockIdx.x].value = D * g.inv_Z;
+    part[t] = acc;
+    __syncthreads();
+    for (int h = kSumThreads / 2; h > 0; h >>= 1) {
+        if (t < h) part[t] += part[t + h];
+        __syncthreads();
+    }
+    if (t == 0) *args.p[blockIdx.x].value = part[0] * g.inv_Z;
 }
 
 hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const BatchArgs &args, unsigned char *ws,
@@ -969,7 +979,7 @@ hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const 
     hipLaunchKernelGGL(k_finalize, dim3(max_regions, nprob), dim3(64), 0, s, geoms, args, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_value_sum, dim3(nprob), dim3(kWave), 0, s, geoms, args, ws);
+    hipLaunchKernelGGL(k_value_sum, dim3(nprob), dim3(kSumThreads), 0, s, geoms, args, ws);
     return hipGetLastError();
 }
 
