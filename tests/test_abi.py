@@ -51,3 +51,22 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.replace("Oracle", "").lower() or f == "build.py", f
+
+
+def test_new_entry_points_reject_null_arguments_without_gpu():
+    """RaPTOR, the fixed-image gradient and the validation of the node-region
+    setting fail with SRWCR_E_INVALID_ARG before any device work."""
+    import paper_1804_05061_amd as S
+    from paper_1804_05061_amd import _lib
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    assert L.raptor_patches_create(None, None, 1, ctypes.byref(h)) == -1
+    assert L.raptor_workspace_bytes(None, None) == 0
+    assert L.raptor_eval(None, None, None, None, None, 0, None, None, 0, None) == -1
+    assert L.raptor_grad(None, None, None, None, None, 0, None, None, None, 0, None) == -1
+    assert L.srwcr_grad_fixed(None, None, None, None, 0, None, None, None, 0, None) == -1
+    # spatial_bins must be all 0 (regions at the FFD nodes) or all in 4..64
+    assert S.Problem((64, 64, 64), (64, 64, 64), 32, (0, 0, 0), (5, 5, 5)).n_regions == 16 ** 3
+    p = S.Problem((64, 64, 64), (64, 64, 64), 32, (0, 4, 4), (5, 5, 5))
+    assert L.srwcr_plan_create(ctypes.byref(p.c()), ctypes.byref(h)) == -1
+    assert b"spatial_bins" in L.srwcr_last_error()
