@@ -548,7 +548,8 @@ hipError_t launch_prep(const Geom *geoms, int mdt, int dense, int with_grad, con
 // atomic touches each bank at most twice.
 constexpr int kHS = 17;
 
-size_t value_lds_bytes(const Geom &g) { return (size_t)g.nb * 3 * kXN * kHS * sizeof(double); }
+// The histogram, then a row counter (16 B).
+size_t value_lds_bytes(const Geom &g) { return (size_t)g.nb * 3 * kXN * kHS * sizeof(double) + 16; }
 
 // Wave-uniform minimum: butterfly inside each 16-lane row (DPP), then the
 // four row results through scalar reads.
@@ -665,7 +666,28 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
         const int nH = nb * 3 * kXN * kHS;
         const int ny = it.y1 - it.y0;
         const int xs = it.x0, xe = it.x1;                // xe - xs <= 64 kSlots
-        for (long r = r0 + wave; r < bend; r += nwaves) {
+        // A long run of rows is handed out one row at a time from an LDS
+        // counter, so that waves whose rows hold fewer bins take more of them;
+        // a short one (small spatial cells) is dealt round-robin, which saves
+        // the barrier.
+        const bool dyn = bend - r0 >= 4 * nwaves;
+        unsigned &next_row = *reinterpret_cast<unsigned *>(H + nH);
+        if (dyn) {
+            if (threadIdx.x == 0) next_row = 0u;
+            __syncthreads();
+        }
+        long rs = r0 + wave;
+        for (;;) {
+            long r;
+            if (dyn) {
+                unsigned rr = 0u;
+                if (lane == 0) rr = atomicAdd(&next_row, 1u);
+                r = r0 + (long)__builtin_amdgcn_readfirstlane(rr);
+            } else {
+                r = rs;
+                rs += nwaves;
+            }
+            if (r >= bend) break;
             const int row = (int)(r - bstart);
             const int y = it.y0 + row % ny, z = it.z0 + row / ny;
             const size_t rowb = ((size_t)z * nfy + y) * nfx;
