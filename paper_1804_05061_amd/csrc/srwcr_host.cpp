@@ -80,11 +80,11 @@ double bspline_piece(int l, double t)
     }
 }
 
-// The staged value pass of a set of value blocks (blocks[i].prob = problem):
-// the block visits of the G persistent workgroups, as the value pass walks
-// them (workgroup w takes rows [w T / G, (w + 1) T / G) and visits every block
-// they touch), and, per region of every problem (problem by problem), the
-// visits that hold it as entries visit * 80 + local region.
+// The staged value pass of a set of value blocks (blocks[i].prob = problem) of
+// 5 x bw x bw regions: the block visits of the G persistent workgroups, as the
+// value pass walks them (workgroup w takes rows [w T / G, (w + 1) T / G) and
+// visits every block they touch), and, per region of every problem (problem by
+// problem), the visits that hold it as entries visit * 5 bw^2 + local region.
 struct StagePlan {
     std::vector<int> vstart;        // [G + 1] first visit id of each workgroup
     std::vector<int> reg_start;     // [regions + 1]
@@ -95,8 +95,9 @@ struct StagePlan {
 };
 
 StagePlan stage_plan(const std::vector<WorkItem> &vb, const std::vector<int> &vr, int G,
-                     const std::vector<const Geom *> &geoms)
+                     const std::vector<const Geom *> &geoms, int bw)
 {
+    const int nreg = kXN * bw * bw, jkn = bw * bw;
     StagePlan sp;
     const long T = vr.back();
     sp.vstart.assign(G + 1, 0);
@@ -120,11 +121,11 @@ StagePlan stage_plan(const std::vector<WorkItem> &vb, const std::vector<int> &vr
     for (size_t v = 0; v < sp.visits; ++v) {
         const WorkItem &b = vb[vblock[v]];
         const Geom &g = *geoms[b.prob];
-        for (int loc = 0; loc < kNReg; ++loc) {
-            const int i = loc >> 4, jk = loc & 15, j = jk & 3, k = jk >> 2;
-            if (b.cx + i >= g.K[0]) continue;
+        for (int loc = 0; loc < nreg; ++loc) {
+            const int i = loc / jkn, jk = loc - i * jkn, k = jk / bw, j = jk - k * bw;
+            if (b.cx + i >= g.K[0] || b.cy + j >= g.K[1] || b.cz + k >= g.K[2]) continue;
             const int R = ((b.cz + k) * g.K[1] + (b.cy + j)) * g.K[0] + (b.cx + i);
-            per[base[b.prob] + R].push_back((int)(v * kNReg + loc));
+            per[base[b.prob] + R].push_back((int)(v * nreg + loc));
         }
     }
     sp.reg_start.assign(base.back() + 1, 0);
@@ -166,6 +167,7 @@ struct srwcr_plan {
     const int *wrow = nullptr;
     std::vector<int> wrow_host;
     int nwblocks = 0;
+    int value_bw = 4;                    // (y, z) regions per axis of a value block: 4 (one cell) or 5 (two)
     // staged value pass (when the staging slots fit): per workgroup its first
     // block-visit id; per region the visits that hold it (CSR: reg_start, ent =
     // visit * 80 + local region); waves per region of the merge
@@ -332,7 +334,7 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
             int scr = std::max(64 + kMaxBins * 3 * kXN, 3 * kSlots * kWave + 12 * np_max);
             g.gscr = (scr + 3) / 4 * 4;
         }
-        P->value_lds = value_lds_bytes(g);
+        P->value_lds = value_lds_bytes(g, 4);
         P->prep_lds = prep_lds_bytes(g);
         if (P->value_lds > (size_t)max_lds) {
             st = fail(SRWCR_E_UNSUPPORTED, "value pass needs %zu B of LDS, device allows %d", P->value_lds, max_lds);
@@ -346,6 +348,21 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
                 const int c = cells[e][x];
                 if (lo[e][c] < 0) lo[e][c] = x;
                 hi[e][c] = x + 1;
+            }
+        }
+        // value blocks of two cells along y and z (5 x 5 x 5 regions) when the
+        // cells are so small that a one-cell block has fewer rows than 4 per wave
+        // and the larger histogram fits
+        {
+            long max_rows = 0;
+            for (int cy = 0; cy < g.K[1] - 3; ++cy)
+                for (int cz = 0; cz < g.K[2] - 3; ++cz)
+                    if (lo[1][cy] >= 0 && lo[2][cz] >= 0)
+                        max_rows = std::max(max_rows, (long)(hi[1][cy] - lo[1][cy]) * (hi[2][cz] - lo[2][cz]));
+            const size_t lds5 = value_lds_bytes(g, 5);
+            if (max_rows < 4 * (kValueThreads / kWave) && lds5 <= (size_t)max_lds) {
+                P->value_bw = 5;
+                P->value_lds = lds5;
             }
         }
         // x chunks: runs of up to xmax voxels that touch at most two spatial
@@ -418,20 +435,33 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         }
         P->nitems = (int)items.size();
         P->items_host = items;
-        // value-pass blocks: an x-chunk by one spatial cell in y and z
+        // value-pass blocks: an x-chunk by one spatial cell in y and z (or two, see above)
         {
             std::vector<WorkItem> vb;
             std::vector<int> vr(1, 0);
             const auto xch = x_chunks(g.xw);
-            for (int cz = 0; cz < g.K[2] - 3; ++cz) {
-                if (lo[2][cz] < 0) continue;
-                for (int cy = 0; cy < g.K[1] - 3; ++cy) {
-                    if (lo[1][cy] < 0) continue;
+            const int cstep = P->value_bw == 5 ? 2 : 1;
+            // voxel range of the non-empty cells c .. c + cstep - 1 of axis e
+            auto span = [&](int e, int c, int &a, int &b) {
+                a = b = -1;
+                for (int cc = c; cc < std::min(c + cstep, g.K[e] - 3); ++cc)
+                    if (lo[e][cc] >= 0) {
+                        if (a < 0) a = lo[e][cc];
+                        b = hi[e][cc];
+                    }
+                return a >= 0;
+            };
+            for (int cz = 0; cz < g.K[2] - 3; cz += cstep) {
+                int za, zb;
+                if (!span(2, cz, za, zb)) continue;
+                for (int cy = 0; cy < g.K[1] - 3; cy += cstep) {
+                    int ya, yb;
+                    if (!span(1, cy, ya, yb)) continue;
                     for (const auto &xr : xch) {
                         WorkItem w{};
                         w.x0 = xr.first; w.x1 = xr.second;
-                        w.y0 = lo[1][cy]; w.y1 = hi[1][cy];
-                        w.z0 = lo[2][cz]; w.z1 = hi[2][cz];
+                        w.y0 = ya; w.y1 = yb;
+                        w.z0 = za; w.z1 = zb;
                         w.cx = cells[0][w.x0]; w.cy = cy; w.cz = cz;
                         vb.push_back(w);
                         vr.push_back(vr.back() + (w.y1 - w.y0) * (w.z1 - w.z0));
@@ -451,9 +481,10 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
             if (he != hipSuccess) { st = hip_fail(he, "hipDeviceGetAttribute(compute units)"); goto bad; }
             P->nwg = std::max(1, std::min(ncu, vr.back()));
             {
-                const StagePlan sp = stage_plan(vb, vr, P->nwg, {&g});
-                const size_t stage_bytes = sp.visits * (size_t)kNReg * g.nb * 3 * sizeof(double);
-                if (stage_bytes <= kStageLimit && sp.visits * kNReg < (size_t)INT32_MAX && !sp.ent.empty()) {
+                const StagePlan sp = stage_plan(vb, vr, P->nwg, {&g}, P->value_bw);
+                const size_t nreg = (size_t)kXN * P->value_bw * P->value_bw;
+                const size_t stage_bytes = sp.visits * nreg * g.nb * 3 * sizeof(double);
+                if (stage_bytes <= kStageLimit && sp.visits * nreg < (size_t)INT32_MAX && !sp.ent.empty()) {
                     if ((st = upload(sp.vstart.data(), sp.vstart.size() * sizeof(int), &dv))) goto bad;
                     P->visit_start = (const int *)dv;
                     if ((st = upload(sp.reg_start.data(), sp.reg_start.size() * sizeof(int), &dv))) goto bad;
@@ -521,7 +552,7 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
         off += 3 * nvox * sizeof(float);
         off = align_up(off, 256);
         P->staging_off = off;
-        if (P->staged) off += P->stage_visits * (size_t)kNReg * g.nb * 3 * sizeof(double);
+        if (P->staged) off += P->stage_visits * (size_t)kXN * P->value_bw * P->value_bw * g.nb * 3 * sizeof(double);
         w.total = align_up(off, 256);
         w.rds = w.total;
         g.ws = w;
@@ -619,13 +650,14 @@ static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, int 
                         args, ws, P->prep_lds, s),
             "warp launch");
     prof_mark(P, 2, s);
-    const long stride = (long)kNReg * g.nb * 3;
+    const int nreg = kXN * P->value_bw * P->value_bw;
+    const long stride = (long)nreg * g.nb * 3;
     HIP_TRY(launch_value(P->geom_dev, g.fdt, P->vblocks, P->vrow, P->nvblocks, P->nwg, args, ws, P->value_lds, s,
-                         P->staged ? (double *)(ws + P->staging_off) : nullptr, P->visit_start, stride),
+                         P->staged ? (double *)(ws + P->staging_off) : nullptr, P->visit_start, stride, P->value_bw),
             "value launch");
     prof_mark(P, 3, s);                     // the merge is timed with the finalisation
     if (P->staged)
-        HIP_TRY(launch_merge(P->geom_dev, (const double *)(ws + P->staging_off), stride, P->reg_start, P->ent,
+        HIP_TRY(launch_merge(P->geom_dev, (const double *)(ws + P->staging_off), stride, nreg, P->reg_start, P->ent,
                              nullptr, g.R, g.nb, P->merge_waves, ws, s),
                 "merge launch");
     HIP_TRY(launch_finalize(P->geom_dev, 1, g.R, args, ws, s), "finalize launch");
@@ -733,13 +765,14 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
     HIP_TRY(launch_prep(plan->geom_dev, g.mdt, 0, 0, plan->wblocks, plan->wrow, plan->nwblocks,
                         plan->wrow_host.back(), args, ws, plan->prep_lds, s),
             "warp launch");
-    const long stride = (long)kNReg * g.nb * 3;
+    const int nreg = kXN * plan->value_bw * plan->value_bw;
+    const long stride = (long)nreg * g.nb * 3;
     HIP_TRY(launch_value(plan->geom_dev, g.fdt, plan->vblocks, plan->vrow, plan->nvblocks, plan->nwg, args, ws,
                          plan->value_lds, s, plan->staged ? (double *)(ws + plan->staging_off) : nullptr,
-                         plan->visit_start, stride),
+                         plan->visit_start, stride, plan->value_bw),
             "value launch");
     if (plan->staged)
-        HIP_TRY(launch_merge(plan->geom_dev, (const double *)(ws + plan->staging_off), stride, plan->reg_start,
+        HIP_TRY(launch_merge(plan->geom_dev, (const double *)(ws + plan->staging_off), stride, nreg, plan->reg_start,
                              plan->ent, nullptr, g.R, g.nb, plan->merge_waves, ws, s),
                 "merge launch");
     const size_t bytes = (size_t)plan->g.R * plan->g.nb * 3 * sizeof(double);
@@ -804,6 +837,7 @@ struct srwcr_batch {
     int *visit_start = nullptr, *reg_start = nullptr, *ent = nullptr;
     int2 *reg_id = nullptr;
     int nregions = 0, max_nb = 0, merge_waves = 1;
+    int bw = 4, nreg = kXN * 16;                 // value-block shape (see srwcr_plan::value_bw)
     long stage_stride = 0;
     size_t staging_off = 0;
 };
@@ -833,6 +867,9 @@ int srwcr_batch_create(int32_t n, const srwcr_plan *const *plans, srwcr_batch **
             return fail(SRWCR_E_INVALID_ARG, "plans[%d] differs from plans[0] in role or storage dtypes", p);
         if (plans[p]->device != plans[0]->device)
             return fail(SRWCR_E_INVALID_ARG, "plans[%d] was made on another device", p);
+        if (plans[p]->value_bw != plans[0]->value_bw)
+            return fail(SRWCR_E_UNSUPPORTED, "plans[%d] uses value blocks of %d (y, z) regions per axis, plans[0] %d",
+                        p, plans[p]->value_bw, plans[0]->value_bw);
     }
     srwcr_batch *b = new srwcr_batch();
     b->plans.assign(plans, plans + n);
@@ -919,10 +956,12 @@ int srwcr_batch_create(int32_t n, const srwcr_plan *const *plans, srwcr_batch **
             gp[p] = &plans[p]->g;
             b->max_nb = std::max(b->max_nb, plans[p]->g.nb);
         }
-        const StagePlan sp = stage_plan(vb, vr, b->nwg, gp);
-        b->stage_stride = (long)kNReg * b->max_nb * 3;
+        b->bw = plans[0]->value_bw;
+        b->nreg = kXN * b->bw * b->bw;
+        const StagePlan sp = stage_plan(vb, vr, b->nwg, gp, b->bw);
+        b->stage_stride = (long)b->nreg * b->max_nb * 3;
         const size_t stage_bytes = sp.visits * (size_t)b->stage_stride * sizeof(double);
-        if (stage_bytes <= kStageLimit && sp.visits * kNReg < (size_t)INT32_MAX && !sp.ent.empty()) {
+        if (stage_bytes <= kStageLimit && sp.visits * b->nreg < (size_t)INT32_MAX && !sp.ent.empty()) {
             auto put = [&](const void *src, size_t bytes, void **dst) {
                 if (e == hipSuccess) e = hipMalloc(dst, bytes);
                 if (e == hipSuccess) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
@@ -973,10 +1012,11 @@ int srwcr_grad_batched(const srwcr_batch *b, const srwcr_batch_item *items, void
             "warp launch");
     double *staging = b->staged ? (double *)(ws + b->staging_off) : nullptr;
     HIP_TRY(launch_value(b->geoms_dev, b->fdt, b->vblocks_dev, b->vrow_dev, b->nvblocks, b->nwg, args, ws,
-                         b->value_lds, s, staging, b->visit_start, b->stage_stride),
+                         b->value_lds, s, staging, b->visit_start, b->stage_stride, b->bw),
             "value launch");
     if (b->staged)
-        HIP_TRY(launch_merge(b->geoms_dev, staging, b->stage_stride, b->reg_start, b->ent, b->reg_id, b->nregions,
+        HIP_TRY(launch_merge(b->geoms_dev, staging, b->stage_stride, b->nreg, b->reg_start, b->ent, b->reg_id,
+                             b->nregions,
                              b->max_nb, b->merge_waves, ws, s),
                 "merge launch");
     HIP_TRY(launch_finalize(b->geoms_dev, n, b->max_regions, args, ws, s), "finalize launch");

@@ -140,17 +140,19 @@ hipError_t launch_prep(const Geom *geoms, int mdt, int dense, int with_grad, con
 // Value pass over region blocks: row_start[b] = first row (in a list of all
 // blocks' rows) of block b, row_start[nblocks] = total; nwg persistent
 // workgroups share the rows evenly.
-// With `staging` set, each workgroup writes its histogram per block visit
+// bw: the (y, z) regions of a value block per axis, 4 (one spatial cell) or 5
+// (two cells).  With `staging` set, each workgroup writes its histogram per block visit
 // (visit_start[w] = the first visit id of workgroup w) to the staging slots
 // of the visit, [80 local regions][nb][3] from visit * stage_stride, and
 // launch_merge forms the moments; otherwise the histograms are merged with
 // FP64 atomics.
 hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *blocks, const int *row_start, int nblocks,
                         int nwg, const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s,
-                        double *staging = nullptr, const int *visit_start = nullptr, long stage_stride = 0);
+                        double *staging = nullptr, const int *visit_start = nullptr, long stage_stride = 0,
+                        int bw = 4);
 // reg_id: (problem, region) per merged region, or null for regions 0 .. n - 1
 // of problem 0.
-hipError_t launch_merge(const Geom *geoms, const double *staging, long stage_stride, const int *reg_start,
+hipError_t launch_merge(const Geom *geoms, const double *staging, long stage_stride, int nreg, const int *reg_start,
                         const int *ent, const int2 *reg_id, int nregions, int max_nb, int waves, unsigned char *ws,
                         hipStream_t s);
 hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const BatchArgs &args, unsigned char *ws,
@@ -169,7 +171,7 @@ hipError_t launch_downsample(const float *in, int nx, int ny, int nz, float *out
                              hipStream_t s);
 hipError_t prepare_kernels();   // once per device: LDS limits of the value and gradient kernels
 size_t prep_lds_bytes(const Geom &g);
-size_t value_lds_bytes(const Geom &g);
+size_t value_lds_bytes(const Geom &g, int bw);
 size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz);
 
 }  // namespace srwcr

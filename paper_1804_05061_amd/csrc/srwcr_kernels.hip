@@ -540,16 +540,26 @@ hipError_t launch_prep(const Geom *geoms, int mdt, int dense, int with_grad, con
 }
 
 // ------------------------------------------------------------ value pass
-// Item histogram layout: H[((a * 3 + m) * 5 + i) * kHS + jk] holds moment m of
-// A-bin a in region (i, j, k) of the item's 5 x 4 x 4 block, jk = 4 k + j.
-// The 16 (y, z) regions of one (a, m, i) are adjacent, so a lane's 16 atomics
-// share one address with immediate offsets; the pad of one double puts the 60
-// lanes of a window (consecutive (a, m, i)) on 32 distinct bank pairs, so an
-// atomic touches each bank at most twice.
-constexpr int kHS = 17;
+// Block histogram layout: H[((a * 3 + m) * 5 + i) * HS + jk] holds moment m of
+// A-bin a in region (i, j, k) of the block's 5 x BW x BW regions, jk = BW k + j.
+// BW = 4: the block lies in one spatial cell along y and z; BW = 5: in two
+// (small cells, see the plan).  The (y, z) regions of one (a, m, i) are
+// adjacent, so a lane's 16 atomics share one address with immediate offsets;
+// the pad of one double (HS = BW^2 + 1) spreads the 60 lanes of a window
+// (consecutive (a, m, i)) over the banks, so that with BW = 4 an atomic
+// touches each bank at most twice.
+template <int BW>
+struct Hist {
+    static constexpr int kJK = BW * BW;          // (y, z) regions of the block
+    static constexpr int kHS = BW * BW + 1;      // doubles per (a, m, i)
+    static constexpr int kReg = kXN * BW * BW;   // regions of the block
+};
 
 // The histogram, then a row counter (16 B).
-size_t value_lds_bytes(const Geom &g) { return (size_t)g.nb * 3 * kXN * kHS * sizeof(double) + 16; }
+size_t value_lds_bytes(const Geom &g, int bw)
+{
+    return (size_t)g.nb * 3 * kXN * (bw * bw + 1) * sizeof(double) + 16;
+}
 
 // Wave-uniform minimum: butterfly inside each 16-lane row (DPP), then the
 // four row results through scalar reads.
@@ -592,8 +602,9 @@ struct VoxA {
 // x 15 (x-node, moment) values across lanes and each lane spreads one total
 // over the 16 (y, z) regions of its column with FP64 LDS atomics.  A voxel
 // outside the row has k < -1 and matches no slot.
+template <int BW>
 __device__ __forceinline__ void value_window(double *H, int L, const int (&b)[kWin], const VoxA (&v)[kSlots],
-                                             const float (&wyz)[16], int lane)
+                                             const float (&wyz)[16], int oyz, int lane)
 {
     float t[kSlots][kWin];
 #pragma unroll
@@ -613,9 +624,11 @@ __device__ __forceinline__ void value_window(double *H, int L, const int (&b)[kW
         const int w = lane / 15, q = lane - 15 * w, i = q / 3, m = q - 3 * i;
         const int a = w == 0 ? b[0] : (w == 1 ? b[1] : (w == 2 ? b[2] : b[3]));
         if (a <= L) {
-            double *h = H + ((a * 3 + m) * kXN + i) * kHS;
+            double *h = H + ((a * 3 + m) * kXN + i) * Hist<BW>::kHS + oyz;
 #pragma unroll
-            for (int jk = 0; jk < 16; ++jk) atomicAdd(h + jk, (double)(T * wyz[jk]));
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) atomicAdd(h + k * BW + j, (double)(T * wyz[k * 4 + j]));
         }
     }
 }
@@ -630,14 +643,15 @@ __device__ __forceinline__ void value_window(double *H, int L, const int (&b)[kW
 // touches it rather than once per small item.  The rows of one block are
 // dealt to the waves round-robin.  Reads the warp pass's per-voxel moving bins
 // (k_prep) and the fixed image.
-template <int FDT>
+template <int FDT, int BW>
 __global__ void __launch_bounds__(kValueThreads)
 k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, const int *__restrict__ row_start,
         int nblocks, int lds_doubles, BatchArgs args, unsigned char *ws, double *__restrict__ staging,
         const int *__restrict__ visit_start, long stage_stride)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    double *H = reinterpret_cast<double *>(smem);     // [nb][3][5][kHS], see kHS
+    double *H = reinterpret_cast<double *>(smem);     // [nb][3][5][HS], see Hist
+    constexpr int HS = Hist<BW>::kHS, JK = Hist<BW>::kJK, NREG = Hist<BW>::kReg;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
@@ -663,7 +677,7 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
         const int *spc_x = g.sp_cell[0];
         const int role = g.role, nfx = g.nf[0], nfy = g.nf[1];
         const int nb = g.nb, L = nb - 1;
-        const int nH = nb * 3 * kXN * kHS;
+        const int nH = nb * 3 * kXN * HS;
         const int ny = it.y1 - it.y0;
         const int xs = it.x0, xe = it.x1;                // xe - xs <= 64 kSlots
         // A long run of rows is handed out one row at a time from an LDS
@@ -726,6 +740,13 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
             }
             float wyv[4], wzv[4];
             row_sp_weights(spw_y, spw_z, y, z, lane, wyv, wzv);
+            int oyz = 0;                                 // the row's (y, z) cells within a two-cell block
+            if constexpr (BW == 5) {
+                int c = 0;
+                if (lane == 0) c = gld(g.sp_cell[1], y);
+                else if (lane == 1) c = gld(g.sp_cell[2], z);
+                oyz = (bcast(c, 1) - it.cz) * BW + (bcast(c, 0) - it.cy);
+            }
             float wyz[16];
 #pragma unroll
             for (int k = 0; k < 4; ++k)
@@ -746,19 +767,20 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
                     b[w] = bins ? (int)__builtin_ctzll(bins) : 1 << 20;
                     bins &= bins - 1;
                 }
-                value_window(H, L, b, v, wyz, lane);
+                value_window<BW>(H, L, b, v, wyz, oyz, lane);
             }
         }
         __syncthreads();
         if (staging) {
-            // the histogram to this visit's staging slots, region-major ([80 local
+            // the histogram to this visit's staging slots, region-major ([5 BW^2 local
             // regions][nb][3]), in plain coalesced stores, clearing it for the next
             // block; k_merge adds up the visits of each region in a fixed order
             double *dst = staging + (size_t)(visit_start[blockIdx.x] + visit) * stage_stride;
-            const int n = kNReg * nb * 3, nb3 = nb * 3;
+            const int n = NREG * nb * 3, nb3 = nb * 3;
             for (int o = threadIdx.x; o < n; o += blockDim.x) {
                 const int loc = o / nb3, rem = o - loc * nb3, a = rem / 3, m = rem - 3 * a;
-                const int e = ((a * 3 + m) * kXN + (loc >> 4)) * kHS + (loc & 15);
+                const int i = loc / JK, jk = loc - i * JK;
+                const int e = ((a * 3 + m) * kXN + i) * HS + jk;
                 dst[o] = H[e];
                 H[e] = 0.0;
             }
@@ -766,12 +788,12 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
             // merge into the global moments, clearing the histogram for the next block
             for (int e = threadIdx.x; e < nH; e += blockDim.x) {
                 const double val = H[e];
-                const int idx = e / kHS, jk = e - idx * kHS;
+                const int idx = e / HS, jk = e - idx * HS;
                 if (val != 0.0) {
                     H[e] = 0.0;
                     const int am = idx / kXN, i = idx - am * kXN, a = am / 3, m = am - 3 * a;
-                    const int j = jk & 3, k = jk >> 2;
-                    if (jk < 16 && it.cx + i < g.K[0]) {
+                    const int k = jk / BW, j = jk - k * BW;
+                    if (jk < JK && it.cx + i < g.K[0] && it.cy + j < g.K[1] && it.cz + k < g.K[2]) {
                         const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
                         unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], val);
                     }
@@ -787,13 +809,13 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
 
 // Moments of a region from the staged value pass: the sum, in a fixed order,
 // of the staging slots of every visit whose block holds it (visits
-// ent[reg_start[q] ..], each entry visit * 80 + local region; a visit's slots
+// ent[reg_start[q] ..], each entry visit * nreg + local region; a visit's slots
 // start at visit * stage_stride).  Workgroup q takes region reg_id[q] =
 // (problem, region), or (0, q) without reg_id; 64 W threads: wave w takes
 // entries w, w + W, ...; lane a < nb the three moments of bin a; the W
 // partial sums are added in wave order.
 __global__ void __launch_bounds__(1024)
-k_merge(const Geom *__restrict__ geoms, const double *__restrict__ staging, long stage_stride,
+k_merge(const Geom *__restrict__ geoms, const double *__restrict__ staging, long stage_stride, int nreg,
         const int *__restrict__ reg_start, const int *__restrict__ ent, const int2 *__restrict__ reg_id,
         unsigned char *ws)
 {
@@ -807,7 +829,7 @@ k_merge(const Geom *__restrict__ geoms, const double *__restrict__ staging, long
     const int e0 = reg_start[q], e1 = reg_start[q + 1];
     auto slot = [&](int e) {
         const int v = ent[e];
-        return staging + (size_t)(v / kNReg) * stage_stride + (size_t)(v % kNReg) * nb3 + 3 * lane;
+        return staging + (size_t)(v / nreg) * stage_stride + (size_t)(v % nreg) * nb3 + 3 * lane;
     };
     double s[3] = {0.0, 0.0, 0.0};
     if (lane < nb) {
@@ -844,14 +866,14 @@ k_merge(const Geom *__restrict__ geoms, const double *__restrict__ staging, long
     }
 }
 
-hipError_t launch_merge(const Geom *geoms, const double *staging, long stage_stride, const int *reg_start,
+hipError_t launch_merge(const Geom *geoms, const double *staging, long stage_stride, int nreg, const int *reg_start,
                         const int *ent, const int2 *reg_id, int nregions, int max_nb, int waves, unsigned char *ws,
                         hipStream_t s)
 {
     if (nregions <= 0) return hipSuccess;
     const size_t lds = (size_t)waves * max_nb * 3 * sizeof(double);
-    hipLaunchKernelGGL(k_merge, dim3(nregions), dim3(waves * kWave), lds, s, geoms, staging, stage_stride, reg_start,
-                       ent, reg_id, ws);
+    hipLaunchKernelGGL(k_merge, dim3(nregions), dim3(waves * kWave), lds, s, geoms, staging, stage_stride, nreg,
+                       reg_start, ent, reg_id, ws);
     return hipGetLastError();
 }
 
@@ -864,13 +886,17 @@ static hipError_t set_lds(F *kernel, size_t bytes)
 
 hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *blocks, const int *row_start, int nblocks,
                         int nwg, const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s,
-                        double *staging, const int *visit_start, long stage_stride)
+                        double *staging, const int *visit_start, long stage_stride, int bw)
 {
     if (nblocks <= 0 || nwg <= 0) return hipSuccess;
     const int ld = (int)(lds_bytes / sizeof(double));
-#define SRWCR_VAL(F) \
-    hipLaunchKernelGGL((k_value<F>), dim3(nwg), dim3(kValueThreads), lds_bytes, s, geoms, blocks, row_start, nblocks, ld, \
-                       args, ws, staging, visit_start, stage_stride)
+#define SRWCR_VAL(F)                                                                                               \
+    if (bw == 5)                                                                                                   \
+        hipLaunchKernelGGL((k_value<F, 5>), dim3(nwg), dim3(kValueThreads), lds_bytes, s, geoms, blocks, row_start, \
+                           nblocks, ld, args, ws, staging, visit_start, stage_stride);                             \
+    else                                                                                                           \
+        hipLaunchKernelGGL((k_value<F, 4>), dim3(nwg), dim3(kValueThreads), lds_bytes, s, geoms, blocks, row_start, \
+                           nblocks, ld, args, ws, staging, visit_start, stage_stride)
     if (fdt == 0) SRWCR_VAL(0);
     else if (fdt == 1) SRWCR_VAL(1);
     else SRWCR_VAL(2);
@@ -1339,11 +1365,11 @@ hipError_t prepare_kernels()
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return e;
     const size_t b = (size_t)max_lds;
-#define SRWCR_SET(T)                                                                \
-    if (e == hipSuccess) e = set_lds(T<0>, b);                                      \
-    if (e == hipSuccess) e = set_lds(T<1>, b);                                      \
-    if (e == hipSuccess) e = set_lds(T<2>, b);
-    SRWCR_SET(k_value)
+#define SRWCR_SET(W)                                                                \
+    if (e == hipSuccess) e = set_lds(k_value<0, W>, b);                             \
+    if (e == hipSuccess) e = set_lds(k_value<1, W>, b);                             \
+    if (e == hipSuccess) e = set_lds(k_value<2, W>, b);
+    SRWCR_SET(4) SRWCR_SET(5)
 #undef SRWCR_SET
 #define SRWCR_SET(A, B)                                                             \
     if (e == hipSuccess) e = set_lds(k_grad<0, A, B>, b);                           \
