@@ -251,6 +251,7 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
     g.fdt = prob->fixed_dtype;
     g.mdt = prob->moving_dtype;
     g.R = g.K[0] * g.K[1] * g.K[2];
+    g.bw = 4;
     const double nvox = (double)g.nf[0] * g.nf[1] * g.nf[2];
     g.inv_Z = 1.0 / nvox;     // sum_r w(r, x) = 1 and sum_a h = 1 make Z the voxel count (eq 3)
 
@@ -360,11 +361,27 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
                     if (lo[1][cy] >= 0 && lo[2][cz] >= 0)
                         max_rows = std::max(max_rows, (long)(hi[1][cy] - lo[1][cy]) * (hi[2][cz] - lo[2][cz]));
             const size_t lds5 = value_lds_bytes(g, 5);
-            if (max_rows < 4 * (kValueThreads / kWave) && lds5 <= (size_t)max_lds) {
+            g.bw = 5;                                   // the gradient pass's tables of 125 regions must fit too
+            const size_t glds5 = grad_lds_bytes(g, 8, 8, 8);
+            g.bw = 4;
+            if (max_rows < 4 * (kValueThreads / kWave) && lds5 <= (size_t)max_lds && glds5 <= (size_t)max_lds) {
                 P->value_bw = 5;
                 P->value_lds = lds5;
+                g.bw = 5;
             }
         }
+        // cells per block along y and z, and the voxel range of the non-empty
+        // cells c .. c + cstep - 1 of axis e
+        const int cstep = P->value_bw == 5 ? 2 : 1;
+        auto span = [&](int e, int c, int &a, int &b) {
+            a = b = -1;
+            for (int cc = c; cc < std::min(c + cstep, g.K[e] - 3); ++cc)
+                if (lo[e][cc] >= 0) {
+                    if (a < 0) a = lo[e][cc];
+                    b = hi[e][cc];
+                }
+            return a >= 0;
+        };
         // x chunks: runs of up to xmax voxels that touch at most two spatial
         // cells, so their regions fit the 5 x-node block of a work item
         auto x_chunks = [&](int xmax) {
@@ -387,11 +404,13 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
             items.clear();
             size_t worst_lds = 0;
             const auto xch = x_chunks(xc_max);
-            for (int cz = 0; cz < g.K[2] - 3; ++cz) {
-                if (lo[2][cz] < 0) continue;
-                for (int cy = 0; cy < g.K[1] - 3; ++cy) {
-                    if (lo[1][cy] < 0) continue;
-                    const int yw = hi[1][cy] - lo[1][cy], zw = hi[2][cz] - lo[2][cz];
+            for (int cz = 0; cz < g.K[2] - 3; cz += cstep) {
+                int za, zb;
+                if (!span(2, cz, za, zb)) continue;
+                for (int cy = 0; cy < g.K[1] - 3; cy += cstep) {
+                    int ya, yb;
+                    if (!span(1, cy, ya, yb)) continue;
+                    const int yw = yb - ya, zw = zb - za;
                     for (const auto &xr : xch) {
                         const int xw = xr.second - xr.first;
                         const double side = std::sqrt(target / xw);
@@ -399,12 +418,12 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
                         if (yc_max) yc = std::min(yc, yc_max);
                         int zc = std::max(1, std::min(zw, (int)std::ceil(target / ((double)xw * yc))));
                         if (zc_max) zc = std::min(zc, zc_max);
-                        for (int z0 = lo[2][cz]; z0 < hi[2][cz]; z0 += zc)
-                            for (int y0 = lo[1][cy]; y0 < hi[1][cy]; y0 += yc) {
+                        for (int z0 = za; z0 < zb; z0 += zc)
+                            for (int y0 = ya; y0 < yb; y0 += yc) {
                                 WorkItem w{};
                                 w.x0 = xr.first; w.x1 = xr.second;
-                                w.y0 = y0; w.y1 = std::min(y0 + yc, hi[1][cy]);
-                                w.z0 = z0; w.z1 = std::min(z0 + zc, hi[2][cz]);
+                                w.y0 = y0; w.y1 = std::min(y0 + yc, yb);
+                                w.z0 = z0; w.z1 = std::min(z0 + zc, zb);
                                 w.cx = cells[0][w.x0]; w.cy = cy; w.cz = cz;
                                 w.gx0 = w.x0 / g.delta[0];
                                 w.gy0 = w.y0 / g.delta[1];
@@ -440,17 +459,6 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
             std::vector<WorkItem> vb;
             std::vector<int> vr(1, 0);
             const auto xch = x_chunks(g.xw);
-            const int cstep = P->value_bw == 5 ? 2 : 1;
-            // voxel range of the non-empty cells c .. c + cstep - 1 of axis e
-            auto span = [&](int e, int c, int &a, int &b) {
-                a = b = -1;
-                for (int cc = c; cc < std::min(c + cstep, g.K[e] - 3); ++cc)
-                    if (lo[e][cc] >= 0) {
-                        if (a < 0) a = lo[e][cc];
-                        b = hi[e][cc];
-                    }
-                return a >= 0;
-            };
             for (int cz = 0; cz < g.K[2] - 3; cz += cstep) {
                 int za, zb;
                 if (!span(2, cz, za, zb)) continue;
@@ -697,7 +705,8 @@ int srwcr_grad(const srwcr_plan *plan, const void *fixed, const void *moving, co
     st = run_value(plan, args, 0, 1, ws, s);
     if (st) return st;
     const Geom &g = plan->g;
-    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.role, 0, plan->items, plan->nitems, args, ws, plan->grad_lds, s),
+    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.role, 0, plan->items, plan->nitems, args, ws, plan->grad_lds, s,
+                        g.bw),
             "gradient launch");
     prof_mark(plan, 5, s);
     const size_t n = 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2];
@@ -719,7 +728,8 @@ int srwcr_grad_dense(const srwcr_plan *plan, const void *fixed, const void *movi
     st = run_value(plan, args, 1, 1, ws, s);
     if (st) return st;
     const Geom &g = plan->g;
-    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.role, 1, plan->items, plan->nitems, args, ws, plan->grad_lds, s),
+    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.role, 1, plan->items, plan->nitems, args, ws, plan->grad_lds, s,
+                        g.bw),
             "gradient launch");
     return SRWCR_OK;
 }
@@ -737,7 +747,8 @@ int srwcr_grad_fixed(const srwcr_plan *plan, const void *fixed, const void *movi
     st = run_value(plan, args, dense, 0, ws, s);
     if (st) return st;
     const Geom &g = plan->g;
-    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.role, 2, plan->items, plan->nitems, args, ws, plan->grad_lds, s),
+    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.role, 2, plan->items, plan->nitems, args, ws, plan->grad_lds, s,
+                        g.bw),
             "fixed-image adjoint launch");
     return SRWCR_OK;
 }
@@ -1020,7 +1031,7 @@ int srwcr_grad_batched(const srwcr_batch *b, const srwcr_batch_item *items, void
                              b->max_nb, b->merge_waves, ws, s),
                 "merge launch");
     HIP_TRY(launch_finalize(b->geoms_dev, n, b->max_regions, args, ws, s), "finalize launch");
-    HIP_TRY(launch_grad(b->geoms_dev, b->fdt, b->role, 0, b->items_dev, b->nitems, args, ws, b->grad_lds, s),
+    HIP_TRY(launch_grad(b->geoms_dev, b->fdt, b->role, 0, b->items_dev, b->nitems, args, ws, b->grad_lds, s, b->bw),
             "gradient launch");
     HIP_TRY(launch_grad_out(b->geoms_dev, n, b->max_params, args, ws, s), "gradient output launch");
     return SRWCR_OK;
@@ -1169,7 +1180,7 @@ static int run_raptor(const srwcr_plan *plan, const raptor_patches *pt, const vo
     mark(4);
     HIP_TRY(launch_raptor_ds(plan->geom_dev, g.fdt, g.role, ra, args, ws, s), "RaPTOR derivative launch");
     mark(5);
-    HIP_TRY(launch_grad(plan->geom_dev, 0, 2, dense, plan->items, plan->nitems, args, ws, plan->grad_lds, s),
+    HIP_TRY(launch_grad(plan->geom_dev, 0, 2, dense, plan->items, plan->nitems, args, ws, plan->grad_lds, s, g.bw),
             "gradient launch");
     if (!dense) {
         const size_t n = 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2];

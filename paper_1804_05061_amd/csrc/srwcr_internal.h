@@ -91,6 +91,8 @@ struct Geom {
     int xw;                    // x-width of the work items (64 or 128 voxels)
     int c1n;                   // FFD x-nodes an item row touches at most: (xw - 1) / delta + 5 (warp pass)
     int gscr;                  // floats of per-wave scratch in the gradient pass
+    int bw;                    // (y, z) regions per axis of a value block and gradient item: 4 (one
+                               // spatial cell) or 5 (two cells, for small cells)
     WsLayout ws;               // this problem's slots in the workspace of a launch
 };
 
@@ -158,7 +160,7 @@ hipError_t launch_merge(const Geom *geoms, const double *staging, long stage_str
 hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const BatchArgs &args, unsigned char *ws,
                            hipStream_t s);
 hipError_t launch_grad(const Geom *geoms, int fdt, int role, int dense, const WorkItem *items, int nitems,
-                       const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s);
+                       const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s, int bw = 4);
 hipError_t launch_grad_out(const Geom *geoms, int nprob, size_t max_params, const BatchArgs &args, unsigned char *ws,
                            hipStream_t s);
 hipError_t launch_raptor_acc(const Geom *geoms, int fdt, int role, const RaptorArgs &ra, const BatchArgs &args,

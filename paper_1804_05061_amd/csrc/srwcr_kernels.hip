@@ -1039,7 +1039,8 @@ __host__ __device__ __forceinline__ int tab_stride(int nb) { return 3 * nb + ((1
 
 size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz)
 {
-    const size_t tab = (size_t)kNReg * tab_stride(g.nb) * sizeof(float) + kNReg * sizeof(float);
+    const size_t nreg = (size_t)kXN * g.bw * g.bw;
+    const size_t tab = nreg * tab_stride(g.nb) * sizeof(float) + nreg * sizeof(float);
     const size_t G = (size_t)gnx * gny * gnz * 3 * sizeof(double);
     const size_t scratch = (size_t)(kGradThreads / kWave) * g.gscr * sizeof(float);
     const size_t bxw = (size_t)g.xw * sizeof(float4);
@@ -1060,7 +1061,7 @@ struct VoxG {
 // args.p[].grad (no chain rule).  ROLE 0 / 1: the adjoints from the SRWCR
 // region tables, moving image as A / B; ROLE 2: dD/ds_M read per voxel from
 // the workspace (RaPTOR), so only the chain rule (eq 16) and the scatter run.
-template <int FDT, int ROLE, int DISP>
+template <int FDT, int ROLE, int DISP, int BW>
 __global__ void __launch_bounds__(kGradThreads)
 k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, BatchArgs args, unsigned char *ws)
 {
@@ -1085,11 +1086,12 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     float4 *bxw = reinterpret_cast<float4 *>(smem);                     // FFD x weights of the item's x range
     double *G = reinterpret_cast<double *>(bxw + g.xw);                 // [gnz][gny][gnx][3]
     float *tab = reinterpret_cast<float *>(G + nG);                      // [80 regions][ts]: (a, c) at a*3 + c
-    float *alph = tab + kNReg * ts;                                      // [80]
+    constexpr int NR = kXN * BW * BW;                                    // regions of the item's block
+    float *alph = tab + NR * ts;                                         // [NR]
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
-    float *scr = alph + kNReg + wave * g.gscr;
+    float *scr = alph + NR + wave * g.gscr;
     // the adjoint taken: of the image that plays A (eq 21) or B (eq 19), and
     // where its tables sit in the four slots per (region, bin)
     constexpr bool FA = DISP == 2 ? ROLE == 1 : ROLE == 0;
@@ -1101,11 +1103,11 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         const double4 b = gld(g.ffd_w[0], it.x0 + i);
         bxw[i] = make_float4((float)b.x, (float)b.y, (float)b.z, (float)b.w);
     }
-    for (int i = threadIdx.x; ROLE < 2 && i < kNReg * nb; i += blockDim.x) {
+    for (int i = threadIdx.x; ROLE < 2 && i < NR * nb; i += blockDim.x) {
         const int rl = i / nb, a = i - rl * nb;
-        const int ii = rl % kXN, jk = rl / kXN, jj = jk & 3, kk = jk >> 2;
+        const int ii = rl % kXN, jk = rl / kXN, kk = jk / BW, jj = jk - kk * BW;
         float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f, al = 0.0f;
-        if (it.cx + ii < g.K[0]) {
+        if (it.cx + ii < g.K[0] && it.cy + jj < g.K[1] && it.cz + kk < g.K[2]) {
             const int R = ((it.cz + kk) * g.K[1] + (it.cy + jj)) * g.K[0] + (it.cx + ii);
             const float *tp = tables + ((size_t)R * nb + a) * 4 + CO;
             t0 = tp[0];
@@ -1168,6 +1170,13 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         } else {
         float wyv[4], wzv[4];
         row_sp_weights(spw_y, spw_z, y, z, lane, wyv, wzv);
+        int oyz = 0;                                                 // the row's (y, z) cells in a two-cell item
+        if constexpr (BW == 5) {
+            int c = 0;
+            if (lane == 0) c = gld(g.sp_cell[1], y);
+            else if (lane == 1) c = gld(g.sp_cell[2], z);
+            oyz = (bcast(c, 1) - it.cz) * BW + (bcast(c, 0) - it.cy);
+        }
 
         // dD/ds_M: the region tables interpolated by w(r, x) = wx wy wz.  Row
         // tables T_row[s][i][c] = sum_jk wy_j wz_k T[(i, j, k)][bin_s][c] are
@@ -1193,11 +1202,11 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             const int i = FA ? r / 3 : r, c = FA ? r - 3 * i : 0;
             float acc = 0.0f;
             if (a <= (FA ? L - 1 : L)) {
-                const float *tp = tab + i * ts + a * 3 + c;
+                const float *tp = tab + (oyz * kXN + i) * ts + a * 3 + c;
 #pragma unroll
                 for (int kz = 0; kz < 4; ++kz)
 #pragma unroll
-                    for (int jy = 0; jy < 4; ++jy) acc = fmaf(wyv[jy] * wzv[kz], tp[(kz * 4 + jy) * kXN * ts], acc);
+                    for (int jy = 0; jy < 4; ++jy) acc = fmaf(wyv[jy] * wzv[kz], tp[(kz * BW + jy) * kXN * ts], acc);
             }
             rowt[e] = acc;
         }
@@ -1208,7 +1217,8 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
 #pragma unroll
                 for (int kz = 0; kz < 4; ++kz)
 #pragma unroll
-                    for (int jy = 0; jy < 4; ++jy) al = fmaf(wyv[jy] * wzv[kz], alph[(kz * 4 + jy) * kXN + lane], al);
+                    for (int jy = 0; jy < 4; ++jy)
+                        al = fmaf(wyv[jy] * wzv[kz], alph[(oyz + kz * BW + jy) * kXN + lane], al);
             }
 #pragma unroll
             for (int i = 0; i < kXN; ++i) arow[i] = bcast(al, i);
@@ -1336,12 +1346,18 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
 }
 
 hipError_t launch_grad(const Geom *geoms, int fdt, int role, int dense, const WorkItem *items, int nitems,
-                       const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s)
+                       const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s, int bw)
 {
     if (nitems <= 0) return hipSuccess;
 #define SRWCR_GRAD(F, R, D)                                                                                     \
-    if (fdt == F && role == R && dense == D)                                                                    \
-        hipLaunchKernelGGL((k_grad<F, R, D>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, geoms, items, args, ws);
+    if (fdt == F && role == R && dense == D) {                                                                  \
+        if (bw == 5)                                                                                            \
+            hipLaunchKernelGGL((k_grad<F, R, D, 5>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, geoms, items,   \
+                               args, ws);                                                                       \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_grad<F, R, D, 4>), dim3(nitems), dim3(kGradThreads), lds_bytes, s, geoms, items,   \
+                               args, ws);                                                                       \
+    }
     SRWCR_GRAD(0, 0, 0) SRWCR_GRAD(0, 0, 1) SRWCR_GRAD(0, 1, 0) SRWCR_GRAD(0, 1, 1)
     SRWCR_GRAD(1, 0, 0) SRWCR_GRAD(1, 0, 1) SRWCR_GRAD(1, 1, 0) SRWCR_GRAD(1, 1, 1)
     SRWCR_GRAD(2, 0, 0) SRWCR_GRAD(2, 0, 1) SRWCR_GRAD(2, 1, 0) SRWCR_GRAD(2, 1, 1)
@@ -1372,19 +1388,26 @@ hipError_t prepare_kernels()
     SRWCR_SET(4) SRWCR_SET(5)
 #undef SRWCR_SET
 #define SRWCR_SET(A, B)                                                             \
-    if (e == hipSuccess) e = set_lds(k_grad<0, A, B>, b);                           \
-    if (e == hipSuccess) e = set_lds(k_grad<1, A, B>, b);                           \
-    if (e == hipSuccess) e = set_lds(k_grad<2, A, B>, b);                           \
+    if (e == hipSuccess) e = set_lds(k_grad<0, A, B, 4>, b);                        \
+    if (e == hipSuccess) e = set_lds(k_grad<1, A, B, 4>, b);                        \
+    if (e == hipSuccess) e = set_lds(k_grad<2, A, B, 4>, b);                        \
+    if (e == hipSuccess) e = set_lds(k_grad<0, A, B, 5>, b);                        \
+    if (e == hipSuccess) e = set_lds(k_grad<1, A, B, 5>, b);                        \
+    if (e == hipSuccess) e = set_lds(k_grad<2, A, B, 5>, b);                        \
     if (e == hipSuccess) e = set_lds(k_prep<0, A, B>, b);                           \
     if (e == hipSuccess) e = set_lds(k_prep<1, A, B>, b);                           \
     if (e == hipSuccess) e = set_lds(k_prep<2, A, B>, b);
     SRWCR_SET(0, 0) SRWCR_SET(0, 1) SRWCR_SET(1, 0) SRWCR_SET(1, 1)
 #undef SRWCR_SET
-    if (e == hipSuccess) e = set_lds(k_grad<0, 2, 0>, b);
-    if (e == hipSuccess) e = set_lds(k_grad<0, 2, 1>, b);
+    if (e == hipSuccess) e = set_lds(k_grad<0, 2, 0, 4>, b);
+    if (e == hipSuccess) e = set_lds(k_grad<0, 2, 1, 4>, b);
+    if (e == hipSuccess) e = set_lds(k_grad<0, 2, 0, 5>, b);
+    if (e == hipSuccess) e = set_lds(k_grad<0, 2, 1, 5>, b);
 #define SRWCR_SET(F)                                                                \
-    if (e == hipSuccess) e = set_lds(k_grad<F, 0, 2>, b);                           \
-    if (e == hipSuccess) e = set_lds(k_grad<F, 1, 2>, b);
+    if (e == hipSuccess) e = set_lds(k_grad<F, 0, 2, 4>, b);                        \
+    if (e == hipSuccess) e = set_lds(k_grad<F, 1, 2, 4>, b);                        \
+    if (e == hipSuccess) e = set_lds(k_grad<F, 0, 2, 5>, b);                        \
+    if (e == hipSuccess) e = set_lds(k_grad<F, 1, 2, 5>, b);
     SRWCR_SET(0) SRWCR_SET(1) SRWCR_SET(2)
 #undef SRWCR_SET
     if (e == hipSuccess && dev < 64) done[dev] = true;

@@ -55,3 +55,44 @@ def test_node_regions_paper_operating_point(orc):
     assert P.n_regions == 55 * 55 * 23
     assert abs(D - Dr) <= 1e-5 * Dr
     assert rel(g, gr) <= 1e-4
+
+
+@pytest.mark.parametrize("role", [0, 1])
+def test_node_regions_dense_fixed_and_raptor(orc, role):
+    """With the regions at the FFD nodes the value blocks and gradient items
+    span two spatial cells along y and z: the dense-field gradient, dD/ds_F
+    and RaPTOR's FFD gradient (which runs through the same gradient pass) all
+    match the oracle."""
+    import paper_1804_05061_amd as S
+    w = synth.blobs(48)
+    nb, d = 32, 5
+    dims = w.fixed_dims
+    flo, fhi, mlo, mhi = float(w.fixed.min()), float(w.fixed.max()), float(w.moving.min()), float(w.moving.max())
+    f = S.normalize(torch.from_numpy(w.fixed).cuda(), flo, fhi, nb)
+    m = S.normalize(torch.from_numpy(w.moving).cuda(), mlo, mhi, nb)
+    fo = orc.normalize(w.fixed, flo, fhi, nb)
+    mo = orc.normalize(w.moving, mlo, mhi, nb)
+    P = S.Problem(dims, dims, nb, (0, 0, 0), (d, d, d), role)
+    plan = S.Plan(P)
+    rng = np.random.default_rng(1804_05061 + 80 + role)
+    u = rng.normal(0.0, 0.8, size=P.field_shape).astype(np.float32)
+    D, gu = plan.grad_dense(f, m, torch.from_numpy(u).cuda())
+    Df, gf = plan.grad_fixed(f, m, torch.from_numpy(u).cuda(), dense=True)
+    ffd = synth.random_ffd(P.ctrl_dims, 1.0, 81 + role)
+    boxes = synth.raptor_patches(dims, side=9, coverage=1.0, k=82 + role)
+    rp = S.RaptorPatches(plan, boxes)
+    R, gr = rp.grad(f, m, torch.from_numpy(ffd).cuda())
+    torch.cuda.synchronize()
+    Pd = orc.Problem(dims, dims, nb, (0, 0, 0), (d, d, d), role, dense=True)
+    Dr, gur = orc.gradient(Pd, fo, mo, u)
+    _, gfr = orc.gradient_fixed(Pd, fo, mo, u)
+    Po = orc.Problem(dims, dims, nb, (0, 0, 0), (d, d, d), role)
+    Rr, grr = orc.raptor(Po, fo, mo, ffd, boxes, want_grad=True)
+    print(f"nodes blobs48 role={role}: dense D rel {abs(float(D) - Dr) / Dr:.1e} grad {rel(gu.cpu().numpy(), gur):.2e}; "
+          f"dD/dF {rel(gf.cpu().numpy(), gfr):.2e}; RaPTOR rel {abs(float(R) - Rr) / Rr:.1e} grad "
+          f"{rel(gr.cpu().numpy(), grr):.2e}", flush=True)
+    assert abs(float(D) - Dr) <= 1e-5 * Dr and abs(float(Df) - Dr) <= 1e-5 * Dr
+    assert rel(gu.cpu().numpy(), gur) <= 1e-4
+    assert rel(gf.cpu().numpy(), gfr) <= 1e-4
+    assert abs(float(R) - Rr) <= 1e-5 * Rr
+    assert rel(gr.cpu().numpy(), grr) <= 1e-4
