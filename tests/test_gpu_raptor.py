@@ -120,3 +120,33 @@ def test_raptor_argument_checks():
     v = rp.eval(f, m, d)
     torch.cuda.synchronize()
     assert float(v) == 0.0
+
+
+@pytest.mark.parametrize("fdt,mdt,role", [(1, 1, 0), (2, 2, 1), (1, 0, 1)])
+def test_raptor_and_fixed_gradient_16bit_storage(orc, fdt, mdt, role):
+    """FP16 / BF16 storage of the normalised volumes: RaPTOR (value and FFD
+    gradient) and dD/ds_F against the oracle run on the same stored values."""
+    import paper_1804_05061_amd as S
+    tdt = {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}
+    dims = (70, 45, 23)
+    fr, mr = synth.smooth_pair(dims[::-1], k=50 + fdt + mdt, n_blobs=10)
+    nb = 32
+    f = S.normalize(torch.from_numpy(fr).cuda(), float(fr.min()), float(fr.max()), nb, tdt[fdt])
+    m = S.normalize(torch.from_numpy(mr).cuda(), float(mr.min()), float(mr.max()), nb, tdt[mdt])
+    fo, mo = f.float().cpu().numpy(), m.float().cpu().numpy()     # the stored values, exactly
+    P = S.Problem(dims, dims, nb, (4, 4, 4), (5, 5, 5), role, fdt, mdt)
+    plan = S.Plan(P)
+    ffd = synth.random_ffd(P.ctrl_dims, 1.0, 51 + role)
+    boxes = synth.raptor_patches(dims, side=9, coverage=1.5, k=52)
+    rp = S.RaptorPatches(plan, boxes)
+    v, g = rp.grad(f, m, torch.from_numpy(ffd).cuda())
+    D, gF = plan.grad_fixed(f, m, torch.from_numpy(ffd).cuda())
+    torch.cuda.synchronize()
+    Po = orc.Problem(dims, dims, nb, (4, 4, 4), (5, 5, 5), role)
+    vr, gr = orc.raptor(Po, fo, mo, ffd, boxes, want_grad=True)
+    Dr, gFr = orc.gradient_fixed(Po, fo, mo, ffd)
+    print(f"16-bit fdt={fdt} mdt={mdt} role={role}: RaPTOR rel {abs(float(v) - vr) / vr:.1e} grad "
+          f"{rel(g.cpu().numpy(), gr):.2e}; D rel {abs(float(D) - Dr) / Dr:.1e} dD/dF {rel(gF.cpu().numpy(), gFr):.2e}",
+          flush=True)
+    assert abs(float(v) - vr) <= 1e-5 * vr and rel(g.cpu().numpy(), gr) <= 1e-4
+    assert abs(float(D) - Dr) <= 1e-5 * Dr and rel(gF.cpu().numpy(), gFr) <= 1e-4
