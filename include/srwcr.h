@@ -74,12 +74,18 @@ int srwcr_ctrl_dims(const srwcr_problem *prob, int32_t out_nc[3]);
  * tables and the launch geometry, uploaded once to the current device.  The
  * plan is immutable and may be shared by concurrent calls on different
  * streams provided each call has its own workspace.  Spatial bins: K nodes per
- * axis at spacing (N - 1) / (K - 3), node j at (j - 1) * spacing (eqs 7, 8). */
+ * axis at spacing (N - 1) / (K - 3), node j at (j - 1) * spacing (eqs 7, 8),
+ * or, with spatial_bins (0, 0, 0), the FFD nodes themselves.  Returns
+ * SRWCR_E_INVALID_ARG for a bad problem and SRWCR_E_UNSUPPORTED when the
+ * passes do not fit the device's LDS (more than 64 bins cannot occur). */
 int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out);
 void srwcr_plan_destroy(srwcr_plan *plan);
 
-/* Device workspace bytes srwcr_eval / srwcr_grad need (moment slots in FP64,
- * per-region tables, gradient accumulators).  Callers allocate it once. */
+/* Device workspace bytes srwcr_eval / srwcr_grad / srwcr_grad_fixed need
+ * (moment slots in FP64, per-region tables, gradient accumulators, the warp
+ * pass's per-voxel samples and the value pass's staging slots; 213 MB at
+ * 256 x 256 x 128).  Callers allocate it once; its contents need no
+ * initialisation and do not persist between calls. */
 size_t srwcr_workspace_bytes(const srwcr_plan *plan);
 
 /* a1 -- intensity normalisation of Sec. II.  out[i] = clamp(fl32(fl32(in[i]

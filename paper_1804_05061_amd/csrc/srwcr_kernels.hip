@@ -634,14 +634,15 @@ __device__ __forceinline__ void value_window(double *H, int L, const int (&b)[kW
 }
 
 // Value pass.  Schedule: one persistent workgroup per compute unit (the FP64
-// histogram of a 5 x 4 x 4 region block fills most of its LDS).  The item
-// rows of all region blocks (an x-chunk of at most two spatial cells by one
-// cell in y and z) form one list ordered by block; workgroup w takes rows
-// [w T / G, (w + 1) T / G) of the T rows, accumulates them in LDS and merges
-// the histogram into the global moments (FP64 atomics) only when its range
-// leaves a block, so that each block is flushed about once per workgroup that
-// touches it rather than once per small item.  The rows of one block are
-// dealt to the waves round-robin.  Reads the warp pass's per-voxel moving bins
+// histogram of a 5 x BW x BW region block fills most of its LDS).  The rows
+// of all region blocks (an x-chunk of at most two spatial cells by one cell in
+// y and z, or two for small cells) form one list ordered by block; workgroup w
+// takes rows [w T / G, (w + 1) T / G) of the T rows, accumulates them in LDS
+// and empties the histogram only when its range leaves a block: into staging
+// slots of its own (merged by k_merge in a fixed order) or, without staging,
+// into the global moments with FP64 atomics.  Inside the workgroup the rows of
+// a block go to the waves one at a time from an LDS counter (long runs) or
+// round-robin (short runs).  Reads the warp pass's per-voxel moving bins
 // (k_prep) and the fixed image.
 template <int FDT, int BW>
 __global__ void __launch_bounds__(kValueThreads)
