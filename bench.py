@@ -6,9 +6,11 @@ displacements N(0, 2 vox)): the FFD warp, the joint-moment value pass, the FP64
 finalisation and the gradient pass with its scatter to the control points.
 Inputs are resident in device memory before the timed region starts.
 
-Prints ONE JSON line.  `roofline` covers the dominant kernel: algorithmic
-bytes (the fixed and moving volumes read once per pass) over its mean
-duration, timed with HIP events recorded on the launch stream.  `cpu_baseline`
+Prints ONE JSON line.  `roofline` covers the dominant kernel, the value
+pass: algorithmic bytes (the fixed and moving volumes read once) over its
+mean duration, timed with one HIP event pair per timed step recorded on the
+launch stream; the per-phase breakdown comes from 10 further steps with every
+phase recorded.  `cpu_baseline`
 times the FP64 CPU oracle on a bounded z-slab of the same workload.
 """
 from __future__ import annotations
@@ -110,30 +112,36 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] warm-up done ({args.warmup} steps), plan {plan.info()}", file=sys.stderr, flush=True)
 
-    plan.profile(True)
+    # the timed steps record one HIP event pair per call, around the value
+    # pass (the dominant kernel); a few more steps with every phase recorded
+    # give the breakdown (events between all kernels would slow the steps)
+    plan.profile(2)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
         plan.grad(f, m, ffd, vbuf, gbuf)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    prof_v = plan.profile_read()
+    plan.profile(1)
+    for _ in range(10):
+        plan.grad(f, m, ffd, vbuf, gbuf)
     prof = plan.profile_read()
-    plan.profile(False)
+    plan.profile(0)
     ms_step = 1e3 * elapsed / args.steps
     D = float(vbuf.item())
-    print(f"[bench] {args.steps} steps in {elapsed:.4f}s, D={D:.10f}, phases(ms total)={prof}", file=sys.stderr,
-          flush=True)
+    print(f"[bench] {args.steps} steps in {elapsed:.4f}s, D={D:.10f}, value pass {prof_v['value']:.4f} ms total, "
+          f"phases of 10 more steps (ms total)={prof}", file=sys.stderr, flush=True)
 
     # dominant kernel and its roofline (algorithmic bytes: F and M read once per pass)
     bytes_f = {"f32": 4, "f16": 2, "bf16": 2}[args.dtype]
     alg_bytes = bytes_f * (nvox + int(np.prod(w.moving_dims)))
-    kern = {"srwcr_warp_pass": prof["warp"] / prof["calls"], "srwcr_value_pass": prof["value"] / prof["calls"],
-            "srwcr_grad_pass": prof["grad"] / prof["calls"]}
-    dom = max(kern, key=kern.get)
-    achieved = alg_bytes / (kern[dom] * 1e-3) / 1e9
+    dom = "srwcr_value_pass"
+    mean_ms = prof_v["value"] / prof_v["calls"]
+    achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "alg_bytes_per_launch": alg_bytes, "mean_ms": round(kern[dom], 5),
+                "alg_bytes_per_launch": alg_bytes, "mean_ms": round(mean_ms, 5),
                 "phase_ms": {k: round(v / prof["calls"], 5) for k, v in prof.items() if k != "calls"}}
 
     rec = TRAFFIC.get((kernel_source_sha(), args.workload, dom, dt[2]))
@@ -324,19 +332,25 @@ def bench_raptor256(args):
     for _ in range(args.warmup):
         rp.grad(f, m, ffd, value_out=vbuf, grad_out=gbuf)
     torch.cuda.synchronize()
-    plan.profile(True)
+    # one event pair per timed call around the patch sums, then 10 more calls
+    # with every phase recorded for the breakdown
+    plan.profile(2)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
         rp.grad(f, m, ffd, value_out=vbuf, grad_out=gbuf)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    prof_v = rp.profile_read()
+    plan.profile(1)
+    for _ in range(10):
+        rp.grad(f, m, ffd, value_out=vbuf, grad_out=gbuf)
     prof = rp.profile_read()
-    plan.profile(False)
+    plan.profile(0)
     ms_step = 1e3 * elapsed / args.steps
     R = float(vbuf.item())
-    print(f"[bench] {args.steps} steps in {elapsed:.4f}s, RaPTOR={R:.10f}, phases(ms total)={prof}",
-          file=sys.stderr, flush=True)
+    print(f"[bench] {args.steps} steps in {elapsed:.4f}s, RaPTOR={R:.10f}, patch sums {prof_v['patch_sums']:.4f} ms "
+          f"total, phases of 10 more calls (ms total)={prof}", file=sys.stderr, flush=True)
 
     # algorithmic bytes per launch of each kernel (its inputs read once, its outputs written once):
     #   warp pass: M read once (4 B / moving voxel)
@@ -345,8 +359,8 @@ def bench_raptor256(args):
     #   chain rule: the per-voxel sum (4 B) and dM/dy (12 B) per fixed voxel
     alg = {"warp": 4 * int(np.prod(w.moving_dims)), "patch_sums": 12 * patch_vox, "derivative": 16 * patch_vox,
            "chain_rule": 16 * nvox}
-    kern = {k: prof[k] / prof["calls"] for k in alg}
-    dom = max(kern, key=kern.get)
+    dom = "patch_sums"
+    kern = {dom: prof_v[dom] / prof_v["calls"]}
     achieved = alg[dom] / (kern[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "alg_bytes_per_launch": alg[dom],

@@ -81,6 +81,20 @@ int srwcr_ctrl_dims(const srwcr_problem *prob, int32_t out_nc[3]);
 int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out);
 void srwcr_plan_destroy(srwcr_plan *plan);
 
+/* Launch-shape knobs of a plan, for autotuning (the Python `tune()` times
+ * candidates on the caller's data and caches the best per problem and
+ * device).  0 keeps the default.  grad_item_voxels: target voxels of a
+ * gradient-pass work item (default |F| / 600 clamped to 2048 .. 65536; items
+ * are also bounded by the spatial cells and the LDS); value_workgroups:
+ * persistent value-pass workgroups (default one per compute unit).  Results
+ * do not depend on the knobs beyond FP summation order.  Returns
+ * SRWCR_E_INVALID_ARG for negative values. */
+typedef struct {
+    int32_t grad_item_voxels;
+    int32_t value_workgroups;
+} srwcr_tuning;
+int srwcr_plan_create_tuned(const srwcr_problem *prob, const srwcr_tuning *tuning, srwcr_plan **out);
+
 /* Device workspace bytes srwcr_eval / srwcr_grad / srwcr_grad_fixed need
  * (moment slots in FP64, per-region tables, gradient accumulators, the warp
  * pass's per-voxel samples and the value pass's staging slots; 213 MB at
@@ -281,8 +295,11 @@ int srwcr_plan_info(const srwcr_plan *plan, int32_t *n_items, int32_t *value_lds
  * gradient output -- and the number of calls
  * recorded.  raptor_grad calls on the plan are recorded too, with the phases
  * zeroing, warp pass, patch sums, patch finalisation, per-voxel derivative,
- * chain rule (gradient pass and output).  Not thread-safe: profile one
- * stream and one kind of call at a time. */
+ * chain rule (gradient pass and output).  enable = 2 records only the two
+ * events around the value pass (patch sums for RaPTOR), so that timing it
+ * adds one event pair per call; the other phases then read 0.  Read the
+ * results before changing the mode.  Not thread-safe: profile one stream and
+ * one kind of call at a time. */
 int srwcr_profile(const srwcr_plan *plan, int32_t enable);
 int srwcr_profile_read(const srwcr_plan *plan, double ms[6], int32_t *calls);
 

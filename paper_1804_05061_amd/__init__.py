@@ -24,7 +24,8 @@ _TORCH_DT = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
 _DT_OF = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
 
 __all__ = ["Problem", "Plan", "Batch", "normalize", "minmax", "register_lbfgs", "LbfgsOptions", "SrwcrError",
-           "MOVING_AS_A", "MOVING_AS_B", "F32", "F16", "BF16", "SRWCRLoss", "SRWCRDenseLoss", "RaptorPatches"]
+           "MOVING_AS_A", "MOVING_AS_B", "F32", "F16", "BF16", "SRWCRLoss", "SRWCRDenseLoss", "RaptorPatches",
+           "tune"]
 
 
 def _stream():
@@ -109,13 +110,18 @@ class Problem:
 class Plan:
     """A plan (device tables and launch geometry) plus its own workspace."""
 
-    def __init__(self, problem: Problem, device=None):
+    def __init__(self, problem: Problem, device=None, tuning=None):
+        """tuning: None, or a dict with grad_item_voxels / value_workgroups
+        (see `tune`; 0 or missing keeps the default)."""
         self.problem = problem
+        self.tuning = dict(tuning or {})
         L = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         with torch.cuda.device(self.device):
             h = ctypes.c_void_p()
-            _lib.check(L.srwcr_plan_create(ctypes.byref(problem.c()), ctypes.byref(h)))
+            t = _lib.SrwcrTuning(int(self.tuning.get("grad_item_voxels", 0)),
+                                 int(self.tuning.get("value_workgroups", 0)))
+            _lib.check(L.srwcr_plan_create_tuned(ctypes.byref(problem.c()), ctypes.byref(t), ctypes.byref(h)))
             self._h = h
             self.workspace_bytes = int(L.srwcr_workspace_bytes(h))
             self.workspace = torch.zeros(self.workspace_bytes, dtype=torch.uint8, device=self.device)
@@ -218,9 +224,10 @@ class Plan:
         _lib.check(_lib.load().ffd_warp(self._h, _ptr(moving), _ptr(ffd), _ptr(out), _stream()))
         return out
 
-    def profile(self, enable: bool):
-        """Start (True) or stop (False) per-kernel HIP-event timing of grad()."""
-        _lib.check(_lib.load().srwcr_profile(self._h, 1 if enable else 0))
+    def profile(self, enable):
+        """Start per-kernel HIP-event timing of grad() (True or 1: every phase;
+        2: only the value pass, one event pair per call) or stop it (False, 0)."""
+        _lib.check(_lib.load().srwcr_profile(self._h, int(enable)))
 
     def profile_read(self) -> dict:
         """Summed milliseconds per phase of the grad() calls recorded so far."""
@@ -238,6 +245,63 @@ class Plan:
         _lib.check(_lib.load().srwcr_debug_moments(self._h, _ptr(fixed), _ptr(moving), _ptr(ffd), _ptr(out),
                                                    _ptr(self.workspace), self.workspace_bytes, _stream()))
         return out
+
+
+def _tune_key(problem: Problem, device) -> str:
+    p = problem
+    return (f"{torch.cuda.get_device_name(device)}|{tuple(p.fixed_dims)}|{tuple(p.moving_dims)}|{p.n_bins}|"
+            f"{tuple(p.spatial_bins)}|{tuple(p.ctrl_spacing)}|{p.role}|{p.fixed_dtype}|{p.moving_dtype}")
+
+
+def tune(problem: Problem, fixed, moving, ffd, item_voxels=None, workgroups=None, steps: int = 10,
+         cache: str | None = None) -> dict:
+    """Autotune a plan's launch shape on the caller's data: every candidate
+    (gradient-pass item size x value-pass workgroup count) is timed over
+    `steps` srwcr_grad calls after a warm-up, and the fastest is returned as
+    {"grad_item_voxels", "value_workgroups", "ms", "timings"}.  Candidates
+    default to |F| / (1200, 600, 300) voxels per item and (1/2, 1) x the
+    compute units.  With `cache` (a JSON file, default $SRWCR_TUNE_CACHE), a
+    result for the same problem and device is reused and new ones are
+    stored."""
+    import json
+    import os
+    import time
+    cache = cache or os.environ.get("SRWCR_TUNE_CACHE")
+    device = fixed.device
+    key = _tune_key(problem, device)
+    db = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as fh:
+            db = json.load(fh)
+        if key in db:
+            return db[key]
+    nvox = int(problem.fixed_dims[0]) * int(problem.fixed_dims[1]) * int(problem.fixed_dims[2])
+    ncu = torch.cuda.get_device_properties(device).multi_processor_count
+    item_voxels = item_voxels or sorted({max(2048, min(65536, nvox // d)) for d in (1200, 600, 300)})
+    workgroups = workgroups or sorted({max(1, ncu // 2), ncu})
+    timings = []
+    for iv in item_voxels:
+        for wg in workgroups:
+            plan = Plan(problem, device.index, {"grad_item_voxels": iv, "value_workgroups": wg})
+            v = torch.empty((), dtype=torch.float64, device=device)
+            g = torch.empty(problem.ffd_shape, dtype=torch.float32, device=device)
+            for _ in range(2):
+                plan.grad(fixed, moving, ffd, v, g)
+            torch.cuda.synchronize(device)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                plan.grad(fixed, moving, ffd, v, g)
+            torch.cuda.synchronize(device)
+            timings.append({"grad_item_voxels": iv, "value_workgroups": wg,
+                            "ms": 1e3 * (time.perf_counter() - t0) / steps})
+            del plan
+    best = dict(min(timings, key=lambda r: r["ms"]))
+    best["timings"] = timings
+    if cache:
+        db[key] = best
+        with open(cache, "w") as fh:
+            json.dump(db, fh, indent=1)
+    return best
 
 
 class Batch:

@@ -18,7 +18,7 @@ EXPORTED = ["srwcr_ctrl_dims", "srwcr_plan_create", "srwcr_plan_destroy", "srwcr
             "srwcr_profile", "srwcr_profile_read", "srwcr_refine_ffd", "srwcr_bending_energy",
             "srwcr_eval_dense", "srwcr_grad_dense", "srwcr_batch_create", "srwcr_batch_destroy", "srwcr_batch_workspace_bytes", "srwcr_grad_batched",
             "raptor_patches_create", "raptor_patches_destroy", "raptor_workspace_bytes", "raptor_eval",
-            "raptor_grad", "srwcr_grad_fixed", "srwcr_last_error"]
+            "raptor_grad", "srwcr_grad_fixed", "srwcr_plan_create_tuned", "srwcr_last_error"]
 
 MAX_BATCH = 32
 
@@ -44,6 +44,10 @@ class SrwcrLbfgsReport(ctypes.Structure):
 class SrwcrBatchItem(ctypes.Structure):
     _fields_ = [("fixed", ctypes.c_void_p), ("moving", ctypes.c_void_p), ("ffd", ctypes.c_void_p),
                 ("d_value", ctypes.c_void_p), ("d_grad", ctypes.c_void_p)]
+
+
+class SrwcrTuning(ctypes.Structure):
+    _fields_ = [("grad_item_voxels", ctypes.c_int32), ("value_workgroups", ctypes.c_int32)]
 
 
 class SrwcrPatch(ctypes.Structure):
@@ -101,6 +105,7 @@ def load() -> ctypes.CDLL:
         "raptor_eval": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, vp, vp, sz, vp]),
         "raptor_grad": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]),
         "srwcr_grad_fixed": (ctypes.c_int, [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]),
+        "srwcr_plan_create_tuned": (ctypes.c_int, [pp, ctypes.POINTER(SrwcrTuning), ctypes.POINTER(vp)]),
         "srwcr_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

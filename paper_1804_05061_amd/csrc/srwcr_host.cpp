@@ -182,7 +182,7 @@ struct srwcr_plan {
     WsLayout ws;
     int device = 0;
     // diagnostics: per-phase HIP events recorded by srwcr_grad while profiling is on
-    mutable bool profiling = false;
+    mutable int profiling = 0;           // 0 off, 1 every phase, 2 the value pass (or patch sums) only
     mutable std::vector<hipEvent_t> ev_pool;
     mutable size_t ev_used = 0;
     mutable int32_t prof_calls = 0;
@@ -192,10 +192,12 @@ namespace {
 constexpr int kPhases = 6;            // zero, warp, value, finalise, gradient, gradient output
 constexpr size_t kProfCalls = 4096;   // calls recorded per profiling session
 
-// record event `k` of the current profiled call (no-op when profiling is off)
+// record event `k` of the current profiled call (no-op when profiling is off;
+// in mode 2 only the two events around phase 2)
 void prof_mark(const srwcr_plan *P, int k, hipStream_t s)
 {
     if (!P->profiling) return;
+    if (P->profiling == 2 && k != 2 && k != 3) return;
     const size_t base = (size_t)P->prof_calls * (kPhases + 1);
     if (base + kPhases + 1 > P->ev_pool.size()) return;
     (void)hipEventRecord(P->ev_pool[base + k], s);
@@ -227,10 +229,19 @@ void srwcr_plan_destroy(srwcr_plan *plan)
 
 int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
 {
+    return srwcr_plan_create_tuned(prob, nullptr, out);
+}
+
+int srwcr_plan_create_tuned(const srwcr_problem *prob, const srwcr_tuning *tuning, srwcr_plan **out)
+{
     if (!out) return fail(SRWCR_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
     int st = validate_problem(prob);
     if (st != SRWCR_OK) return st;
+    srwcr_tuning tune{0, 0};
+    if (tuning) tune = *tuning;
+    if (tune.grad_item_voxels < 0 || tune.value_workgroups < 0)
+        return fail(SRWCR_E_INVALID_ARG, "tuning values must be >= 0 (0: default)");
     const bool at_nodes = prob->spatial_bins[0] == 0;   // validated: all three 0, regions at the FFD nodes
     srwcr_plan *P = new srwcr_plan();
     P->prob = *prob;
@@ -397,7 +408,8 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
             }
             return ch;
         };
-        const double target = std::min(65536.0, std::max(2048.0, nvox / 600.0));
+        const double target = tune.grad_item_voxels > 0 ? std::max(256.0, (double)tune.grad_item_voxels)
+                                                         : std::min(65536.0, std::max(2048.0, nvox / 600.0));
         int xc_max = g.xw, yc_max = 0, zc_max = 0;
         std::vector<WorkItem> items;
         for (int attempt = 0; attempt < 64; ++attempt) {
@@ -487,7 +499,7 @@ int srwcr_plan_create(const srwcr_problem *prob, srwcr_plan **out)
             int ncu = 0;
             he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
             if (he != hipSuccess) { st = hip_fail(he, "hipDeviceGetAttribute(compute units)"); goto bad; }
-            P->nwg = std::max(1, std::min(ncu, vr.back()));
+            P->nwg = std::max(1, std::min(tune.value_workgroups > 0 ? tune.value_workgroups : ncu, vr.back()));
             {
                 const StagePlan sp = stage_plan(vb, vr, P->nwg, {&g}, P->value_bw);
                 const size_t nreg = (size_t)kXN * P->value_bw * P->value_bw;
@@ -807,7 +819,8 @@ int srwcr_profile(const srwcr_plan *plan, int32_t enable)
         plan->ev_pool.resize(kProfCalls * (kPhases + 1));
         for (auto &e : plan->ev_pool) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
     }
-    plan->profiling = enable != 0;
+    if (enable < 0 || enable > 2) return fail(SRWCR_E_INVALID_ARG, "profile mode %d is not 0, 1 or 2", enable);
+    plan->profiling = enable;
     plan->prof_calls = 0;
     return SRWCR_OK;
 }
@@ -818,6 +831,13 @@ int srwcr_profile_read(const srwcr_plan *plan, double ms[6], int32_t *calls)
     for (int k = 0; k < kPhases; ++k) ms[k] = 0.0;
     for (int32_t c = 0; c < plan->prof_calls; ++c) {
         const size_t base = (size_t)c * (kPhases + 1);
+        if (plan->profiling == 2) {
+            float t = 0.0f;
+            HIP_TRY(hipEventSynchronize(plan->ev_pool[base + 3]), "hipEventSynchronize");
+            HIP_TRY(hipEventElapsedTime(&t, plan->ev_pool[base + 2], plan->ev_pool[base + 3]), "hipEventElapsedTime");
+            ms[2] += t;
+            continue;
+        }
         HIP_TRY(hipEventSynchronize(plan->ev_pool[base + kPhases]), "hipEventSynchronize");
         for (int k = 0; k < kPhases; ++k) {
             float t = 0.0f;
