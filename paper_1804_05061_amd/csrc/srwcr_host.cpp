@@ -656,18 +656,29 @@ static BatchArgs one_problem(const void *fixed, const void *moving, const float 
     return a;
 }
 
-// zero -> warp pass -> value pass -> finalise (phases 0..3 of the profile)
+// zero -> warp pass -> value pass -> finalise (phases 0..3 of the profile; a
+// staged plan has no zero launch, its warp pass clears what needs clearing)
 static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, int with_grad, unsigned char *ws,
                      hipStream_t s)
 {
     const Geom &g = P->g;
     double *moments = (double *)(ws + P->ws.moments);
     const size_t nzero = (P->ws.counter + sizeof(double) - P->ws.moments) / sizeof(double);
+    // A staged value pass writes every moment slot, so only an FFD gradient's
+    // accumulators need clearing, and the warp pass does that on the side;
+    // otherwise a fill kernel clears the moments and accumulators first.
+    double *side_zero = nullptr;
+    long side_n = 0;
     prof_mark(P, 0, s);
-    HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
+    if (!P->staged) {
+        HIP_TRY(launch_zero(moments, nzero, s), "zero launch");
+    } else if (with_grad && !dense) {
+        side_zero = (double *)(ws + P->ws.grad);
+        side_n = 3L * g.nc[0] * g.nc[1] * g.nc[2];
+    }
     prof_mark(P, 1, s);
     HIP_TRY(launch_prep(P->geom_dev, g.mdt, dense, with_grad, P->wblocks, P->wrow, P->nwblocks, P->wrow_host.back(),
-                        args, ws, P->prep_lds, s),
+                        args, ws, P->prep_lds, s, side_zero, side_n),
             "warp launch");
     prof_mark(P, 2, s);
     const int nreg = kXN * P->value_bw * P->value_bw;
@@ -680,7 +691,7 @@ static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, int 
         HIP_TRY(launch_merge(P->geom_dev, (const double *)(ws + P->staging_off), stride, nreg, P->reg_start, P->ent,
                              nullptr, g.R, g.nb, P->merge_waves, ws, s),
                 "merge launch");
-    HIP_TRY(launch_finalize(P->geom_dev, 1, g.R, args, ws, s), "finalize launch");
+    HIP_TRY(launch_finalize(P->geom_dev, 1, g.R, args, ws, s, P->staged), "finalize launch");
     prof_mark(P, 4, s);
     return SRWCR_OK;
 }
@@ -1050,7 +1061,7 @@ int srwcr_grad_batched(const srwcr_batch *b, const srwcr_batch_item *items, void
                              b->nregions,
                              b->max_nb, b->merge_waves, ws, s),
                 "merge launch");
-    HIP_TRY(launch_finalize(b->geoms_dev, n, b->max_regions, args, ws, s), "finalize launch");
+    HIP_TRY(launch_finalize(b->geoms_dev, n, b->max_regions, args, ws, s, b->staged), "finalize launch");
     HIP_TRY(launch_grad(b->geoms_dev, b->fdt, b->role, 0, b->items_dev, b->nitems, args, ws, b->grad_lds, s, b->bw),
             "gradient launch");
     HIP_TRY(launch_grad_out(b->geoms_dev, n, b->max_params, args, ws, s), "gradient output launch");

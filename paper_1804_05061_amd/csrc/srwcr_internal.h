@@ -136,9 +136,10 @@ hipError_t launch_zero(double *p, size_t n, hipStream_t s);
 hipError_t launch_normalize(const float *in, int64_t n, float lo, float scale, float L, void *out, int dt,
                             hipStream_t s);
 hipError_t launch_minmax(const float *in, int64_t n, float *partial, int nblocks, hipStream_t s);
+// zero / nzero: doubles the warp pass clears on the side (or none).
 hipError_t launch_prep(const Geom *geoms, int mdt, int dense, int with_grad, const WorkItem *blocks,
                        const int *row_start, int nblocks, long nrows, const BatchArgs &args, unsigned char *ws,
-                       size_t lds_bytes, hipStream_t s);
+                       size_t lds_bytes, hipStream_t s, double *zero = nullptr, long nzero = 0);
 // Value pass over region blocks: row_start[b] = first row (in a list of all
 // blocks' rows) of block b, row_start[nblocks] = total; nwg persistent
 // workgroups share the rows evenly.
@@ -153,12 +154,14 @@ hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *blocks, cons
                         double *staging = nullptr, const int *visit_start = nullptr, long stage_stride = 0,
                         int bw = 4);
 // reg_id: (problem, region) per merged region, or null for regions 0 .. n - 1
-// of problem 0.
+// of problem 0.  Also finalises each region (results, gradient tables).
 hipError_t launch_merge(const Geom *geoms, const double *staging, long stage_stride, int nreg, const int *reg_start,
                         const int *ent, const int2 *reg_id, int nregions, int max_nb, int waves, unsigned char *ws,
                         hipStream_t s);
+// Region results and tables (skipped when `merged`: launch_merge wrote them),
+// then the value D of each problem.
 hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const BatchArgs &args, unsigned char *ws,
-                           hipStream_t s);
+                           hipStream_t s, bool merged = false);
 hipError_t launch_grad(const Geom *geoms, int fdt, int role, int dense, const WorkItem *items, int nitems,
                        const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s, int bw = 4);
 hipError_t launch_grad_out(const Geom *geoms, int nprob, size_t max_params, const BatchArgs &args, unsigned char *ws,

@@ -467,9 +467,12 @@ size_t prep_lds_bytes(const Geom &g) { return (size_t)(kValueThreads / kWave) * 
 template <int MDT, int DISP, int GRAD>
 __global__ void __launch_bounds__(kValueThreads)
 k_prep(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, const int *__restrict__ row_start,
-       int nblocks, BatchArgs args, unsigned char *ws)
+       int nblocks, BatchArgs args, unsigned char *ws, double *__restrict__ zero, long nzero)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    // clear `zero` (accumulators of a later pass) on the side, saving a launch
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nzero; i += (long)gridDim.x * blockDim.x)
+        zero[i] = 0.0;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long r = (long)blockIdx.x * (kValueThreads / kWave) + wave;
     if (r >= row_start[nblocks]) return;
@@ -521,13 +524,13 @@ k_prep(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, cons
 
 #define SRWCR_PREP(M, D, G)                                                                                   \
     hipLaunchKernelGGL((k_prep<M, D, G>), dim3(nwg), dim3(kValueThreads), lds_bytes, s, geoms, blocks, row_start, \
-                       nblocks, args, ws)
+                       nblocks, args, ws, zero, nzero)
 
 hipError_t launch_prep(const Geom *geoms, int mdt, int dense, int with_grad, const WorkItem *blocks,
                        const int *row_start, int nblocks, long nrows, const BatchArgs &args, unsigned char *ws,
-                       size_t lds_bytes, hipStream_t s)
+                       size_t lds_bytes, hipStream_t s, double *zero, long nzero)
 {
-    if (nblocks <= 0 || nrows <= 0) return hipSuccess;
+    if (nblocks <= 0 || nrows <= 0) return nzero > 0 ? launch_zero(zero, (size_t)nzero, s) : hipSuccess;
     const int nwg = (int)((nrows + kValueThreads / kWave - 1) / (kValueThreads / kWave));
 #define SRWCR_PREP_M(M)                                                                                      \
     if (mdt == M) {                                                                                          \
@@ -808,124 +811,17 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
     }
 }
 
-// Moments of a region from the staged value pass: the sum, in a fixed order,
-// of the staging slots of every visit whose block holds it (visits
-// ent[reg_start[q] ..], each entry visit * nreg + local region; a visit's slots
-// start at visit * stage_stride).  Workgroup q takes region reg_id[q] =
-// (problem, region), or (0, q) without reg_id; 64 W threads: wave w takes
-// entries w, w + W, ...; lane a < nb the three moments of bin a; the W
-// partial sums are added in wave order.
-__global__ void __launch_bounds__(1024)
-k_merge(const Geom *__restrict__ geoms, const double *__restrict__ staging, long stage_stride, int nreg,
-        const int *__restrict__ reg_start, const int *__restrict__ ent, const int2 *__restrict__ reg_id,
-        unsigned char *ws)
-{
-    extern __shared__ double part[];                     // [W][nb][3]
-    const int q = blockIdx.x;
-    const int2 id = reg_id ? reg_id[q] : make_int2(0, q);
-    const Geom &g = geoms[id.x];
-    double *__restrict__ moments = reinterpret_cast<double *>(ws + g.ws.moments);
-    const int r = id.y, nb = g.nb, lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
-    const int W = blockDim.x >> 6, nb3 = nb * 3;
-    const int e0 = reg_start[q], e1 = reg_start[q + 1];
-    auto slot = [&](int e) {
-        const int v = ent[e];
-        return staging + (size_t)(v / nreg) * stage_stride + (size_t)(v % nreg) * nb3 + 3 * lane;
-    };
-    double s[3] = {0.0, 0.0, 0.0};
-    if (lane < nb) {
-        int e = e0 + w;
-        for (; e + 3 * W < e1; e += 4 * W) {             // four entries in flight
-            double v[4][3];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double *p = slot(e + u * W);
-#pragma unroll
-                for (int m = 0; m < 3; ++m) v[u][m] = p[m];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int m = 0; m < 3; ++m) s[m] += v[u][m];
-        }
-        for (; e < e1; e += W) {
-            const double *p = slot(e);
-#pragma unroll
-            for (int m = 0; m < 3; ++m) s[m] += p[m];
-        }
-#pragma unroll
-        for (int m = 0; m < 3; ++m) part[(w * nb + lane) * 3 + m] = s[m];
-    }
-    __syncthreads();
-    if (w == 0 && lane < nb) {
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            double t = 0.0;
-            for (int ww = 0; ww < W; ++ww) t += part[(ww * nb + lane) * 3 + m];
-            moments[((size_t)r * nb + lane) * 3 + m] = t;
-        }
-    }
-}
-
-hipError_t launch_merge(const Geom *geoms, const double *staging, long stage_stride, int nreg, const int *reg_start,
-                        const int *ent, const int2 *reg_id, int nregions, int max_nb, int waves, unsigned char *ws,
-                        hipStream_t s)
-{
-    if (nregions <= 0) return hipSuccess;
-    const size_t lds = (size_t)waves * max_nb * 3 * sizeof(double);
-    hipLaunchKernelGGL(k_merge, dim3(nregions), dim3(waves * kWave), lds, s, geoms, staging, stage_stride, nreg,
-                       reg_start, ent, reg_id, ws);
-    return hipGetLastError();
-}
-
-template <typename F>
-static hipError_t set_lds(F *kernel, size_t bytes)
-{
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
-}
-
-hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *blocks, const int *row_start, int nblocks,
-                        int nwg, const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s,
-                        double *staging, const int *visit_start, long stage_stride, int bw)
-{
-    if (nblocks <= 0 || nwg <= 0) return hipSuccess;
-    const int ld = (int)(lds_bytes / sizeof(double));
-#define SRWCR_VAL(F)                                                                                               \
-    if (bw == 5)                                                                                                   \
-        hipLaunchKernelGGL((k_value<F, 5>), dim3(nwg), dim3(kValueThreads), lds_bytes, s, geoms, blocks, row_start, \
-                           nblocks, ld, args, ws, staging, visit_start, stage_stride);                             \
-    else                                                                                                           \
-        hipLaunchKernelGGL((k_value<F, 4>), dim3(nwg), dim3(kValueThreads), lds_bytes, s, geoms, blocks, row_start, \
-                           nblocks, ld, args, ws, staging, visit_start, stage_stride)
-    if (fdt == 0) SRWCR_VAL(0);
-    else if (fdt == 1) SRWCR_VAL(1);
-    else SRWCR_VAL(2);
-#undef SRWCR_VAL
-    return hipGetLastError();
-}
-
 // ---------------------------------------------------------- finalisation
-// One wave per region r (lane = intensity bin a).  region[4 r + 0..3] =
-// (U_r / sigma_r^2, p_r, sigma_r^2, CR_r), and the region's gradient tables;
-// k_value_sum then writes D = (1/Z) sum_r U_r / sigma_r^2.
-__global__ void __launch_bounds__(64)
-k_finalize(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
+// Called by one whole wave for region r of g, lane = intensity bin a holding
+// the bin's moments (P, S1, S2) (zeros for a >= nb):
+// region[4 r + 0..3] = (U_r / sigma_r^2, p_r, sigma_r^2, CR_r), and the
+// region's gradient tables and alpha_r.
+__device__ void finalize_region(const Geom &g, int r, int a, double P, double S1, double S2, unsigned char *ws)
 {
-    const Geom &g = geoms[blockIdx.y];
-    const int r = blockIdx.x, a = threadIdx.x, nb = g.nb;
-    if (r >= g.R) return;
-    const double *__restrict__ moments = reinterpret_cast<const double *>(ws + g.ws.moments);
+    const int nb = g.nb;
     double *region = reinterpret_cast<double *>(ws + g.ws.region);
     float *tables = reinterpret_cast<float *>(ws + g.ws.tables);
     float *alpha = reinterpret_cast<float *>(ws + g.ws.alpha);
-    double P = 0.0, S1 = 0.0, S2 = 0.0;
-    if (a < nb) {
-        const double *mp = moments + ((size_t)r * nb + a) * 3;
-        P = mp[0];
-        S1 = mp[1];
-        S2 = mp[2];
-    }
     const double Pr = wave_sum_d(P), S1r = wave_sum_d(S1), S2r = wave_sum_d(S2);
     const bool filled = P > 0.0;
     const double mu_a = filled ? S1 / P : 0.0;
@@ -991,6 +887,126 @@ k_finalize(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
     }
 }
 
+// One wave per region r (lane = intensity bin a) of problem blockIdx.y,
+// reading the moments the value pass merged with atomics; k_value_sum then
+// writes D = (1/Z) sum_r U_r / sigma_r^2.
+__global__ void __launch_bounds__(64)
+k_finalize(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
+{
+    const Geom &g = geoms[blockIdx.y];
+    const int r = blockIdx.x, a = threadIdx.x, nb = g.nb;
+    if (r >= g.R) return;
+    const double *__restrict__ moments = reinterpret_cast<const double *>(ws + g.ws.moments);
+    double P = 0.0, S1 = 0.0, S2 = 0.0;
+    if (a < nb) {
+        const double *mp = moments + ((size_t)r * nb + a) * 3;
+        P = mp[0];
+        S1 = mp[1];
+        S2 = mp[2];
+    }
+    finalize_region(g, r, a, P, S1, S2, ws);
+}
+
+// Moments of a region from the staged value pass: the sum, in a fixed order,
+// of the staging slots of every visit whose block holds it (visits
+// ent[reg_start[q] ..], each entry visit * nreg + local region; a visit's slots
+// start at visit * stage_stride).  Workgroup q takes region reg_id[q] =
+// (problem, region), or (0, q) without reg_id; 64 W threads: wave w takes
+// entries w, w + W, ...; lane a < nb the three moments of bin a; the W
+// partial sums are added in wave order, and wave 0 then finalises the region.
+__global__ void __launch_bounds__(1024)
+k_merge(const Geom *__restrict__ geoms, const double *__restrict__ staging, long stage_stride, int nreg,
+        const int *__restrict__ reg_start, const int *__restrict__ ent, const int2 *__restrict__ reg_id,
+        unsigned char *ws)
+{
+    extern __shared__ double part[];                     // [W][nb][3]
+    const int q = blockIdx.x;
+    const int2 id = reg_id ? reg_id[q] : make_int2(0, q);
+    const Geom &g = geoms[id.x];
+    double *__restrict__ moments = reinterpret_cast<double *>(ws + g.ws.moments);
+    const int r = id.y, nb = g.nb, lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    const int W = blockDim.x >> 6, nb3 = nb * 3;
+    const int e0 = reg_start[q], e1 = reg_start[q + 1];
+    auto slot = [&](int e) {
+        const int v = ent[e];
+        return staging + (size_t)(v / nreg) * stage_stride + (size_t)(v % nreg) * nb3 + 3 * lane;
+    };
+    double s[3] = {0.0, 0.0, 0.0};
+    if (lane < nb) {
+        int e = e0 + w;
+        for (; e + 3 * W < e1; e += 4 * W) {             // four entries in flight
+            double v[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double *p = slot(e + u * W);
+#pragma unroll
+                for (int m = 0; m < 3; ++m) v[u][m] = p[m];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) s[m] += v[u][m];
+        }
+        for (; e < e1; e += W) {
+            const double *p = slot(e);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) s[m] += p[m];
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) part[(w * nb + lane) * 3 + m] = s[m];
+    }
+    __syncthreads();
+    if (w == 0) {
+        double t[3] = {0.0, 0.0, 0.0};
+        if (lane < nb) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                for (int ww = 0; ww < W; ++ww) t[m] += part[(ww * nb + lane) * 3 + m];
+                moments[((size_t)r * nb + lane) * 3 + m] = t[m];
+            }
+        }
+        finalize_region(g, r, lane, t[0], t[1], t[2], ws);
+    }
+}
+
+hipError_t launch_merge(const Geom *geoms, const double *staging, long stage_stride, int nreg, const int *reg_start,
+                        const int *ent, const int2 *reg_id, int nregions, int max_nb, int waves, unsigned char *ws,
+                        hipStream_t s)
+{
+    if (nregions <= 0) return hipSuccess;
+    const size_t lds = (size_t)waves * max_nb * 3 * sizeof(double);
+    hipLaunchKernelGGL(k_merge, dim3(nregions), dim3(waves * kWave), lds, s, geoms, staging, stage_stride, nreg,
+                       reg_start, ent, reg_id, ws);
+    return hipGetLastError();
+}
+
+template <typename F>
+static hipError_t set_lds(F *kernel, size_t bytes)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *blocks, const int *row_start, int nblocks,
+                        int nwg, const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s,
+                        double *staging, const int *visit_start, long stage_stride, int bw)
+{
+    if (nblocks <= 0 || nwg <= 0) return hipSuccess;
+    const int ld = (int)(lds_bytes / sizeof(double));
+#define SRWCR_VAL(F)                                                                                               \
+    if (bw == 5)                                                                                                   \
+        hipLaunchKernelGGL((k_value<F, 5>), dim3(nwg), dim3(kValueThreads), lds_bytes, s, geoms, blocks, row_start, \
+                           nblocks, ld, args, ws, staging, visit_start, stage_stride);                             \
+    else                                                                                                           \
+        hipLaunchKernelGGL((k_value<F, 4>), dim3(nwg), dim3(kValueThreads), lds_bytes, s, geoms, blocks, row_start, \
+                           nblocks, ld, args, ws, staging, visit_start, stage_stride)
+    if (fdt == 0) SRWCR_VAL(0);
+    else if (fdt == 1) SRWCR_VAL(1);
+    else SRWCR_VAL(2);
+#undef SRWCR_VAL
+    return hipGetLastError();
+}
+
 // D = (1/Z) sum_r U_r / sigma_r^2 of problem blockIdx.x, summed in a fixed
 // order: thread t adds regions t, t + 1024, ... in increasing order (eight
 // loads in flight), then a fixed tree over the 1024 partial sums.  A launch of
@@ -1023,11 +1039,13 @@ k_value_sum(const Geom *__restrict__ geoms, BatchArgs args, unsigned char *ws)
 }
 
 hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const BatchArgs &args, unsigned char *ws,
-                           hipStream_t s)
+                           hipStream_t s, bool merged)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(max_regions, nprob), dim3(64), 0, s, geoms, args, ws);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (!merged) {
+        hipLaunchKernelGGL(k_finalize, dim3(max_regions, nprob), dim3(64), 0, s, geoms, args, ws);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_value_sum, dim3(nprob), dim3(kSumThreads), 0, s, geoms, args, ws);
     return hipGetLastError();
 }
