@@ -290,9 +290,10 @@ int srwcr_plan_info(const srwcr_plan *plan, int32_t *n_items, int32_t *value_lds
  * srwcr_profile(plan, 1) starts a session (up to 4096 calls are recorded, the
  * first call creates the events), srwcr_profile(plan, 0) stops recording.
  * srwcr_profile_read synchronises the recorded events and returns the summed
- * milliseconds of the six phases -- zeroing, warp pass, value pass,
- * finalisation (with the merge of a staged value pass), gradient pass,
- * gradient output -- and the number of calls
+ * milliseconds of the six phases -- zeroing (no kernel for a plan with a
+ * staged value pass, whose warp pass clears the gradient accumulators), warp
+ * pass, value pass, finalisation (with the merge of a staged value pass),
+ * gradient pass, gradient output -- and the number of calls
  * recorded.  raptor_grad calls on the plan are recorded too, with the phases
  * zeroing, warp pass, patch sums, patch finalisation, per-voxel derivative,
  * chain rule (gradient pass and output).  enable = 2 records only the two
