@@ -41,6 +41,14 @@ TRAFFIC = {
         "scale_fetch": 1.9991, "scale_write": 1.0, "copy_kernel": "k_normalize, 32 MiB in, 32 MiB out"},
 }
 
+# Issue counters of the same kernel, from rocprofv3's derived metrics over
+# SQ_ACTIVE_INST_VALU, SQ_LDS_BANK_CONFLICT and GRBM_GUI_ACTIVE (one XCD's
+# cycles), with the same key: the value pass is bound by instruction issue.
+ISSUE = {
+    ("38a6c96d8c38824408068d1fdbf5d5ac37201795844017b7e84cd1caef0fae47", "ct256", "srwcr_value_pass", "f32"): {
+        "VALUBusy": 0.7161, "LDSBankConflict": 0.0199, "valu_insts": 101899651, "lds_insts": 3983866},
+}
+
 
 def kernel_source_sha():
     import hashlib
@@ -144,10 +152,12 @@ def main():
                 "alg_bytes_per_launch": alg_bytes, "mean_ms": round(mean_ms, 5),
                 "phase_ms": {k: round(v / prof["calls"], 5) for k, v in prof.items() if k != "calls"}}
 
-    rec = TRAFFIC.get((kernel_source_sha(), args.workload, dom, dt[2]))
+    key = (kernel_source_sha(), args.workload, dom, dt[2])
+    rec = TRAFFIC.get(key)
     if rec is not None:
         roofline["traffic"] = rec["fetch_bytes"] + rec["write_bytes"]
         roofline["traffic_detail"] = rec
+    roofline["issue"] = ISSUE.get(key)
 
     cold = None
     if args.cold:
