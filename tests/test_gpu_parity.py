@@ -207,3 +207,26 @@ def test_constant_estimated_image(S, orc, role):
             assert float(g.abs().max().item()) == 0.0
         gg = g.cpu().numpy().astype(np.float64)
         assert np.linalg.norm(gg - gr) <= GRAD_TOL * max(np.linalg.norm(gr), 1e-12) + 1e-12
+
+
+def test_repeated_calls_on_one_workspace(S, orc):
+    """Calls in a row on one plan and workspace start clean: an FFD gradient
+    that follows another FFD gradient, a dense-field gradient and a value call
+    matches the oracle for its own input (a plan whose value pass is staged
+    clears the FFD gradient accumulators inside the warp pass)."""
+    w = synth.blobs()
+    prob, P, f_g, m_g, f_o, m_o = prepare(S, orc, w.fixed, w.moving, 32, (4, 4, 4), (8, 8, 8), 0)
+    plan = S.Plan(prob)
+    field = dev(np.zeros((3,) + w.fixed.shape, np.float32))
+    ffds = [synth.random_ffd(prob.ctrl_dims, 1.0, 21), synth.random_ffd(prob.ctrl_dims, 1.0, 22)]
+    for i, ffd in enumerate(ffds):
+        plan.grad(f_g, m_g, dev(ffds[1 - i]))
+        plan.grad_dense(f_g, m_g, field)
+        plan.eval(f_g, m_g, dev(ffds[1 - i]))
+        D, g = plan.grad(f_g, m_g, dev(ffd))
+        torch.cuda.synchronize()
+        D, g = float(D.item()), g.cpu().numpy().astype(np.float64)
+        Dr, gr = orc.gradient(P, f_o, m_o, ffd)
+        rel_v, rel_g = abs(D - Dr) / abs(Dr), np.linalg.norm(g - gr) / np.linalg.norm(gr)
+        print(f"call {i}: D rel={rel_v:.2e} grad relL2={rel_g:.2e}", flush=True)
+        assert rel_v <= VALUE_TOL and rel_g <= GRAD_TOL, (i, rel_v, rel_g)
