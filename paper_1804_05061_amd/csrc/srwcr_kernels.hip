@@ -636,6 +636,59 @@ __device__ __forceinline__ void value_window(double *H, int L, const int (&b)[kW
     }
 }
 
+// The last window of a row when it holds at most two bins b0 < b1 (b1 above
+// L when unused): 30 sums instead of 60, so the transpose runs one stage
+// short -- the total of value i ends in lanes 2i and 2i + 1 -- and the two
+// lanes split the 16 (y, z) atomics, z-nodes 0-1 and 2-3.  The odd lane's
+// weights are picked by multiplying with 0 or 1 (exact for finite weights):
+// a select would become an indexed load and move wyz to scratch memory.
+template <int BW>
+__device__ __forceinline__ void value_window2(double *H, int L, int b0, int b1, const VoxA (&v)[kSlots],
+                                              const float (&wyz)[16], int oyz, int lane)
+{
+    float t[kSlots][2];
+#pragma unroll
+    for (int sl = 0; sl < kSlots; ++sl) {
+        t[sl][0] = (v[sl].k == b0) ? v[sl].a0 : ((v[sl].k + 1 == b0) ? v[sl].a1 : 0.0f);
+        t[sl][1] = (v[sl].k == b1) ? v[sl].a0 : ((v[sl].k + 1 == b1) ? v[sl].a1 : 0.0f);
+    }
+    float V[32];
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+#pragma unroll
+        for (int q = 0; q < 15; ++q) V[w * 15 + q] = fmaf(t[1][w], v[1].wxv[q], t[0][w] * v[0].wxv[q]);
+    V[30] = 0.0f;
+    V[31] = 0.0f;
+    float w16[16], w8[8], w4[4], w2[2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) w16[i] = xadd_swap32(V[i], V[i + 16]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w8[i] = xadd_swap16(w16[i], w16[i + 8]);
+    const bool b3 = lane & 8, b2 = lane & 4, b1l = lane & 2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w4[i] = xadd_x8(w8[i], w8[i + 4], b3);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) w2[i] = xadd_x4(w4[i], w4[i + 2], b2);
+    float T = xadd_x2(w2[0], w2[1], b1l);
+    T += dpp<0xB1>(T);                                   // lanes 2i and 2i + 1 hold the same partial sums
+    const int idx = lane >> 1, odd = lane & 1;
+    const float fo = (float)odd, fe = 1.0f - fo;
+    if (idx < 30 && T != 0.0f) {
+        const int w = idx / 15, q = idx - 15 * w, i = q / 3, m = q - 3 * i;
+        const int a = w == 0 ? b0 : b1;
+        if (a <= L) {
+            double *h = H + ((a * 3 + m) * kXN + i) * Hist<BW>::kHS + oyz + 2 * BW * odd;
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float wv = fmaf(wyz[(kk + 2) * 4 + j], fo, wyz[kk * 4 + j] * fe);
+                    atomicAdd(h + kk * BW + j, (double)(T * wv));
+                }
+        }
+    }
+}
+
 // Value pass.  Schedule: one persistent workgroup per compute unit (the FP64
 // histogram of a 5 x BW x BW region block fills most of its LDS).  The rows
 // of all region blocks (an x-chunk of at most two spatial cells by one cell in
@@ -765,6 +818,13 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
             unsigned long long bins = (unsigned long long)wave_or_dpp((unsigned)(mine >> 32)) << 32 |
                                       wave_or_dpp((unsigned)mine);
             while (bins != 0ull) {
+                if (__builtin_popcountll(bins) <= 2) {      // a last window of one or two bins
+                    const int b0 = (int)__builtin_ctzll(bins);
+                    bins &= bins - 1;
+                    const int b1 = bins ? (int)__builtin_ctzll(bins) : 1 << 20;
+                    value_window2<BW>(H, L, b0, b1, v, wyz, oyz, lane);
+                    break;
+                }
                 int b[kWin];
 #pragma unroll
                 for (int w = 0; w < kWin; ++w) {
