@@ -1112,18 +1112,26 @@ hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const 
 
 // --------------------------------------------------------- gradient pass
 
-// Region stride of the LDS copy of the gradient tables in floats: 3 nb plus a
-// pad that puts consecutive regions 12 banks apart (conflict-free row tables).
-__host__ __device__ __forceinline__ int tab_stride(int nb) { return 3 * nb + ((12 - 3 * nb) % 64 + 64) % 64; }
+// LDS copy of the gradient tables: tab[x-node i][bin a][coefficient c][jk],
+// the BW^2 (y, z) regions jk = BW k + j of one (i, a, c) contiguous, so that a
+// row-table entry reads them at fixed offsets (four 16-byte loads when BW =
+// 4).  The stride of 20 (BW = 4) or 28 (BW = 5) floats keeps each group of
+// eight lanes' 16-byte loads on distinct banks.
+__host__ __device__ constexpr int tab_jk_stride(int bw) { return bw == 5 ? 28 : 20; }
+
+// Offset of the tables in the gradient pass's LDS: after the item's FFD x
+// weights and node block, rounded up to 16 bytes.
+__host__ __device__ __forceinline__ size_t grad_tab_offset(int xw, int nG)
+{
+    return ((size_t)xw * 16 + (size_t)nG * 8 + 15) / 16 * 16;
+}
 
 size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz)
 {
     const size_t nreg = (size_t)kXN * g.bw * g.bw;
-    const size_t tab = nreg * tab_stride(g.nb) * sizeof(float) + nreg * sizeof(float);
-    const size_t G = (size_t)gnx * gny * gnz * 3 * sizeof(double);
+    const size_t tab = (size_t)kXN * g.nb * 3 * tab_jk_stride(g.bw) * sizeof(float) + nreg * sizeof(float);
     const size_t scratch = (size_t)(kGradThreads / kWave) * g.gscr * sizeof(float);
-    const size_t bxw = (size_t)g.xw * sizeof(float4);
-    return bxw + G + tab + scratch;
+    return grad_tab_offset(g.xw, gnx * gny * gnz * 3) + tab + scratch;
 }
 
 // Per-voxel quantities of the gradient pass.
@@ -1160,13 +1168,14 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     const double4 *fw_y = g.ffd_w[1], *fw_z = g.ffd_w[2];
     const int nfx = g.nf[0], nfy = g.nf[1], dx = g.delta[0];
     const float ratio[3] = {g.ratio[0], g.ratio[1], g.ratio[2]};
-    const int nb = g.nb, L = nb - 1, ts = tab_stride(nb);
+    const int nb = g.nb, L = nb - 1;
     const int nG = it.gnx * it.gny * it.gnz * 3;
     float4 *bxw = reinterpret_cast<float4 *>(smem);                     // FFD x weights of the item's x range
     double *G = reinterpret_cast<double *>(bxw + g.xw);                 // [gnz][gny][gnx][3]
-    float *tab = reinterpret_cast<float *>(G + nG);                      // [80 regions][ts]: (a, c) at a*3 + c
+    float *tab = reinterpret_cast<float *>(smem + grad_tab_offset(g.xw, nG));   // [kXN][nb][3][JKS]
     constexpr int NR = kXN * BW * BW;                                    // regions of the item's block
-    float *alph = tab + NR * ts;                                         // [NR]
+    constexpr int JKS = tab_jk_stride(BW);
+    float *alph = tab + kXN * nb * 3 * JKS;                              // [NR]
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
@@ -1196,9 +1205,10 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             }
             al = alpha[R];
         }
-        tab[rl * ts + a * 3 + 0] = t0;
-        tab[rl * ts + a * 3 + 1] = t1;
-        tab[rl * ts + a * 3 + 2] = t2;
+        float *tq = tab + ((ii * nb + a) * 3) * JKS + jk;
+        tq[0] = t0;
+        tq[JKS] = t1;
+        tq[2 * JKS] = t2;
         if (a == 0) alph[rl] = al;
     }
     __syncthreads();
@@ -1281,11 +1291,22 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             const int i = FA ? r / 3 : r, c = FA ? r - 3 * i : 0;
             float acc = 0.0f;
             if (a <= (FA ? L - 1 : L)) {
-                const float *tp = tab + (oyz * kXN + i) * ts + a * 3 + c;
+                const float *tp = tab + ((i * nb + a) * 3 + c) * JKS + oyz;
+                if constexpr (BW == 4) {
 #pragma unroll
-                for (int kz = 0; kz < 4; ++kz)
+                    for (int kz = 0; kz < 4; ++kz) {
+                        const float4 q = reinterpret_cast<const float4 *>(tp)[kz];
+                        acc = fmaf(wyv[0] * wzv[kz], q.x, acc);
+                        acc = fmaf(wyv[1] * wzv[kz], q.y, acc);
+                        acc = fmaf(wyv[2] * wzv[kz], q.z, acc);
+                        acc = fmaf(wyv[3] * wzv[kz], q.w, acc);
+                    }
+                } else {
 #pragma unroll
-                    for (int jy = 0; jy < 4; ++jy) acc = fmaf(wyv[jy] * wzv[kz], tp[(kz * BW + jy) * kXN * ts], acc);
+                    for (int kz = 0; kz < 4; ++kz)
+#pragma unroll
+                        for (int jy = 0; jy < 4; ++jy) acc = fmaf(wyv[jy] * wzv[kz], tp[kz * BW + jy], acc);
+                }
             }
             rowt[e] = acc;
         }
