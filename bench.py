@@ -36,17 +36,17 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1804_05061_amd", "csrc", "srwcr_kernel
 # the SHA-256 of the kernel source the counters were taken on and by the
 # workload, so the figure is reported as null once the kernels change.
 TRAFFIC = {
-    ("5342d3a5be7e5935f54f6860a43e1b64ab4e3ac0fc5391a2fbd546b1148c3671", "ct256", "srwcr_value_pass", "f32"): {
-        "fetch_bytes": 100940524, "write_bytes": 33300480, "fetch_size_kib": 49312.0, "write_size_kib": 32520.0,
-        "scale_fetch": 1.999, "scale_write": 1.0, "copy_kernel": "k_normalize, 32 MiB in, 32 MiB out"},
+    ("6148a369c044776fa36baa2cb350daddcf2a6da41af1cd2c00a9344ad4acc1ad", "ct256", "srwcr_value_pass", "f32"): {
+        "fetch_bytes": 100946785, "write_bytes": 33300480, "fetch_size_kib": 49311.8, "write_size_kib": 32520.0,
+        "scale_fetch": 1.9991, "scale_write": 1.0, "copy_kernel": "k_normalize, 32 MiB in, 32 MiB out"},
 }
 
 # Issue counters of the same kernel, from rocprofv3's derived metrics over
 # SQ_ACTIVE_INST_VALU, SQ_LDS_BANK_CONFLICT and GRBM_GUI_ACTIVE (one XCD's
 # cycles), with the same key: the value pass is bound by instruction issue.
 ISSUE = {
-    ("5342d3a5be7e5935f54f6860a43e1b64ab4e3ac0fc5391a2fbd546b1148c3671", "ct256", "srwcr_value_pass", "f32"): {
-        "VALUBusy": 0.7139, "LDSBankConflict": 0.0229, "valu_insts": 98202944, "lds_insts": 3782578},
+    ("6148a369c044776fa36baa2cb350daddcf2a6da41af1cd2c00a9344ad4acc1ad", "ct256", "srwcr_value_pass", "f32"): {
+        "VALUBusy": 0.7136, "LDSBankConflict": 0.0229, "valu_insts": 98202944, "lds_insts": 3782578},
 }
 
 
