@@ -591,6 +591,17 @@ __device__ __forceinline__ unsigned wave_or_dpp(unsigned v)
     return (r0 | r1) | (r2 | r3);
 }
 
+// A voxel's four x weights on its block's five x-nodes: its cell is the
+// block's first x-cell (o1 false) or the second (rows span at most two).
+__device__ __forceinline__ void x_node_weights(const float4 &w, bool o1, float (&wn)[kXN])
+{
+    wn[0] = o1 ? 0.0f : w.x;
+    wn[1] = o1 ? w.x : w.y;
+    wn[2] = o1 ? w.y : w.z;
+    wn[3] = o1 ? w.z : w.w;
+    wn[4] = o1 ? w.w : 0.0f;
+}
+
 // Per-voxel quantities of the value pass.
 struct VoxA {
     int k;          // A-bin (lower tap)
@@ -784,15 +795,13 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
                 const float m1 = (float)kB + b1w;
                 const float m2 = fmaf((float)(2 * kB + 1), b1w, (float)(kB * kB));
                 // x weights on the item's 5 x-nodes (the voxel's cell is it.cx or it.cx + 1)
-                const float4 wx4 = gld(spw_x, xc);
-                const int ox = gld(spc_x, xc) - it.cx;
-                const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
+                float wn[kXN];
+                x_node_weights(gld(spw_x, xc), gld(spc_x, xc) != it.cx, wn);
 #pragma unroll
                 for (int n = 0; n < kXN; ++n) {
-                    const float wn = (n - ox >= 0 && n - ox < 4) ? wl[(n - ox) & 3] : 0.0f;
-                    v[sl].wxv[3 * n + 0] = wn;
-                    v[sl].wxv[3 * n + 1] = wn * m1;
-                    v[sl].wxv[3 * n + 2] = wn * m2;
+                    v[sl].wxv[3 * n + 0] = wn[n];
+                    v[sl].wxv[3 * n + 1] = wn[n] * m1;
+                    v[sl].wxv[3 * n + 2] = wn[n] * m2;
                 }
             }
             float wyv[4], wzv[4];
@@ -1246,11 +1255,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             v[sl].a0 = ROLE ? f0w : m0w;
             v[sl].a1 = ROLE ? f1w : m1w;
             v[sl].m1 = (float)v[sl].kB + (ROLE ? m1w : f1w);
-            const float4 wx4 = gld(spw_x, xc);
-            const int ox = gld(spc_x, xc) - it.cx;
-            const float wl[4] = {wx4.x, wx4.y, wx4.z, wx4.w};
-#pragma unroll
-            for (int n = 0; n < kXN; ++n) v[sl].wx5[n] = (n - ox >= 0 && n - ox < 4) ? wl[(n - ox) & 3] : 0.0f;
+            x_node_weights(gld(spw_x, xc), gld(spc_x, xc) != it.cx, v[sl].wx5);
         }
         float gs[kSlots] = {0.0f, 0.0f};
         if constexpr (ROLE == 2) {
