@@ -36,7 +36,7 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1804_05061_amd", "csrc", "srwcr_kernel
 # the SHA-256 of the kernel source the counters were taken on and by the
 # workload, so the figure is reported as null once the kernels change.
 TRAFFIC = {
-    ("10e649e34a38a273cd54078559222d0fb35313d279aa7672a93e725dc6847297", "ct256", "srwcr_value_pass", "f32"): {
+    ("022db896af7cbf4614bb37629e602ec1eb3a8cf1798b7438a87923b8bd5e2e37", "ct256", "srwcr_value_pass", "f32"): {
         "fetch_bytes": 100942962, "write_bytes": 33300480, "fetch_size_kib": 49310.3, "write_size_kib": 32520.0,
         "scale_fetch": 1.9991, "scale_write": 1.0, "copy_kernel": "k_normalize, 32 MiB in, 32 MiB out"},
 }
@@ -45,7 +45,7 @@ TRAFFIC = {
 # SQ_ACTIVE_INST_VALU, SQ_LDS_BANK_CONFLICT and GRBM_GUI_ACTIVE (one XCD's
 # cycles), with the same key: the value pass is bound by instruction issue.
 ISSUE = {
-    ("10e649e34a38a273cd54078559222d0fb35313d279aa7672a93e725dc6847297", "ct256", "srwcr_value_pass", "f32"): {
+    ("022db896af7cbf4614bb37629e602ec1eb3a8cf1798b7438a87923b8bd5e2e37", "ct256", "srwcr_value_pass", "f32"): {
         "VALUBusy": 0.6946, "LDSBankConflict": 0.0234, "valu_insts": 93091136, "lds_insts": 3782578},
 }
 

@@ -17,21 +17,26 @@
 // eq (3) only needs per (region, A-bin) the moments P = sum w h(a - A),
 // S1 = sum w h(a - A) m1(B), S2 = sum w h(a - A) m2(B).  One persistent
 // workgroup per compute unit walks a share of the rows; a wave folds its
-// voxels into windows of four A-bins x 5 x-nodes x 3 moments, sums them
-// across lanes with a register transpose (v_permlane32/16_swap and DPP) and
-// spreads each total over the 16 (y, z) regions with FP64 LDS atomics; the
-// LDS histogram is merged into the global FP64 moments when the workgroup
-// leaves a region block.
+// voxels into windows of four A-bins x 5 x-nodes x 3 moments (a row's last
+// one or two bins into a half window), sums them across lanes with a
+// register transpose (v_permlane32/16_swap and DPP) and spreads each total
+// over the 16 (y, z) regions with FP64 LDS atomics.  When the workgroup
+// leaves a region block its histogram goes to staging slots of its own,
+// which k_merge sums per region in a fixed order (or, when the slots would
+// be too large, into the global moments with FP64 atomics).
 //
-// Finalisation (eqs 4, 9-12, 18-21) runs in FP64, one wave per region, and
+// Finalisation (eqs 4, 9-12, 18-21) runs in FP64, one wave per region (wave 0
+// of the region's merge workgroup, or k_finalize after an atomic merge), and
 // writes the per-region terms and gradient tables (FP32, scaled by
-// 1/(Z sigma_r^2)); a one-wave launch sums D in region order.
+// 1/(Z sigma_r^2)); k_value_sum then adds the terms into D in a fixed order.
 //
-// Gradient pass (eqs 16-21).  Interpolates the region tables through the
-// same separable weights (row tables per wave), forms q = dD/ds * grad M *
-// dy/dT per voxel and scatters it to the FFD nodes: per-cell moments along x,
-// then FP64 LDS atomics over the 16 (y, z) node weights, merged globally once
-// per box.  A dense field's gradient is q itself.
+// Gradient pass (eqs 16-21).  Stages the block's region tables in LDS with
+// the 16 (y, z) regions of one (x-node, bin, coefficient) contiguous,
+// interpolates them through the same separable weights (row tables per
+// wave), forms q = dD/ds * grad M * dy/dT per voxel and scatters it to the
+// FFD nodes: per-cell moments along x, then FP64 LDS atomics over the 16
+// (y, z) node weights, merged globally once per box.  A dense field's
+// gradient is q itself.
 #include "srwcr_internal.h"
 
 #include <hip/hip_bf16.h>
