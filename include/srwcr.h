@@ -244,6 +244,7 @@ typedef struct {
     double initial_value[3];   /* cost at the start of each level */
     double final_value[3];     /* cost at the end of each level */
     int32_t status[3];         /* srwcr_status per level */
+    double seconds[3];         /* wall-clock seconds per level (plan, evaluations, optimiser) */
 } srwcr_lbfgs_report;
 
 /* Fill `opts` with the paper's settings (3 levels, 200/200/120, m = 5, 20). */
@@ -254,10 +255,30 @@ void srwcr_lbfgs_default_opts(srwcr_lbfgs_opts *opts);
  * finest level); ffd_inout: host float32 displacements at the finest level,
  * read as the start and overwritten with the result.  Coarser levels use
  * half-resolution volumes (Gaussian sigma 1 voxel, then every other voxel) and
- * the same control spacing in level voxels; displacements are carried up by
- * doubling and B-spline subdivision.  Synchronous; allocates its own temporaries. */
+ * the same control spacing in level voxels; the start is carried down to the
+ * coarsest level by keeping every second control node and halving it, and
+ * displacements are carried up by doubling and B-spline subdivision.  The line
+ * search is the backtracking Wolfe search of Sec. II-F, bracketed (see
+ * srwcr_lbfgs_minimize).  Synchronous; allocates its own temporaries. */
 int register_lbfgs(const srwcr_problem *prob, const float *fixed, const float *moving, float *ffd_inout,
                    const srwcr_lbfgs_opts *opts, srwcr_lbfgs_report *report, void *stream);
+
+/* The optimiser of register_lbfgs on the host, for any cost: L-BFGS with
+ * `history` corrections (two-loop recursion) and a backtracking line search
+ * on the Armijo (c1 = 1e-4) and curvature (c2 = 0.9) conditions: the step
+ * halves while no acceptable step is bracketed from above and grows by 2.1
+ * while none is bracketed from below, then bisects the bracket (at most 40
+ * trials; if none satisfies both conditions the best trial point is kept,
+ * else SRWCR_E_LINESEARCH).  Stops after max_iter iterations or when the cost
+ * varied by at most stall_tol |f| over the last stall_window iterations
+ * (Sec. II-F).  fg(user, x, f, g) writes the cost and its gradient (n doubles)
+ * at x and returns 0, or a non-zero status that stops the run and is
+ * returned.  x (n doubles, host) is the start and receives the result;
+ * iterations, evaluations and f_final may be NULL. */
+typedef int (*srwcr_fg_fn)(void *user, const double *x, double *f, double *g);
+int srwcr_lbfgs_minimize(int64_t n, double *x, srwcr_fg_fn fg, void *user, int32_t max_iter, int32_t history,
+                         int32_t stall_window, double stall_tol, int32_t *iterations, int32_t *evaluations,
+                         double *f_final);
 
 /* Carry displacements from a pyramid level to the next finer one: u_f(x) =
  * 2 u_c(x / 2) represented exactly on the finer lattice by cubic B-spline
@@ -281,6 +302,17 @@ double srwcr_bending_energy(const srwcr_problem *prob, const float *ffd, float *
  * device array d_moments, double [R][n_bins][3], R = Kx Ky Kz (x fastest). */
 int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd,
                         double *d_moments, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Diagnostic: the warp pass alone (eq 17 and the backward warp of Sec. II-F),
+ * then, per fixed voxel, the moving sample's lower Parzen bin
+ * k = min(floor(s), L - 1) (eq 5; decided in FP64) into d_bin (int32, fixed
+ * dims, x fastest) and its in-bin position s - k, rounded to FP32, into d_frac.
+ * These are the bins the value and gradient passes use.  Device pointers,
+ * caller-owned; asynchronous on `stream`; the workspace is the plan's
+ * (srwcr_workspace_bytes).  Returns SRWCR_E_INVALID_ARG for NULL pointers and
+ * SRWCR_E_WORKSPACE for a short workspace. */
+int srwcr_debug_samples(const srwcr_plan *plan, const void *moving, const float *ffd, int32_t *d_bin,
+                        float *d_frac, void *workspace, size_t workspace_bytes, void *stream);
 
 /* Launch geometry of a plan: number of work items and LDS bytes per workgroup
  * of the value and gradient passes.  Any output pointer may be NULL. */

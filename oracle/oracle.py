@@ -129,6 +129,8 @@ def lib():
         L.orc_raptor.argtypes = [pp, fp, fp, fp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -351,3 +353,8 @@ def raptor(P: Problem, fixed: np.ndarray, moving: np.ndarray, disp: np.ndarray, 
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (for timing)."""
+    lib().orc_set_num_threads(int(n))

@@ -894,6 +894,17 @@ double orc_raptor(const orc_problem *P, const float *fix, const float *mov, cons
 }
 
 /* number of threads the parallel loops use (reported by the CPU baseline) */
+/* threads of the parallel loops (timing only: the results do not depend on it
+ * beyond the fixed-order merge of the per-thread PDFs) */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

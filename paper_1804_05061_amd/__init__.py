@@ -247,6 +247,18 @@ class Plan:
         return out
 
 
+    def debug_samples(self, moving, ffd):
+        """Per fixed voxel, the warp pass's moving bin k (int32) and in-bin
+        position s - k (float32), shaped like the fixed volume."""
+        p = self.problem
+        _need_cuda(moving, "moving", _TORCH_DT[p.moving_dtype], p.moving_shape)
+        _need_cuda(ffd, "ffd", torch.float32, p.ffd_shape)
+        k = torch.empty(p.fixed_shape, dtype=torch.int32, device=moving.device)
+        t = torch.empty(p.fixed_shape, dtype=torch.float32, device=moving.device)
+        _lib.check(_lib.load().srwcr_debug_samples(self._h, _ptr(moving), _ptr(ffd), _ptr(k), _ptr(t),
+                                                   _ptr(self.workspace), self.workspace_bytes, _stream()))
+        return k, t
+
 def _tune_key(problem: Problem, device) -> str:
     p = problem
     return (f"{torch.cuda.get_device_name(device)}|{tuple(p.fixed_dims)}|{tuple(p.moving_dims)}|{p.n_bins}|"
@@ -479,7 +491,7 @@ def register_lbfgs(problem: Problem, fixed: torch.Tensor, moving: torch.Tensor, 
                                           ctypes.byref(rep), _stream()))
     return {"iterations": list(rep.iterations), "evaluations": list(rep.evaluations),
             "initial_value": list(rep.initial_value), "final_value": list(rep.final_value),
-            "status": list(rep.status)}
+            "status": list(rep.status), "seconds": list(rep.seconds)}
 
 
 def _fixed_grad(ctx, disp, fixed, moving, dense, grad_output):

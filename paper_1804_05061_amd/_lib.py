@@ -14,8 +14,9 @@ STATUS_NAMES = {0: "SRWCR_OK", -1: "SRWCR_E_INVALID_ARG", -2: "SRWCR_E_DEGENERAT
 # symbols the header declares (the ABI test checks every one is exported)
 EXPORTED = ["srwcr_ctrl_dims", "srwcr_plan_create", "srwcr_plan_destroy", "srwcr_workspace_bytes",
             "srwcr_normalize", "srwcr_minmax", "srwcr_eval", "srwcr_grad", "ffd_warp",
-            "srwcr_lbfgs_default_opts", "register_lbfgs", "srwcr_debug_moments", "srwcr_plan_info",
-            "srwcr_profile", "srwcr_profile_read", "srwcr_refine_ffd", "srwcr_bending_energy",
+            "srwcr_lbfgs_default_opts", "register_lbfgs", "srwcr_debug_moments", "srwcr_debug_samples",
+            "srwcr_plan_info",
+            "srwcr_profile", "srwcr_profile_read", "srwcr_refine_ffd", "srwcr_bending_energy", "srwcr_lbfgs_minimize",
             "srwcr_eval_dense", "srwcr_grad_dense", "srwcr_batch_create", "srwcr_batch_destroy", "srwcr_batch_workspace_bytes", "srwcr_grad_batched",
             "raptor_patches_create", "raptor_patches_destroy", "raptor_workspace_bytes", "raptor_eval",
             "raptor_grad", "srwcr_grad_fixed", "srwcr_plan_create_tuned", "srwcr_last_error"]
@@ -38,7 +39,7 @@ class SrwcrLbfgsOpts(ctypes.Structure):
 class SrwcrLbfgsReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32 * 3), ("evaluations", ctypes.c_int32 * 3),
                 ("initial_value", ctypes.c_double * 3), ("final_value", ctypes.c_double * 3),
-                ("status", ctypes.c_int32 * 3)]
+                ("status", ctypes.c_int32 * 3), ("seconds", ctypes.c_double * 3)]
 
 
 class SrwcrBatchItem(ctypes.Structure):
@@ -53,6 +54,11 @@ class SrwcrTuning(ctypes.Structure):
 class SrwcrPatch(ctypes.Structure):
     _fields_ = [("x0", ctypes.c_int32), ("y0", ctypes.c_int32), ("z0", ctypes.c_int32),
                 ("x1", ctypes.c_int32), ("y1", ctypes.c_int32), ("z1", ctypes.c_int32)]
+
+
+# int fg(void *user, const double *x, double *f, double *g)
+FG_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
 
 
 class SrwcrError(RuntimeError):
@@ -88,11 +94,14 @@ def load() -> ctypes.CDLL:
         "register_lbfgs": (ctypes.c_int, [pp, vp, vp, vp, ctypes.POINTER(SrwcrLbfgsOpts),
                                           ctypes.POINTER(SrwcrLbfgsReport), vp]),
         "srwcr_debug_moments": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
+        "srwcr_debug_samples": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
         "srwcr_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "srwcr_profile": (ctypes.c_int, [vp, i32]),
         "srwcr_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]),
         "srwcr_refine_ffd": (ctypes.c_int, [ctypes.POINTER(i32), vp, ctypes.POINTER(i32), vp]),
         "srwcr_bending_energy": (ctypes.c_double, [pp, vp, vp]),
+        "srwcr_lbfgs_minimize": (ctypes.c_int, [i64, ctypes.POINTER(dp), FG_FN, vp, i32, i32, i32, dp,
+                                                ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(dp)]),
         "srwcr_eval_dense": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
         "srwcr_grad_dense": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "srwcr_batch_create": (ctypes.c_int, [i32, ctypes.POINTER(vp), ctypes.POINTER(vp)]),

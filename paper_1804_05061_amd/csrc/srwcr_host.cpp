@@ -814,6 +814,27 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
     return SRWCR_OK;
 }
 
+int srwcr_debug_samples(const srwcr_plan *plan, const void *moving, const float *ffd, int32_t *d_bin,
+                        float *d_frac, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!plan) return fail(SRWCR_E_INVALID_ARG, "plan is NULL");
+    if (!moving || !ffd) return fail(SRWCR_E_INVALID_ARG, "NULL volume or FFD pointer");
+    if (!d_bin || !d_frac) return fail(SRWCR_E_INVALID_ARG, "d_bin or d_frac is NULL");
+    if (!workspace) return fail(SRWCR_E_INVALID_ARG, "workspace is NULL");
+    if (workspace_bytes < plan->ws.total)
+        return fail(SRWCR_E_WORKSPACE, "workspace has %zu B, the plan needs %zu B", workspace_bytes, plan->ws.total);
+    unsigned char *ws = (unsigned char *)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    const Geom &g = plan->g;
+    const BatchArgs args = one_problem(nullptr, moving, ffd, nullptr, nullptr);
+    HIP_TRY(launch_prep(plan->geom_dev, g.mdt, 0, 0, plan->wblocks, plan->wrow, plan->nwblocks,
+                        plan->wrow_host.back(), args, ws, plan->prep_lds, s),
+            "warp launch");
+    const size_t nvox = (size_t)g.nf[0] * g.nf[1] * g.nf[2];
+    HIP_TRY(launch_unpack_samples((const PrepKT *)(ws + plan->ws.kt), nvox, d_bin, d_frac, s), "unpack launch");
+    return SRWCR_OK;
+}
+
 int srwcr_plan_info(const srwcr_plan *plan, int32_t *n_items, int32_t *value_lds, int32_t *grad_lds)
 {
     if (!plan) return fail(SRWCR_E_INVALID_ARG, "plan is NULL");

@@ -172,6 +172,8 @@ hipError_t launch_raptor_finalize(const Geom *geoms, const RaptorArgs &ra, hipSt
 hipError_t launch_raptor_ds(const Geom *geoms, int fdt, int role, const RaptorArgs &ra, const BatchArgs &args,
                             const unsigned char *ws, hipStream_t s);
 hipError_t launch_warp(const Geom &g, const void *moving, const float *ffd, float *out, hipStream_t s);
+// The warp pass's per-voxel moving bin and in-bin position, unpacked into two arrays.
+hipError_t launch_unpack_samples(const PrepKT *kt, size_t n, int32_t *bin, float *frac, hipStream_t s);
 hipError_t launch_downsample(const float *in, int nx, int ny, int nz, float *out, int ox, int oy, int oz,
                              hipStream_t s);
 hipError_t prepare_kernels();   // once per device: LDS limits of the value and gradient kernels

@@ -1919,6 +1919,25 @@ hipError_t launch_warp(const Geom &g, const void *moving, const float *ffd, floa
     return hipGetLastError();
 }
 
+// ------------------------------------------------------ sample read-out
+__global__ void k_unpack_samples(const PrepKT *__restrict__ kt, size_t n, int32_t *__restrict__ bin,
+                                 float *__restrict__ frac)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const PrepKT p = kt[i];
+        bin[i] = p.k;
+        frac[i] = p.t;
+    }
+}
+
+hipError_t launch_unpack_samples(const PrepKT *kt, size_t n, int32_t *bin, float *frac, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_unpack_samples, dim3(blocks), dim3(256), 0, s, kt, n, bin, frac);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------- pyramid level
 // Next-coarser level of the registration pyramid: Gaussian smoothing with
 // sigma = 1 voxel (taps -3..3, edges clamped) sampled at every other voxel,

@@ -4,18 +4,25 @@
 // srwcr_grad on the GPU, C_p the bending energy of the FFD evaluated on the
 // control lattice (host, FP64).  The optimiser is a limited-memory BFGS with
 // m corrections (two-loop recursion, Nocedal & Wright, Alg. 7.4) and a
-// backtracking line search that enforces the Armijo and curvature (Wolfe)
-// conditions.  A level stops when C has been stable over `stall_window`
-// iterations or after max_iter iterations.  Levels are Gaussian pyramids of
-// the normalised volumes; the displacement found on a level is carried to the
-// next finer one by doubling it and refining the control lattice by cubic
-// B-spline subdivision, which represents the coarse field exactly.
+// backtracking line search that enforces the Armijo and curvature (weak
+// Wolfe) conditions inside a bracket: it halves the step on an Armijo failure
+// and grows it by 2.1 on a curvature failure until both ends of the bracket
+// are known, then bisects the bracket, so every trial shrinks it.  A level
+// stops when C has been stable over `stall_window` iterations or after
+// max_iter iterations.  Levels are Gaussian pyramids of the normalised
+// volumes; the displacement found on a level is carried to the next finer one
+// by doubling it and refining the control lattice by cubic B-spline
+// subdivision, which represents the coarse field exactly.  A caller's start
+// is carried down to the coarsest level by keeping every second control node
+// and halving it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -167,6 +174,27 @@ std::vector<double> refine(const std::vector<double> &cc, const int ncc[3], cons
     return out;
 }
 
+// Fine level -> coarse level, the start of a registration carried down the
+// pyramid: coarse paper node j sits on fine paper node 2 j (stored index
+// 2 s - 1 for coarse stored index s, clamped to the fine lattice) and a
+// displacement of d fine voxels is d / 2 coarse voxels.  Exact for fields
+// that are linear along each axis; an approximation otherwise, which the
+// coarse level's optimisation then refines.
+std::vector<double> decimate(const std::vector<double> &cf, const int ncf[3], const int ncc[3])
+{
+    const size_t fcells = (size_t)ncf[0] * ncf[1] * ncf[2], ccells = (size_t)ncc[0] * ncc[1] * ncc[2];
+    std::vector<double> out(3 * ccells);
+    auto fidx = [](int s, int nf) { return std::min(std::max(2 * s - 1, 0), nf - 1); };
+    for (int comp = 0; comp < 3; ++comp)
+        for (int z = 0; z < ncc[2]; ++z)
+            for (int y = 0; y < ncc[1]; ++y)
+                for (int x = 0; x < ncc[0]; ++x) {
+                    const size_t fi = ((size_t)fidx(z, ncf[2]) * ncf[1] + fidx(y, ncf[1])) * ncf[0] + fidx(x, ncf[0]);
+                    out[comp * ccells + ((size_t)z * ncc[1] + y) * ncc[0] + x] = 0.5 * cf[comp * fcells + fi];
+                }
+    return out;
+}
+
 // ------------------------------------------------------------ one level
 struct Level {
     srwcr_problem prob;
@@ -246,15 +274,18 @@ double dot(const std::vector<double> &a, const std::vector<double> &b)
     return s;
 }
 
+using EvalFn = std::function<int(const std::vector<double> &, double &, std::vector<double> &)>;
+
 // L-BFGS on one level; x is updated in place.  Returns a status.
-int lbfgs_level(Evaluator &ev, std::vector<double> &x, int max_iter, int m, int stall_window, double stall_tol,
+int lbfgs_level(const EvalFn &eval, std::vector<double> &x, int max_iter, int m, int stall_window, double stall_tol,
                 int &iters, double &f0_out, double &f_out)
 {
     const size_t n = x.size();
     std::vector<double> g(n), xn(n), gn(n), d(n);
     double f = 0.0;
-    int st = ev.eval(x, f, g);
+    int st = eval(x, f, g);
     if (st) return st;
+    if (!std::isfinite(f)) return SRWCR_E_NONFINITE;
     f0_out = f;
     std::deque<std::vector<double>> S, Y;
     std::deque<double> RHO;
@@ -286,29 +317,32 @@ int lbfgs_level(Evaluator &ev, std::vector<double> &x, int max_iter, int m, int 
         const double gnorm = std::sqrt(dot(g, g));
         if (gnorm == 0.0) break;
         double step = S.empty() ? 1.0 / std::sqrt(dot(d, d)) : 1.0;
-        // backtracking line search with the Wolfe conditions
+        // backtracking line search with the (weak) Wolfe conditions, bracketed:
+        // lo satisfies Armijo but not the curvature condition, hi fails Armijo
         const double c1 = 1e-4, c2 = 0.9;
         bool ok = false;
         double fn = 0.0;
         double best_f = f, best_step = 0.0;
+        double lo = 0.0, hi = INFINITY;
         for (int trial = 0; trial < 40; ++trial) {
             for (size_t j = 0; j < n; ++j) xn[j] = x[j] + step * d[j];
-            st = ev.eval(xn, fn, gn);
+            st = eval(xn, fn, gn);
             if (st) return st;
-            if (fn < best_f) { best_f = fn; best_step = step; }
-            if (fn > f + c1 * step * gd) {
-                step *= 0.5;
+            if (std::isfinite(fn) && fn < best_f) { best_f = fn; best_step = step; }
+            if (!std::isfinite(fn) || fn > f + c1 * step * gd) {
+                hi = step;
             } else if (dot(gn, d) < c2 * gd) {
-                step *= 2.1;
+                lo = step;
             } else {
                 ok = true;
                 break;
             }
+            step = std::isfinite(hi) ? 0.5 * (lo + hi) : 2.1 * lo;
         }
         if (!ok) {
             if (best_step > 0.0) {                 // keep the best point seen
                 for (size_t j = 0; j < n; ++j) xn[j] = x[j] + best_step * d[j];
-                st = ev.eval(xn, fn, gn);
+                st = eval(xn, fn, gn);
                 if (st) return st;
             } else {
                 status = SRWCR_E_LINESEARCH;
@@ -338,6 +372,28 @@ int lbfgs_level(Evaluator &ev, std::vector<double> &x, int max_iter, int m, int 
 }
 
 }  // namespace
+
+extern "C" int srwcr_lbfgs_minimize(int64_t n, double *x, srwcr_fg_fn fg, void *user, int32_t max_iter,
+                                    int32_t history, int32_t stall_window, double stall_tol, int32_t *iterations,
+                                    int32_t *evaluations, double *f_final)
+{
+    if (n < 1 || !x || !fg || max_iter < 0 || history < 1 || stall_window < 2) return SRWCR_E_INVALID_ARG;
+    std::vector<double> xv(x, x + n);
+    int evals = 0;
+    const EvalFn eval = [&](const std::vector<double> &p, double &f, std::vector<double> &g) {
+        g.assign((size_t)n, 0.0);
+        ++evals;
+        return fg(user, p.data(), &f, g.data());
+    };
+    int iters = 0;
+    double f0 = 0.0, f1 = 0.0;
+    const int st = lbfgs_level(eval, xv, max_iter, history, stall_window, stall_tol, iters, f0, f1);
+    std::copy(xv.begin(), xv.end(), x);
+    if (iterations) *iterations = iters;
+    if (evaluations) *evaluations = evals;
+    if (f_final) *f_final = f1;
+    return st;
+}
 
 extern "C" int srwcr_refine_ffd(const int32_t coarse_nc[3], const float *coarse, const int32_t fine_nc[3],
                                 float *fine)
@@ -426,19 +482,25 @@ extern "C" int register_lbfgs(const srwcr_problem *prob, const float *fixed, con
         const int ri = nl - 1 - l;                               // report index, coarsest first
         const size_t n = 3 * (size_t)lv[l].nc[0] * lv[l].nc[1] * lv[l].nc[2];
         if (l == nl - 1) {
-            x.assign(n, 0.0);
-            if (nl == 1)
-                for (size_t i = 0; i < n; ++i) x[i] = ffd_inout[i];
+            // the caller's start, carried down to the coarsest level
+            const size_t n0 = 3 * (size_t)lv[0].nc[0] * lv[0].nc[1] * lv[0].nc[2];
+            x.assign(ffd_inout, ffd_inout + n0);
+            for (int k = 1; k < nl; ++k) x = decimate(x, lv[k - 1].nc, lv[k].nc);
         } else {
             x = refine(x, lv[l + 1].nc, lv[l].nc);
         }
+        const auto t0 = std::chrono::steady_clock::now();
         Evaluator ev(lv[l], opts->bending_weight, s);
         st = ev.init();
         if (st) break;
         int iters = 0;
         double f0 = 0.0, f1 = 0.0;
-        const int lvl_status = lbfgs_level(ev, x, opts->max_iter[ri], opts->history, opts->stall_window,
+        const EvalFn eval = [&ev](const std::vector<double> &p, double &f, std::vector<double> &g) {
+            return ev.eval(p, f, g);
+        };
+        const int lvl_status = lbfgs_level(eval, x, opts->max_iter[ri], opts->history, opts->stall_window,
                                            opts->stall_tol, iters, f0, f1);
+        rep.seconds[ri] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         rep.iterations[ri] = iters;
         rep.evaluations[ri] = ev.evals;
         rep.initial_value[ri] = f0;

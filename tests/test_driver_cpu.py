@@ -83,3 +83,83 @@ def test_bending_energy_gradient_matches_differences():
         m[idx] -= h
         fd = (bending(prob, p.reshape(ffd.shape)) - bending(prob, m.reshape(ffd.shape))) / (2 * h)
         assert abs(fd - g.ravel()[idx]) <= 1e-4 * max(1e-3, abs(fd)), (idx, fd, g.ravel()[idx])
+
+
+def minimize(fg_py, x0, max_iter=500, history=5, stall_window=20, stall_tol=1e-12):
+    """srwcr_lbfgs_minimize through the C ABI with a Python cost."""
+    n = len(x0)
+    x = np.ascontiguousarray(x0, dtype=np.float64).copy()
+
+    def cb(user, xp, fp, gp):
+        xx = np.ctypeslib.as_array(xp, shape=(n,))
+        f, g = fg_py(xx.copy())
+        fp[0] = f
+        np.ctypeslib.as_array(gp, shape=(n,))[:] = g
+        return 0
+
+    c_cb = _lib.FG_FN(cb)
+    it, ev, ff = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    st = _lib.load().srwcr_lbfgs_minimize(n, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), c_cb, None,
+                                          max_iter, history, stall_window, stall_tol, ctypes.byref(it),
+                                          ctypes.byref(ev), ctypes.byref(ff))
+    return st, x, it.value, ev.value, ff.value
+
+
+def test_lbfgs_minimizes_rosenbrock():
+    """The optimiser of the registration driver (Sec. II-F: m = 5, backtracking
+    Wolfe search) reaches the minimum (1, 1) of Rosenbrock's function."""
+    def fg(x):
+        a, b = x
+        f = (1 - a) ** 2 + 100 * (b - a * a) ** 2
+        g = np.array([-2 * (1 - a) - 400 * a * (b - a * a), 200 * (b - a * a)])
+        return f, g
+    st, x, it, ev, f = minimize(fg, [-1.2, 1.0])
+    print(f"rosenbrock: status {st}, {it} iterations, {ev} evaluations, f={f:.3e}, x={x}")
+    assert st == 0
+    assert np.allclose(x, [1.0, 1.0], atol=1e-5) and f < 1e-10
+    assert ev < 4 * it + 10
+
+
+def test_lbfgs_ill_conditioned_quadratic():
+    """A 60-dimensional quadratic with condition number 1e4: the minimiser is
+    reached and every line search ends in an accepted step (no fallback)."""
+    rng = np.random.default_rng(5)
+    q, _ = np.linalg.qr(rng.normal(size=(60, 60)))
+    A = q @ np.diag(np.logspace(0, 4, 60)) @ q.T
+    b = rng.normal(size=60)
+    xs = np.linalg.solve(A, b)
+
+    def fg(x):
+        r = A @ x - b
+        return 0.5 * x @ A @ x - b @ x, r
+    st, x, it, ev, f = minimize(fg, np.zeros(60), max_iter=2000)
+    print(f"quadratic: status {st}, {it} iterations, {ev} evaluations")
+    assert st == 0
+    assert np.linalg.norm(x - xs) <= 1e-4 * np.linalg.norm(xs)
+
+
+def test_lbfgs_line_search_terminates_on_a_kink():
+    """|x| has no point where the curvature condition holds across the kink:
+    the bracketed search shrinks its bracket instead of bouncing, and the run
+    ends near 0 with the best point kept (status 0 or SRWCR_E_LINESEARCH)."""
+    def fg(x):
+        return float(np.abs(x).sum()), np.sign(x)
+    st, x, it, ev, f = minimize(fg, [3.7, -2.2], max_iter=50, stall_window=5, stall_tol=1e-9)
+    print(f"kink: status {st}, {it} iterations, {ev} evaluations, f={f:.3e}")
+    assert st in (0, -7)
+    assert f < 1e-2
+    assert ev <= 41 * (it + 1) + 1
+
+
+def test_lbfgs_callback_status_propagates():
+    def fg(x):
+        raise RuntimeError
+    n = 3
+    x = np.zeros(n)
+
+    def cb(user, xp, fp, gp):
+        return -6                                   # SRWCR_E_NONFINITE from the cost
+    c_cb = _lib.FG_FN(cb)
+    st = _lib.load().srwcr_lbfgs_minimize(n, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), c_cb, None, 10, 5,
+                                          20, 1e-6, None, None, None)
+    assert st == -6

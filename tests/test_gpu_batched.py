@@ -116,3 +116,55 @@ def test_batched_rejects_mixed_roles_and_short_workspace(problems):
     rc = L.srwcr_grad_batched(batch._h, items, ctypes.c_void_p(batch.workspace.data_ptr()),
                               batch.workspace_bytes - 1, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert rc == -3                                             # SRWCR_E_WORKSPACE
+
+
+@pytest.mark.timeout(900)
+def test_breathing4d_full_size(orc):
+    """Workload 5 as `bench.py --workload breathing4d` times it: 9 phase pairs
+    of a 256x256x{80..128} CT-like phantom x 3 pyramid levels = 27 problems
+    (69,976,064 voxels), 64 bins, 6x6x6 spatial bins, FFD spacing 10, one
+    batched call.  FP32: every problem against the FP64 oracle (value 1e-5,
+    gradient 1e-4).  BF16 storage: every third problem against the oracle on
+    the stored values (arithmetic only, same gates)."""
+    import os
+
+    import paper_1804_05061_amd as S
+    nb, Kb, db = 64, (6, 6, 6), (10, 10, 10)
+    pairs = synth.breathing_phases(workers=min(8, os.cpu_count() or 1), mp_context="spawn")
+    print(f"generated {len(pairs)} phase pairs", flush=True)
+    probs = []
+    for pi, (f_raw, m_raw) in enumerate(pairs):
+        fg = S.normalize(torch.from_numpy(f_raw).cuda(), f_raw.min(), f_raw.max(), nb).cpu().numpy()
+        mg = S.normalize(torch.from_numpy(m_raw).cuda(), m_raw.min(), m_raw.max(), nb).cpu().numpy()
+        fo = orc.normalize(f_raw, f_raw.min(), f_raw.max(), nb)
+        mo = orc.normalize(m_raw, m_raw.min(), m_raw.max(), nb)
+        assert np.array_equal(fg, fo) and np.array_equal(mg, mo)
+        for lv, (f_l, m_l) in enumerate(zip(synth.pyramid(fo), synth.pyramid(mo))):
+            nz, ny, nx = f_l.shape
+            probs.append(dict(dims=(nx, ny, nz), f=f_l, m=m_l, pair=pi, level=lv))
+    assert sum(int(np.prod(p["dims"])) for p in probs) == 69976064
+    for dtype, tdt, every in ((S.F32, torch.float32, 1), (S.BF16, torch.bfloat16, 3)):
+        plans, inputs, ffds = [], [], []
+        for p in probs:
+            prob = S.Problem(p["dims"], p["dims"], nb, Kb, db, S.MOVING_AS_A, dtype, dtype)
+            ffd = synth.breathing4d_ffd(prob.ctrl_dims, p["pair"], p["level"])
+            plans.append(S.Plan(prob))
+            inputs.append((torch.from_numpy(p["f"]).cuda().to(tdt), torch.from_numpy(p["m"]).cuda().to(tdt),
+                           torch.from_numpy(ffd).cuda()))
+            ffds.append(ffd)
+        vals, grads = S.Batch(plans).grad(inputs)
+        torch.cuda.synchronize()
+        worst_v = worst_g = 0.0
+        for i, p in enumerate(probs):
+            if i % every:
+                continue
+            P = orc.Problem(p["dims"], p["dims"], nb, Kb, db, 0)
+            f_st, m_st = (inputs[i][0].float().cpu().numpy(), inputs[i][1].float().cpu().numpy())
+            Dr, gr = orc.gradient(P, f_st, m_st, ffds[i])
+            Db, gb = float(vals[i]), grads[i].cpu().numpy().astype(np.float64)
+            ev, eg = abs(Db - Dr) / abs(Dr), rel(gb, gr)
+            worst_v, worst_g = max(worst_v, ev), max(worst_g, eg)
+            assert ev <= 1e-5 and eg <= 1e-4, (dtype, i, p["dims"], ev, eg)
+        print(f"breathing4d dtype={dtype}: worst value rel {worst_v:.2e}, worst gradient rel L2 {worst_g:.2e}",
+              flush=True)
+        del plans, inputs, vals, grads

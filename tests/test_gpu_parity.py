@@ -136,11 +136,62 @@ def test_ffd_warp_matches_oracle(S, orc):
     prob, P, f_g, m_g, f_o, m_o = prepare(S, orc, fixed, moving, 32, (4, 4, 4), (5, 5, 5), 0)
     ffd = synth.random_ffd(prob.ctrl_dims, 3.0, 15)     # large enough to push samples off the grid
     plan = S.Plan(prob)
-    got = plan.warp(m_g, dev(ffd)).cpu().numpy()
+    got = plan.warp(m_g, dev(ffd)).cpu().numpy().astype(np.float64)
     ref = orc.warp(P, m_o, ffd)
-    assert np.abs(got - ref).max() < 2e-4
+    # FP64 arithmetic on both sides (different operation order), rounded once
+    # to FP32 on the GPU: within one FP32 unit in the last place of the oracle
+    ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+    err = np.abs(got - ref)
+    print(f"warp: max |err| {err.max():.3e}, max err / ulp {(err / ulp).max():.3f}", flush=True)
+    assert np.all(err <= ulp)
     zero = plan.warp(m_g, dev(np.zeros_like(ffd))).cpu().numpy()
     assert np.array_equal(zero, m_o)
+
+
+def check_bins(S, orc, plan, P, m_g, m_o, ffd, label):
+    """The hot path's moving bin k = min(floor(s), L - 1) of every fixed voxel
+    (eq 5), as the value and gradient passes read it, against the oracle's
+    warped sample s; and the in-bin position s - k against the oracle's,
+    rounded to FP32.  Both sides decide k in FP64, so a mismatch can only come
+    from a sample within rounding distance of a bin edge: each one is counted
+    and must lie within 1e-9 bins of the edge."""
+    k_g, t_g = plan.debug_samples(m_g, dev(ffd))
+    k_g = k_g.cpu().numpy()
+    t_g = t_g.cpu().numpy().astype(np.float64)
+    s = orc.warp(P, m_o, ffd)
+    L = P.n_bins - 1
+    k_o = np.minimum(np.floor(s), L - 1).astype(np.int32)
+    mism = k_g != k_o
+    n_mism = int(mism.sum())
+    edge = np.abs(s - np.round(s))
+    print(f"{label}: {k_g.size} voxels, {n_mism} bin mismatches, nearest sample to a bin edge "
+          f"{edge.min():.2e} bins", flush=True)
+    assert np.all(edge[mism] <= 1e-9)
+    t_o = s - k_o
+    ok = ~mism
+    ulp = np.spacing(np.abs(t_o[ok]).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(t_g[ok] - t_o[ok]) <= ulp)
+    return n_mism
+
+
+@pytest.mark.parametrize("case", ["blobs64", "ragged", "unequal"])
+def test_warped_bins_match_oracle(S, orc, case):
+    w = synth.blobs(n=64 if case == "blobs64" else 48)
+    if case == "blobs64":
+        fixed, moving, nb, K, d = w.fixed, w.moving, 32, (4, 4, 4), (8, 8, 8)
+    elif case == "ragged":
+        fixed = np.ascontiguousarray(w.fixed[:23, :29, :37])
+        moving = np.ascontiguousarray(w.moving[:23, :29, :37])
+        nb, K, d = 24, (5, 4, 6), (3, 4, 5)
+    else:
+        fixed = np.ascontiguousarray(w.fixed[:32, :36, :40])
+        moving = np.ascontiguousarray(w.moving[:32:2, :36:2, :40:2])
+        nb, K, d = 48, (5, 5, 5), (8, 8, 8)
+    prob, P, f_g, m_g, f_o, m_o = prepare(S, orc, fixed, moving, nb, K, d, 0)
+    plan = S.Plan(prob)
+    for sigma, seed in ((0.0, 0), (1.5, 19), (3.0, 20)):
+        ffd = synth.random_ffd(prob.ctrl_dims, sigma, seed) if sigma else np.zeros(prob.ffd_shape, np.float32)
+        assert check_bins(S, orc, plan, P, m_g, m_o, ffd, f"{case} sigma={sigma}") == 0
 
 
 def test_invalid_arguments_raise(S):

@@ -3,9 +3,9 @@ bench.py times: the value and the whole gradient against the FP64 oracle
 (which finishes these sizes in seconds with all host threads).
 
 Workload 3 also reports the precision pattern: 16-bit intensity storage with
-FP32 arithmetic, checked end to end against the oracle on the FP32 data
-(gate 1e-3) and, arithmetic only, against the oracle on the stored 16-bit
-values (gates 1e-5 / 1e-4)."""
+FP32 arithmetic, checked arithmetic only against the oracle on the stored
+16-bit values (gates 1e-5 / 1e-4) and end to end against the oracle on the
+FP32 data (value 1e-3; the gradient at the format's own measured bound)."""
 import numpy as np
 import pytest
 
@@ -48,16 +48,38 @@ def S():
     return S
 
 
+@pytest.fixture(scope="module")
+def ct256():
+    return synth.ct_phantom()
+
+
 @pytest.mark.parametrize("role", [0, 1])
-def test_ct256_full_size(S, orc, role):
+def test_ct256_full_size(S, orc, ct256, role):
     """Workload 2 at 256x256x128, the benchmark configuration."""
-    w = synth.ct_phantom()
+    w = ct256
     D, g, ffd, r, _, _ = run_gpu(S, w, S.F32, role)
     Dr, gr = oracle_grad(orc, w, ffd, r, role)
     print(f"ct256 role={role} D={D:.12f} oracle={Dr:.12f} rel={abs(D - Dr) / Dr:.2e} grad={rel(g, gr):.2e}",
           flush=True)
     assert abs(D - Dr) <= 1e-5 * abs(Dr)
     assert rel(g, gr) <= 1e-4
+
+
+def test_ct256_warped_bins(S, orc, ct256):
+    """Workload 2 at full size: every fixed voxel's moving bin as the hot path
+    uses it equals the oracle's min(floor(s), L - 1) of its warped sample
+    (eq 5), mismatches only within 1e-9 bins of an edge."""
+    from test_gpu_parity import check_bins
+    w = ct256
+    mr = torch.from_numpy(w.moving).cuda()
+    mlo, mhi = S.minmax(mr)
+    m = S.normalize(mr, mlo, mhi, w.n_bins)
+    prob = S.Problem(w.fixed_dims, w.moving_dims, w.n_bins, w.spatial_bins, w.ctrl_spacing, 0)
+    ffd = synth.random_ffd(prob.ctrl_dims, 2.0, 2)
+    P = orc.Problem(w.fixed_dims, w.moving_dims, w.n_bins, w.spatial_bins, w.ctrl_spacing, 0)
+    mo = orc.normalize(w.moving, mlo, mhi, w.n_bins)
+    n = check_bins(S, orc, S.Plan(prob), P, m, mo, ffd, "ct256")
+    assert n == 0
 
 
 def test_ctpet_full_size(S, orc):
@@ -85,5 +107,16 @@ def test_oct512_precision(S, orc, dtype):
     assert ar_v <= 1e-5 and ar_g <= 1e-4
     if dtype == "f32":
         assert e2e_v <= 1e-5 and e2e_g <= 1e-4
-    else:
-        assert e2e_v <= 1e-3
+        return
+    # The end-to-end error is the storage format's, not the arithmetic's: the
+    # FP64 oracle itself, given the 16-bit values, differs from the oracle on
+    # the FP32 data by the same amount (the step of FP16 is 1/32 bin near the
+    # top of [0, 63], of BF16 1/4 bin, and dM/dy takes differences of
+    # neighbouring stored values).  The value meets the 1e-3 bar; the
+    # gradient is gated at the measured bound of each format.
+    fmt_v, fmt_g = abs(Dq - Dr) / Dr, rel(gq, gr)
+    print(f"oct512 {dtype}: format-only (oracle on stored vs FP32 data) value {fmt_v:.2e} grad {fmt_g:.2e}",
+          flush=True)
+    assert e2e_v <= 1e-3
+    assert abs(e2e_g - fmt_g) <= 0.05 * fmt_g
+    assert e2e_g <= {"f16": 6e-3, "bf16": 4e-2}[dtype]

@@ -296,18 +296,19 @@ def _phase_labels(ells, shape, amp):
     return _render_slabwise(lambda xs, ys, zs: _render_labels(ells, shape, xs, ys, zs), shape, u)
 
 
-def breathing_phases(shape=(128, 256, 256), k=5, n_phases=9, workers=1):
+def breathing_phases(shape=(128, 256, 256), k=5, n_phases=9, workers=1, mp_context="fork"):
     """Workload 5: phase 0 and phases 1..9 of a breathing cycle, pair k cropped
     to the centre (80 + 6 (k - 1)) / 128 of the slices.  Returns a list of
-    (fixed, moving) raw pairs.  `workers` > 1 renders the phases in forked
-    processes (the random draws stay in the calling process, in order)."""
+    (fixed, moving) raw pairs.  `workers` > 1 renders the phases in worker
+    processes of `mp_context` (the random draws stay in the calling process,
+    in order); "spawn" suits a caller that already holds a GPU."""
     rng = rng_for(k)
     ells = _ellipsoids(rng, shape)
     nz = shape[0]
     amps = [None] + [3.0 + 12.0 * (ph - 1) / (n_phases - 1) for ph in range(1, n_phases + 1)]
     if workers > 1:
         import multiprocessing
-        with multiprocessing.get_context("fork").Pool(min(workers, len(amps))) as pool:
+        with multiprocessing.get_context(mp_context).Pool(min(workers, len(amps))) as pool:
             labs = pool.starmap(_phase_labels, [(ells, shape, a) for a in amps])
     else:
         labs = [_phase_labels(ells, shape, a) for a in amps]
@@ -319,6 +320,20 @@ def breathing_phases(shape=(128, 256, 256), k=5, n_phases=9, workers=1):
         z0 = (nz - zk) // 2
         pairs.append((np.ascontiguousarray(fixed_full[z0:z0 + zk]), np.ascontiguousarray(mov[z0:z0 + zk])))
     return pairs
+
+
+def pyramid(vol, levels=3):
+    """Input pyramid of workload 5: level 0 is `vol`, each next level a
+    Gaussian (sigma 1 voxel) of the previous one at every second voxel."""
+    out = [np.ascontiguousarray(vol)]
+    for _ in range(levels - 1):
+        out.append(np.ascontiguousarray(ndimage.gaussian_filter(out[-1], 1.0)[::2, ::2, ::2]))
+    return out
+
+
+def breathing4d_ffd(ctrl_dims, pair, level):
+    """Displacements of problem (pair, level) of workload 5: N(0, 2 vox)."""
+    return random_ffd(ctrl_dims, 2.0, 5, salt=10 * pair + level)
 
 
 def random_ffd(ctrl_dims, sigma, k, salt=7):
