@@ -154,7 +154,10 @@ def check_bins(S, orc, plan, P, m_g, m_o, ffd, label):
     warped sample s; and the in-bin position s - k against the oracle's,
     rounded to FP32.  Both sides decide k in FP64, so a mismatch can only come
     from a sample within rounding distance of a bin edge: each one is counted
-    and must lie within 1e-9 bins of the edge."""
+    and must lie within 1e-9 bins of the edge.  The two FP64 evaluations of s
+    differ in operation order by a few FP64 units of |s| <= L (~1e-14); where
+    t is near 0 that exceeds the FP32 unit of t, so t is held to one FP32 unit
+    plus 1e-12."""
     k_g, t_g = plan.debug_samples(m_g, dev(ffd))
     k_g = k_g.cpu().numpy()
     t_g = t_g.cpu().numpy().astype(np.float64)
@@ -170,7 +173,7 @@ def check_bins(S, orc, plan, P, m_g, m_o, ffd, label):
     t_o = s - k_o
     ok = ~mism
     ulp = np.spacing(np.abs(t_o[ok]).astype(np.float32)).astype(np.float64)
-    assert np.all(np.abs(t_g[ok] - t_o[ok]) <= ulp)
+    assert np.all(np.abs(t_g[ok] - t_o[ok]) <= ulp + 1e-12)
     return n_mism
 
 
