@@ -288,7 +288,7 @@ int srwcr_lbfgs_minimize(int64_t n, double *x, srwcr_fg_fn fg, void *user, int32
 int srwcr_refine_ffd(const int32_t coarse_nc[3], const float *coarse, const int32_t fine_nc[3], float *fine);
 
 /* Bending energy C_p of eq (1) (the constraint term, after Rueckert et al.):
- * the mean over control-node positions inside the fixed grid of
+ * the sum over control-node positions inside the fixed grid of
  * sum_e [u_xx^2 + u_yy^2 + u_zz^2 + 2 (u_xy^2 + u_xz^2 + u_yz^2)] of the FFD
  * displacement u.  Host arrays; `grad` (optional) receives dC_p/dd.
  * Returns -1 on invalid arguments. */

@@ -8,8 +8,10 @@
 // Wolfe) conditions inside a bracket: it halves the step on an Armijo failure
 // and grows it by 2.1 on a curvature failure until both ends of the bracket
 // are known, then bisects the bracket, so every trial shrinks it.  A level
-// stops when C has been stable over `stall_window` iterations or after
-// max_iter iterations.  Levels are Gaussian pyramids of the normalised
+// stops when C has been stable over `stall_window` iterations, after
+// max_iter iterations, or when no step along the quasi-Newton direction nor
+// along -g lowers C (convergence at the FP32 resolution of the FFD the cost
+// is evaluated on).  Levels are Gaussian pyramids of the normalised
 // volumes; the displacement found on a level is carried to the next finer one
 // by doubling it and refining the control lattice by cubic B-spline
 // subdivision, which represents the coarse field exactly.  A caller's start
@@ -39,7 +41,7 @@ struct Grid3 {
 };
 
 // ---------------------------------------------------------- bending energy
-// C_p = mean over control-node positions inside the image of
+// C_p = sum over control-node positions inside the image of
 // sum_e [u_xx^2 + u_yy^2 + u_zz^2 + 2 (u_xy^2 + u_xz^2 + u_yz^2)], with the
 // derivatives of the cubic B-spline at a node: value weights (1, 4, 1) / 6,
 // first derivative (-1, 0, 1) / (2 delta), second (1, -2, 1) / delta^2 over
@@ -60,7 +62,6 @@ double bending_energy(const std::vector<double> &c, const int nc[3], const int n
     const size_t ncell = (size_t)nc[0] * nc[1] * nc[2];
     int np[3];
     for (int e = 0; e < 3; ++e) np[e] = (nf[e] - 1) / delta[e] + 1;     // paper nodes 0 .. floor((N-1)/delta)
-    const double npts = (double)np[0] * np[1] * np[2];
     if (grad) grad->assign(3 * ncell, 0.0);
     double E = 0.0;
     for (int pz = 0; pz < np[2]; ++pz)
@@ -80,9 +81,9 @@ double bending_energy(const std::vector<double> &c, const int nc[3], const int n
                                                        (s[0] - 1 + a);
                                     val += w[0][a] * w[1][b] * w[2][c2] * c[comp * ncell + idx];
                                 }
-                        E += mult[t] * val * val / npts;
+                        E += mult[t] * val * val;
                         if (grad) {
-                            const double gv = 2.0 * mult[t] * val / npts;
+                            const double gv = 2.0 * mult[t] * val;
                             for (int c2 = 0; c2 < 3; ++c2)
                                 for (int b = 0; b < 3; ++b)
                                     for (int a = 0; a < 3; ++a) {
@@ -316,38 +317,52 @@ int lbfgs_level(const EvalFn &eval, std::vector<double> &x, int max_iter, int m,
         }
         const double gnorm = std::sqrt(dot(g, g));
         if (gnorm == 0.0) break;
-        double step = S.empty() ? 1.0 / std::sqrt(dot(d, d)) : 1.0;
         // backtracking line search with the (weak) Wolfe conditions, bracketed:
-        // lo satisfies Armijo but not the curvature condition, hi fails Armijo
+        // lo satisfies Armijo but not the curvature condition, hi fails Armijo.
+        // When no trial lowers the cost along a quasi-Newton direction, the
+        // search is repeated once along -g with the history cleared.
         const double c1 = 1e-4, c2 = 0.9;
-        bool ok = false;
+        bool ok = false, decreased = false;
         double fn = 0.0;
-        double best_f = f, best_step = 0.0;
-        double lo = 0.0, hi = INFINITY;
-        for (int trial = 0; trial < 40; ++trial) {
-            for (size_t j = 0; j < n; ++j) xn[j] = x[j] + step * d[j];
-            st = eval(xn, fn, gn);
-            if (st) return st;
-            if (std::isfinite(fn) && fn < best_f) { best_f = fn; best_step = step; }
-            if (!std::isfinite(fn) || fn > f + c1 * step * gd) {
-                hi = step;
-            } else if (dot(gn, d) < c2 * gd) {
-                lo = step;
-            } else {
-                ok = true;
-                break;
+        for (int attempt = 0; attempt < 2 && !ok && !decreased; ++attempt) {
+            if (attempt == 1) {
+                if (S.empty()) break;               // already steepest descent
+                S.clear(); Y.clear(); RHO.clear();
+                for (size_t j = 0; j < n; ++j) d[j] = -g[j];
+                gd = dot(g, d);
             }
-            step = std::isfinite(hi) ? 0.5 * (lo + hi) : 2.1 * lo;
-        }
-        if (!ok) {
-            if (best_step > 0.0) {                 // keep the best point seen
+            double step = S.empty() ? 1.0 / std::sqrt(dot(d, d)) : 1.0;
+            double best_f = f, best_step = 0.0;
+            double lo = 0.0, hi = INFINITY;
+            for (int trial = 0; trial < 40; ++trial) {
+                for (size_t j = 0; j < n; ++j) xn[j] = x[j] + step * d[j];
+                st = eval(xn, fn, gn);
+                if (st) return st;
+                if (std::isfinite(fn) && fn < best_f) { best_f = fn; best_step = step; }
+                if (!std::isfinite(fn) || fn > f + c1 * step * gd) {
+                    hi = step;
+                } else if (dot(gn, d) < c2 * gd) {
+                    lo = step;
+                } else {
+                    ok = true;
+                    break;
+                }
+                step = std::isfinite(hi) ? 0.5 * (lo + hi) : 2.1 * lo;
+            }
+            if (!ok && best_step > 0.0) {           // keep the best point seen
                 for (size_t j = 0; j < n; ++j) xn[j] = x[j] + best_step * d[j];
                 st = eval(xn, fn, gn);
                 if (st) return st;
-            } else {
-                status = SRWCR_E_LINESEARCH;
-                break;
+                decreased = true;
             }
+        }
+        if (!ok && !decreased) {
+            // no step lowers the cost: D is evaluated on the FFD rounded to FP32,
+            // so below that resolution the cost is flat.  After progress this is
+            // convergence at working precision; at the first iteration it means
+            // the gradient does not describe the cost.
+            if (iters == 0) status = SRWCR_E_LINESEARCH;
+            break;
         }
         std::vector<double> s(n), yv(n);
         for (size_t j = 0; j < n; ++j) { s[j] = xn[j] - x[j]; yv[j] = gn[j] - g[j]; }

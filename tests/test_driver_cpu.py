@@ -60,7 +60,8 @@ def test_bending_energy_vanishes_on_affine_fields():
 
 def test_bending_energy_of_a_quadratic_field():
     """u_x = a x^2 is reproduced by cubic B-spline coefficients a (x_i^2 - delta^2 / 3),
-    so u_xx = 2a everywhere and the energy is (2a)^2."""
+    so u_xx = 2a everywhere and the energy is (2a)^2 at each of the control-node
+    positions inside the grid: 9 x 5 x 4 nodes at spacing 5 in 41 x 21 x 16."""
     prob = S.Problem((41, 21, 16), (41, 21, 16), 32, (4, 4, 4), (5, 5, 5))
     ncx, ncy, ncz = prob.ctrl_dims
     a = 0.01
@@ -68,7 +69,8 @@ def test_bending_energy_of_a_quadratic_field():
     xi = (np.arange(ncx) - 1) * 5.0
     ffd[0] = (a * (xi ** 2 - 25.0 / 3.0))[None, None, :]
     E = bending(prob, ffd.astype(np.float32))
-    assert abs(E - 4 * a * a) < 1e-6 * 4 * a * a
+    npts = 9 * 5 * 4
+    assert abs(E - 4 * a * a * npts) < 1e-6 * 4 * a * a * npts
 
 
 def test_bending_energy_gradient_matches_differences():
