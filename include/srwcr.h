@@ -131,6 +131,21 @@ int srwcr_eval(const srwcr_plan *plan, const void *fixed, const void *moving, co
 int srwcr_grad(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd,
                double *d_value, float *d_grad, void *workspace, size_t workspace_bytes, void *stream);
 
+/* srwcr_grad for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same passes and results, with the workspace taken from a static device array
+ * of SRWCR_NOALLOC_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends (its address is looked up once per device;
+ * the call allocates nothing).  The plan must have been made on the current
+ * device and need at most that much workspace (srwcr_workspace_bytes),
+ * otherwise SRWCR_E_INVALID_ARG or SRWCR_E_WORKSPACE.  All calls on one device
+ * share the array: calls that overlap in time on one device race and must be
+ * serialised by the caller (one stream, or events).  The array keeps the last
+ * call's contents; srwcr_grad clears what has to start at zero itself. */
+#define SRWCR_NOALLOC_SCRATCH_BYTES (64u << 20)
+int srwcr_grad_noalloc(const srwcr_plan *plan, const void *fixed, const void *moving, const float *ffd,
+                       double *d_value, float *d_grad, void *stream);
+
 /* Dense-displacement variants (a loss for learning-based registration): the
  * warp is T(x) = x + u(x) with u a device float32 field [3][nz][ny][nx] on the
  * fixed grid (fixed-voxel units), instead of the FFD of eq 17; everything

@@ -170,6 +170,16 @@ class Plan:
                                           _ptr(grad_out), _ptr(self.workspace), self.workspace_bytes, _stream()))
         return value_out, grad_out
 
+    def grad_noalloc(self, fixed, moving, ffd, value_out, grad_out):
+        """grad() on the library's static device workspace instead of the plan's
+        (srwcr_grad_noalloc); the caller passes both outputs."""
+        self._check_inputs(fixed, moving, ffd)
+        _need_cuda(value_out, "value_out", torch.float64, ())
+        _need_cuda(grad_out, "grad_out", torch.float32, self.problem.ffd_shape)
+        _lib.check(_lib.load().srwcr_grad_noalloc(self._h, _ptr(fixed), _ptr(moving), _ptr(ffd), _ptr(value_out),
+                                                  _ptr(grad_out), _stream()))
+        return value_out, grad_out
+
     def _check_dense(self, fixed, moving, field):
         p = self.problem
         _need_cuda(fixed, "fixed", _TORCH_DT[p.fixed_dtype], p.fixed_shape)

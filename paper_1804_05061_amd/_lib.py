@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "SRWCR_OK", -1: "SRWCR_E_INVALID_ARG", -2: "SRWCR_E_DEGENERAT
 # symbols the header declares (the ABI test checks every one is exported)
 EXPORTED = ["srwcr_ctrl_dims", "srwcr_plan_create", "srwcr_plan_destroy", "srwcr_workspace_bytes",
             "srwcr_normalize", "srwcr_minmax", "srwcr_eval", "srwcr_grad", "ffd_warp",
-            "srwcr_lbfgs_default_opts", "register_lbfgs", "srwcr_debug_moments", "srwcr_debug_samples",
+            "srwcr_grad_noalloc", "srwcr_lbfgs_default_opts", "register_lbfgs", "srwcr_debug_moments", "srwcr_debug_samples",
             "srwcr_plan_info",
             "srwcr_profile", "srwcr_profile_read", "srwcr_refine_ffd", "srwcr_bending_energy", "srwcr_lbfgs_minimize",
             "srwcr_eval_dense", "srwcr_grad_dense", "srwcr_batch_create", "srwcr_batch_destroy", "srwcr_batch_workspace_bytes", "srwcr_grad_batched",
@@ -22,6 +22,7 @@ EXPORTED = ["srwcr_ctrl_dims", "srwcr_plan_create", "srwcr_plan_destroy", "srwcr
             "raptor_grad", "srwcr_grad_fixed", "srwcr_plan_create_tuned", "srwcr_last_error"]
 
 MAX_BATCH = 32
+NOALLOC_SCRATCH_BYTES = 64 << 20   # SRWCR_NOALLOC_SCRATCH_BYTES
 
 
 class SrwcrProblem(ctypes.Structure):
@@ -89,6 +90,7 @@ def load() -> ctypes.CDLL:
         "srwcr_minmax": (ctypes.c_int, [vp, i64, ctypes.POINTER(dp), ctypes.POINTER(dp), vp]),
         "srwcr_eval": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
         "srwcr_grad": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "srwcr_grad_noalloc": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "ffd_warp": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "srwcr_lbfgs_default_opts": (None, [ctypes.POINTER(SrwcrLbfgsOpts)]),
         "register_lbfgs": (ctypes.c_int, [pp, vp, vp, vp, ctypes.POINTER(SrwcrLbfgsOpts),

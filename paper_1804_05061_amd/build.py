@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/srwcr_kernels.hip", "csrc/srwcr_host.cpp", "csrc/srwcr_lbfgs.cpp"]
+SOURCES = ["csrc/srwcr_kernels.hip", "csrc/srwcr_host.cpp", "csrc/srwcr_lbfgs.cpp", "csrc/srwcr_noalloc.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",                       # native FP64 atomics in LDS and L2

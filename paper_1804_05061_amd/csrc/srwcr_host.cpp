@@ -204,6 +204,19 @@ void prof_mark(const srwcr_plan *P, int k, hipStream_t s)
 }
 }  // namespace
 
+int srwcr::report_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int srwcr::plan_device(const srwcr_plan *plan) { return plan->device; }
+
 extern "C" {
 
 const char *srwcr_last_error(void) { return g_last_error.c_str(); }

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct srwcr_plan;
+
 namespace srwcr {
 
 constexpr int kMaxBins = 64;      // L_eps + 1 <= 64: one wave lane per intensity bin
@@ -177,6 +179,11 @@ hipError_t launch_unpack_samples(const PrepKT *kt, size_t n, int32_t *bin, float
 hipError_t launch_downsample(const float *in, int nx, int ny, int nz, float *out, int ox, int oy, int oz,
                              hipStream_t s);
 hipError_t prepare_kernels();   // once per device: LDS limits of the value and gradient kernels
+
+// Host library (srwcr_host.cpp): set the calling thread's srwcr_last_error()
+// message (printf format) and return `code`; the device a plan was made on.
+int report_error(int code, const char *fmt, ...);
+int plan_device(const ::srwcr_plan *plan);
 size_t prep_lds_bytes(const Geom &g);
 size_t value_lds_bytes(const Geom &g, int bw);
 size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz);
