@@ -354,11 +354,7 @@ int srwcr_plan_create_tuned(const srwcr_problem *prob, const srwcr_tuning *tunin
         // the per-wave scratch, else 64
         g.xw = g.delta[0] >= 3 ? kSlots * kWave : kWave;
         g.c1n = (g.xw - 1) / g.delta[0] + 5;
-        {
-            const int np_max = (g.xw - 1) / g.delta[0] + 2;
-            int scr = std::max(64 + kMaxBins * 3 * kXN, 3 * kSlots * kWave + 12 * np_max);
-            g.gscr = (scr + 3) / 4 * 4;
-        }
+        g.gscr = grad_scratch_floats((g.xw - 1) / g.delta[0] + 2);
         P->value_lds = value_lds_bytes(g, 4);
         P->prep_lds = prep_lds_bytes(g);
         if (P->value_lds > (size_t)max_lds) {
@@ -443,12 +439,19 @@ int srwcr_plan_create_tuned(const srwcr_problem *prob, const srwcr_tuning *tunin
                         if (yc_max) yc = std::min(yc, yc_max);
                         int zc = std::max(1, std::min(zw, (int)std::ceil(target / ((double)xw * yc))));
                         if (zc_max) zc = std::min(zc, zc_max);
-                        for (int z0 = za; z0 < zb; z0 += zc)
+                        // z-ranges end on FFD cell boundaries (mz whole FFD z-cells, fewer
+                        // at the spatial cell's edges), so that a wave's consecutive rows
+                        // share an FFD z-cell and the gradient pass scatters them together
+                        const int dz = g.delta[2];
+                        const int mz = std::max(1, (int)std::lround((double)zc / dz));
+                        for (int z0 = za, z1 = 0; z0 < zb; z0 = z1) {
+                            z1 = std::min(zb, (z0 / dz + mz) * dz);
+                            if (zc_max) z1 = std::min(z1, z0 + zc_max);
                             for (int y0 = ya; y0 < yb; y0 += yc) {
                                 WorkItem w{};
                                 w.x0 = xr.first; w.x1 = xr.second;
                                 w.y0 = y0; w.y1 = std::min(y0 + yc, yb);
-                                w.z0 = z0; w.z1 = std::min(z0 + zc, zb);
+                                w.z0 = z0; w.z1 = z1;
                                 w.cx = cells[0][w.x0]; w.cy = cy; w.cz = cz;
                                 w.gx0 = w.x0 / g.delta[0];
                                 w.gy0 = w.y0 / g.delta[1];
@@ -459,6 +462,7 @@ int srwcr_plan_create_tuned(const srwcr_problem *prob, const srwcr_tuning *tunin
                                 worst_lds = std::max(worst_lds, grad_lds_bytes(g, w.gnx, w.gny, w.gnz));
                                 items.push_back(w);
                             }
+                        }
                     }
                 }
             }

@@ -15,7 +15,9 @@ constexpr int kXN = 5;            // x-nodes of a work item (its x-range spans a
 constexpr int kNReg = kXN * 16;   // regions of a work item: 5 (x) x 4 (y) x 4 (z)
 constexpr int kWin = 4;           // bin slots of one value-pass window (A-bins kmin .. kmin + 3)
 constexpr int kValueThreads = 768;
-constexpr int kGradThreads = 768;
+constexpr int kGradThreads = 1024;
+constexpr int kRowBins = 32;      // gradient pass: bins of one chunk of a row's tables
+constexpr int kRowEntry = 20;     // floats per row-table entry: 15 used, padded for 16-byte loads on distinct banks
 constexpr int kMaxNodeSeg = 68;   // FFD x-nodes one 64-voxel row segment can touch (delta >= 1)
 constexpr int kSlots = 2;         // voxels per lane: an item row holds up to 2 x 64 voxels
 constexpr int kMaxBatch = 32;     // problems of one batched launch
@@ -187,5 +189,14 @@ int plan_device(const ::srwcr_plan *plan);
 size_t prep_lds_bytes(const Geom &g);
 size_t value_lds_bytes(const Geom &g, int bw);
 size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz);
+// Floats of per-wave LDS scratch of the gradient pass, for rows whose FFD
+// x-range covers at most np_max cells: the row's bin list (64), its row
+// tables (kRowBins entries) or, later in the row, q per voxel ([128][3]), and
+// the cell moments ([np_max + 6][4][3], three zero cells on either side).
+inline int grad_scratch_floats(int np_max)
+{
+    const int tables = kRowBins * kRowEntry, q = 3 * kSlots * kWave;
+    return (64 + (tables > q ? tables : q) + 12 * (np_max + 6) + 3) / 4 * 4;
+}
 
 }  // namespace srwcr

@@ -34,9 +34,12 @@
 // the 16 (y, z) regions of one (x-node, bin, coefficient) contiguous,
 // interpolates them through the same separable weights (row tables per
 // wave), forms q = dD/ds * grad M * dy/dT per voxel and scatters it to the
-// FFD nodes: per-cell moments along x, then FP64 LDS atomics over the 16
-// (y, z) node weights, merged globally once per box.  A dense field's
-// gradient is q itself.
+// FFD nodes.  The scatter is contracted over z first: a wave takes
+// consecutive rows of one y (boxes end on FFD z-cell boundaries) and sums
+// beta_c(z) q per voxel in registers; once per such group it forms, per
+// z-node, the per-cell moments along x and adds them to the four y-nodes
+// with FP64 LDS atomics; the box's node block is merged globally once.  A
+// dense field's gradient is q itself.
 #include "srwcr_internal.h"
 
 #include <hip/hip_bf16.h>
@@ -1140,21 +1143,70 @@ __host__ __device__ __forceinline__ size_t grad_tab_offset(int xw, int nG)
     return ((size_t)xw * 16 + (size_t)nG * 8 + 15) / 16 * 16;
 }
 
+// Regions of an item's block, padded so that the per-wave scratch after their
+// alpha values starts on 16 bytes.
+__host__ __device__ constexpr int grad_nreg_padded(int bw) { return (kXN * bw * bw + 3) / 4 * 4; }
+
 size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz)
 {
-    const size_t nreg = (size_t)kXN * g.bw * g.bw;
-    const size_t tab = (size_t)kXN * g.nb * 3 * tab_jk_stride(g.bw) * sizeof(float) + nreg * sizeof(float);
+    const size_t tab = (size_t)kXN * g.nb * 3 * tab_jk_stride(g.bw) * sizeof(float) +
+                       (size_t)grad_nreg_padded(g.bw) * sizeof(float);
     const size_t scratch = (size_t)(kGradThreads / kWave) * g.gscr * sizeof(float);
     return grad_tab_offset(g.xw, gnx * gny * gnz * 3) + tab + scratch;
 }
 
-// Per-voxel quantities of the gradient pass.
-struct VoxG {
-    int kA, kB;
-    float tA, tB, a0, a1, m1;
-    float wx5[kXN];
-    float dm[3];      // dM/dy (FP32)
+// Global inputs of one row of the gradient pass, loaded a row ahead.
+struct RowG {
+    PrepKT pk[kSlots];  // the warped moving sample
+    float s[kSlots];    // the fixed image's value, or dD/ds_M of the voxel (ROLE 2)
+    float dm[kSlots][3];// dM/dy
+    float us;           // lanes 0-3 / 4-7: spatial weights of y / z
+    double uf;          // lanes 0-3 / 4-7: FFD weights of y / z
+    int c;              // lanes 0 / 1: FFD cells of y / z; 2 / 3: spatial cells of y / z
 };
+
+// Row-uniform tables the gradient pass reads per row (hoisted pointers).
+struct RowTabs {
+    const float *spy, *spz;     // spatial weights [4 per coordinate]
+    const double *fwy, *fwz;    // FFD weights [4 per coordinate]
+    const int *fpy, *fpz;       // FFD cells
+    const int *scy, *scz;       // spatial cells
+};
+
+// Every lane issues each load (at a valid address) and keeps the value its
+// lane stands for: lane-dependent branches around loads into one register
+// would make the compiler wait for all loads in flight, the prefetch included.
+template <int FDT, int ROLE, int DISP, int BW>
+__device__ __forceinline__ void grad_load_row(RowG &in, const RowTabs &tb, const void *__restrict__ fixed,
+                                              const PrepKT *__restrict__ kt, const float *__restrict__ dmi,
+                                              const float *__restrict__ rds, size_t nvox, size_t rowb, int y, int z,
+                                              const int (&xc)[kSlots], int lane)
+{
+#pragma unroll
+    for (int sl = 0; sl < kSlots; ++sl) {
+        if constexpr (DISP != 2) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e) in.dm[sl][e] = dmi[e * nvox + rowb + xc[sl]];
+        }
+        if constexpr (ROLE == 2) {
+            in.s[sl] = gld(rds, rowb + xc[sl]);
+        } else {
+            in.pk[sl] = kt[rowb + xc[sl]];
+            in.s[sl] = ld_int<FDT>(fixed, rowb + xc[sl]);
+        }
+    }
+    const int l3 = lane & 3;
+    const bool zl = lane & 4;
+    if constexpr (ROLE < 2) in.us = gld(zl ? tb.spz + 4 * z : tb.spy + 4 * y, l3);
+    if constexpr (DISP == 0) in.uf = gld(zl ? tb.fwz + 4 * z : tb.fwy + 4 * y, l3);
+    if constexpr (DISP == 0 || (ROLE < 2 && BW == 5)) {
+        const int *pc = tb.fpy + y;
+        if (DISP == 0 && l3 == 1) pc = tb.fpz + z;
+        if (ROLE < 2 && BW == 5 && l3 == 2) pc = tb.scy + y;
+        if (ROLE < 2 && BW == 5 && l3 == 3) pc = tb.scz + z;
+        in.c = gld(pc, 0);
+    }
+}
 
 // DISP 0: scatter dD/dT to the FFD nodes (eq 17) into the workspace
 // accumulators; DISP 1: write dD/du(x) of a dense field to args.p[].grad;
@@ -1177,9 +1229,6 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     const float *__restrict__ alpha = reinterpret_cast<const float *>(ws + g.ws.alpha);
     const float *__restrict__ rds = reinterpret_cast<const float *>(ws + g.ws.rds);
     double *__restrict__ grad = reinterpret_cast<double *>(ws + g.ws.grad);
-    const float4 *spw_x = g.sp_w[0], *spw_y = g.sp_w[1], *spw_z = g.sp_w[2];
-    const int *spc_x = g.sp_cell[0], *fp_x = g.ffd_p[0], *fp_y = g.ffd_p[1], *fp_z = g.ffd_p[2];
-    const double4 *fw_y = g.ffd_w[1], *fw_z = g.ffd_w[2];
     const int nfx = g.nf[0], nfy = g.nf[1], dx = g.delta[0];
     const float ratio[3] = {g.ratio[0], g.ratio[1], g.ratio[2]};
     const int nb = g.nb, L = nb - 1;
@@ -1193,133 +1242,216 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
-    float *scr = alph + NR + wave * g.gscr;
+    // per-wave scratch: bin list [64] | row tables [kRowBins][NE] or q [128][3] | cell moments
+    float *scr = alph + grad_nreg_padded(BW) + wave * g.gscr;
+    int *blist = reinterpret_cast<int *>(scr);
+    float *rowt = scr + 64;
+    float *qb = rowt;
+    float *cm = rowt + (kRowBins * kRowEntry > 3 * kSlots * kWave ? kRowBins * kRowEntry : 3 * kSlots * kWave);
     // the adjoint taken: of the image that plays A (eq 21) or B (eq 19), and
     // where its tables sit in the four slots per (region, bin)
     constexpr bool FA = DISP == 2 ? ROLE == 1 : ROLE == 0;
     constexpr int CO = DISP == 2 ? (ROLE == 0 ? 3 : 1) : 0;
+    // a row-table entry: the 5 x-nodes x 3 coefficients of a bin of A (15 of
+    // kRowEntry floats), or the 5 x-nodes of a bin of B (5 of 8)
+    constexpr int NE = FA ? kRowEntry : 8;
+    constexpr int NU = FA ? kXN * 3 : kXN;
 
+    const int xs = it.x0, xe = it.x1;
     if (DISP == 0)
         for (int i = threadIdx.x; i < nG; i += blockDim.x) G[i] = 0.0;
-    for (int i = threadIdx.x; DISP == 0 && i < it.x1 - it.x0; i += blockDim.x) {
-        const double4 b = gld(g.ffd_w[0], it.x0 + i);
+    for (int i = threadIdx.x; DISP == 0 && i < xe - xs; i += blockDim.x) {
+        const double4 b = gld(g.ffd_w[0], xs + i);
         bxw[i] = make_float4((float)b.x, (float)b.y, (float)b.z, (float)b.w);
     }
-    for (int i = threadIdx.x; ROLE < 2 && i < NR * nb; i += blockDim.x) {
-        const int rl = i / nb, a = i - rl * nb;
-        const int ii = rl % kXN, jk = rl / kXN, kk = jk / BW, jj = jk - kk * BW;
-        float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f, al = 0.0f;
-        if (it.cx + ii < g.K[0] && it.cy + jj < g.K[1] && it.cz + kk < g.K[2]) {
-            const int R = ((it.cz + kk) * g.K[1] + (it.cy + jj)) * g.K[0] + (it.cx + ii);
-            const float *tp = tables + ((size_t)R * nb + a) * 4 + CO;
-            t0 = tp[0];
-            if (FA) {
-                t1 = tp[1];
-                t2 = tp[2];
+    // the block's tables to LDS: lane = bin (nb <= 64) and regions rl = wave,
+    // wave + nwaves, ... so that the index arithmetic is wave-uniform; kStage
+    // regions per wave at a time, all their loads issued before the first
+    // store (a region outside the lattice reads region 0 and stores zeros)
+    constexpr int kStage = 8;
+    for (int r0 = wave; ROLE < 2 && r0 < NR; r0 += kStage * nwaves) {
+        float t0[kStage], t1[kStage], t2[kStage], al[kStage];
+        bool ok[kStage];
+        const int a = lane < nb ? lane : 0;
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int rl = r0 + u * nwaves;
+            const int ii = rl % kXN, jk = rl / kXN, kk = jk / BW, jj = jk - kk * BW;
+            ok[u] = rl < NR && it.cx + ii < g.K[0] && it.cy + jj < g.K[1] && it.cz + kk < g.K[2];
+            const int R = ok[u] ? ((it.cz + kk) * g.K[1] + (it.cy + jj)) * g.K[0] + (it.cx + ii) : 0;
+            const size_t o = ((size_t)R * nb + a) * 4 + CO;
+            if constexpr (FA && CO == 0) {
+                const float4 q = gld(reinterpret_cast<const float4 *>(tables), o / 4);
+                t0[u] = q.x;
+                t1[u] = q.y;
+                t2[u] = q.z;
+            } else {
+                t0[u] = gld(tables, o);
+                t1[u] = FA ? gld(tables, o + 1) : 0.0f;
+                t2[u] = FA ? gld(tables, o + 2) : 0.0f;
             }
-            al = alpha[R];
+            al[u] = gld(alpha, R);
         }
-        float *tq = tab + ((ii * nb + a) * 3) * JKS + jk;
-        tq[0] = t0;
-        tq[JKS] = t1;
-        tq[2 * JKS] = t2;
-        if (a == 0) alph[rl] = al;
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int rl = r0 + u * nwaves;
+            if (rl >= NR) break;
+            const int ii = rl % kXN, jk = rl / kXN;
+            if (lane < nb) {
+                float *tq = tab + ((ii * nb + lane) * 3) * JKS + jk;
+                tq[0] = ok[u] ? t0[u] : 0.0f;
+                tq[JKS] = ok[u] ? t1[u] : 0.0f;
+                tq[2 * JKS] = ok[u] ? t2[u] : 0.0f;
+            }
+            if (lane == 0) alph[rl] = ok[u] ? al[u] : 0.0f;
+        }
+    }
+    // the item's x range is the same for all its rows: the voxels of each
+    // lane, their x-node weights and the FFD cells of the range
+    bool pend[kSlots];
+    int xcl[kSlots];
+    float wx5[kSlots][kXN];
+#pragma unroll
+    for (int sl = 0; sl < kSlots; ++sl) {
+        const int x = xs + sl * kWave + lane;
+        pend[sl] = x < xe;
+        xcl[sl] = pend[sl] ? x : xe - 1;
+        if constexpr (ROLE < 2) x_node_weights(gld(g.sp_w[0], xcl[sl]), gld(g.sp_cell[0], xcl[sl]) != it.cx, wx5[sl]);
+    }
+    int px_lo = 0, np = 0;
+    if constexpr (DISP == 0) {
+        int pxc = 0;
+        if (lane == 0) pxc = gld(g.ffd_p[0], xs);
+        else if (lane == 1) pxc = gld(g.ffd_p[0], xe - 1);
+        px_lo = bcast(pxc, 0);
+        np = bcast(pxc, 1) - px_lo + 1;
+        for (int i = lane; i < 12 * (np + 6); i += kWave) cm[i] = 0.0f;   // pad cells stay zero
     }
     __syncthreads();
 
-    const int ny = it.y1 - it.y0, nz = it.z1 - it.z0;
-    const int xs = it.x0, xe = it.x1;
-    for (int row = wave; row < ny * nz; row += nwaves) {
-        const int y = it.y0 + row % ny, z = it.z0 + row / ny;
-        const size_t rowb = ((size_t)z * nfy + y) * nfx;
-        VoxG v[kSlots];
-        bool pend[kSlots];
+    // each wave takes a contiguous run of the item's rows, z fastest, so that
+    // consecutive rows of a wave mostly share y and the FFD z-cell (see the
+    // scatter below); its global inputs are loaded a row ahead
+    const int ny = it.y1 - it.y0, nz = it.z1 - it.z0, nrows = ny * nz;
+    const int rb = wave * nrows / nwaves, re = (wave + 1) * nrows / nwaves;
+    const RowTabs tb{reinterpret_cast<const float *>(g.sp_w[1]), reinterpret_cast<const float *>(g.sp_w[2]),
+                     reinterpret_cast<const double *>(g.ffd_w[1]), reinterpret_cast<const double *>(g.ffd_w[2]),
+                     g.ffd_p[1], g.ffd_p[2], g.sp_cell[1], g.sp_cell[2]};
+    RowG cur{}, nxt{};
+    if (rb < re) {
+        const int y = it.y0 + rb / nz, z = it.z0 + rb % nz;
+        grad_load_row<FDT, ROLE, DISP, BW>(cur, tb, fixed, kt, dmi, rds, nvox, ((size_t)z * nfy + y) * nfx, y, z, xcl,
+                                           lane);
+    }
+    // the scatter's group: q of the rows with one y and one FFD z-cell,
+    // contracted over the z-nodes, Q[sl][c][e] = sum_rows beta_c(z) q_e
+    float Q[kSlots][4][3];
+    int gyr = 0, gpy = 0, gpz = -1;
+    float gby[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // ... then per z-node c the x-scatter of the group (eq 17): per FFD cell p
+    // of the row range the four moments M[p][l][e] = sum_{x in p}
+    // beta_l(eta_x) Q_c,e(x), node sums R1[n][e] = sum_l M[n - l][l][e]
+    // (cells outside the range read the zero pads), and the four y-nodes
+    auto flush = [&]() {
+        const int sy = it.gnx * 3;
 #pragma unroll
-        for (int sl = 0; sl < kSlots; ++sl) {
-            const int x = xs + sl * kWave + lane;
-            pend[sl] = x < xe;
-            const int xc = pend[sl] ? x : xe - 1;
+        for (int c = 0; c < 4; ++c) {
 #pragma unroll
-            for (int e = 0; DISP != 2 && e < 3; ++e) v[sl].dm[e] = dmi[e * nvox + rowb + xc];
-            if constexpr (ROLE == 2) {
-                v[sl].tA = pend[sl] ? gld(rds, rowb + xc) : 0.0f;      // dD/ds_M of the voxel
-                continue;
+            for (int sl = 0; sl < kSlots; ++sl)
+#pragma unroll
+                for (int e = 0; e < 3; ++e) qb[(sl * kWave + lane) * 3 + e] = Q[sl][c][e];
+            wave_sync();
+            for (int t = lane; t < np * 3; t += kWave) {
+                const int p = t / 3, e = t - 3 * p;
+                const int xa = max(xs, (px_lo + p) * dx), xb = min(xe, (px_lo + p + 1) * dx);
+                float m0 = 0.0f, m1_ = 0.0f, m2_ = 0.0f, m3 = 0.0f;
+                for (int xx = xa; xx < xb; xx += 2) {                // two voxels per step, loads issued together
+                    const int x1 = min(xx + 1, xb - 1);
+                    const float qa = qb[(xx - xs) * 3 + e], qn = qb[(x1 - xs) * 3 + e];
+                    const float4 ba = bxw[xx - xs], bn = bxw[x1 - xs];
+                    const float q2 = xx + 1 < xb ? qn : 0.0f;
+                    m0 = fmaf(bn.x, q2, fmaf(ba.x, qa, m0));
+                    m1_ = fmaf(bn.y, q2, fmaf(ba.y, qa, m1_));
+                    m2_ = fmaf(bn.z, q2, fmaf(ba.z, qa, m2_));
+                    m3 = fmaf(bn.w, q2, fmaf(ba.w, qa, m3));
+                }
+                float *cp = cm + (p + 3) * 12 + e;
+                cp[0] = m0;
+                cp[3] = m1_;
+                cp[6] = m2_;
+                cp[9] = m3;
             }
-            const PrepKT pk = kt[rowb + xc];
-            const float sf = ld_int<FDT>(fixed, rowb + xc);
-            int kF;
-            float tF, m0w, m1w, f0w, f1w;
-            const int kM = pk.k;
-            const float tM = pk.t;
-            parzen_w(tM, m0w, m1w);
-            parzen(sf, L, kF, tF, f0w, f1w);
-            v[sl].kA = ROLE ? kF : kM;
-            v[sl].kB = ROLE ? kM : kF;
-            v[sl].tA = ROLE ? tF : tM;
-            v[sl].tB = ROLE ? tM : tF;
-            v[sl].a0 = ROLE ? f0w : m0w;
-            v[sl].a1 = ROLE ? f1w : m1w;
-            v[sl].m1 = (float)v[sl].kB + (ROLE ? m1w : f1w);
-            x_node_weights(gld(spw_x, xc), gld(spc_x, xc) != it.cx, v[sl].wx5);
+            wave_sync();
+            for (int t = lane; t < (np + 3) * 3; t += kWave) {
+                const int n = t / 3, e = t - 3 * n;
+                const float *cp = cm + (n + 3) * 12 + e;
+                const float r1 = ((cp[0] + cp[-12 + 3]) + cp[-24 + 6]) + cp[-36 + 9];
+                if (r1 != 0.0f) {
+                    double *gp = G + ((gpz + c - it.gz0) * it.gny + (gpy - it.gy0)) * sy + (px_lo + n - it.gx0) * 3 + e;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) atomicAdd(gp + b * sy, (double)(r1 * gby[b]));
+                }
+            }
+            wave_sync();
+        }
+    };
+    for (int row = rb; row < re; ++row) {
+        const int y = it.y0 + row / nz, z = it.z0 + row % nz;
+        const size_t rowb = ((size_t)z * nfy + y) * nfx;
+        if (row + 1 < re) {
+            const int yn = it.y0 + (row + 1) / nz, zn = it.z0 + (row + 1) % nz;
+            grad_load_row<FDT, ROLE, DISP, BW>(nxt, tb, fixed, kt, dmi, rds, nvox, ((size_t)zn * nfy + yn) * nfx, yn,
+                                               zn, xcl, lane);
         }
         float gs[kSlots] = {0.0f, 0.0f};
         if constexpr (ROLE == 2) {
 #pragma unroll
-            for (int sl = 0; sl < kSlots; ++sl) gs[sl] = v[sl].tA;
+            for (int sl = 0; sl < kSlots; ++sl) gs[sl] = pend[sl] ? cur.s[sl] : 0.0f;   // dD/ds_M of the voxel
         } else {
-        float wyv[4], wzv[4];
-        row_sp_weights(spw_y, spw_z, y, z, lane, wyv, wzv);
-        int oyz = 0;                                                 // the row's (y, z) cells in a two-cell item
-        if constexpr (BW == 5) {
-            int c = 0;
-            if (lane == 0) c = gld(g.sp_cell[1], y);
-            else if (lane == 1) c = gld(g.sp_cell[2], z);
-            oyz = (bcast(c, 1) - it.cz) * BW + (bcast(c, 0) - it.cy);
+        int kA[kSlots], kB[kSlots];
+        float tA[kSlots], tB[kSlots], a0[kSlots], a1[kSlots], m1[kSlots];
+#pragma unroll
+        for (int sl = 0; sl < kSlots; ++sl) {
+            int kF;
+            float tF, m0w, m1w, f0w, f1w;
+            const int kM = cur.pk[sl].k;
+            const float tM = cur.pk[sl].t;
+            parzen_w(tM, m0w, m1w);
+            parzen(cur.s[sl], L, kF, tF, f0w, f1w);
+            kA[sl] = ROLE ? kF : kM;
+            kB[sl] = ROLE ? kM : kF;
+            tA[sl] = ROLE ? tF : tM;
+            tB[sl] = ROLE ? tM : tF;
+            a0[sl] = ROLE ? f0w : m0w;
+            a1[sl] = ROLE ? f1w : m1w;
+            m1[sl] = (float)kB[sl] + (ROLE ? m1w : f1w);
         }
+        float wyv[4], wzv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            wyv[j] = bcast(cur.us, j);
+            wzv[j] = bcast(cur.us, 4 + j);
+        }
+        int oyz = 0;                                                 // the row's (y, z) cells in a two-cell item
+        if constexpr (BW == 5) oyz = (bcast(cur.c, 3) - it.cz) * BW + (bcast(cur.c, 2) - it.cy);
 
         // dD/ds_M: the region tables interpolated by w(r, x) = wx wy wz.  Row
         // tables T_row[s][i][c] = sum_jk wy_j wz_k T[(i, j, k)][bin_s][c] are
-        // built for every bin s the row's voxels need (a wave-uniform 64-bit
+        // built for the bins s the row's voxels need (a wave-uniform 64-bit
         // set: k_A, and k_A + 1 when the moving image is B), one entry per
-        // lane; each voxel then combines its bin's 5 x-node entries, found at
-        // slot popcount(bins below k_A).
-        int *blist = reinterpret_cast<int *>(scr);                  // [64] the row's bins, ascending
-        float *rowt = scr + 64;                                      // [nd][NE]
-        constexpr int NE = FA ? kXN * 3 : kXN;
+        // lane, kRowBins bins at a time; each voxel then combines its bin's 5
+        // x-node entries, found at slot popcount(bins below k_A).
         unsigned long long mine = 0ull;
 #pragma unroll
         for (int sl = 0; sl < kSlots; ++sl)
-            if (pend[sl]) mine |= (FA ? 1ull : 3ull) << v[sl].kA;
+            if (pend[sl]) mine |= (FA ? 1ull : 3ull) << kA[sl];
         const unsigned long long bins = (unsigned long long)wave_or_dpp((unsigned)(mine >> 32)) << 32 |
                                         wave_or_dpp((unsigned)mine);
         const int nd = __builtin_popcountll(bins);
+        int sbv[kSlots];
+#pragma unroll
+        for (int sl = 0; sl < kSlots; ++sl) sbv[sl] = __builtin_popcountll(bins & ((1ull << kA[sl]) - 1ull));
         if ((bins >> lane) & 1ull) blist[__builtin_popcountll(bins & ((1ull << lane) - 1ull))] = lane;
-        wave_sync();
-        for (int e = lane; e < nd * NE; e += kWave) {
-            const int sb = e / NE, r = e - sb * NE;
-            const int a = blist[sb];
-            const int i = FA ? r / 3 : r, c = FA ? r - 3 * i : 0;
-            float acc = 0.0f;
-            if (a <= (FA ? L - 1 : L)) {
-                const float *tp = tab + ((i * nb + a) * 3 + c) * JKS + oyz;
-                if constexpr (BW == 4) {
-#pragma unroll
-                    for (int kz = 0; kz < 4; ++kz) {
-                        const float4 q = reinterpret_cast<const float4 *>(tp)[kz];
-                        acc = fmaf(wyv[0] * wzv[kz], q.x, acc);
-                        acc = fmaf(wyv[1] * wzv[kz], q.y, acc);
-                        acc = fmaf(wyv[2] * wzv[kz], q.z, acc);
-                        acc = fmaf(wyv[3] * wzv[kz], q.w, acc);
-                    }
-                } else {
-#pragma unroll
-                    for (int kz = 0; kz < 4; ++kz)
-#pragma unroll
-                        for (int jy = 0; jy < 4; ++jy) acc = fmaf(wyv[jy] * wzv[kz], tp[kz * BW + jy], acc);
-                }
-            }
-            rowt[e] = acc;
-        }
         float arow[kXN];                                             // B's adjoint: CR_r / (sigma_r^2 Z) per x-node
         if (!FA) {
             float al = 0.0f;
@@ -1334,41 +1466,81 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             for (int i = 0; i < kXN; ++i) arow[i] = bcast(al, i);
         }
         wave_sync();
+        // chunks of kRowBins bins; with B's adjoint a voxel needs bins k_A and
+        // k_A + 1 (adjacent in the set), so chunks overlap by one bin
+        constexpr int STEP = FA ? kRowBins : kRowBins - 1;
+        for (int c0 = 0; c0 + (FA ? 0 : 1) < nd; c0 += STEP) {
+            const int nc = min(kRowBins, nd - c0);
+            for (int e = lane; e < nc * NU; e += kWave) {
+                const int sb = e / NU, r = e - sb * NU;
+                const int a = blist[c0 + sb];
+                float acc = 0.0f;
+                if (a <= (FA ? L - 1 : L)) {
+                    const int i = FA ? r / 3 : r, c = FA ? r - 3 * i : 0;
+                    const float *tp = tab + ((i * nb + a) * 3 + c) * JKS + oyz;
+                    if constexpr (BW == 4) {
 #pragma unroll
-        for (int sl = 0; sl < kSlots; ++sl) {
-            if (!pend[sl]) continue;
-            const int sb = __builtin_popcountll(bins & ((1ull << v[sl].kA) - 1ull));
-            if (FA) {
-                const float *rt = rowt + sb * NE;
-                float C[3];
+                        for (int kz = 0; kz < 4; ++kz) {
+                            const float4 q = reinterpret_cast<const float4 *>(tp)[kz];
+                            acc = fmaf(wyv[0] * wzv[kz], q.x, acc);
+                            acc = fmaf(wyv[1] * wzv[kz], q.y, acc);
+                            acc = fmaf(wyv[2] * wzv[kz], q.z, acc);
+                            acc = fmaf(wyv[3] * wzv[kz], q.w, acc);
+                        }
+                    } else {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
+                        for (int kz = 0; kz < 4; ++kz)
+#pragma unroll
+                            for (int jy = 0; jy < 4; ++jy) acc = fmaf(wyv[jy] * wzv[kz], tp[kz * BW + jy], acc);
+                    }
+                }
+                rowt[sb * NE + r] = acc;
+            }
+            wave_sync();
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) {
+                const int s = sbv[sl] - c0;
+                if (!pend[sl] || s < 0 || s > nc - (FA ? 1 : 2)) continue;
+                if (FA) {
+                    const float4 *rt = reinterpret_cast<const float4 *>(rowt + s * NE);
+                    const float4 q0 = rt[0], q1 = rt[1], q2 = rt[2], q3 = rt[3];
+                    const float r[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                                         q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+                    float C[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        float acc = 0.0f;
+#pragma unroll
+                        for (int i = 0; i < kXN; ++i) acc = fmaf(wx5[sl][i], r[i * 3 + c], acc);
+                        C[c] = acc;
+                    }
+                    gs[sl] = parzen_dw0(tA[sl]) * fmaf(fmaf(C[0], m1[sl], C[1]), m1[sl], C[2]);
+                } else {
+                    const float *r0 = rowt + s * NE, *r1 = r0 + NE;     // bins k_A and k_A + 1
+                    const float4 p0 = *reinterpret_cast<const float4 *>(r0);
+                    const float4 p1 = *reinterpret_cast<const float4 *>(r1);
+                    const float e0[kXN] = {p0.x, p0.y, p0.z, p0.w, r0[4]};
+                    const float e1[kXN] = {p1.x, p1.y, p1.z, p1.w, r1[4]};
+                    const float k21 = (float)(2 * kB[sl] + 1);
                     float acc = 0.0f;
 #pragma unroll
-                    for (int i = 0; i < kXN; ++i) acc = fmaf(v[sl].wx5[i], rt[i * 3 + c], acc);
-                    C[c] = acc;
+                    for (int i = 0; i < kXN; ++i) {
+                        const float t = k21 * arow[i] - a0[sl] * e0[i] - a1[sl] * e1[i];
+                        acc = fmaf(wx5[sl][i], t, acc);
+                    }
+                    gs[sl] = -parzen_dw0(tB[sl]) * acc;                   // d m1 / d s_B = -d w0 / d s
                 }
-                gs[sl] = parzen_dw0(v[sl].tA) * fmaf(fmaf(C[0], v[sl].m1, C[1]), v[sl].m1, C[2]);
-            } else {
-                const float *r0 = rowt + sb * NE, *r1 = r0 + NE;        // bins k_A and k_A + 1 (adjacent in the set)
-                const float k21 = (float)(2 * v[sl].kB + 1);
-                float acc = 0.0f;
-#pragma unroll
-                for (int i = 0; i < kXN; ++i) {
-                    const float t = k21 * arow[i] - v[sl].a0 * r0[i] - v[sl].a1 * r1[i];
-                    acc = fmaf(v[sl].wx5[i], t, acc);
-                }
-                gs[sl] = -parzen_dw0(v[sl].tB) * acc;                   // d m1 / d s_B = -d w0 / d s
             }
+            wave_sync();                                             // the next chunk or q reuses the tables
         }
-        wave_sync();                                                 // the scatter reuses the scratch
         }
 
         if (DISP == 2) {                                             // the fixed image's dD/ds_F
             float *out = args.p[it.prob].grad;
 #pragma unroll
             for (int sl = 0; sl < kSlots; ++sl)
-                if (xs + sl * kWave + lane < xe) out[rowb + xs + sl * kWave + lane] = gs[sl];
+                if (pend[sl]) out[rowb + xs + sl * kWave + lane] = gs[sl];
+            cur = nxt;
             continue;
         }
         // q = dD/ds * dM/dy * dy/dT  (eq 16): a dense field's gradient is q itself
@@ -1376,85 +1548,71 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             float *out = args.p[it.prob].grad;
 #pragma unroll
             for (int sl = 0; sl < kSlots; ++sl)
-                if (xs + sl * kWave + lane < xe) {         // the windows have cleared pend[]
+                if (pend[sl]) {
                     const size_t vi = rowb + xs + sl * kWave + lane;
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) out[e * nvox + vi] = gs[sl] * v[sl].dm[e] * ratio[e];
+                    for (int e = 0; e < 3; ++e) out[e * nvox + vi] = gs[sl] * cur.dm[sl][e] * ratio[e];
                 }
+            cur = nxt;
             continue;
         }
-        // ... then the scatter to the control points (eq 17): per FFD cell p of
-        // the row the four moments M[p][l][e] = sum_{x in p} beta_l(eta_x) q_e(x) ...
-        int pxc = 0;                                                 // vector loads, see row_sp_weights
-        if (lane == 0) pxc = gld(fp_x, xs);
-        else if (lane == 1) pxc = gld(fp_x, xe - 1);
-        const int px_lo = bcast(pxc, 0), px_hi = bcast(pxc, 1);
-        const int np = px_hi - px_lo + 1, nn = np + 3;
-        float *qb = scr;                                             // [128][3]
-        float *cm = scr + 3 * kSlots * kWave;                        // [np][4][3]
-#pragma unroll
-        for (int sl = 0; sl < kSlots; ++sl)
-#pragma unroll
-            for (int e = 0; e < 3; ++e)
-                qb[(sl * kWave + lane) * 3 + e] = gs[sl] * v[sl].dm[e] * ratio[e];
-        wave_sync();
-        for (int t = lane; t < np * 3; t += kWave) {
-            const int p = t / 3, e = t - 3 * p;
-            const int xa = max(xs, (px_lo + p) * dx), xb = min(xe, (px_lo + p + 1) * dx);
-            float m0 = 0.0f, m1_ = 0.0f, m2_ = 0.0f, m3 = 0.0f;
-            for (int xx = xa; xx < xb; ++xx) {
-                const float q = qb[(xx - xs) * 3 + e];
-                const float4 b = bxw[xx - xs];
-                m0 = fmaf(b.x, q, m0);
-                m1_ = fmaf(b.y, q, m1_);
-                m2_ = fmaf(b.z, q, m2_);
-                m3 = fmaf(b.w, q, m3);
-            }
-            cm[(p * 4 + 0) * 3 + e] = m0;
-            cm[(p * 4 + 1) * 3 + e] = m1_;
-            cm[(p * 4 + 2) * 3 + e] = m2_;
-            cm[(p * 4 + 3) * 3 + e] = m3;
-        }
-        wave_sync();
-        // ... node sums R1[n][e] = sum_l M[n - l][l][e], then the 16 (y, z) node weights
-        int py, pz;
+        // ... then the scatter to the control points (eq 17), first contracted
+        // over the z-nodes into the wave's group (flushed when y or the FFD
+        // z-cell changes)
+        const float fu = (float)cur.uf;
         float byv[4], bzv[4];
-        row_ffd_weights(fw_y, fw_z, fp_y, fp_z, y, z, lane, py, pz, byv, bzv);
-        for (int t = lane; t < nn * 3; t += kWave) {
-            const int n = t / 3, e = t - 3 * n;
-            float r1 = 0.0f;
 #pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                const int p = n - l;
-                if (p >= 0 && p < np) r1 += cm[(p * 4 + l) * 3 + e];
-            }
-            if (r1 != 0.0f) {
-                const int gx = px_lo + n - it.gx0;
+        for (int j = 0; j < 4; ++j) {
+            byv[j] = bcast(fu, j);
+            bzv[j] = bcast(fu, 4 + j);
+        }
+        const int py = bcast(cur.c, 0), pz = bcast(cur.c, 1);
+        if (gpz >= 0 && (y != gyr || pz != gpz)) {
+            flush();
+            gpz = -1;
+        }
+        if (gpz < 0) {
+            gyr = y;
+            gpy = py;
+            gpz = pz;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) gby[b] = byv[b];
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl)
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int gy = py + b - it.gy0, gz = pz + c - it.gz0;
-                        atomicAdd(&G[((gz * it.gny + gy) * it.gnx + gx) * 3 + e], (double)(r1 * (byv[b] * bzv[c])));
-                    }
-            }
+                    for (int e = 0; e < 3; ++e) Q[sl][c][e] = 0.0f;
         }
-        wave_sync();
+#pragma unroll
+        for (int sl = 0; sl < kSlots; ++sl)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const float q = gs[sl] * cur.dm[sl][e] * ratio[e];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) Q[sl][c][e] = fmaf(bzv[c], q, Q[sl][c][e]);
+            }
+        cur = nxt;
     }
     if (DISP != 0) return;
+    if (gpz >= 0) flush();
     __syncthreads();
+    // the item's node block to the global accumulators, one (gz, gy) row of
+    // nodes per wave at a time
     const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
-    for (int i = threadIdx.x; i < nG; i += blockDim.x) {
-        const double val = G[i];
-        if (val != 0.0) {
-            const int e = i % 3, c = i / 3;
-            const int gx = c % it.gnx, gy = (c / it.gnx) % it.gny, gz = c / (it.gnx * it.gny);
-            const size_t node = ((size_t)(gz + it.gz0) * g.nc[1] + (gy + it.gy0)) * g.nc[0] + (gx + it.gx0);
-            unsafeAtomicAdd(&grad[e * ncell + node], val);
+    for (int r = wave; r < it.gny * it.gnz; r += nwaves) {
+        const int gy = r % it.gny, gz = r / it.gny;
+        const size_t node0 = ((size_t)(gz + it.gz0) * g.nc[1] + (gy + it.gy0)) * g.nc[0] + it.gx0;
+        const double *src = G + (size_t)r * it.gnx * 3;
+        for (int t = lane; t < it.gnx * 3; t += kWave) {
+            const double val = src[t];
+            if (val != 0.0) {
+                const int gx = t / 3, e = t - 3 * gx;
+                unsafeAtomicAdd(&grad[e * ncell + node0 + gx], val);
+            }
         }
     }
 }
-
 hipError_t launch_grad(const Geom *geoms, int fdt, int role, int dense, const WorkItem *items, int nitems,
                        const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s, int bw)
 {
