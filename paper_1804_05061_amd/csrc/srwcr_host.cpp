@@ -481,6 +481,13 @@ int srwcr_plan_create_tuned(const srwcr_problem *prob, const srwcr_tuning *tunin
                 }
             }
         }
+        // the largest boxes first: the hardware hands boxes to the compute units
+        // in launch order, so the small ones fill the tail
+        {
+            auto rows = [](const WorkItem &w) { return (long)(w.y1 - w.y0) * (w.z1 - w.z0) * (w.x1 - w.x0); };
+            std::stable_sort(items.begin(), items.end(),
+                             [&](const WorkItem &a, const WorkItem &c) { return rows(a) > rows(c); });
+        }
         P->nitems = (int)items.size();
         P->items_host = items;
         // value-pass blocks: an x-chunk by one spatial cell in y and z (or two, see above)
