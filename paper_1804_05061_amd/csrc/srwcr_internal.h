@@ -21,6 +21,7 @@ constexpr int kRowEntry = 20;     // floats per row-table entry: 15 used, padded
 constexpr int kMaxNodeSeg = 68;   // FFD x-nodes one 64-voxel row segment can touch (delta >= 1)
 constexpr int kSlots = 2;         // voxels per lane: an item row holds up to 2 x 64 voxels
 constexpr int kMaxBatch = 32;     // problems of one batched launch
+constexpr int kXcds = 8;          // accelerator complex dies of an MI355X, each with its own L2
 
 // One unit of work of the value and gradient passes: a box of fixed voxels
 // inside one spatial-bin cell along y and z and at most two cells along x, so

@@ -482,7 +482,12 @@ k_prep(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, cons
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nzero; i += (long)gridDim.x * blockDim.x)
         zero[i] = 0.0;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const long r = (long)blockIdx.x * (kValueThreads / kWave) + wave;
+    // workgroups are dealt to the 8 XCDs in turn; give each XCD a contiguous
+    // run of rows, so that the moving-image rows that neighbouring output rows
+    // share are fetched into one L2 (the grid is a multiple of kXcds)
+    const long per = gridDim.x / kXcds;
+    const long wg = (long)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    const long r = wg * (kValueThreads / kWave) + wave;
     if (r >= row_start[nblocks]) return;
     int lo = 0, hi = nblocks - 1;                       // block of row r: row_start[lo] <= r < row_start[lo + 1]
     while (lo < hi) {
@@ -539,7 +544,8 @@ hipError_t launch_prep(const Geom *geoms, int mdt, int dense, int with_grad, con
                        size_t lds_bytes, hipStream_t s, double *zero, long nzero)
 {
     if (nblocks <= 0 || nrows <= 0) return nzero > 0 ? launch_zero(zero, (size_t)nzero, s) : hipSuccess;
-    const int nwg = (int)((nrows + kValueThreads / kWave - 1) / (kValueThreads / kWave));
+    int nwg = (int)((nrows + kValueThreads / kWave - 1) / (kValueThreads / kWave));
+    nwg = (nwg + kXcds - 1) / kXcds * kXcds;
 #define SRWCR_PREP_M(M)                                                                                      \
     if (mdt == M) {                                                                                          \
         if (dense) { if (with_grad) SRWCR_PREP(M, 1, 1); else SRWCR_PREP(M, 1, 0); }                         \
