@@ -168,6 +168,7 @@ struct srwcr_plan {
     std::vector<int> wrow_host;
     int nwblocks = 0;
     int value_bw = 4;                    // (y, z) regions per axis of a value block: 4 (one cell) or 5 (two)
+    bool cols = false;                   // value pass per block column on the matrix cores (launch_value_cols)
     // staged value pass (when the staging slots fit): per workgroup its first
     // block-visit id; per region the visits that hold it (CSR: reg_start, ent =
     // visit * 80 + local region); waves per region of the merge
@@ -524,7 +525,10 @@ int srwcr_plan_create_tuned(const srwcr_problem *prob, const srwcr_tuning *tunin
             he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
             if (he != hipSuccess) { st = hip_fail(he, "hipDeviceGetAttribute(compute units)"); goto bad; }
             P->nwg = std::max(1, std::min(tune.value_workgroups > 0 ? tune.value_workgroups : ncu, vr.back()));
-            {
+            // blocks of two small cells per axis: the column value pass (FP64
+            // atomics into the moments, no staging)
+            P->cols = P->value_bw == 5;
+            if (!P->cols) {
                 const StagePlan sp = stage_plan(vb, vr, P->nwg, {&g}, P->value_bw);
                 const size_t nreg = (size_t)kXN * P->value_bw * P->value_bw;
                 const size_t stage_bytes = sp.visits * nreg * g.nb * 3 * sizeof(double);
@@ -707,9 +711,13 @@ static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, int 
     prof_mark(P, 2, s);
     const int nreg = kXN * P->value_bw * P->value_bw;
     const long stride = (long)nreg * g.nb * 3;
-    HIP_TRY(launch_value(P->geom_dev, g.fdt, P->vblocks, P->vrow, P->nvblocks, P->nwg, args, ws, P->value_lds, s,
-                         P->staged ? (double *)(ws + P->staging_off) : nullptr, P->visit_start, stride, P->value_bw),
-            "value launch");
+    if (P->cols)
+        HIP_TRY(launch_value_cols(P->geom_dev, g.fdt, P->vblocks, P->nvblocks, args, ws, s), "value launch");
+    else
+        HIP_TRY(launch_value(P->geom_dev, g.fdt, P->vblocks, P->vrow, P->nvblocks, P->nwg, args, ws, P->value_lds, s,
+                             P->staged ? (double *)(ws + P->staging_off) : nullptr, P->visit_start, stride,
+                             P->value_bw),
+                "value launch");
     prof_mark(P, 3, s);                     // the merge is timed with the finalisation
     if (P->staged)
         HIP_TRY(launch_merge(P->geom_dev, (const double *)(ws + P->staging_off), stride, nreg, P->reg_start, P->ent,
@@ -825,10 +833,13 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
             "warp launch");
     const int nreg = kXN * plan->value_bw * plan->value_bw;
     const long stride = (long)nreg * g.nb * 3;
-    HIP_TRY(launch_value(plan->geom_dev, g.fdt, plan->vblocks, plan->vrow, plan->nvblocks, plan->nwg, args, ws,
-                         plan->value_lds, s, plan->staged ? (double *)(ws + plan->staging_off) : nullptr,
-                         plan->visit_start, stride, plan->value_bw),
-            "value launch");
+    if (plan->cols)
+        HIP_TRY(launch_value_cols(plan->geom_dev, g.fdt, plan->vblocks, plan->nvblocks, args, ws, s), "value launch");
+    else
+        HIP_TRY(launch_value(plan->geom_dev, g.fdt, plan->vblocks, plan->vrow, plan->nvblocks, plan->nwg, args, ws,
+                             plan->value_lds, s, plan->staged ? (double *)(ws + plan->staging_off) : nullptr,
+                             plan->visit_start, stride, plan->value_bw),
+                "value launch");
     if (plan->staged)
         HIP_TRY(launch_merge(plan->geom_dev, (const double *)(ws + plan->staging_off), stride, nreg, plan->reg_start,
                              plan->ent, nullptr, g.R, g.nb, plan->merge_waves, ws, s),

@@ -894,6 +894,186 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
     }
 }
 
+// Value pass for region blocks of small spatial cells (two cells along each
+// axis, 5 x 5 x 5 regions, e.g. the regions at the FFD nodes), where rows
+// along x are a few voxels long.  One wave per block; a lane owns a column
+// (x, y) of the block and sums over its z voxels, for a window of four A-bins,
+// Acc[w][m][k] = sum_z h_w(A) m_m(B) wz_k(z) (eqs 3, 5, 7) in registers.
+// What is left of the block's sums is a dense product over the columns,
+//   H[(i, j)][(w, m, k)] += sum_col wx_i(x) wy_j(y) Acc_col[w][m][k],
+// which runs on the matrix cores (v_mfma_f32_16x16x4f32, four columns per
+// step) from the columns' Acc and weights staged in LDS; the block's sums go
+// to the global moments with FP64 atomics once per window.
+constexpr int kColWaves = 2;                 // waves (blocks) per workgroup
+constexpr int kColN = 4 * 3 * 5;             // (w, m, k) sums of a window: 60 of 64 slots
+constexpr int kColAccFloats = 64 * 64;       // per wave: [column][64] window sums
+constexpr int kColWxyFloats = 64 * 32;       // per wave: [column][32] (x, y) node weights (25 used)
+
+size_t value_cols_lds_bytes() { return (size_t)kColWaves * (kColAccFloats + kColWxyFloats) * sizeof(float); }
+
+// Rotated LDS slots: the writes (one column per lane) and the MFMA operand
+// reads (16 consecutive entries of four columns) both touch 64 distinct banks.
+__device__ __forceinline__ int col_acc_slot(int col, int n) { return col * 64 + ((n + 16 * (col & 3) + (col >> 2)) & 63); }
+__device__ __forceinline__ int col_wxy_slot(int col, int m) { return col * 32 + ((m + 8 * (col & 3)) & 31); }
+
+// One voxel of the value pass: its A-bin, the two Parzen tap weights and the
+// moments m1, m2 of B (as in k_value).
+template <int FDT>
+__device__ __forceinline__ void value_voxel(const PrepKT *__restrict__ kt, const void *__restrict__ fixed, size_t v,
+                                            int L, int role, int &kA, float &a0, float &a1, float &m1, float &m2)
+{
+    const PrepKT pk = kt[v];
+    const float sf = ld_int<FDT>(fixed, v);
+    int kF;
+    float tF, m0w, m1w, f0w, f1w;
+    const int kM = pk.k;
+    parzen_w(pk.t, m0w, m1w);
+    parzen(sf, L, kF, tF, f0w, f1w);
+    const int kB = role ? kM : kF;
+    const float b1w = role ? m1w : f1w;
+    kA = role ? kF : kM;
+    a0 = role ? f0w : m0w;
+    a1 = role ? f1w : m1w;
+    m1 = (float)kB + b1w;
+    m2 = fmaf((float)(2 * kB + 1), b1w, (float)(kB * kB));
+}
+
+template <int FDT>
+__global__ void __launch_bounds__(kColWaves * kWave)
+k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, int nblocks, BatchArgs args,
+             unsigned char *ws)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int bi = blockIdx.x * kColWaves + wave;
+    if (bi >= nblocks) return;
+    float *accl = reinterpret_cast<float *>(smem) + wave * (kColAccFloats + kColWxyFloats);
+    float *wxyl = accl + kColAccFloats;
+    const WorkItem it = blocks[bi];
+    const Geom &g = geoms[it.prob];
+    const void *__restrict__ fixed = args.p[it.prob].fixed;
+    const PrepKT *__restrict__ kt = reinterpret_cast<const PrepKT *>(ws + g.ws.kt);
+    double *__restrict__ moments = reinterpret_cast<double *>(ws + g.ws.moments);
+    const float4 *spw_x = g.sp_w[0], *spw_y = g.sp_w[1], *spw_z = g.sp_w[2];
+    const int *spc_x = g.sp_cell[0], *spc_y = g.sp_cell[1], *spc_z = g.sp_cell[2];
+    const int nb = g.nb, L = nb - 1, role = g.role;
+    const int nfx = g.nf[0], nfy = g.nf[1];
+    const int nx = it.x1 - it.x0, ncol = nx * (it.y1 - it.y0);
+
+    // the A-bins the block's taps touch
+    unsigned long long mine = 0ull;
+    for (int c0 = 0; c0 < ncol; c0 += kWave) {
+        const int col = c0 + lane;
+        if (col >= ncol) continue;
+        const int x = it.x0 + col % nx, y = it.y0 + col / nx;
+        for (int z = it.z0; z < it.z1; ++z) {
+            int kA;
+            float a0, a1, m1, m2;
+            value_voxel<FDT>(kt, fixed, ((size_t)z * nfy + y) * nfx + x, L, role, kA, a0, a1, m1, m2);
+            mine |= 3ull << kA;
+        }
+    }
+    unsigned long long bins = (unsigned long long)wave_or_dpp((unsigned)(mine >> 32)) << 32 | wave_or_dpp((unsigned)mine);
+
+    const int l16 = lane & 15, kq = lane >> 4;
+    while (bins != 0ull) {
+        int b[kWin];
+#pragma unroll
+        for (int w = 0; w < kWin; ++w) {
+            b[w] = bins ? (int)__builtin_ctzll(bins) : 1 << 20;
+            bins &= bins - 1;
+        }
+        f4 D[2][4];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) D[mt][nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int c0 = 0; c0 < ncol; c0 += kWave) {
+            const int col = c0 + lane;
+            float acc[kColN];
+#pragma unroll
+            for (int n = 0; n < kColN; ++n) acc[n] = 0.0f;
+            float wx5[kXN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, wy5[kXN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            if (col < ncol) {
+                const int x = it.x0 + col % nx, y = it.y0 + col / nx;
+                x_node_weights(gld(spw_x, x), gld(spc_x, x) != it.cx, wx5);
+                x_node_weights(gld(spw_y, y), gld(spc_y, y) != it.cy, wy5);
+                for (int z = it.z0; z < it.z1; ++z) {
+                    int kA;
+                    float a0, a1, m1, m2;
+                    value_voxel<FDT>(kt, fixed, ((size_t)z * nfy + y) * nfx + x, L, role, kA, a0, a1, m1, m2);
+                    float wz5[kXN];
+                    x_node_weights(gld(spw_z, z), gld(spc_z, z) != it.cz, wz5);
+#pragma unroll
+                    for (int w = 0; w < kWin; ++w) {
+                        const float t = kA == b[w] ? a0 : (kA + 1 == b[w] ? a1 : 0.0f);
+                        const float tm[3] = {t, t * m1, t * m2};
+#pragma unroll
+                        for (int m = 0; m < 3; ++m)
+#pragma unroll
+                            for (int k = 0; k < kXN; ++k)
+                                acc[(w * 3 + m) * kXN + k] = fmaf(tm[m], wz5[k], acc[(w * 3 + m) * kXN + k]);
+                    }
+                }
+            }
+            // this lane's column to LDS (zeros for a lane past the block's columns)
+#pragma unroll
+            for (int n = 0; n < 64; ++n) accl[col_acc_slot(lane, n)] = n < kColN ? acc[n] : 0.0f;
+#pragma unroll
+            for (int m = 0; m < 32; ++m) wxyl[col_wxy_slot(lane, m)] = m < kXN * kXN ? wx5[m / kXN] * wy5[m % kXN] : 0.0f;
+            wave_sync();
+            // D[(i, j)][(w, m, k)] += sum over this chunk's columns, four per step:
+            // A[r][q] = weight (i, j) = 16 mt + r of column 4 s + q, B[q][c] =
+            // sum 16 nt + c of that column (lane r + 16 q / c + 16 q)
+            const int steps = (min(kWave, ncol - c0) + 3) >> 2;
+            for (int s = 0; s < steps; ++s) {
+                const int cq = 4 * s + kq;
+                const float A0 = wxyl[col_wxy_slot(cq, l16)], A1 = wxyl[col_wxy_slot(cq, 16 + l16)];
+                float B[4];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) B[nt] = accl[col_acc_slot(cq, 16 * nt + l16)];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    D[0][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A0, B[nt], D[0][nt], 0, 0, 0);
+                    D[1][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A1, B[nt], D[1][nt], 0, 0, 0);
+                }
+            }
+            wave_sync();
+        }
+        // the window's block sums to the global moments: D[mt][nt][r] holds
+        // (i, j) = 16 mt + 4 kq + r, (w, m, k) = 16 nt + l16
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ij = 16 * mt + 4 * kq + r, n = 16 * nt + l16;
+                    const float val = D[mt][nt][r];
+                    if (ij >= kXN * kXN || n >= kColN || val == 0.0f) continue;
+                    const int i = ij / kXN, j = ij - kXN * i, w = n / 15, m = (n - 15 * w) / kXN, k = n % kXN;
+                    const int a = w == 0 ? b[0] : (w == 1 ? b[1] : (w == 2 ? b[2] : b[3]));
+                    if (a > L || it.cx + i >= g.K[0] || it.cy + j >= g.K[1] || it.cz + k >= g.K[2]) continue;
+                    const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
+                    unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], (double)val);
+                }
+    }
+}
+
+hipError_t launch_value_cols(const Geom *geoms, int fdt, const WorkItem *blocks, int nblocks, const BatchArgs &args,
+                             unsigned char *ws, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    const int nwg = (nblocks + kColWaves - 1) / kColWaves;
+    const size_t lds = value_cols_lds_bytes();
+    if (fdt == 0) hipLaunchKernelGGL(k_value_cols<0>, dim3(nwg), dim3(kColWaves * kWave), lds, s, geoms, blocks, nblocks, args, ws);
+    else if (fdt == 1) hipLaunchKernelGGL(k_value_cols<1>, dim3(nwg), dim3(kColWaves * kWave), lds, s, geoms, blocks, nblocks, args, ws);
+    else hipLaunchKernelGGL(k_value_cols<2>, dim3(nwg), dim3(kColWaves * kWave), lds, s, geoms, blocks, nblocks, args, ws);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------- finalisation
 // Called by one whole wave for region r of g, lane = intensity bin a holding
 // the bin's moments (P, S1, S2) (zeros for a >= nb):
