@@ -143,6 +143,19 @@ StagePlan stage_plan(const std::vector<WorkItem> &vb, const std::vector<int> &vr
 }
 
 constexpr size_t kStageLimit = (size_t)512 << 20;   // staging slots above this: atomic merge
+constexpr int kColUnit = 128;                        // columns of a work unit of the column value pass
+
+// Work units of the column value pass over a list of value blocks: runs of up
+// to kColUnit columns of one block (x, y), columns numbered x fastest.
+std::vector<int4> column_units(const std::vector<WorkItem> &vb)
+{
+    std::vector<int4> cu;
+    for (size_t b = 0; b < vb.size(); ++b) {
+        const int ncol = (vb[b].x1 - vb[b].x0) * (vb[b].y1 - vb[b].y0);
+        for (int c = 0; c < ncol; c += kColUnit) cu.push_back(make_int4((int)b, c, std::min(ncol, c + kColUnit), 0));
+    }
+    return cu;
+}
 
 }  // namespace
 
@@ -169,6 +182,8 @@ struct srwcr_plan {
     int nwblocks = 0;
     int value_bw = 4;                    // (y, z) regions per axis of a value block: 4 (one cell) or 5 (two)
     bool cols = false;                   // value pass per block column on the matrix cores (launch_value_cols)
+    const int4 *cunits = nullptr;        // its work units (value block, first column, end column)
+    int ncunits = 0;
     // staged value pass (when the staging slots fit): per workgroup its first
     // block-visit id; per region the visits that hold it (CSR: reg_start, ent =
     // visit * 80 + local region); waves per region of the merge
@@ -525,10 +540,16 @@ int srwcr_plan_create_tuned(const srwcr_problem *prob, const srwcr_tuning *tunin
             he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
             if (he != hipSuccess) { st = hip_fail(he, "hipDeviceGetAttribute(compute units)"); goto bad; }
             P->nwg = std::max(1, std::min(tune.value_workgroups > 0 ? tune.value_workgroups : ncu, vr.back()));
-            // blocks of two small cells per axis: the column value pass (FP64
-            // atomics into the moments, no staging)
+            // blocks of two small cells per axis (short rows): the column value
+            // pass (FP64 atomics into the moments, no staging); for one-cell
+            // blocks, whose rows are long, the row value pass
             P->cols = P->value_bw == 5;
-            if (!P->cols) {
+            if (P->cols) {
+                const std::vector<int4> cu = column_units(vb);
+                if ((st = upload(cu.data(), cu.size() * sizeof(int4), &dv))) goto bad;
+                P->cunits = (const int4 *)dv;
+                P->ncunits = (int)cu.size();
+            } else {
                 const StagePlan sp = stage_plan(vb, vr, P->nwg, {&g}, P->value_bw);
                 const size_t nreg = (size_t)kXN * P->value_bw * P->value_bw;
                 const size_t stage_bytes = sp.visits * nreg * g.nb * 3 * sizeof(double);
@@ -712,7 +733,8 @@ static int run_value(const srwcr_plan *P, const BatchArgs &args, int dense, int 
     const int nreg = kXN * P->value_bw * P->value_bw;
     const long stride = (long)nreg * g.nb * 3;
     if (P->cols)
-        HIP_TRY(launch_value_cols(P->geom_dev, g.fdt, P->vblocks, P->nvblocks, args, ws, s), "value launch");
+        HIP_TRY(launch_value_cols(P->geom_dev, g.fdt, P->vblocks, P->cunits, P->ncunits, args, ws, s, P->value_bw),
+                "value launch");
     else
         HIP_TRY(launch_value(P->geom_dev, g.fdt, P->vblocks, P->vrow, P->nvblocks, P->nwg, args, ws, P->value_lds, s,
                              P->staged ? (double *)(ws + P->staging_off) : nullptr, P->visit_start, stride,
@@ -834,7 +856,9 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
     const int nreg = kXN * plan->value_bw * plan->value_bw;
     const long stride = (long)nreg * g.nb * 3;
     if (plan->cols)
-        HIP_TRY(launch_value_cols(plan->geom_dev, g.fdt, plan->vblocks, plan->nvblocks, args, ws, s), "value launch");
+        HIP_TRY(launch_value_cols(plan->geom_dev, g.fdt, plan->vblocks, plan->cunits, plan->ncunits, args, ws, s,
+                                  plan->value_bw),
+                "value launch");
     else
         HIP_TRY(launch_value(plan->geom_dev, g.fdt, plan->vblocks, plan->vrow, plan->nvblocks, plan->nwg, args, ws,
                              plan->value_lds, s, plan->staged ? (double *)(ws + plan->staging_off) : nullptr,
@@ -936,6 +960,8 @@ struct srwcr_batch {
     int2 *reg_id = nullptr;
     int nregions = 0, max_nb = 0, merge_waves = 1;
     int bw = 4, nreg = kXN * 16;                 // value-block shape (see srwcr_plan::value_bw)
+    int4 *cunits_dev = nullptr;                  // column value pass (bw = 5), see srwcr_plan::cols
+    int ncunits = 0;
     long stage_stride = 0;
     size_t staging_off = 0;
 };
@@ -945,6 +971,7 @@ void srwcr_batch_destroy(srwcr_batch *b)
     if (!b) return;
     if (b->geoms_dev) (void)hipFree(b->geoms_dev);
     if (b->items_dev) (void)hipFree(b->items_dev);
+    if (b->cunits_dev) (void)hipFree(b->cunits_dev);
     if (b->vblocks_dev) (void)hipFree(b->vblocks_dev);
     if (b->vrow_dev) (void)hipFree(b->vrow_dev);
     for (void *p : {(void *)b->visit_start, (void *)b->reg_start, (void *)b->ent, (void *)b->reg_id})
@@ -1048,14 +1075,21 @@ int srwcr_batch_create(int32_t n, const srwcr_plan *const *plans, srwcr_batch **
     if (e == hipSuccess) e = hipMalloc(&b->vrow_dev, vr.size() * sizeof(int));
     if (e == hipSuccess) e = hipMemcpy(b->vrow_dev, vr.data(), vr.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        // staged value pass over all problems' blocks, when its slots fit
-        std::vector<const Geom *> gp(n);
-        for (int p = 0; p < n; ++p) {
-            gp[p] = &plans[p]->g;
-            b->max_nb = std::max(b->max_nb, plans[p]->g.nb);
-        }
+        for (int p = 0; p < n; ++p) b->max_nb = std::max(b->max_nb, plans[p]->g.nb);
         b->bw = plans[0]->value_bw;
         b->nreg = kXN * b->bw * b->bw;
+        if (b->bw == 5) {
+            // the single plans' column value pass, over all problems' blocks
+            const std::vector<int4> cu = column_units(vb);
+            b->ncunits = (int)cu.size();
+            e = hipMalloc(&b->cunits_dev, cu.size() * sizeof(int4));
+            if (e == hipSuccess) e = hipMemcpy(b->cunits_dev, cu.data(), cu.size() * sizeof(int4), hipMemcpyHostToDevice);
+        }
+    }
+    if (e == hipSuccess && b->bw != 5) {
+        // staged value pass over all problems' blocks, when its slots fit
+        std::vector<const Geom *> gp(n);
+        for (int p = 0; p < n; ++p) gp[p] = &plans[p]->g;
         const StagePlan sp = stage_plan(vb, vr, b->nwg, gp, b->bw);
         b->stage_stride = (long)b->nreg * b->max_nb * 3;
         const size_t stage_bytes = sp.visits * (size_t)b->stage_stride * sizeof(double);
@@ -1109,9 +1143,13 @@ int srwcr_grad_batched(const srwcr_batch *b, const srwcr_batch_item *items, void
                         b->prep_lds, s),
             "warp launch");
     double *staging = b->staged ? (double *)(ws + b->staging_off) : nullptr;
-    HIP_TRY(launch_value(b->geoms_dev, b->fdt, b->vblocks_dev, b->vrow_dev, b->nvblocks, b->nwg, args, ws,
-                         b->value_lds, s, staging, b->visit_start, b->stage_stride, b->bw),
-            "value launch");
+    if (b->bw == 5)
+        HIP_TRY(launch_value_cols(b->geoms_dev, b->fdt, b->vblocks_dev, b->cunits_dev, b->ncunits, args, ws, s, b->bw),
+                "value launch");
+    else
+        HIP_TRY(launch_value(b->geoms_dev, b->fdt, b->vblocks_dev, b->vrow_dev, b->nvblocks, b->nwg, args, ws,
+                             b->value_lds, s, staging, b->visit_start, b->stage_stride, b->bw),
+                "value launch");
     if (b->staged)
         HIP_TRY(launch_merge(b->geoms_dev, staging, b->stage_stride, b->nreg, b->reg_start, b->ent, b->reg_id,
                              b->nregions,

@@ -158,11 +158,12 @@ hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *blocks, cons
                         int nwg, const BatchArgs &args, unsigned char *ws, size_t lds_bytes, hipStream_t s,
                         double *staging = nullptr, const int *visit_start = nullptr, long stage_stride = 0,
                         int bw = 4);
-// Value pass for blocks of 5 x 5 x 5 regions with short rows (small spatial
-// cells): one wave per block, column sums on the matrix cores, FP64 atomics
-// into the global moments (which must start at zero).
-hipError_t launch_value_cols(const Geom *geoms, int fdt, const WorkItem *blocks, int nblocks, const BatchArgs &args,
-                             unsigned char *ws, hipStream_t s);
+// Value pass by block columns: units[u] = (value block, first column, end
+// column) with columns (x, y) of the block numbered x fastest; one wave per
+// unit, column sums on the matrix cores, FP64 atomics into the global moments
+// (which must start at zero).  bw: the blocks' (y, z) regions per axis.
+hipError_t launch_value_cols(const Geom *geoms, int fdt, const WorkItem *blocks, const int4 *units, int nunits,
+                             const BatchArgs &args, unsigned char *ws, hipStream_t s, int bw);
 size_t value_cols_lds_bytes();
 // reg_id: (problem, region) per merged region, or null for regions 0 .. n - 1
 // of problem 0.  Also finalises each region (results, gradient tables).

@@ -894,20 +894,20 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
     }
 }
 
-// Value pass for region blocks of small spatial cells (two cells along each
-// axis, 5 x 5 x 5 regions, e.g. the regions at the FFD nodes), where rows
-// along x are a few voxels long.  One wave per block; a lane owns a column
-// (x, y) of the block and sums over its z voxels, for a window of four A-bins,
-// Acc[w][m][k] = sum_z h_w(A) m_m(B) wz_k(z) (eqs 3, 5, 7) in registers.
-// What is left of the block's sums is a dense product over the columns,
+// Value pass by block columns.  A work unit is a range of columns (x, y) of
+// one region block (an x-chunk of at most two spatial cells by BW = 4 (one
+// cell) or BW = 5 (two cells) regions along y and z); one wave per unit.  A
+// lane owns a column and sums over its z voxels, for a window of four A-bins,
+// Acc[w][m][k] = sum_z h_w(A) m_m(B) wz_k(z) (eqs 3, 5, 7) in registers -- the
+// z weights are wave-uniform.  What is left of the block's sums is a dense
+// product over the columns,
 //   H[(i, j)][(w, m, k)] += sum_col wx_i(x) wy_j(y) Acc_col[w][m][k],
 // which runs on the matrix cores (v_mfma_f32_16x16x4f32, four columns per
-// step) from the columns' Acc and weights staged in LDS; the block's sums go
+// step) from the columns' Acc and weights staged in LDS; the unit's sums go
 // to the global moments with FP64 atomics once per window.
-constexpr int kColWaves = 2;                 // waves (blocks) per workgroup
-constexpr int kColN = 4 * 3 * 5;             // (w, m, k) sums of a window: 60 of 64 slots
+constexpr int kColWaves = 2;                 // waves (units) per workgroup
 constexpr int kColAccFloats = 64 * 64;       // per wave: [column][64] window sums
-constexpr int kColWxyFloats = 64 * 32;       // per wave: [column][32] (x, y) node weights (25 used)
+constexpr int kColWxyFloats = 64 * 32;       // per wave: [column][32] (x, y) node weights
 
 size_t value_cols_lds_bytes() { return (size_t)kColWaves * (kColAccFloats + kColWxyFloats) * sizeof(float); }
 
@@ -938,20 +938,40 @@ __device__ __forceinline__ void value_voxel(const PrepKT *__restrict__ kt, const
     m2 = fmaf((float)(2 * kB + 1), b1w, (float)(kB * kB));
 }
 
-template <int FDT>
+// A coordinate's spatial weights on the block's BW nodes along y or z: its
+// four B-spline weights, shifted by one node when it lies in the block's
+// second cell (BW = 5).
+template <int BW>
+__device__ __forceinline__ void block_node_weights(const float4 &w, bool o1, float (&wn)[BW])
+{
+    if constexpr (BW == 5) {
+        x_node_weights(w, o1, wn);
+    } else {
+        wn[0] = w.x;
+        wn[1] = w.y;
+        wn[2] = w.z;
+        wn[3] = w.w;
+    }
+}
+
+template <int FDT, int BW>
 __global__ void __launch_bounds__(kColWaves * kWave)
-k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, int nblocks, BatchArgs args,
-             unsigned char *ws)
+k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, const int4 *__restrict__ units,
+             int nunits, BatchArgs args, unsigned char *ws)
 {
     typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr int NIJ = kXN * BW;            // (x, y) nodes of a block: 20 or 25 (two 16-row tiles)
+    constexpr int NN = kWin * 3 * BW;        // (w, m, k) sums of a window: 48 or 60
+    constexpr int NT = (NN + 15) / 16;       // 16-column tiles of them
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int bi = blockIdx.x * kColWaves + wave;
-    if (bi >= nblocks) return;
+    const int ui = blockIdx.x * kColWaves + wave;
+    if (ui >= nunits) return;
     float *accl = reinterpret_cast<float *>(smem) + wave * (kColAccFloats + kColWxyFloats);
     float *wxyl = accl + kColAccFloats;
-    const WorkItem it = blocks[bi];
+    const int4 un = units[ui];                                   // (block, first column, end column)
+    const WorkItem it = blocks[un.x];
     const Geom &g = geoms[it.prob];
     const void *__restrict__ fixed = args.p[it.prob].fixed;
     const PrepKT *__restrict__ kt = reinterpret_cast<const PrepKT *>(ws + g.ws.kt);
@@ -960,13 +980,13 @@ k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks
     const int *spc_x = g.sp_cell[0], *spc_y = g.sp_cell[1], *spc_z = g.sp_cell[2];
     const int nb = g.nb, L = nb - 1, role = g.role;
     const int nfx = g.nf[0], nfy = g.nf[1];
-    const int nx = it.x1 - it.x0, ncol = nx * (it.y1 - it.y0);
+    const int nx = it.x1 - it.x0;
 
-    // the A-bins the block's taps touch
+    // the A-bins the unit's taps touch
     unsigned long long mine = 0ull;
-    for (int c0 = 0; c0 < ncol; c0 += kWave) {
+    for (int c0 = un.y; c0 < un.z; c0 += kWave) {
         const int col = c0 + lane;
-        if (col >= ncol) continue;
+        if (col >= un.z) continue;
         const int x = it.x0 + col % nx, y = it.y0 + col / nx;
         for (int z = it.z0; z < it.z1; ++z) {
             int kA;
@@ -985,27 +1005,29 @@ k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks
             b[w] = bins ? (int)__builtin_ctzll(bins) : 1 << 20;
             bins &= bins - 1;
         }
-        f4 D[2][4];
+        f4 D[2][NT];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) D[mt][nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int c0 = 0; c0 < ncol; c0 += kWave) {
+            for (int nt = 0; nt < NT; ++nt) D[mt][nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int c0 = un.y; c0 < un.z; c0 += kWave) {
             const int col = c0 + lane;
-            float acc[kColN];
+            float acc[NN];
 #pragma unroll
-            for (int n = 0; n < kColN; ++n) acc[n] = 0.0f;
-            float wx5[kXN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, wy5[kXN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            if (col < ncol) {
+            for (int n = 0; n < NN; ++n) acc[n] = 0.0f;
+            float wx5[kXN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, wy[BW];
+#pragma unroll
+            for (int j = 0; j < BW; ++j) wy[j] = 0.0f;
+            if (col < un.z) {
                 const int x = it.x0 + col % nx, y = it.y0 + col / nx;
                 x_node_weights(gld(spw_x, x), gld(spc_x, x) != it.cx, wx5);
-                x_node_weights(gld(spw_y, y), gld(spc_y, y) != it.cy, wy5);
+                block_node_weights<BW>(gld(spw_y, y), gld(spc_y, y) != it.cy, wy);
                 for (int z = it.z0; z < it.z1; ++z) {
                     int kA;
                     float a0, a1, m1, m2;
                     value_voxel<FDT>(kt, fixed, ((size_t)z * nfy + y) * nfx + x, L, role, kA, a0, a1, m1, m2);
-                    float wz5[kXN];
-                    x_node_weights(gld(spw_z, z), gld(spc_z, z) != it.cz, wz5);
+                    float wz[BW];
+                    block_node_weights<BW>(gld(spw_z, z), gld(spc_z, z) != it.cz, wz);
 #pragma unroll
                     for (int w = 0; w < kWin; ++w) {
                         const float t = kA == b[w] ? a0 : (kA + 1 == b[w] ? a1 : 0.0f);
@@ -1013,47 +1035,47 @@ k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks
 #pragma unroll
                         for (int m = 0; m < 3; ++m)
 #pragma unroll
-                            for (int k = 0; k < kXN; ++k)
-                                acc[(w * 3 + m) * kXN + k] = fmaf(tm[m], wz5[k], acc[(w * 3 + m) * kXN + k]);
+                            for (int k = 0; k < BW; ++k)
+                                acc[(w * 3 + m) * BW + k] = fmaf(tm[m], wz[k], acc[(w * 3 + m) * BW + k]);
                     }
                 }
             }
-            // this lane's column to LDS (zeros for a lane past the block's columns)
+            // this lane's column to LDS (zeros for a lane past the unit's columns)
 #pragma unroll
-            for (int n = 0; n < 64; ++n) accl[col_acc_slot(lane, n)] = n < kColN ? acc[n] : 0.0f;
+            for (int n = 0; n < 64; ++n) accl[col_acc_slot(lane, n)] = n < NN ? acc[n] : 0.0f;
 #pragma unroll
-            for (int m = 0; m < 32; ++m) wxyl[col_wxy_slot(lane, m)] = m < kXN * kXN ? wx5[m / kXN] * wy5[m % kXN] : 0.0f;
+            for (int m = 0; m < 32; ++m) wxyl[col_wxy_slot(lane, m)] = m < NIJ ? wx5[m / BW] * wy[m % BW] : 0.0f;
             wave_sync();
             // D[(i, j)][(w, m, k)] += sum over this chunk's columns, four per step:
             // A[r][q] = weight (i, j) = 16 mt + r of column 4 s + q, B[q][c] =
             // sum 16 nt + c of that column (lane r + 16 q / c + 16 q)
-            const int steps = (min(kWave, ncol - c0) + 3) >> 2;
+            const int steps = (min(kWave, un.z - c0) + 3) >> 2;
             for (int s = 0; s < steps; ++s) {
                 const int cq = 4 * s + kq;
                 const float A0 = wxyl[col_wxy_slot(cq, l16)], A1 = wxyl[col_wxy_slot(cq, 16 + l16)];
-                float B[4];
+                float B[NT];
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt) B[nt] = accl[col_acc_slot(cq, 16 * nt + l16)];
+                for (int nt = 0; nt < NT; ++nt) B[nt] = accl[col_acc_slot(cq, 16 * nt + l16)];
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt) {
+                for (int nt = 0; nt < NT; ++nt) {
                     D[0][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A0, B[nt], D[0][nt], 0, 0, 0);
                     D[1][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A1, B[nt], D[1][nt], 0, 0, 0);
                 }
             }
             wave_sync();
         }
-        // the window's block sums to the global moments: D[mt][nt][r] holds
+        // the window's sums to the global moments: D[mt][nt][r] holds
         // (i, j) = 16 mt + 4 kq + r, (w, m, k) = 16 nt + l16
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
+            for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int ij = 16 * mt + 4 * kq + r, n = 16 * nt + l16;
                     const float val = D[mt][nt][r];
-                    if (ij >= kXN * kXN || n >= kColN || val == 0.0f) continue;
-                    const int i = ij / kXN, j = ij - kXN * i, w = n / 15, m = (n - 15 * w) / kXN, k = n % kXN;
+                    if (ij >= NIJ || n >= NN || val == 0.0f) continue;
+                    const int i = ij / BW, j = ij - BW * i, w = n / (3 * BW), m = (n - 3 * BW * w) / BW, k = n % BW;
                     const int a = w == 0 ? b[0] : (w == 1 ? b[1] : (w == 2 ? b[2] : b[3]));
                     if (a > L || it.cx + i >= g.K[0] || it.cy + j >= g.K[1] || it.cz + k >= g.K[2]) continue;
                     const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
@@ -1062,15 +1084,18 @@ k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks
     }
 }
 
-hipError_t launch_value_cols(const Geom *geoms, int fdt, const WorkItem *blocks, int nblocks, const BatchArgs &args,
-                             unsigned char *ws, hipStream_t s)
+hipError_t launch_value_cols(const Geom *geoms, int fdt, const WorkItem *blocks, const int4 *units, int nunits,
+                             const BatchArgs &args, unsigned char *ws, hipStream_t s, int bw)
 {
-    if (nblocks <= 0) return hipSuccess;
-    const int nwg = (nblocks + kColWaves - 1) / kColWaves;
+    if (nunits <= 0) return hipSuccess;
+    const int nwg = (nunits + kColWaves - 1) / kColWaves;
     const size_t lds = value_cols_lds_bytes();
-    if (fdt == 0) hipLaunchKernelGGL(k_value_cols<0>, dim3(nwg), dim3(kColWaves * kWave), lds, s, geoms, blocks, nblocks, args, ws);
-    else if (fdt == 1) hipLaunchKernelGGL(k_value_cols<1>, dim3(nwg), dim3(kColWaves * kWave), lds, s, geoms, blocks, nblocks, args, ws);
-    else hipLaunchKernelGGL(k_value_cols<2>, dim3(nwg), dim3(kColWaves * kWave), lds, s, geoms, blocks, nblocks, args, ws);
+#define SRWCR_COLS(F, W) \
+    if (fdt == F && bw == W) \
+        hipLaunchKernelGGL((k_value_cols<F, W>), dim3(nwg), dim3(kColWaves * kWave), lds, s, geoms, blocks, units, \
+                           nunits, args, ws);
+    SRWCR_COLS(0, 4) SRWCR_COLS(1, 4) SRWCR_COLS(2, 4) SRWCR_COLS(0, 5) SRWCR_COLS(1, 5) SRWCR_COLS(2, 5)
+#undef SRWCR_COLS
     return hipGetLastError();
 }
 
