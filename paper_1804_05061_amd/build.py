@@ -1,39 +1,88 @@
-"""Build libsrwcr.so in-tree for gfx950 with hipcc (no JIT, no torch extension)."""
+"""Build libsrwcr.so in-tree for gfx950 with hipcc (no JIT, no torch extension).
+
+Each HIP source is compiled in two steps: its device code alone, for gfx950,
+with packed FP32 (v_pk_*_f32) turned off -- some of those instructions have
+been seen to give wrong results on gfx950 -- then its host code alone,
+embedding that device code object.  The target feature is a gfx950 one; kept
+out of the host (x86) pass, it leaves the build log free of "not a
+recognized feature" lines.  C++ sources are compiled as usual, and all
+objects are linked into one shared library.  device_assembly() gives the
+gfx950 assembly of a source as built here (a CPU test checks it for packed
+FP32 instructions).
+"""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["csrc/srwcr_kernels.hip", "csrc/srwcr_host.cpp", "csrc/srwcr_lbfgs.cpp", "csrc/srwcr_noalloc.hip"]
-HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+ARCH = "gfx950"
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc"),
+          "-Wno-unused-command-line-argument"]
+DEVICE_FLAGS = [
+    "--offload-arch=" + ARCH, "--cuda-device-only",
     "-munsafe-fp-atomics",                       # native FP64 atomics in LDS and L2
-    # No packed FP32 (v_pk_*_f32) in the device code: some of its forms have
-    # been seen to give wrong results on gfx950.  hipcc's host (x86) pass prints
-    # "'-packed-fp32-ops' is not a recognized feature for this target" once per
-    # source; the gfx950 pass honours the flag (its code objects hold no
-    # v_pk_*_f32 with it, hundreds without).
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-command-line-argument",
 ]
+HOST_FLAGS = ["--offload-arch=" + ARCH, "--cuda-host-only", "-munsafe-fp-atomics"]
+PACKED_FP32 = ("v_pk_fma_f32", "v_pk_mul_f32", "v_pk_add_f32")
 
 
-def build(verbose: bool = False) -> str:
-    out = os.path.join(HERE, "libsrwcr.so")
-    tmp = out + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc"),
-           "-o", tmp, *[os.path.join(HERE, s) for s in SOURCES]]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libsrwcr.so")
-    os.replace(tmp, out)
+        raise RuntimeError("hipcc failed: " + " ".join(cmd[:3]) + " ...")
+    return r.stdout + r.stderr
+
+
+def _object(src: str, tmp: str, verbose: bool) -> str:
+    path = os.path.join(HERE, src)
+    stem = os.path.join(tmp, os.path.basename(src))
+    obj = stem + ".o"
+    if src.endswith(".hip"):
+        dev = stem + ".hipfb"
+        _run(["hipcc", *COMMON, *DEVICE_FLAGS, "-c", "-o", dev, path], verbose)
+        _run(["hipcc", *COMMON, *HOST_FLAGS, "-Xclang", "-fcuda-include-gpubinary", "-Xclang", dev, "-c", "-o", obj,
+              path], verbose)
+    else:
+        _run(["hipcc", *COMMON, "-c", "-o", obj, path], verbose)
+    return obj
+
+
+def device_assembly(src: str = "csrc/srwcr_kernels.hip") -> str:
+    """gfx950 assembly of one HIP source, compiled with the library's device flags."""
+    with tempfile.TemporaryDirectory() as tmp:
+        out = os.path.join(tmp, "k.s")
+        _run(["hipcc", *COMMON, *DEVICE_FLAGS, "-S", "-o", out, os.path.join(HERE, src)], False)
+        with open(out) as fh:
+            return fh.read()
+
+
+def build(verbose: bool = False) -> str:
+    out = os.path.join(HERE, "libsrwcr.so")
+    with tempfile.TemporaryDirectory() as tmp:
+        with ThreadPoolExecutor(len(SOURCES)) as ex:
+            objs = list(ex.map(lambda s: _object(s, tmp, verbose), SOURCES))
+        lib = os.path.join(tmp, "libsrwcr.so")
+        _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", lib, *objs], verbose)
+        _copy(lib, out)
     return out
+
+
+def _copy(src: str, dst: str) -> None:
+    tmp = dst + ".tmp"
+    with open(src, "rb") as fi, open(tmp, "wb") as fo:
+        fo.write(fi.read())
+    os.chmod(tmp, 0o755)
+    os.replace(tmp, dst)
 
 
 if __name__ == "__main__":
