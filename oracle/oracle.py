@@ -19,17 +19,23 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "srwcr_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liborc.so")
+# ORC_LIB names another build of the oracle (the sanitizer build of the
+# tests); by default the one next to this file.
+_LIB_PATH = os.environ.get("ORC_LIB") or os.path.join(_HERE, "liborc.so")
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no fast-math, no FP contraction)."""
-    if force or not os.path.exists(_LIB_PATH):
-        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+def build(force: bool = True, out: str = None, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, no FP contraction);
+    sanitize: with AddressSanitizer and UndefinedBehaviorSanitizer, into `out`."""
+    out = out or _LIB_PATH
+    if force or not os.path.exists(out):
+        san = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined"] \
+            if sanitize else []
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", *san,
+               "-o", out + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
-    return _LIB_PATH
+        os.replace(out + ".tmp", out)
+    return out
 
 
 class _Problem(ctypes.Structure):

@@ -5,7 +5,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsrwcr.so")
+# SRWCR_LIB names another build of the same library (the host-sanitizer
+# build of the tests); by default the in-tree one.
+LIB_PATH = os.environ.get("SRWCR_LIB") or os.path.join(_HERE, "libsrwcr.so")
 
 SRWCR_OK = 0
 STATUS_NAMES = {0: "SRWCR_OK", -1: "SRWCR_E_INVALID_ARG", -2: "SRWCR_E_DEGENERATE", -3: "SRWCR_E_WORKSPACE",

@@ -77,6 +77,43 @@ def build(verbose: bool = False) -> str:
     return out
 
 
+def build_host_asan(out: str, verbose: bool = False) -> str:
+    """The library with its host code under AddressSanitizer (device code as
+    in build()), into `out`, for CPU tests of the host logic; load it with the
+    clang ASan runtime preloaded (asan_runtime())."""
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+    with tempfile.TemporaryDirectory() as tmp:
+        def obj(src):
+            path = os.path.join(HERE, src)
+            stem = os.path.join(tmp, os.path.basename(src))
+            o = stem + ".o"
+            if src.endswith(".hip"):
+                dev = stem + ".hipfb"
+                _run(["hipcc", *COMMON, *DEVICE_FLAGS, "-c", "-o", dev, path], verbose)
+                _run(["hipcc", *COMMON, *HOST_FLAGS, *san, "-Xclang", "-fcuda-include-gpubinary", "-Xclang", dev,
+                      "-c", "-o", o, path], verbose)
+            else:
+                _run(["hipcc", *COMMON, *san, "-c", "-o", o, path], verbose)
+            return o
+        with ThreadPoolExecutor(len(SOURCES)) as ex:
+            objs = list(ex.map(obj, SOURCES))
+        lib = os.path.join(tmp, "libsrwcr_asan.so")
+        _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", lib, *objs], verbose)
+        _copy(lib, out)
+    return out
+
+
+def asan_runtime() -> str:
+    """The clang AddressSanitizer runtime of this toolchain (for LD_PRELOAD)."""
+    r = subprocess.run(["hipcc", "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        import glob
+        found = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+        path = found[-1] if found else ""
+    return path
+
+
 def _copy(src: str, dst: str) -> None:
     tmp = dst + ".tmp"
     with open(src, "rb") as fi, open(tmp, "wb") as fo:
