@@ -329,6 +329,18 @@ int srwcr_debug_moments(const srwcr_plan *plan, const void *fixed, const void *m
 int srwcr_debug_samples(const srwcr_plan *plan, const void *moving, const float *ffd, int32_t *d_bin,
                         float *d_frac, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Diagnostic of the bounds-checked debug build (a library compiled with
+ * SRWCR_CHECK, see build.py): its kernels range-check the computed indices of
+ * their scatters, atomics and voxel reads, skip an access that falls outside
+ * its array and record the failed check as a bit of a device-wide word
+ * (bit 0: warp-pass voxel, 1: value-pass block region, 2: moment slot, 3:
+ * gradient-table slot, 4: gradient scratch, 5: node block, 6: gradient
+ * accumulator, 7: gradient-pass voxel, 8: column value-pass voxel).
+ * Synchronises the device, writes the word to *flags (host int32) and, if
+ * `reset`, clears it.  Returns SRWCR_E_UNSUPPORTED in the normal build,
+ * SRWCR_E_INVALID_ARG for a NULL flags. */
+int srwcr_debug_check_flags(int32_t *flags, int32_t reset);
+
 /* Launch geometry of a plan: number of work items and LDS bytes per workgroup
  * of the value and gradient passes.  Any output pointer may be NULL. */
 int srwcr_plan_info(const srwcr_plan *plan, int32_t *n_items, int32_t *value_lds, int32_t *grad_lds);

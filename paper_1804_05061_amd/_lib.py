@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "SRWCR_OK", -1: "SRWCR_E_INVALID_ARG", -2: "SRWCR_E_DEGENERAT
 EXPORTED = ["srwcr_ctrl_dims", "srwcr_plan_create", "srwcr_plan_destroy", "srwcr_workspace_bytes",
             "srwcr_normalize", "srwcr_minmax", "srwcr_eval", "srwcr_grad", "ffd_warp",
             "srwcr_grad_noalloc", "srwcr_lbfgs_default_opts", "register_lbfgs", "srwcr_debug_moments", "srwcr_debug_samples",
-            "srwcr_plan_info",
+            "srwcr_plan_info", "srwcr_debug_check_flags",
             "srwcr_profile", "srwcr_profile_read", "srwcr_refine_ffd", "srwcr_bending_energy", "srwcr_lbfgs_minimize",
             "srwcr_eval_dense", "srwcr_grad_dense", "srwcr_batch_create", "srwcr_batch_destroy", "srwcr_batch_workspace_bytes", "srwcr_grad_batched",
             "raptor_patches_create", "raptor_patches_destroy", "raptor_workspace_bytes", "raptor_eval",
@@ -93,6 +93,7 @@ def load() -> ctypes.CDLL:
         "srwcr_eval": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, sz, vp]),
         "srwcr_grad": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "srwcr_grad_noalloc": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "srwcr_debug_check_flags": (ctypes.c_int, [ctypes.POINTER(i32), i32]),
         "ffd_warp": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "srwcr_lbfgs_default_opts": (None, [ctypes.POINTER(SrwcrLbfgsOpts)]),
         "register_lbfgs": (ctypes.c_int, [pp, vp, vp, vp, ctypes.POINTER(SrwcrLbfgsOpts),

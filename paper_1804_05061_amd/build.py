@@ -43,17 +43,18 @@ def _run(cmd, verbose):
     return r.stdout + r.stderr
 
 
-def _object(src: str, tmp: str, verbose: bool) -> str:
+def _object(src: str, tmp: str, verbose: bool, check: bool = False) -> str:
     path = os.path.join(HERE, src)
     stem = os.path.join(tmp, os.path.basename(src))
     obj = stem + ".o"
+    extra = ["-DSRWCR_CHECK"] if check else []
     if src.endswith(".hip"):
         dev = stem + ".hipfb"
-        _run(["hipcc", *COMMON, *DEVICE_FLAGS, "-c", "-o", dev, path], verbose)
-        _run(["hipcc", *COMMON, *HOST_FLAGS, "-Xclang", "-fcuda-include-gpubinary", "-Xclang", dev, "-c", "-o", obj,
-              path], verbose)
+        _run(["hipcc", *COMMON, *extra, *DEVICE_FLAGS, "-c", "-o", dev, path], verbose)
+        _run(["hipcc", *COMMON, *extra, *HOST_FLAGS, "-Xclang", "-fcuda-include-gpubinary", "-Xclang", dev, "-c",
+              "-o", obj, path], verbose)
     else:
-        _run(["hipcc", *COMMON, "-c", "-o", obj, path], verbose)
+        _run(["hipcc", *COMMON, *extra, "-c", "-o", obj, path], verbose)
     return obj
 
 
@@ -66,11 +67,13 @@ def device_assembly(src: str = "csrc/srwcr_kernels.hip") -> str:
             return fh.read()
 
 
-def build(verbose: bool = False) -> str:
-    out = os.path.join(HERE, "libsrwcr.so")
+def build(verbose: bool = False, check: bool = False) -> str:
+    """libsrwcr.so; check: the bounds-checked debug build (-DSRWCR_CHECK, see
+    srwcr_debug_check_flags) as libsrwcr_check.so beside it."""
+    out = os.path.join(HERE, "libsrwcr_check.so" if check else "libsrwcr.so")
     with tempfile.TemporaryDirectory() as tmp:
         with ThreadPoolExecutor(len(SOURCES)) as ex:
-            objs = list(ex.map(lambda s: _object(s, tmp, verbose), SOURCES))
+            objs = list(ex.map(lambda s: _object(s, tmp, verbose, check), SOURCES))
         lib = os.path.join(tmp, "libsrwcr.so")
         _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", lib, *objs], verbose)
         _copy(lib, out)

@@ -40,6 +40,7 @@
 // z-node, the per-cell moments along x and adds them to the four y-nodes
 // with FP64 LDS atomics; the box's node block is merged globally once.  A
 // dense field's gradient is q itself.
+#include "srwcr.h"
 #include "srwcr_internal.h"
 
 #include <hip/hip_bf16.h>
@@ -60,6 +61,31 @@ __device__ __forceinline__ float ld_int(const void *p, size_t i)
         return __uint_as_float(((unsigned)b) << 16);
     }
 }
+
+// Bounds checks of the debug build (SRWCR_CHECK): a computed index outside
+// its array sets bit `bit` of g_check_flags (read by srwcr_debug_check_flags)
+// and the access is skipped; in the normal build the checks compile away.
+#ifdef SRWCR_CHECK
+__device__ unsigned g_check_flags;
+__device__ __forceinline__ bool check_ok(bool c, int bit)
+{
+    if (!c) atomicOr(&g_check_flags, 1u << bit);
+    return c;
+}
+#else
+__device__ __forceinline__ constexpr bool check_ok(bool, int) { return true; }
+#endif
+enum CheckBit {
+    kChkPrepVoxel = 0,     // warp pass: voxel index < nvox
+    kChkHistJK = 1,        // value pass: (y, z) region offset inside the block
+    kChkMoments = 2,       // moment slot < R nb 3
+    kChkTabJK = 3,         // gradient pass: table (y, z) slot < JKS
+    kChkScratch = 4,       // gradient pass: per-wave scratch of the row range fits
+    kChkNodeBlock = 5,     // gradient pass: node block index < nG
+    kChkGrad = 6,          // gradient accumulator < 3 n_c
+    kChkGradVoxel = 7,     // gradient pass: voxel index < nvox
+    kChkColVoxel = 8,      // column value pass: voxel index < nvox
+};
 
 // Read of a per-axis table through a global-address-space pointer.  The
 // tables are reached through generic pointers held in Geom, which the
@@ -517,7 +543,7 @@ k_prep(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, cons
 #pragma unroll
         for (int sl = 0; sl < kSlots; ++sl) {
             const int x = xs + sl * kWave + lane;
-            if (x < xe) {
+            if (x < xe && check_ok(rowb + x < nv, kChkPrepVoxel)) {
                 double u[3], dm[3];
                 if (DISP == 0) ffd_u(g, c1, px_lo, x, u);
                 else dense_u(g, ffd, x, y, z, u);
@@ -651,7 +677,7 @@ __device__ __forceinline__ void value_window(double *H, int L, const int (&b)[kW
     if (lane < kWin * 15 && T != 0.0f) {
         const int w = lane / 15, q = lane - 15 * w, i = q / 3, m = q - 3 * i;
         const int a = w == 0 ? b[0] : (w == 1 ? b[1] : (w == 2 ? b[2] : b[3]));
-        if (a <= L) {
+        if (a <= L && check_ok(oyz + 3 * BW + 3 < BW * BW, kChkHistJK)) {
             double *h = H + ((a * 3 + m) * kXN + i) * Hist<BW>::kHS + oyz;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
@@ -701,7 +727,7 @@ __device__ __forceinline__ void value_window2(double *H, int L, int b0, int b1, 
     if (idx < 30 && T != 0.0f) {
         const int w = idx / 15, q = idx - 15 * w, i = q / 3, m = q - 3 * i;
         const int a = w == 0 ? b0 : b1;
-        if (a <= L) {
+        if (a <= L && check_ok(oyz + 3 * BW + 3 < BW * BW, kChkHistJK)) {
             double *h = H + ((a * 3 + m) * kXN + i) * Hist<BW>::kHS + oyz + 2 * BW * odd;
 #pragma unroll
             for (int kk = 0; kk < 2; ++kk)
@@ -882,7 +908,8 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
                     const int k = jk / BW, j = jk - k * BW;
                     if (jk < JK && it.cx + i < g.K[0] && it.cy + j < g.K[1] && it.cz + k < g.K[2]) {
                         const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
-                        unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], val);
+                        if (check_ok(R < g.R && a < nb, kChkMoments))
+                            unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], val);
                     }
                 }
             }
@@ -980,6 +1007,7 @@ k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks
     const int *spc_x = g.sp_cell[0], *spc_y = g.sp_cell[1], *spc_z = g.sp_cell[2];
     const int nb = g.nb, L = nb - 1, role = g.role;
     const int nfx = g.nf[0], nfy = g.nf[1];
+    const size_t nvox = (size_t)nfx * nfy * g.nf[2];
     const int nx = it.x1 - it.x0;
 
     // the A-bins the unit's taps touch
@@ -989,9 +1017,11 @@ k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks
         if (col >= un.z) continue;
         const int x = it.x0 + col % nx, y = it.y0 + col / nx;
         for (int z = it.z0; z < it.z1; ++z) {
+            const size_t v = ((size_t)z * nfy + y) * nfx + x;
+            if (!check_ok(v < nvox, kChkColVoxel)) continue;
             int kA;
             float a0, a1, m1, m2;
-            value_voxel<FDT>(kt, fixed, ((size_t)z * nfy + y) * nfx + x, L, role, kA, a0, a1, m1, m2);
+            value_voxel<FDT>(kt, fixed, v, L, role, kA, a0, a1, m1, m2);
             mine |= 3ull << kA;
         }
     }
@@ -1023,9 +1053,11 @@ k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks
                 x_node_weights(gld(spw_x, x), gld(spc_x, x) != it.cx, wx5);
                 block_node_weights<BW>(gld(spw_y, y), gld(spc_y, y) != it.cy, wy);
                 for (int z = it.z0; z < it.z1; ++z) {
+                    const size_t v = ((size_t)z * nfy + y) * nfx + x;
+                    if (!check_ok(v < nvox, kChkColVoxel)) continue;
                     int kA;
                     float a0, a1, m1, m2;
-                    value_voxel<FDT>(kt, fixed, ((size_t)z * nfy + y) * nfx + x, L, role, kA, a0, a1, m1, m2);
+                    value_voxel<FDT>(kt, fixed, v, L, role, kA, a0, a1, m1, m2);
                     float wz[BW];
                     block_node_weights<BW>(gld(spw_z, z), gld(spc_z, z) != it.cz, wz);
 #pragma unroll
@@ -1079,7 +1111,8 @@ k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks
                     const int a = w == 0 ? b[0] : (w == 1 ? b[1] : (w == 2 ? b[2] : b[3]));
                     if (a > L || it.cx + i >= g.K[0] || it.cy + j >= g.K[1] || it.cz + k >= g.K[2]) continue;
                     const int R = ((it.cz + k) * g.K[1] + (it.cy + j)) * g.K[0] + (it.cx + i);
-                    unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], (double)val);
+                    if (check_ok(R < g.R && a < nb, kChkMoments))
+                        unsafeAtomicAdd(&moments[((size_t)R * nb + a) * 3 + m], (double)val);
                 }
     }
 }
@@ -1395,6 +1428,7 @@ __device__ __forceinline__ void grad_load_row(RowG &in, const RowTabs &tb, const
 {
 #pragma unroll
     for (int sl = 0; sl < kSlots; ++sl) {
+        if (!check_ok(rowb + xc[sl] < nvox, kChkGradVoxel)) continue;
         if constexpr (DISP != 2) {
 #pragma unroll
             for (int e = 0; e < 3; ++e) in.dm[sl][e] = dmi[e * nvox + rowb + xc[sl]];
@@ -1508,7 +1542,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             const int rl = r0 + u * nwaves;
             if (rl >= NR) break;
             const int ii = rl % kXN, jk = rl / kXN;
-            if (lane < nb) {
+            if (lane < nb && check_ok(jk < JKS, kChkTabJK)) {
                 float *tq = tab + ((ii * nb + lane) * 3) * JKS + jk;
                 tq[0] = ok[u] ? t0[u] : 0.0f;
                 tq[JKS] = ok[u] ? t1[u] : 0.0f;
@@ -1536,6 +1570,9 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
         else if (lane == 1) pxc = gld(g.ffd_p[0], xe - 1);
         px_lo = bcast(pxc, 0);
         np = bcast(pxc, 1) - px_lo + 1;
+        if (!check_ok(64 + (kRowBins * kRowEntry > 3 * kSlots * kWave ? kRowBins * kRowEntry : 3 * kSlots * kWave) +
+                          12 * (np + 6) <= g.gscr, kChkScratch))
+            np = 0;
         for (int i = lane; i < 12 * (np + 6); i += kWave) cm[i] = 0.0f;   // pad cells stay zero
     }
     __syncthreads();
@@ -1598,9 +1635,11 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
                 const float *cp = cm + (n + 3) * 12 + e;
                 const float r1 = ((cp[0] + cp[-12 + 3]) + cp[-24 + 6]) + cp[-36 + 9];
                 if (r1 != 0.0f) {
-                    double *gp = G + ((gpz + c - it.gz0) * it.gny + (gpy - it.gy0)) * sy + (px_lo + n - it.gx0) * 3 + e;
+                    const int o = ((gpz + c - it.gz0) * it.gny + (gpy - it.gy0)) * sy + (px_lo + n - it.gx0) * 3 + e;
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) atomicAdd(gp + b * sy, (double)(r1 * gby[b]));
+                    for (int b = 0; b < 4; ++b)
+                        if (check_ok(o >= 0 && o + b * sy < nG, kChkNodeBlock))
+                            atomicAdd(G + o + b * sy, (double)(r1 * gby[b]));
                 }
             }
             wave_sync();
@@ -1819,7 +1858,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             const double val = src[t];
             if (val != 0.0) {
                 const int gx = t / 3, e = t - 3 * gx;
-                unsafeAtomicAdd(&grad[e * ncell + node0 + gx], val);
+                if (check_ok(node0 + gx < ncell, kChkGrad)) unsafeAtomicAdd(&grad[e * ncell + node0 + gx], val);
             }
         }
     }
@@ -2351,3 +2390,25 @@ hipError_t launch_downsample(const float *in, int nx, int ny, int nz, float *out
 }
 
 }  // namespace srwcr
+
+extern "C" int srwcr_debug_check_flags(int32_t *flags, int32_t reset)
+{
+#ifdef SRWCR_CHECK
+    if (!flags) return srwcr::report_error(SRWCR_E_INVALID_ARG, "flags is NULL");
+    unsigned v = 0;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpyFromSymbol(&v, HIP_SYMBOL(srwcr::g_check_flags), sizeof v);
+    if (e == hipSuccess && reset) {
+        const unsigned zero = 0;
+        e = hipMemcpyToSymbol(HIP_SYMBOL(srwcr::g_check_flags), &zero, sizeof zero);
+    }
+    if (e != hipSuccess) return srwcr::report_error(SRWCR_E_HIP, "bounds-check flags: %s", hipGetErrorString(e));
+    *flags = (int32_t)v;
+    return SRWCR_OK;
+#else
+    (void)flags;
+    (void)reset;
+    return srwcr::report_error(SRWCR_E_UNSUPPORTED, "this library was built without SRWCR_CHECK");
+#endif
+}
+
