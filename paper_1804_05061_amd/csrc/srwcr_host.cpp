@@ -184,6 +184,7 @@ struct srwcr_plan {
     bool cols = false;                   // value pass per block column on the matrix cores (launch_value_cols)
     const int4 *cunits = nullptr;        // its work units (value block, first column, end column)
     int ncunits = 0;
+    bool gcols = false;                  // FFD gradient by box columns (launch_grad_cols)
     // staged value pass (when the staging slots fit): per workgroup its first
     // block-visit id; per region the visits that hold it (CSR: reg_start, ent =
     // visit * 80 + local region); waves per region of the merge
@@ -506,6 +507,12 @@ int srwcr_plan_create_tuned(const srwcr_problem *prob, const srwcr_tuning *tunin
         }
         P->nitems = (int)items.size();
         P->items_host = items;
+        // the column gradient pass: boxes of two small cells per axis, the moving
+        // image as A, and boxes small enough for its one-wave layout
+        P->gcols = P->value_bw == 5 && g.role == 0;
+        for (const WorkItem &w : items)
+            P->gcols = P->gcols && (w.x1 - w.x0) * (w.y1 - w.y0) <= 2 * kWave && w.gnx * w.gny <= 32 && w.gnz <= kXN &&
+                       w.z1 - w.z0 <= 12;
         // value-pass blocks: an x-chunk by one spatial cell in y and z (or two, see above)
         {
             std::vector<WorkItem> vb;
@@ -782,9 +789,12 @@ int srwcr_grad(const srwcr_plan *plan, const void *fixed, const void *moving, co
     st = run_value(plan, args, 0, 1, ws, s);
     if (st) return st;
     const Geom &g = plan->g;
-    HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.role, 0, plan->items, plan->nitems, args, ws, plan->grad_lds, s,
-                        g.bw),
-            "gradient launch");
+    if (plan->gcols)
+        HIP_TRY(launch_grad_cols(plan->geom_dev, g.fdt, plan->items, plan->nitems, args, ws, s), "gradient launch");
+    else
+        HIP_TRY(launch_grad(plan->geom_dev, g.fdt, g.role, 0, plan->items, plan->nitems, args, ws, plan->grad_lds, s,
+                            g.bw),
+                "gradient launch");
     prof_mark(plan, 5, s);
     const size_t n = 3 * (size_t)g.nc[0] * g.nc[1] * g.nc[2];
     HIP_TRY(launch_grad_out(plan->geom_dev, 1, n, args, ws, s), "gradient output launch");
@@ -962,6 +972,7 @@ struct srwcr_batch {
     int bw = 4, nreg = kXN * 16;                 // value-block shape (see srwcr_plan::value_bw)
     int4 *cunits_dev = nullptr;                  // column value pass (bw = 5), see srwcr_plan::cols
     int ncunits = 0;
+    bool gcols = false;                          // every plan takes the column gradient pass
     long stage_stride = 0;
     size_t staging_off = 0;
 };
@@ -1050,6 +1061,8 @@ int srwcr_batch_create(int32_t n, const srwcr_plan *const *plans, srwcr_batch **
     auto vox = [](const WorkItem &w) { return (long)(w.x1 - w.x0) * (w.y1 - w.y0) * (w.z1 - w.z0); };
     std::stable_sort(items.begin(), items.end(), [&](const WorkItem &a, const WorkItem &c) { return vox(a) > vox(c); });
     b->nitems = (int)items.size();
+    b->gcols = true;
+    for (int p = 0; p < n; ++p) b->gcols = b->gcols && plans[p]->gcols;
     // value-pass blocks of every problem, one row list
     std::vector<WorkItem> vb;
     std::vector<int> vr(1, 0);
@@ -1156,8 +1169,12 @@ int srwcr_grad_batched(const srwcr_batch *b, const srwcr_batch_item *items, void
                              b->max_nb, b->merge_waves, ws, s),
                 "merge launch");
     HIP_TRY(launch_finalize(b->geoms_dev, n, b->max_regions, args, ws, s, b->staged), "finalize launch");
-    HIP_TRY(launch_grad(b->geoms_dev, b->fdt, b->role, 0, b->items_dev, b->nitems, args, ws, b->grad_lds, s, b->bw),
-            "gradient launch");
+    if (b->gcols)
+        HIP_TRY(launch_grad_cols(b->geoms_dev, b->fdt, b->items_dev, b->nitems, args, ws, s), "gradient launch");
+    else
+        HIP_TRY(launch_grad(b->geoms_dev, b->fdt, b->role, 0, b->items_dev, b->nitems, args, ws, b->grad_lds, s,
+                            b->bw),
+                "gradient launch");
     HIP_TRY(launch_grad_out(b->geoms_dev, n, b->max_params, args, ws, s), "gradient output launch");
     return SRWCR_OK;
 }

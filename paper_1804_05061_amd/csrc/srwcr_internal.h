@@ -165,6 +165,11 @@ hipError_t launch_value(const Geom *geoms, int fdt, const WorkItem *blocks, cons
 hipError_t launch_value_cols(const Geom *geoms, int fdt, const WorkItem *blocks, const int4 *units, int nunits,
                              const BatchArgs &args, unsigned char *ws, hipStream_t s, int bw);
 size_t value_cols_lds_bytes();
+// Gradient pass by box columns (moving image as A, FFD): one wave per box of
+// at most 128 columns (x, y), 5 FFD z-nodes and 32 FFD (x, y) nodes, inside
+// two spatial cells per axis; FP64 atomics into the gradient accumulators.
+hipError_t launch_grad_cols(const Geom *geoms, int fdt, const WorkItem *items, int nitems, const BatchArgs &args,
+                            unsigned char *ws, hipStream_t s);
 // reg_id: (problem, region) per merged region, or null for regions 0 .. n - 1
 // of problem 0.  Also finalises each region (results, gradient tables).
 hipError_t launch_merge(const Geom *geoms, const double *staging, long stage_stride, int nreg, const int *reg_start,

@@ -1132,6 +1132,282 @@ hipError_t launch_value_cols(const Geom *geoms, int fdt, const WorkItem *blocks,
     return hipGetLastError();
 }
 
+// Gradient pass by box columns for boxes of two small cells per axis (the
+// regions at the FFD nodes), the moving image as A and an FFD.  One wave per
+// box (at most 128 columns (x, y), kGcZ slices, 5 FFD z-nodes and 32 FFD
+// (x, y) nodes).  For a window of four A-bins the box's region tables are
+// contracted over the 25 (x, y) region weights of every column on the matrix
+// cores,
+//   Tc[col][(k, w, c)] = sum_(i, j) wx_i(x) wy_j(y) T[(i, j, k)][b_w][c],
+// then a lane walks its column's voxels whose bin is in the window: the
+// z-contraction gives the interpolated tables C_c (eq 21), dD/ds_M and
+// q = dD/ds_M * dM/dy * dy/dT (eq 16), summed over the FFD z-nodes in
+// registers, Qz[col][(gz, e)] += beta_gz(z) q_e.  Last, the x and y B-spline
+// weights of the FFD (eq 17) are applied on the matrix cores,
+//   G[(gx, gy)][(gz, e)] += sum_col bx_gx(x) by_gy(y) Qz[col][(gz, e)],
+// and added to the global accumulators with FP64 atomics.
+constexpr int kGcWaves = 2;                  // waves (boxes) per workgroup
+constexpr int kGcZ = 12;                     // z slices of a box at most
+// per wave: operands (tables [32][64] + column weights [32][64], then the
+// column sums [64][64] over them) | the chunk's voxels [6][kGcZ][64]
+constexpr int kGcFloats = 64 * 64 + 6 * kGcZ * 64;
+
+size_t grad_cols_lds_bytes() { return (size_t)kGcWaves * kGcFloats * sizeof(float); }
+
+// [row][64] with rows rotated by 16 entries: reads of 16 consecutive entries
+// of four consecutive rows, and writes of one entry per lane, hit distinct banks
+__device__ __forceinline__ int gc_tab_slot(int row, int n) { return row * 64 + ((n + 16 * (row & 3)) & 63); }
+// [column][16] rotated for reads of 16 entries of four consecutive columns
+__device__ __forceinline__ int gc_q_slot(int col, int n) { return col * 16 + ((n + 4 * (col & 3)) & 15); }
+
+template <int FDT>
+__global__ void __launch_bounds__(kGcWaves * kWave)
+k_grad_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, int nitems, BatchArgs args,
+            unsigned char *ws)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int bi = blockIdx.x * kGcWaves + wave;
+    if (bi >= nitems) return;
+    float *U = reinterpret_cast<float *>(smem) + wave * kGcFloats;
+    float *Tw = U, *Wl = U + 32 * 64, *Dc = U;                          // Dc overlays Tw and Wl
+    float *Cv = U + 64 * 64;                                            // [6][kGcZ][64]: k, t, F, dM/dy
+    const WorkItem it = items[bi];
+    const Geom &g = geoms[it.prob];
+    const void *__restrict__ fixed = args.p[it.prob].fixed;
+    const PrepKT *__restrict__ kt = reinterpret_cast<const PrepKT *>(ws + g.ws.kt);
+    const float *__restrict__ dmi = reinterpret_cast<const float *>(ws + g.ws.dm);
+    const float *__restrict__ tables = reinterpret_cast<const float *>(ws + g.ws.tables);
+    double *__restrict__ grad = reinterpret_cast<double *>(ws + g.ws.grad);
+    const int nfx = g.nf[0], nfy = g.nf[1];
+    const size_t nvox = (size_t)nfx * nfy * g.nf[2];
+    const size_t ncell = (size_t)g.nc[0] * g.nc[1] * g.nc[2];
+    const float ratio[3] = {g.ratio[0], g.ratio[1], g.ratio[2]};
+    const int nb = g.nb, L = nb - 1;
+    const int nx = it.x1 - it.x0, ncol = nx * (it.y1 - it.y0), nz = it.z1 - it.z0;   // nz <= kGcZ
+    const int l16 = lane & 15, kq = lane >> 4;
+
+    // the z weights of the box's slices, lane zi holding slice z0 + zi: the
+    // regions' (spatial) and the FFD's, each on the box's 5 z-nodes
+    float wzl[kXN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, bzl[kXN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (lane < nz) {
+        const int z = it.z0 + lane;
+        x_node_weights(gld(g.sp_w[2], z), gld(g.sp_cell[2], z) != it.cz, wzl);
+        const double4 bd = gld(g.ffd_w[2], z);
+        x_node_weights(make_float4((float)bd.x, (float)bd.y, (float)bd.z, (float)bd.w), gld(g.ffd_p[2], z) != it.gz0,
+                       bzl);
+    }
+
+    f4 G2[2] = {f4{0.0f, 0.0f, 0.0f, 0.0f}, f4{0.0f, 0.0f, 0.0f, 0.0f}};
+    for (int c0 = 0; c0 < ncol; c0 += kWave) {
+        const int col = c0 + lane;
+        const bool on = col < ncol;
+        const int x = it.x0 + (on ? col % nx : 0), y = it.y0 + (on ? col / nx : 0);
+        // the column's voxels to LDS, all loads issued together: warped bin and
+        // position, fixed value, dM/dy (bin -1 marks a slice past the box)
+        unsigned long long mine = 0ull;
+#pragma unroll
+        for (int zi = 0; zi < kGcZ; ++zi) {
+            int k = -1;
+            float t = 0.0f, sf = 0.0f, d0 = 0.0f, d1 = 0.0f, d2 = 0.0f;
+            const size_t v = ((size_t)(it.z0 + zi) * nfy + y) * nfx + x;
+            if (on && zi < nz && check_ok(v < nvox, kChkGradVoxel)) {
+                const PrepKT pk = kt[v];
+                k = pk.k;
+                t = pk.t;
+                sf = ld_int<FDT>(fixed, v);
+                d0 = dmi[v];
+                d1 = dmi[nvox + v];
+                d2 = dmi[2 * nvox + v];
+                mine |= 1ull << pk.k;
+            }
+            Cv[(0 * kGcZ + zi) * 64 + lane] = __int_as_float(k);
+            Cv[(1 * kGcZ + zi) * 64 + lane] = t;
+            Cv[(2 * kGcZ + zi) * 64 + lane] = sf;
+            Cv[(3 * kGcZ + zi) * 64 + lane] = d0;
+            Cv[(4 * kGcZ + zi) * 64 + lane] = d1;
+            Cv[(5 * kGcZ + zi) * 64 + lane] = d2;
+        }
+        unsigned long long bins = (unsigned long long)wave_or_dpp((unsigned)(mine >> 32)) << 32 |
+                                  wave_or_dpp((unsigned)mine);
+        float wx5[kXN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, wy5[kXN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (on) {
+            x_node_weights(gld(g.sp_w[0], x), gld(g.sp_cell[0], x) != it.cx, wx5);
+            x_node_weights(gld(g.sp_w[1], y), gld(g.sp_cell[1], y) != it.cy, wy5);
+        }
+        float Qz[kXN][3];
+#pragma unroll
+        for (int k = 0; k < kXN; ++k) Qz[k][0] = Qz[k][1] = Qz[k][2] = 0.0f;
+        while (bins != 0ull) {
+            int b[kWin];
+#pragma unroll
+            for (int w = 0; w < kWin; ++w) {
+                b[w] = bins ? (int)__builtin_ctzll(bins) : 1 << 20;
+                bins &= bins - 1;
+            }
+            // the window's tables: row (i, j) (25 of 32), entry n = lane = (k, w, c)
+            // (60 of 64), every load issued unconditionally (region 0 for an
+            // entry outside the lattice, then zeroed); the columns' region
+            // weights: row (i, j), entry column
+            {
+                const int k = lane / 12, w = (lane % 12) / 3, c = lane % 3;
+                const int a = w == 0 ? b[0] : (w == 1 ? b[1] : (w == 2 ? b[2] : b[3]));
+                const bool okn = lane < 60 && a <= L - 1 && it.cz + k < g.K[2];
+                const int Rk = (it.cz + (okn ? k : 0)) * g.K[1];
+                const size_t ac = (size_t)(okn ? a : 0) * 4 + c;
+#pragma unroll
+                for (int i = 0; i < kXN; ++i) {
+                    float vj[kXN];
+#pragma unroll
+                    for (int j = 0; j < kXN; ++j) {
+                        const bool ok = okn && it.cx + i < g.K[0] && it.cy + j < g.K[1];
+                        const int R = ok ? (Rk + it.cy + j) * g.K[0] + it.cx + i : 0;
+                        vj[j] = tables[(size_t)R * nb * 4 + (ok ? ac : 0)];
+                        vj[j] = ok ? vj[j] : 0.0f;
+                    }
+#pragma unroll
+                    for (int j = 0; j < kXN; ++j) Tw[gc_tab_slot(i * kXN + j, lane)] = vj[j];
+                }
+#pragma unroll
+                for (int ij = kXN * kXN; ij < 32; ++ij) Tw[gc_tab_slot(ij, lane)] = 0.0f;
+            }
+#pragma unroll
+            for (int m = 0; m < 32; ++m)
+                Wl[gc_tab_slot(m, lane)] = m < kXN * kXN ? wx5[m / kXN] * wy5[m % kXN] : 0.0f;
+            wave_sync();
+            // Tc[col][n] = sum_ij Wl[ij][col] Tw[ij][n]: A[r][q] = weight q of column
+            // 16 mt + r, B[q][c] = table entry 16 nt + c of row q (rows 4 s ..)
+            f4 D[4][4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) D[mt][nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s = 0; s < 7; ++s) {
+                float A[4], B[4];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) A[mt] = Wl[gc_tab_slot(4 * s + kq, 16 * mt + l16)];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) B[nt] = Tw[gc_tab_slot(4 * s + kq, 16 * nt + l16)];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+                        D[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[mt], B[nt], D[mt][nt], 0, 0, 0);
+            }
+            wave_sync();                                             // the column sums overwrite the operands
+            // D[mt][nt][r]: column 16 mt + 4 kq + r, entry 16 nt + l16
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Dc[col_acc_slot(16 * mt + 4 * kq + r, 16 * nt + l16)] = D[mt][nt][r];
+            wave_sync();
+            // this lane's voxels whose A-bin is in the window
+            for (int zi = 0; zi < nz; ++zi) {
+                const int kA = __float_as_int(Cv[(0 * kGcZ + zi) * 64 + lane]);
+                const int w = kA == b[0] ? 0 : (kA == b[1] ? 1 : (kA == b[2] ? 2 : (kA == b[3] ? 3 : -1)));
+                float wz[kXN], bz[kXN];
+#pragma unroll
+                for (int k = 0; k < kXN; ++k) {
+                    wz[k] = bcast(wzl[k], zi);
+                    bz[k] = bcast(bzl[k], zi);
+                }
+                if (w < 0) continue;
+                int kF;
+                float tF, f0w, f1w;
+                parzen(Cv[(2 * kGcZ + zi) * 64 + lane], L, kF, tF, f0w, f1w);
+                const float m1 = (float)kF + f1w;
+                float C[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < kXN; ++k) acc = fmaf(wz[k], Dc[col_acc_slot(lane, (k * 4 + w) * 3 + c)], acc);
+                    C[c] = acc;
+                }
+                const float gs = parzen_dw0(Cv[(1 * kGcZ + zi) * 64 + lane]) * fmaf(fmaf(C[0], m1, C[1]), m1, C[2]);
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const float q = gs * Cv[((3 + e) * kGcZ + zi) * 64 + lane] * ratio[e];
+#pragma unroll
+                    for (int k = 0; k < kXN; ++k) Qz[k][e] = fmaf(bz[k], q, Qz[k][e]);
+                }
+            }
+            wave_sync();                                             // the next window restages the operands
+        }
+        // G[(gx, gy)][(gz, e)] += sum_col bx_gx(x) by_gy(y) Qz[col][(gz, e)] for this chunk:
+        // the FFD weights [column][32] (col_wxy_slot) at U, the sums [column][16] after them
+        float *Wg = U, *Qs = U + 64 * 32;
+        {
+            float bx4[4] = {0.0f, 0.0f, 0.0f, 0.0f}, by4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            int ox = 0, oy = 0;
+            if (on) {
+                const double4 bxd = gld(g.ffd_w[0], x), byd = gld(g.ffd_w[1], y);
+                bx4[0] = (float)bxd.x; bx4[1] = (float)bxd.y; bx4[2] = (float)bxd.z; bx4[3] = (float)bxd.w;
+                by4[0] = (float)byd.x; by4[1] = (float)byd.y; by4[2] = (float)byd.z; by4[3] = (float)byd.w;
+                ox = gld(g.ffd_p[0], x) - it.gx0;
+                oy = gld(g.ffd_p[1], y) - it.gy0;
+            }
+            const unsigned rgny = (65536u + it.gny - 1) / it.gny;     // m / gny = (m rgny) >> 16 for m < 32
+#pragma unroll
+            for (int m = 0; m < 32; ++m) {
+                const int gx = (int)(((unsigned)m * rgny) >> 16), gy = m - gx * it.gny;
+                const int lx = gx - ox, ly = gy - oy;
+                float wv = 0.0f;
+                if (m < it.gnx * it.gny && lx >= 0 && lx < 4 && ly >= 0 && ly < 4)
+                    wv = (lx == 0 ? bx4[0] : (lx == 1 ? bx4[1] : (lx == 2 ? bx4[2] : bx4[3]))) *
+                         (ly == 0 ? by4[0] : (ly == 1 ? by4[1] : (ly == 2 ? by4[2] : by4[3])));
+                Wg[col_wxy_slot(lane, m)] = wv;
+            }
+#pragma unroll
+            for (int n = 0; n < 16; ++n) {
+                const int k = n / 3, e = n - 3 * k;
+                Qs[gc_q_slot(lane, n)] = n < 3 * kXN ? Qz[k < kXN ? k : 0][e] : 0.0f;
+            }
+            wave_sync();
+            // A[r][q] = weight of node 16 mt + r for column 4 s + q, B[q][c] = sum c of that column
+            const int steps = (min(kWave, ncol - c0) + 3) >> 2;
+            for (int s = 0; s < steps; ++s) {
+                const int cq = 4 * s + kq;
+                const float A0 = Wg[col_wxy_slot(cq, l16)], A1 = Wg[col_wxy_slot(cq, 16 + l16)];
+                const float B = Qs[gc_q_slot(cq, l16)];
+                G2[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(A0, B, G2[0], 0, 0, 0);
+                G2[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(A1, B, G2[1], 0, 0, 0);
+            }
+            wave_sync();
+        }
+    }
+    // G2[mt][r]: node (gx, gy) = 16 mt + 4 kq + r, entry (gz, e) = l16
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * mt + 4 * kq + r, n = l16;
+            const float val = G2[mt][r];
+            if (m >= it.gnx * it.gny || n >= 3 * it.gnz || val == 0.0f) continue;
+            const int gx = (int)(((unsigned)m * ((65536u + it.gny - 1) / it.gny)) >> 16), gy = m - gx * it.gny;
+            const int gz = n / 3, e = n - 3 * gz;
+            const size_t node = ((size_t)(it.gz0 + gz) * g.nc[1] + (it.gy0 + gy)) * g.nc[0] + (it.gx0 + gx);
+            if (check_ok(node < ncell, kChkGrad)) unsafeAtomicAdd(&grad[e * ncell + node], (double)val);
+        }
+}
+
+hipError_t launch_grad_cols(const Geom *geoms, int fdt, const WorkItem *items, int nitems, const BatchArgs &args,
+                            unsigned char *ws, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    const int nwg = (nitems + kGcWaves - 1) / kGcWaves;
+    const size_t lds = grad_cols_lds_bytes();
+    if (fdt == 0) hipLaunchKernelGGL(k_grad_cols<0>, dim3(nwg), dim3(kGcWaves * kWave), lds, s, geoms, items, nitems, args, ws);
+    else if (fdt == 1) hipLaunchKernelGGL(k_grad_cols<1>, dim3(nwg), dim3(kGcWaves * kWave), lds, s, geoms, items, nitems, args, ws);
+    else hipLaunchKernelGGL(k_grad_cols<2>, dim3(nwg), dim3(kGcWaves * kWave), lds, s, geoms, items, nitems, args, ws);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------- finalisation
 // Called by one whole wave for region r of g, lane = intensity bin a holding
 // the bin's moments (P, S1, S2) (zeros for a >= nb):
