@@ -6,11 +6,13 @@ displacements N(0, 2 vox)): the FFD warp, the joint-moment value pass, the FP64
 finalisation and the gradient pass with its scatter to the control points.
 Inputs are resident in device memory before the timed region starts.
 
-Prints ONE JSON line.  `roofline` covers the dominant kernel, the value
-pass: algorithmic bytes (the fixed and moving volumes read once) over its
+Prints ONE JSON line.  `roofline` covers the dominant kernel (the value
+pass on the 6x6x6-bin workload, the gradient pass with the regions at the
+FFD nodes), named by 10 steps with every phase recorded before the timed
+ones: algorithmic bytes (the fixed and moving volumes read once) over its
 mean duration, timed with one HIP event pair per timed step recorded on the
-launch stream; the per-phase breakdown comes from 10 further steps with every
-phase recorded.  `cpu_baseline`
+launch stream around that pass.  `cold_ms_per_step` is the median of 10 more
+steps with the last-level cache flushed before each.  `cpu_baseline`
 times the FP64 CPU oracle on the whole workload with all host threads (and on
 one core over a z-slab); the same oracle run certifies the measured step:
 `parity` holds the value's relative error and the gradient's relative L2
@@ -39,17 +41,20 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1804_05061_amd", "csrc", "srwcr_kernel
 # the SHA-256 of the kernel source the counters were taken on and by the
 # workload, so the figure is reported as null once the kernels change.
 TRAFFIC = {
-    ("022db896af7cbf4614bb37629e602ec1eb3a8cf1798b7438a87923b8bd5e2e37", "ct256", "srwcr_value_pass", "f32"): {
-        "fetch_bytes": 100942962, "write_bytes": 33300480, "fetch_size_kib": 49310.3, "write_size_kib": 32520.0,
-        "scale_fetch": 1.9991, "scale_write": 1.0, "copy_kernel": "k_normalize, 32 MiB in, 32 MiB out"},
+    ("32cafecbe086cd64795156ad452bf62b1053ef1e85e555a05950be9e51ef5a75", "ct256", "srwcr_value_pass", "f32"): {
+        "fetch_bytes": 100896166, "write_bytes": 33300480, "fetch_size_kib": 49304.0, "write_size_kib": 32520.0,
+        "scale_fetch": 1.9984, "scale_write": 1.0, "copy_kernel": "k_normalize, 32 MiB in, 32 MiB out"},
 }
 
 # Issue counters of the same kernel, from rocprofv3's derived metrics over
 # SQ_ACTIVE_INST_VALU, SQ_LDS_BANK_CONFLICT and GRBM_GUI_ACTIVE (one XCD's
-# cycles), with the same key: the value pass is bound by instruction issue.
+# cycles), with the same key.  `limiter` names what bounds the kernel: the
+# value pass is bound by vector instruction issue (its lane instructions per
+# voxel are SQ_INSTS_VALU x 64 / voxels), not by HBM.
 ISSUE = {
-    ("022db896af7cbf4614bb37629e602ec1eb3a8cf1798b7438a87923b8bd5e2e37", "ct256", "srwcr_value_pass", "f32"): {
-        "VALUBusy": 0.6946, "LDSBankConflict": 0.0234, "valu_insts": 93091136, "lds_insts": 3782578},
+    ("32cafecbe086cd64795156ad452bf62b1053ef1e85e555a05950be9e51ef5a75", "ct256", "srwcr_value_pass", "f32"): {
+        "VALUBusy": 0.6949, "LDSBankConflict": 0.0234, "valu_insts": 93091136, "lds_insts": 3782578,
+        "lane_insts_per_voxel": 710.2, "limiter": "valu-issue"},
 }
 
 
@@ -66,7 +71,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-slices", type=int, default=8, help="z-slices of the one-core oracle sample")
-    ap.add_argument("--cold", action="store_true", help="also time steps with the last-level cache flushed")
+    ap.add_argument("--no-cold", action="store_true",
+                    help="skip the 10 extra steps timed with the last-level cache flushed before each")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--workload", default="ct256", choices=["ct256", "nodes256x99", "breathing4d", "raptor256"],
                     help="ct256: the headline single pair; nodes256x99: the paper's own setting (regions at the "
@@ -123,32 +129,35 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] warm-up done ({args.warmup} steps), plan {plan.info()}", file=sys.stderr, flush=True)
 
-    # the timed steps record one HIP event pair per call, around the value
-    # pass (the dominant kernel); a few more steps with every phase recorded
-    # give the breakdown (events between all kernels would slow the steps)
-    plan.profile(2)
+    # 10 steps with every phase recorded give the breakdown and name the
+    # dominant pass (value or gradient); the timed steps then record one HIP
+    # event pair per call, around that pass only (events between all kernels
+    # would slow the steps)
+    plan.profile(1)
+    for _ in range(10):
+        plan.grad(f, m, ffd, vbuf, gbuf)
+    prof = plan.profile_read()
+    dom_phase = "value" if prof["value"] >= prof["grad"] else "grad"
+    dom = {"value": "srwcr_value_pass", "grad": "srwcr_gradient_pass"}[dom_phase]
+    plan.profile(2 if dom_phase == "value" else 3)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
         plan.grad(f, m, ffd, vbuf, gbuf)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    prof_v = plan.profile_read()
-    plan.profile(1)
-    for _ in range(10):
-        plan.grad(f, m, ffd, vbuf, gbuf)
-    prof = plan.profile_read()
+    prof_d = plan.profile_read()
     plan.profile(0)
     ms_step = 1e3 * elapsed / args.steps
     D = float(vbuf.item())
-    print(f"[bench] {args.steps} steps in {elapsed:.4f}s, D={D:.10f}, value pass {prof_v['value']:.4f} ms total, "
-          f"phases of 10 more steps (ms total)={prof}", file=sys.stderr, flush=True)
+    print(f"[bench] {args.steps} steps in {elapsed:.4f}s, D={D:.10f}, {dom} {prof_d[dom_phase]:.4f} ms total, "
+          f"phases of 10 earlier steps (ms total)={prof}", file=sys.stderr, flush=True)
 
-    # dominant kernel and its roofline (algorithmic bytes: F and M read once per pass)
+    # dominant kernel and its roofline (algorithmic bytes: both passes read F
+    # and the warped M once, b_F + 4 B per fixed voxel)
     bytes_f = {"f32": 4, "f16": 2, "bf16": 2}[args.dtype]
     alg_bytes = bytes_f * (nvox + int(np.prod(w.moving_dims)))
-    dom = "srwcr_value_pass"
-    mean_ms = prof_v["value"] / prof_v["calls"]
+    mean_ms = prof_d[dom_phase] / prof_d["calls"]
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
@@ -161,9 +170,10 @@ def main():
         roofline["traffic"] = rec["fetch_bytes"] + rec["write_bytes"]
         roofline["traffic_detail"] = rec
     roofline["issue"] = ISSUE.get(key)
+    roofline["limiter"] = roofline["issue"]["limiter"] if roofline["issue"] else None
 
     cold = None
-    if args.cold:
+    if not args.no_cold:
         flush = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")   # 512 MiB > last-level cache
         times = []
         for _ in range(10):

@@ -356,9 +356,11 @@ int srwcr_plan_info(const srwcr_plan *plan, int32_t *n_items, int32_t *value_lds
  * recorded.  raptor_grad calls on the plan are recorded too, with the phases
  * zeroing, warp pass, patch sums, patch finalisation, per-voxel derivative,
  * chain rule (gradient pass and output).  enable = 2 records only the two
- * events around the value pass (patch sums for RaPTOR), so that timing it
- * adds one event pair per call; the other phases then read 0.  Read the
- * results before changing the mode.  Not thread-safe: profile one stream and
+ * events around the value pass (patch sums for RaPTOR), enable = 3 only those
+ * around the gradient pass (per-voxel derivative for RaPTOR), so that timing
+ * one pass adds one event pair per call; the other phases then read 0.  Any
+ * other mode is SRWCR_E_INVALID_ARG.  Read the results before changing the
+ * mode.  Not thread-safe: profile one stream and
  * one kind of call at a time. */
 int srwcr_profile(const srwcr_plan *plan, int32_t enable);
 int srwcr_profile_read(const srwcr_plan *plan, double ms[6], int32_t *calls);

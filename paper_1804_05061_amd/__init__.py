@@ -236,7 +236,8 @@ class Plan:
 
     def profile(self, enable):
         """Start per-kernel HIP-event timing of grad() (True or 1: every phase;
-        2: only the value pass, one event pair per call) or stop it (False, 0)."""
+        2: only the value pass, 3: only the gradient pass, one event pair per
+        call) or stop it (False, 0)."""
         _lib.check(_lib.load().srwcr_profile(self._h, int(enable)))
 
     def profile_read(self) -> dict:

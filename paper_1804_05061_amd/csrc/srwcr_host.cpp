@@ -209,12 +209,15 @@ namespace {
 constexpr int kPhases = 6;            // zero, warp, value, finalise, gradient, gradient output
 constexpr size_t kProfCalls = 4096;   // calls recorded per profiling session
 
+// the one phase that modes 2 and 3 time: the value pass, the gradient pass
+inline int prof_phase(int mode) { return mode == 2 ? 2 : 4; }
+
 // record event `k` of the current profiled call (no-op when profiling is off;
-// in mode 2 only the two events around phase 2)
+// in modes 2 and 3 only the two events around that mode's phase)
 void prof_mark(const srwcr_plan *P, int k, hipStream_t s)
 {
     if (!P->profiling) return;
-    if (P->profiling == 2 && k != 2 && k != 3) return;
+    if (P->profiling >= 2 && k != prof_phase(P->profiling) && k != prof_phase(P->profiling) + 1) return;
     const size_t base = (size_t)P->prof_calls * (kPhases + 1);
     if (base + kPhases + 1 > P->ev_pool.size()) return;
     (void)hipEventRecord(P->ev_pool[base + k], s);
@@ -920,7 +923,7 @@ int srwcr_profile(const srwcr_plan *plan, int32_t enable)
         plan->ev_pool.resize(kProfCalls * (kPhases + 1));
         for (auto &e : plan->ev_pool) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
     }
-    if (enable < 0 || enable > 2) return fail(SRWCR_E_INVALID_ARG, "profile mode %d is not 0, 1 or 2", enable);
+    if (enable < 0 || enable > 3) return fail(SRWCR_E_INVALID_ARG, "profile mode %d is not 0, 1, 2 or 3", enable);
     plan->profiling = enable;
     plan->prof_calls = 0;
     return SRWCR_OK;
@@ -932,11 +935,13 @@ int srwcr_profile_read(const srwcr_plan *plan, double ms[6], int32_t *calls)
     for (int k = 0; k < kPhases; ++k) ms[k] = 0.0;
     for (int32_t c = 0; c < plan->prof_calls; ++c) {
         const size_t base = (size_t)c * (kPhases + 1);
-        if (plan->profiling == 2) {
+        if (plan->profiling >= 2) {
+            const int k = prof_phase(plan->profiling);
             float t = 0.0f;
-            HIP_TRY(hipEventSynchronize(plan->ev_pool[base + 3]), "hipEventSynchronize");
-            HIP_TRY(hipEventElapsedTime(&t, plan->ev_pool[base + 2], plan->ev_pool[base + 3]), "hipEventElapsedTime");
-            ms[2] += t;
+            HIP_TRY(hipEventSynchronize(plan->ev_pool[base + k + 1]), "hipEventSynchronize");
+            HIP_TRY(hipEventElapsedTime(&t, plan->ev_pool[base + k], plan->ev_pool[base + k + 1]),
+                    "hipEventElapsedTime");
+            ms[k] += t;
             continue;
         }
         HIP_TRY(hipEventSynchronize(plan->ev_pool[base + kPhases]), "hipEventSynchronize");

@@ -303,3 +303,31 @@ def test_repeated_calls_on_one_workspace(S, orc):
         rel_v, rel_g = abs(D - Dr) / abs(Dr), np.linalg.norm(g - gr) / np.linalg.norm(gr)
         print(f"call {i}: D rel={rel_v:.2e} grad relL2={rel_g:.2e}", flush=True)
         assert rel_v <= VALUE_TOL and rel_g <= GRAD_TOL, (i, rel_v, rel_g)
+
+
+def test_profile_modes(S):
+    """HIP-event timing: mode 1 times every phase, modes 2 and 3 only the
+    value pass and only the gradient pass; a mode outside 0..3 is refused.
+    Timing does not change the results."""
+    w = synth.blobs()
+    nb = 32
+    prob = S.Problem(w.fixed_dims, w.moving_dims, nb, (4, 4, 4), (8, 8, 8), S.MOVING_AS_A)
+    f = S.normalize(dev(w.fixed), float(w.fixed.min()), float(w.fixed.max()), nb)
+    m = S.normalize(dev(w.moving), float(w.moving.min()), float(w.moving.max()), nb)
+    ffd = dev(synth.random_ffd(prob.ctrl_dims, 1.0, 23))
+    plan = S.Plan(prob)
+    D0, g0 = plan.grad(f, m, ffd)
+    for mode, timed in ((1, {"warp", "value", "finalize", "grad", "grad_out"}), (2, {"value"}), (3, {"grad"})):
+        plan.profile(mode)
+        for _ in range(3):
+            D, g = plan.grad(f, m, ffd)
+        r = plan.profile_read()
+        plan.profile(0)
+        print(mode, r, flush=True)
+        assert r["calls"] == 3
+        for k in ("warp", "value", "finalize", "grad", "grad_out"):
+            assert (r[k] > 0) == (k in timed), (mode, k, r)
+        assert float(D.item()) == float(D0.item()) or abs(float(D.item()) - float(D0.item())) <= 1e-12
+        assert torch.allclose(g, g0, rtol=1e-5, atol=1e-9)
+    with pytest.raises(S.SrwcrError, match="INVALID_ARG"):
+        plan.profile(4)
