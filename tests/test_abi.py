@@ -71,3 +71,29 @@ def test_new_entry_points_reject_null_arguments_without_gpu():
     p = S.Problem((64, 64, 64), (64, 64, 64), 32, (0, 4, 4), (5, 5, 5))
     assert L.srwcr_plan_create(ctypes.byref(p.c()), ctypes.byref(h)) == -1
     assert b"spatial_bins" in L.srwcr_last_error()
+
+
+def test_boundary_rejects_bad_arguments_without_gpu():
+    """Argument checks that run before any device work: batches outside 1..32
+    problems or without plans, profiling without a plan, and the srwcr_grad
+    family and the no-alloc entry point without a plan."""
+    from paper_1804_05061_amd import _lib
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    plans = (ctypes.c_void_p * 33)()
+    assert L.srwcr_batch_create(0, plans, ctypes.byref(h)) == -1
+    assert L.srwcr_batch_create(33, plans, ctypes.byref(h)) == -1
+    assert b"outside 1..32" in L.srwcr_last_error()
+    assert L.srwcr_batch_create(1, None, ctypes.byref(h)) == -1
+    assert L.srwcr_batch_create(1, plans, None) == -1
+    assert L.srwcr_batch_create(1, plans, ctypes.byref(h)) == -1          # plans[0] is NULL
+    assert L.srwcr_batch_workspace_bytes(None) == 0
+    assert L.srwcr_grad_batched(None, None, None, 0, None) == -1
+    assert L.srwcr_profile(None, 1) == -1
+    ms = (ctypes.c_double * 6)()
+    assert L.srwcr_profile_read(None, ms, None) == -1
+    assert L.srwcr_eval(None, None, None, None, None, None, 0, None) == -1
+    assert L.srwcr_grad(None, None, None, None, None, None, None, 0, None) == -1
+    assert L.srwcr_grad_dense(None, None, None, None, None, None, None, 0, None) == -1
+    assert L.srwcr_grad_noalloc(None, None, None, None, None, None, None) == -1
+    assert L.srwcr_workspace_bytes(None) == 0
