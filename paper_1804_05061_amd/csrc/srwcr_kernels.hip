@@ -930,13 +930,14 @@ k_value(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks, con
 // product over the columns,
 //   H[(i, j)][(w, m, k)] += sum_col wx_i(x) wy_j(y) Acc_col[w][m][k],
 // which runs on the matrix cores (v_mfma_f32_16x16x4f32, four columns per
-// step) from the columns' Acc and weights staged in LDS; the unit's sums go
-// to the global moments with FP64 atomics once per window.
-constexpr int kColWaves = 2;                 // waves (units) per workgroup
-constexpr int kColAccFloats = 64 * 64;       // per wave: [column][64] window sums
-constexpr int kColWxyFloats = 64 * 32;       // per wave: [column][32] (x, y) node weights
+// step) from the columns' weights and Acc staged in LDS 16 values at a time
+// (the weights become matrix operands in registers); the unit's sums go to
+// the global moments with FP64 atomics once per window.
+constexpr int kColWaves = 4;                 // waves (units) per workgroup
+constexpr int kColRow = 17;                  // LDS floats per column of a staged piece (16 used, odd stride)
+constexpr int kColStage = 64 * kColRow;      // per wave: [column][kColRow]
 
-size_t value_cols_lds_bytes() { return (size_t)kColWaves * (kColAccFloats + kColWxyFloats) * sizeof(float); }
+size_t value_cols_lds_bytes() { return (size_t)kColWaves * kColStage * sizeof(float); }
 
 // Rotated LDS slots: the writes (one column per lane) and the MFMA operand
 // reads (16 consecutive entries of four columns) both touch 64 distinct banks.
@@ -995,8 +996,7 @@ k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ui = blockIdx.x * kColWaves + wave;
     if (ui >= nunits) return;
-    float *accl = reinterpret_cast<float *>(smem) + wave * (kColAccFloats + kColWxyFloats);
-    float *wxyl = accl + kColAccFloats;
+    float *stg = reinterpret_cast<float *>(smem) + wave * kColStage;  // [column][kColRow]
     const int4 un = units[ui];                                   // (block, first column, end column)
     const WorkItem it = blocks[un.x];
     const Geom &g = geoms[it.prob];
@@ -1072,29 +1072,42 @@ k_value_cols(const Geom *__restrict__ geoms, const WorkItem *__restrict__ blocks
                     }
                 }
             }
-            // this lane's column to LDS (zeros for a lane past the unit's columns)
-#pragma unroll
-            for (int n = 0; n < 64; ++n) accl[col_acc_slot(lane, n)] = n < NN ? acc[n] : 0.0f;
-#pragma unroll
-            for (int m = 0; m < 32; ++m) wxyl[col_wxy_slot(lane, m)] = m < NIJ ? wx5[m / BW] * wy[m % BW] : 0.0f;
-            wave_sync();
             // D[(i, j)][(w, m, k)] += sum over this chunk's columns, four per step:
             // A[r][q] = weight (i, j) = 16 mt + r of column 4 s + q, B[q][c] =
-            // sum 16 nt + c of that column (lane r + 16 q / c + 16 q)
+            // sum 16 nt + c of that column (lane r + 16 q / c + 16 q).  Each
+            // 16-value piece of a column (weights, then sums) goes to LDS with
+            // one column per lane (odd row stride: distinct banks); the
+            // weights are read back as the steps' A operands into registers.
+            // A lane past the unit's columns writes zeros.
             const int steps = (min(kWave, un.z - c0) + 3) >> 2;
-            for (int s = 0; s < steps; ++s) {
-                const int cq = 4 * s + kq;
-                const float A0 = wxyl[col_wxy_slot(cq, l16)], A1 = wxyl[col_wxy_slot(cq, 16 + l16)];
-                float B[NT];
+            float aop[2][16];
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) B[nt] = accl[col_acc_slot(cq, 16 * nt + l16)];
+            for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    D[0][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A0, B[nt], D[0][nt], 0, 0, 0);
-                    D[1][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A1, B[nt], D[1][nt], 0, 0, 0);
+                for (int e = 0; e < 16; ++e) {
+                    const int m = 16 * mt + e;
+                    stg[lane * kColRow + e] = m < NIJ ? wx5[m < NIJ ? m / BW : 0] * wy[m % BW] : 0.0f;
                 }
+                wave_sync();
+#pragma unroll
+                for (int st = 0; st < 16; ++st) aop[mt][st] = stg[(4 * st + kq) * kColRow + l16];
+                wave_sync();
             }
-            wave_sync();
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) stg[lane * kColRow + e] = 16 * nt + e < NN ? acc[16 * nt + e] : 0.0f;
+                wave_sync();
+#pragma unroll
+                for (int st = 0; st < 16; ++st) {
+                    if (st < steps) {
+                        const float B = stg[(4 * st + kq) * kColRow + l16];
+                        D[0][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[0][st], B, D[0][nt], 0, 0, 0);
+                        D[1][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[1][st], B, D[1][nt], 0, 0, 0);
+                    }
+                }
+                wave_sync();
+            }
         }
         // the window's sums to the global moments: D[mt][nt][r] holds
         // (i, j) = 16 mt + 4 kq + r, (w, m, k) = 16 nt + l16
