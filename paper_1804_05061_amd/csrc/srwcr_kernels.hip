@@ -1665,9 +1665,26 @@ hipError_t launch_finalize(const Geom *geoms, int nprob, int max_regions, const 
 // LDS copy of the gradient tables: tab[x-node i][bin a][coefficient c][jk],
 // the BW^2 (y, z) regions jk = BW k + j of one (i, a, c) contiguous, so that a
 // row-table entry reads them at fixed offsets (four 16-byte loads when BW =
-// 4).  The stride of 20 (BW = 4) or 28 (BW = 5) floats keeps each group of
-// eight lanes' 16-byte loads on distinct banks.
+// 4).  The stride of 20 (BW = 4) or 28 (BW = 5) floats keeps the loads of
+// consecutive (a, c) on distinct banks.
 __host__ __device__ constexpr int tab_jk_stride(int bw) { return bw == 5 ? 28 : 20; }
+
+// Stride of the x-nodes in the tables, in floats: nb * 3 * JKS, padded.  The
+// lanes that build a row table read the 15 (i, c) entries of one bin together,
+// and unpadded (a multiple of 64 floats at 64 bins) all five x-nodes of one
+// coefficient would sit on the same banks.  Padded to -4 mod 64 floats (BW =
+// 4), the 16-byte loads of any 8 consecutive (i, c) take distinct 16-byte
+// slots of 128 bytes, and those of all 15 distinct slots of 256 bytes; padded
+// to 3 mod 64 (BW = 5, 4-byte loads), the 15 fall on distinct banks of 32 and
+// of 64.
+__host__ __device__ constexpr int tab_i_stride(int nb, int bw)
+{
+    const int s = nb * 3 * tab_jk_stride(bw), want = bw == 5 ? 3 : 60;
+    return s + ((want - s % 64) % 64 + 64) % 64;
+}
+
+// Floats of the tables, rounded up to 16 bytes (the alpha values follow).
+__host__ __device__ constexpr int tab_floats(int nb, int bw) { return (kXN * tab_i_stride(nb, bw) + 3) / 4 * 4; }
 
 // Offset of the tables in the gradient pass's LDS: after the item's FFD x
 // weights and node block, rounded up to 16 bytes.
@@ -1682,8 +1699,7 @@ __host__ __device__ constexpr int grad_nreg_padded(int bw) { return (kXN * bw * 
 
 size_t grad_lds_bytes(const Geom &g, int gnx, int gny, int gnz)
 {
-    const size_t tab = (size_t)kXN * g.nb * 3 * tab_jk_stride(g.bw) * sizeof(float) +
-                       (size_t)grad_nreg_padded(g.bw) * sizeof(float);
+    const size_t tab = (size_t)tab_floats(g.nb, g.bw) * sizeof(float) + (size_t)grad_nreg_padded(g.bw) * sizeof(float);
     const size_t scratch = (size_t)(kGradThreads / kWave) * g.gscr * sizeof(float);
     return grad_tab_offset(g.xw, gnx * gny * gnz * 3) + tab + scratch;
 }
@@ -1769,10 +1785,11 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
     const int nG = it.gnx * it.gny * it.gnz * 3;
     float4 *bxw = reinterpret_cast<float4 *>(smem);                     // FFD x weights of the item's x range
     double *G = reinterpret_cast<double *>(bxw + g.xw);                 // [gnz][gny][gnx][3]
-    float *tab = reinterpret_cast<float *>(smem + grad_tab_offset(g.xw, nG));   // [kXN][nb][3][JKS]
+    float *tab = reinterpret_cast<float *>(smem + grad_tab_offset(g.xw, nG));   // [kXN (stride TS)][nb][3][JKS]
     constexpr int NR = kXN * BW * BW;                                    // regions of the item's block
     constexpr int JKS = tab_jk_stride(BW);
-    float *alph = tab + kXN * nb * 3 * JKS;                              // [NR]
+    const int TS = tab_i_stride(nb, BW);
+    float *alph = tab + tab_floats(nb, BW);                              // [NR]
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
@@ -1832,7 +1849,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
             if (rl >= NR) break;
             const int ii = rl % kXN, jk = rl / kXN;
             if (lane < nb && check_ok(jk < JKS, kChkTabJK)) {
-                float *tq = tab + ((ii * nb + lane) * 3) * JKS + jk;
+                float *tq = tab + ii * TS + lane * 3 * JKS + jk;
                 tq[0] = ok[u] ? t0[u] : 0.0f;
                 tq[JKS] = ok[u] ? t1[u] : 0.0f;
                 tq[2 * JKS] = ok[u] ? t2[u] : 0.0f;
@@ -2016,7 +2033,7 @@ k_grad(const Geom *__restrict__ geoms, const WorkItem *__restrict__ items, Batch
                 float acc = 0.0f;
                 if (a <= (FA ? L - 1 : L)) {
                     const int i = FA ? r / 3 : r, c = FA ? r - 3 * i : 0;
-                    const float *tp = tab + ((i * nb + a) * 3 + c) * JKS + oyz;
+                    const float *tp = tab + i * TS + (a * 3 + c) * JKS + oyz;
                     if constexpr (BW == 4) {
 #pragma unroll
                         for (int kz = 0; kz < 4; ++kz) {
