@@ -49,9 +49,10 @@ def test_srwcr_loss_backward_matches_finite_differences(orc):
     ga = np.array([g[p] for p in pts])
     gra = np.array([gr[p] for p in pts])
     e_fd, e_an = rel(ga, fd), rel(ga, gra)
-    print(f"ctpet autograd: D={float(D):.12f} oracle={Dr:.12f}; vs FD {e_fd:.2e} "
+    Dv = float(D.detach())
+    print(f"ctpet autograd: D={Dv:.12f} oracle={Dr:.12f}; vs FD {e_fd:.2e} "
           f"(oracle analytic vs FD {rel(gra, fd):.2e}); vs oracle analytic {e_an:.2e}", flush=True)
-    assert abs(float(D) - Dr) <= 1e-5 * Dr
+    assert abs(Dv - Dr) <= 1e-5 * Dr
     assert e_an <= 1e-4
     # FD truncation and Parzen / trilinear kink crossings inside the 2h step:
     # the oracle's own analytic gradient sits 7.5e-4 from these differences
